@@ -1,0 +1,209 @@
+"""Python access to the plain serial FP64 oracle (``vdac_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Imported by ``tests/``, by ``__graft_entry__.smoke()`` and by the
+CPU-baseline leg of ``bench.py``; never by the product package.  It shares no code with the GPU
+library: it has its own C source, its own header and this ctypes wrapper.
+
+Arrays at this interface are float64 numpy arrays ``[4, ny, nx]`` holding (rho, rho*u, rho*v, p)
+with the pressure itself.  Single-point helpers take the internal conserved vector
+Q = (rho, rho*u, rho*v, p/beta) of the paper's compact form (Sec. 2.1.2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vdac_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+BC_WALL = 0
+BC_PERIODIC = 1
+
+
+def build() -> str:
+    """Compile the oracle (plain C99, -O2, no contraction, no fast-math)."""
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-Wall",
+           "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("bc", ctypes.c_int * 4),
+        ("solid", ctypes.POINTER(ctypes.c_ubyte)),
+        ("stages", ctypes.c_int),
+        ("alpha", ctypes.c_double * 8),
+        ("cfl", ctypes.c_double),
+        ("k", ctypes.c_double),
+        ("local_dtau", ctypes.c_int),
+        ("bdf", ctypes.c_int),
+        ("wall_slip", ctypes.c_int),
+    ]
+
+
+class _Detail(ctypes.Structure):
+    _fields_ = [(name, ctypes.POINTER(ctypes.c_double))
+                for name in ("prim", "grad", "fx", "fy", "resid", "dtau")]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_limiter.restype = ctypes.c_double
+        L.orc_limiter.argtypes = [ctypes.c_double] * 3
+        for name in ("orc_flux_phys",):
+            getattr(L, name).argtypes = [dp, ctypes.c_double, dp]
+        L.orc_eigen.argtypes = [dp, ctypes.c_double, dp, dp, dp]
+        L.orc_abs_jacobian.argtypes = [dp, ctypes.c_double, dp]
+        L.orc_osher_x.argtypes = [dp, dp, ctypes.c_double, dp]
+        L.orc_face_flux.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_stage.restype = ctypes.c_int
+        L.orc_stage.argtypes = [ctypes.POINTER(_Problem), dp, dp, dp, dp, ctypes.c_double,
+                                ctypes.c_int, dp, ctypes.POINTER(_Detail)]
+        L.orc_step.restype = ctypes.c_int
+        L.orc_step.argtypes = [ctypes.POINTER(_Problem), dp, dp, ctypes.c_double, ctypes.c_int,
+                               ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@dataclass
+class Problem:
+    """Grid, physics and pseudo-time settings of one tank."""
+    nx: int
+    ny: int
+    lx: float
+    ly: float
+    gx: float = 0.0
+    gy: float = -9.81
+    beta: float = 1000.0
+    bc: tuple = (BC_WALL, BC_WALL, BC_WALL, BC_WALL)
+    solid: np.ndarray | None = None
+    stages: int = 3
+    alpha: tuple = (1.0 / 3.0, 0.5, 1.0)
+    cfl: float = 0.48
+    k: float = 1.0
+    local_dtau: bool = True
+    bdf: int = 1
+    wall_slip: bool = False
+    _keep: list = field(default_factory=list, repr=False)
+
+    def c_struct(self) -> _Problem:
+        p = _Problem()
+        p.nx, p.ny, p.lx, p.ly = self.nx, self.ny, self.lx, self.ly
+        p.gx, p.gy, p.beta = self.gx, self.gy, self.beta
+        for i in range(4):
+            p.bc[i] = int(self.bc[i])
+        if self.solid is not None:
+            s = np.ascontiguousarray(self.solid, dtype=np.uint8)
+            assert s.shape == (self.ny, self.nx)
+            self._keep = [s]
+            p.solid = s.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
+        p.stages = self.stages
+        for i, a in enumerate(self.alpha):
+            p.alpha[i] = a
+        p.cfl, p.k = self.cfl, self.k
+        p.local_dtau = int(bool(self.local_dtau))
+        p.bdf = self.bdf
+        p.wall_slip = int(bool(self.wall_slip))
+        return p
+
+
+def limiter(a: float, b: float, k: float) -> float:
+    return lib().orc_limiter(a, b, k)
+
+
+def flux_phys(q, beta):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    f = np.zeros(4)
+    lib().orc_flux_phys(_ptr(q), beta, _ptr(f))
+    return f
+
+
+def eigen(q, beta):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    R, L, lam = np.zeros(16), np.zeros(16), np.zeros(4)
+    lib().orc_eigen(_ptr(q), beta, _ptr(R), _ptr(L), _ptr(lam))
+    return R.reshape(4, 4), L.reshape(4, 4), lam
+
+
+def abs_jacobian(q, beta):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    A = np.zeros(16)
+    lib().orc_abs_jacobian(_ptr(q), beta, _ptr(A))
+    return A.reshape(4, 4)
+
+
+def osher_x(ql, qr, beta):
+    ql = np.ascontiguousarray(ql, dtype=np.float64)
+    qr = np.ascontiguousarray(qr, dtype=np.float64)
+    f = np.zeros(4)
+    lib().orc_osher_x(_ptr(ql), _ptr(qr), beta, _ptr(f))
+    return f
+
+
+def face_flux(qa, qb, normal, beta):
+    qa = np.ascontiguousarray(qa, dtype=np.float64)
+    qb = np.ascontiguousarray(qb, dtype=np.float64)
+    f = np.zeros(4)
+    lib().orc_face_flux(_ptr(qa), _ptr(qb), float(normal[0]), float(normal[1]), beta, _ptr(f))
+    return f
+
+
+def stage(pb: Problem, qprev, q0, qn, dt, s, qnm1=None):
+    """One Runge-Kutta stage; returns (q_out, detail dict)."""
+    ny, nx = pb.ny, pb.nx
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
+            for a in (qprev, q0, qn, qnm1)]
+    out = np.zeros((4, ny, nx))
+    det = {"prim": np.zeros((4, ny, nx)), "grad": np.zeros((8, ny, nx)),
+           "fx": np.zeros((4, ny, nx + 1)), "fy": np.zeros((4, ny + 1, nx)),
+           "resid": np.zeros((4, ny, nx)), "dtau": np.zeros((ny, nx))}
+    d = _Detail(*[_ptr(det[k]) for k in ("prim", "grad", "fx", "fy", "resid", "dtau")])
+    st = pb.c_struct()
+    rc = lib().orc_stage(ctypes.byref(st), _ptr(arrs[0]), _ptr(arrs[1]), _ptr(arrs[2]),
+                         _ptr(arrs[3]), dt, s, _ptr(out), ctypes.byref(d))
+    if rc != 0:
+        raise ValueError(f"orc_stage returned {rc}")
+    return out, det
+
+
+def step(pb: Problem, q, dt, max_pseudo, tol=0.0, norm=0, qnm1=None):
+    """One real-time step.  Returns (q_new, iterations, norms[4], status)."""
+    q = np.array(q, dtype=np.float64, order="C", copy=True)
+    assert q.shape == (4, pb.ny, pb.nx)
+    qm = None if qnm1 is None else np.ascontiguousarray(qnm1, dtype=np.float64)
+    it = ctypes.c_int(0)
+    res = np.zeros(4)
+    st = pb.c_struct()
+    rc = lib().orc_step(ctypes.byref(st), _ptr(q), _ptr(qm), dt, int(max_pseudo), float(tol),
+                        int(norm), ctypes.byref(it), _ptr(res))
+    if rc == -1:
+        raise ValueError("orc_step: invalid arguments")
+    return q, it.value, res, rc
