@@ -1,0 +1,163 @@
+"""Benchmark: cell-updates per second per pseudo-time stage of the dual-time Godunov solver.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dam_break] [--precision f64]
+
+A step is one real-time step (Algorithm 1): level n <- state, then pseudo-iterations of
+s_max Runge-Kutta stages until the RMS residual is below the workload's tolerance or the
+iteration cap is reached.  The default workload is the 512 x 256 dam break (water column
+x < 1, y < 1 in a 4 x 2 walled tank, beta = 1100, dt = 1e-4, up to 100 pseudo-iterations to an
+RMS residual of 1e-6) in FP64, synthetic initial data.  The state stays resident in HBM for the
+whole timed region; nothing crosses PCIe inside it except the per-step status read.
+
+value = fluid cells x stages executed / seconds over exactly K timed steps.  The roofline entry
+is the Runge-Kutta stage kernel: algorithmic bytes per launch (109.3 B per fluid cell for FP64,
+the mean of 88 B at stage 1 and 120 B at later stages of a three-stage scheme) divided by its
+mean launch duration, measured with HIP events on the library's stream during the timed region.
+cpu_baseline times the serial FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_CELL_STAGE = {       # algorithmic bytes per fluid cell per stage, three-stage mean
+    "f64": (88.0 + 120.0 + 120.0) / 3.0,
+}
+
+
+def build_workload(name: str, precision: str):
+    from paper_2108_08769_amd import workloads as wl
+    if name == "dam_break":
+        return wl.dam_break(precision=precision)
+    if name == "hydrostatic":
+        return wl.hydrostatic()
+    if name == "rayleigh_taylor":
+        return wl.rayleigh_taylor(precision=precision)
+    if name == "obstacle_dam_break":
+        return wl.obstacle_dam_break(precision=precision)
+    if name == "sloshing_ensemble":
+        return wl.sloshing_ensemble(precision=precision)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(wk, budget_s: float):
+    """The oracle as it stands (serial FP64 C), timed on a bounded sample of the workload: the
+    first real step with as many pseudo-iterations as fit the budget (estimated from one)."""
+    import numpy as np
+    import oracle
+    t = wk.tanks[0]
+    pb = oracle.Problem(t.nx, t.ny, t.lx, t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
+                        solid=t.solid, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl, k=wk.k,
+                        local_dtau=wk.local_dtau, bdf=1)
+    t0 = time.perf_counter()
+    oracle.step(pb, t.q, wk.dt, 1, 0.0)
+    one = time.perf_counter() - t0
+    iters = int(max(1, min(wk.max_pseudo, budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    _, it, _, rc = oracle.step(pb, t.q, wk.dt, iters, 0.0)
+    dt = time.perf_counter() - t0
+    cell_stages = t.fluid_cells * wk.stages * it
+    return {"value": cell_stages / dt, "unit": "cell-updates/s per pseudo-time stage",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{wk.name}: first real step, {it} pseudo-iterations x {wk.stages} stages "
+                      f"({cell_stages:.3g} cell-stages, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dam_break")
+    ap.add_argument("--precision", default="f64")
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle time for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-stage-timing", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this solver has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2108_08769_amd import vdac
+
+    wk = build_workload(args.workload, args.precision)
+    tanks = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
+                  solid=t.solid) for t in wk.tanks]
+    opts = vdac.make_options(precision=wk.precision, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl,
+                             k=wk.k, bdf=wk.bdf)
+    torch.cuda.set_device(0)
+    grid = vdac.Grid(tanks, opts)
+    for i, t in enumerate(wk.tanks):
+        grid.set_state(i, t.q)
+    for _ in range(args.warmup):
+        grid.step(wk.dt, wk.max_pseudo, wk.tol)
+    torch.cuda.synchronize()
+
+    if not args.no_stage_timing:
+        grid.stage_timing(True)
+    iters = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, done = grid.step(wk.dt, wk.max_pseudo, wk.tol)
+        iters += int(done.sum())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    fluid = wk.fluid_cells
+    if len(wk.tanks) == 1:
+        cell_stages = float(fluid) * wk.stages * iters
+    else:
+        cell_stages = None
+    roofline = None
+    if not args.no_stage_timing:
+        kms, launches, kcs = grid.stage_timing_read()
+        cell_stages = kcs if cell_stages is None else cell_stages
+        if launches > 0 and kms > 0:
+            bpc = BYTES_PER_CELL_STAGE[wk.precision]
+            avg_s = kms / 1e3 / launches
+            bytes_per_launch = bpc * kcs / launches
+            achieved = bytes_per_launch / avg_s / 1e9
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "stage", "avg_launch_us": round(avg_s * 1e6, 3),
+                        "launches": launches, "bytes_per_launch": bytes_per_launch,
+                        "kernel_share": round(kms / 1e3 / elapsed, 4)}
+    value = cell_stages / elapsed
+    grid.close()
+
+    line = {
+        "metric": "cell-updates/s per pseudo-time stage",
+        "value": value,
+        "unit": "cell-updates/s per pseudo-time stage",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if wk.precision == "f64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wk.name, "cells": fluid, "precision": wk.precision,
+                   "dt": wk.dt, "max_pseudo": wk.max_pseudo, "tol": wk.tol,
+                   "rk_stages": wk.stages, "pseudo_iterations": iters},
+        "roofline": roofline,
+    }
+    if args.cpu_budget > 0:
+        line["cpu_baseline"] = cpu_baseline(wk, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

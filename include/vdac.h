@@ -1,0 +1,133 @@
+/*
+ * vdac.h -- C ABI of the MI355X (gfx950) solver for the inviscid variable-density
+ * artificial-compressibility equations with dual time stepping, after Leakey, Glenis & Hewett,
+ * "Riemann solvers and pressure gradients in Godunov-type schemes for variable density
+ * incompressible flows" (arXiv:2108.08769).
+ *
+ * One call of step_dual_time advances every tank of a grid by one real-time step (Algorithm 1,
+ * Sec. 2.2.2): level n <- current state, then explicit Runge-Kutta pseudo-time iterations
+ * (eqs. RK1-RK2) until every residual norm is below the tolerance.  Each Runge-Kutta stage runs,
+ * on the GPU and per cell: limited MUSCL gradients of rho, u, v (Sec. 2.3.1), the new pressure
+ * gradient from the rearranged momentum equation (Sec. 2.3.2), face states, the
+ * Osher-Dumbser-Toro flux (Sec. 2.4.3) rotated to each face (Sec. 2.4), the flux divergence,
+ * the real-time and body-force sources frozen at stage 0 and the point-implicit update
+ * (eq. point_implicit), with the local pseudo-time step of Sec. 2.2.3.  Walls are ghost cells
+ * with zero-gradient rho and p, mirrored velocity and reversed gravity (Sec. 2.5).
+ *
+ * Conventions shared by every entry point
+ *   - Host state arrays are float64 structure-of-arrays planes [4][ny][nx], x fastest, holding
+ *     (rho, rho*u, rho*v, p) -- the pressure itself, not p/beta.
+ *   - Every function returns a VDAC_* status and never aborts or throws across the ABI; on
+ *     failure last_error() describes the cause (thread-local, valid until the next call).
+ *   - A grid is not thread-safe; distinct grids are independent.  All device work is issued on
+ *     the stream given to create_grid.  Host buffers are owned by the caller and copied
+ *     synchronously: the library keeps no pointer to them.
+ */
+#ifndef VDAC_H
+#define VDAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vdac_grid vdac_grid; /* opaque, owned by the library */
+
+enum {
+    VDAC_OK = 0,
+    VDAC_E_INVALID = 1,  /* bad argument, shape or option */
+    VDAC_E_NOMEM = 2,    /* device allocation failed or workspace too small */
+    VDAC_E_DEVICE = 3,   /* a HIP call failed */
+    VDAC_E_DIVERGED = 4  /* non-finite residual or rho <= 0 during stepping */
+};
+
+/* Boundary kind per side, in the order x-, x+, y-, y+ (periodic sides must come in pairs). */
+enum { VDAC_BC_WALL = 0, VDAC_BC_PERIODIC = 1 };
+
+enum { VDAC_FP64 = 0, VDAC_FP32_MIXED = 1 };
+enum { VDAC_NORM_RMS = 0, VDAC_NORM_MAX = 1 };
+
+/* One tank: a rectangle of nx * ny cells of size (lx/nx) x (ly/ny). */
+typedef struct {
+    int32_t nx, ny;
+    double lx, ly;
+    double gx, gy;        /* gravity */
+    double beta;          /* artificial compressibility coefficient (Sec. 2.1.1), > 0 */
+    int32_t bc[4];        /* VDAC_BC_* for x-, x+, y-, y+ */
+    const uint8_t *solid; /* nullable host mask [ny][nx], nonzero = solid cell; copied at
+                             create_grid.  Each fluid-solid face acts as a wall.  Solid cells keep
+                             the state given to set_state. */
+} vdac_tank;
+
+typedef struct {
+    int32_t precision;   /* VDAC_FP64 or VDAC_FP32_MIXED */
+    int32_t rk_stages;   /* s_max, 1..8 */
+    double rk_alpha[8];  /* alpha_1..alpha_smax; alpha_smax must be 1 (Sec. 2.2.2) */
+    double cfl_tau;      /* pseudo-time Courant number (Sec. 2.2.3), > 0 */
+    double limiter_k;    /* k-limiter: 1 minmod, 2 superbee, in [1, 2] (Sec. 2.3.1) */
+    int32_t local_dtau;  /* must be 1: local pseudo-time steps (Sec. 2.2.3) */
+    int32_t bdf_order;   /* 1 backward Euler, 2 BDF2 (Table 1) */
+    int32_t norm;        /* VDAC_NORM_RMS or VDAC_NORM_MAX over fluid cells */
+    int32_t wall_slip;   /* 0: no-slip wall ghosts as in Sec. 2.5; 1: free-slip ghosts */
+    int32_t tile_x, tile_y; /* 0 = automatic choice */
+} vdac_options;
+
+/* Fills o with the defaults: FP64, 3 stages alpha = (1/3, 1/2, 1), CFL_tau 0.48, minmod,
+ * local dtau, backward Euler, RMS norm, no-slip walls, automatic tiles. */
+void vdac_default_options(vdac_options *o);
+
+/* Device bytes create_grid needs for these tanks and options (0 on invalid arguments). */
+size_t workspace_bytes(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o);
+
+/* Builds a grid of n_tanks independent tanks.  o may be NULL (defaults).  device_workspace, if
+ * not NULL, is a device buffer of at least ws_bytes >= workspace_bytes(...) bytes that the
+ * library borrows until destroy_grid (the caller keeps it alive); if NULL the library allocates
+ * and frees its own.  hip_stream is a hipStream_t (NULL = the null stream).  The initial state
+ * of every tank is rho = 1, zero velocity and pressure until set_state is called. */
+int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
+                void *device_workspace, size_t ws_bytes, void *hip_stream, vdac_grid **out);
+
+/* Sets the state of one tank from a host array q [4][ny][nx] (rho, rho*u, rho*v, p).  Also
+ * sets level n to q and discards the BDF2 history, so the next step uses backward Euler
+ * (Sec. 2.2.2).  rho must be finite and > 0 in every fluid cell, else VDAC_E_INVALID. */
+int set_state(vdac_grid *g, int32_t tank, const double *q);
+
+/* One real-time step of size dt > 0 for every tank (Algorithm 1).  Pseudo-iterations stop per
+ * tank once every residual norm is below tol; tol <= 0 runs exactly max_pseudo iterations.
+ * pseudo_done (nullable, [n_tanks]) receives the iterations each tank ran.  Returns
+ * VDAC_E_DIVERGED if any tank produced a non-finite residual or rho <= 0 (that tank stops; its
+ * state is the one after the failing iteration). */
+int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol,
+                   int32_t *pseudo_done);
+
+/* Residual norms (rho, rho*u, rho*v, p) of the last pseudo-iteration of one tank: the norm of
+ * the last Runge-Kutta stage's bracket, the p row as beta times the p/beta row (= dp/dtau). */
+int residual_norm(const vdac_grid *g, int32_t tank, double out[4]);
+
+/* Copies one tank's state to the host array q [4][ny][nx] (rho, rho*u, rho*v, p). */
+int get_state(const vdac_grid *g, int32_t tank, double *q);
+
+/* Measurement: while enabled, step_dual_time brackets every Runge-Kutta stage kernel it
+ * launches with a pair of HIP events on the grid's stream and accumulates their elapsed times;
+ * enabling resets the totals.  The events add a marker on each side of each stage launch and
+ * nothing else. */
+int stage_timing(vdac_grid *g, int32_t enable);
+
+/* Totals since stage timing was enabled: summed stage-kernel milliseconds, number of stage
+ * launches, and fluid cell-stages those launches updated (launches of tanks that had already
+ * stopped count neither time nor cells).  Any output pointer may be NULL. */
+int stage_timing_read(const vdac_grid *g, double *kernel_ms, int64_t *launches,
+                      double *cell_stages);
+
+/* Frees the grid (and the device memory it allocated).  NULL is ignored. */
+void destroy_grid(vdac_grid *g);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,407 @@
+// kernels_f64.hip -- FP64 kernels of one real-time step on gfx950: begin-of-step bookkeeping,
+// the Runge-Kutta stage and the deterministic residual finalize.
+//
+// stage_direct_f64 is the plain form of a stage: one thread per cell, which reconstructs itself
+// and its four neighbours and evaluates all four of its faces.  Every face is therefore computed
+// twice across the grid (once per side, with identical operands in identical order, so both
+// sides agree bit for bit and the scheme stays conservative).
+#include <hip/hip_runtime.h>
+
+#include "vdac_device.h"
+#include "vdac_internal.h"
+
+namespace vdac {
+
+namespace {
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ Prim<double> load_prim(const double *q, size_t plane, size_t c)
+{
+    Prim<double> w;
+    w.r = q[c];
+    w.u = q[plane + c] / w.r;
+    w.v = q[2 * plane + c] / w.r;
+    w.p = q[3 * plane + c];
+    return w;
+}
+
+// A fluid cell as the reconstruction sees it: W, limited slopes along x and y, and the stage-0
+// sources (real-time term of rho, rho u, rho v and rho^0 for the body force).
+struct CellRec {
+    Prim<double> w;
+    Slope<double> gx, gy;
+    double d_r, d_ru, d_rv, rho0;
+};
+
+__device__ __forceinline__ void reconstruct(const TankDev &t, const Scheme &sc,
+                                            const StepParams &sp, const double *qprev,
+                                            const double *q0, int i, int j, CellRec &rec)
+{
+    const size_t plane = t.plane;
+    const size_t c = (size_t)j * t.nx + i;
+    const uint8_t f = t.flags[c];
+    const bool slip = sc.slip != 0;
+    rec.w = load_prim(qprev, plane, c);
+    // a wall face shows the cell its own mirror image (Sec. 2.5)
+    Prim<double> xm = (f & FLAG_WALL_XM) ? mirror(rec.w, 0, slip)
+                                         : load_prim(qprev, plane, (size_t)j * t.nx + wrap(i - 1, t.nx));
+    Prim<double> xp = (f & FLAG_WALL_XP) ? mirror(rec.w, 0, slip)
+                                         : load_prim(qprev, plane, (size_t)j * t.nx + wrap(i + 1, t.nx));
+    Prim<double> ym = (f & FLAG_WALL_YM) ? mirror(rec.w, 1, slip)
+                                         : load_prim(qprev, plane, (size_t)wrap(j - 1, t.ny) * t.nx + i);
+    Prim<double> yp = (f & FLAG_WALL_YP) ? mirror(rec.w, 1, slip)
+                                         : load_prim(qprev, plane, (size_t)wrap(j + 1, t.ny) * t.nx + i);
+    rec.gx = slopes(xm, rec.w, xp, t.inv_dx, sc.k);
+    rec.gy = slopes(ym, rec.w, yp, t.inv_dy, sc.k);
+    // real-time term (B0 Q^0 + B1 Q^n + B2 Q^{n-1})/dt on rho, rho u, rho v (eq. bdf)
+    const double *qn = t.level_n;
+    double num[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        num[k] = sp.b0 * q0[k * plane + c] + sp.b1 * qn[k * plane + c];
+        if (sp.b2 != 0.0) num[k] += sp.b2 * t.level_nm1[k * plane + c];
+    }
+    rec.d_r = num[0] * sp.inv_dt;
+    rec.d_ru = num[1] * sp.inv_dt;
+    rec.d_rv = num[2] * sp.inv_dt;
+    rec.rho0 = q0[c];
+}
+
+// State of a reconstructed cell at its face on side sd (+1 / -1) of axis (0 = x, 1 = y):
+// W + grad W . (x_f - x_i), with the new pressure gradient for p.
+__device__ __forceinline__ Prim<double> own_state(const TankDev &t, const CellRec &c, int axis,
+                                                  int sd)
+{
+    Prim<double> s;
+    if (axis == 0) {
+        const double h = sd > 0 ? t.half_dx : -t.half_dx;
+        const double px = gradp_x(c.w, c.gx, c.gy, c.d_ru, c.rho0 * t.gx);
+        s.r = c.w.r + c.gx.r * h;
+        s.u = c.w.u + c.gx.u * h;
+        s.v = c.w.v + c.gx.v * h;
+        s.p = c.w.p + px * h;
+    } else {
+        const double h = sd > 0 ? t.half_dy : -t.half_dy;
+        const double py = gradp_y(c.w, c.gx, c.gy, c.d_rv, c.rho0 * t.gy);
+        s.r = c.w.r + c.gy.r * h;
+        s.u = c.w.u + c.gy.u * h;
+        s.v = c.w.v + c.gy.v * h;
+        s.p = c.w.p + py * h;
+    }
+    return s;
+}
+
+// State of the wall ghost on side sd of axis, at the face it shares with cell c.  The ghost
+// mirrors c and its stencil mirrors c's stencil, so (limiter symmetric and odd) its slope normal
+// to the wall equals c's and its tangential slopes are c's with the mirror's signs; its sources
+// are mirrored and gravity is reversed in it (Sec. 2.5).
+__device__ __forceinline__ Prim<double> ghost_state(const TankDev &t, const CellRec &c, int axis,
+                                                    int sd, bool slip)
+{
+    const double su = (!slip || axis == 0) ? -1.0 : 1.0;  // mirror sign of u
+    const double sv = (!slip || axis == 1) ? -1.0 : 1.0;  // mirror sign of v
+    Prim<double> w = {c.w.r, su * c.w.u, sv * c.w.v, c.w.p};
+    Prim<double> s;
+    if (axis == 0) {
+        Slope<double> gx = c.gx;
+        Slope<double> gy = {c.gy.r, su * c.gy.u, sv * c.gy.v};
+        const double px = gradp_x(w, gx, gy, su * c.d_ru, -(c.rho0 * t.gx));
+        const double h = sd > 0 ? -t.half_dx : t.half_dx;  // ghost's face toward c
+        s.r = w.r + gx.r * h;
+        s.u = w.u + gx.u * h;
+        s.v = w.v + gx.v * h;
+        s.p = w.p + px * h;
+    } else {
+        Slope<double> gy = c.gy;
+        Slope<double> gx = {c.gx.r, su * c.gx.u, sv * c.gx.v};
+        const double py = gradp_y(w, gx, gy, sv * c.d_rv, -(c.rho0 * t.gy));
+        const double h = sd > 0 ? -t.half_dy : t.half_dy;
+        s.r = w.r + gy.r * h;
+        s.u = w.u + gy.u * h;
+        s.v = w.v + gy.v * h;
+        s.p = w.p + py * h;
+    }
+    return s;
+}
+
+// Pseudo-time step of Sec. 2.2.3 in 2D: CFL dx dy / ((|u| + c_x) dy/2 + (|v| + c_y) dx/2).
+__device__ __forceinline__ double local_dtau(const TankDev &t, double cfl, double rho, double u,
+                                             double v)
+{
+    const double cx = sqrt(u * u + 4.0 * t.beta / rho);
+    const double cy = sqrt(v * v + 4.0 * t.beta / rho);
+    const double lx = 0.5 * (fabs(u) + cx) * t.dy;
+    const double ly = 0.5 * (fabs(v) + cy) * t.dx;
+    return cfl * (t.dx * t.dy) / (lx + ly);
+}
+
+template <bool NORM_MAX>
+__device__ __forceinline__ double combine(double a, double b)
+{
+    return NORM_MAX ? (a > b || a != a ? a : b) : a + b;
+}
+
+// Workgroup reduction of the residual partials (fixed order: deterministic).
+template <bool NORM_MAX, int NT>
+__device__ __forceinline__ void block_reduce_store(double v[kPartialWidth], double *out)
+{
+#pragma unroll
+    for (int k = 0; k < kPartialWidth; ++k) {
+        double x = v[k];
+        const bool mx = NORM_MAX && k < 4;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double y = __shfl_xor(x, off, 64);
+            x = mx ? combine<true>(x, y) : x + y;
+        }
+        v[k] = x;
+    }
+    __shared__ double red[NT / 64][kPartialWidth];
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0)
+        for (int k = 0; k < kPartialWidth; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (tid == 0) {
+        for (int k = 0; k < kPartialWidth; ++k) {
+            double x = red[0][k];
+            for (int w = 1; w < NT / 64; ++w)
+                x = (NORM_MAX && k < 4) ? combine<true>(x, red[w][k]) : x + red[w][k];
+            out[k] = x;
+        }
+    }
+}
+
+constexpr int kDirectTX = 16, kDirectTY = 16;
+
+template <bool NORM_MAX>
+__global__ void __launch_bounds__(kDirectTX *kDirectTY)
+    stage_direct_f64(TankDev t, Scheme sc, int stage)
+{
+    const Status *st = t.status;
+    if (st->done) return;
+    const int cur = st->cur;
+    const StageBuffers b = stage_buffers(cur, stage);
+    const double *qprev = t.state[b.in];
+    const double *q0 = t.state[cur];
+    double *qout = t.state[b.out];
+    const StepParams sp = *t.step;
+    const double alpha = sc.alpha[stage - 1];
+    const bool last = (stage == sc.smax);
+    const bool slip = sc.slip != 0;
+    const size_t plane = t.plane;
+
+    const int i = blockIdx.x * kDirectTX + threadIdx.x;
+    const int j = blockIdx.y * kDirectTY + threadIdx.y;
+    double part[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+    if (i < t.nx && j < t.ny) {
+        const size_t c = (size_t)j * t.nx + i;
+        const uint8_t f = t.flags[c];
+        if (!(f & FLAG_SOLID)) {
+            CellRec me;
+            reconstruct(t, sc, sp, qprev, q0, i, j, me);
+            double Fxm[4], Fxp[4], Fym[4], Fyp[4];
+            {
+                Prim<double> L, R;
+                R = own_state(t, me, 0, -1);
+                if (f & FLAG_WALL_XM) {
+                    L = ghost_state(t, me, 0, -1, slip);
+                } else {
+                    CellRec nb;
+                    reconstruct(t, sc, sp, qprev, q0, wrap(i - 1, t.nx), j, nb);
+                    L = own_state(t, nb, 0, +1);
+                }
+                osher_x(L, R, t.beta, t.inv_beta, Fxm);
+                L = own_state(t, me, 0, +1);
+                if (f & FLAG_WALL_XP) {
+                    R = ghost_state(t, me, 0, +1, slip);
+                } else {
+                    CellRec nb;
+                    reconstruct(t, sc, sp, qprev, q0, wrap(i + 1, t.nx), j, nb);
+                    R = own_state(t, nb, 0, -1);
+                }
+                osher_x(L, R, t.beta, t.inv_beta, Fxp);
+                R = own_state(t, me, 1, -1);
+                if (f & FLAG_WALL_YM) {
+                    L = ghost_state(t, me, 1, -1, slip);
+                } else {
+                    CellRec nb;
+                    reconstruct(t, sc, sp, qprev, q0, i, wrap(j - 1, t.ny), nb);
+                    L = own_state(t, nb, 1, +1);
+                }
+                osher_y(L, R, t.beta, t.inv_beta, Fym);
+                L = own_state(t, me, 1, +1);
+                if (f & FLAG_WALL_YP) {
+                    R = ghost_state(t, me, 1, +1, slip);
+                } else {
+                    CellRec nb;
+                    reconstruct(t, sc, sp, qprev, q0, i, wrap(j + 1, t.ny), nb);
+                    R = own_state(t, nb, 1, -1);
+                }
+                osher_y(L, R, t.beta, t.inv_beta, Fyp);
+            }
+            // bracket of eq. RK2 and the point-implicit update (eq. point_implicit)
+            const double r0 = q0[c], m0 = q0[plane + c], n0 = q0[2 * plane + c];
+            const double p0 = q0[3 * plane + c];
+            const double dtau = local_dtau(t, t.cfl, r0, m0 / r0, n0 / r0);
+            const double src[3] = {-me.d_r, -me.d_ru + r0 * t.gx, -me.d_rv + r0 * t.gy};
+            const double base[3] = {r0, m0, n0};
+            const double ad = alpha * dtau;
+            const double api = 1.0 + sp.b0 * ad * sp.inv_dt;
+            double R4[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double div = (Fxp[k] - Fxm[k]) * t.inv_dx + (Fyp[k] - Fym[k]) * t.inv_dy;
+                R4[k] = -div + (k < 3 ? src[k] : 0.0);
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) qout[k * plane + c] = base[k] + (ad / api) * R4[k];
+            const double pnew = p0 + t.beta * (ad * R4[3]);
+            qout[3 * plane + c] = pnew;
+            if (last) {
+                const double rp = t.beta * R4[3];
+                if (NORM_MAX) {
+                    part[0] = fabs(R4[0]);
+                    part[1] = fabs(R4[1]);
+                    part[2] = fabs(R4[2]);
+                    part[3] = fabs(rp);
+                } else {
+                    part[0] = R4[0] * R4[0];
+                    part[1] = R4[1] * R4[1];
+                    part[2] = R4[2] * R4[2];
+                    part[3] = rp * rp;
+                }
+                const double rn = qout[c];
+                part[4] = (rn > 0.0 && rn < INFINITY) ? 0.0 : 1.0;
+            }
+        }
+    }
+    if (last) {
+        const int blk = blockIdx.x + blockIdx.y * gridDim.x;
+        block_reduce_store<NORM_MAX, kDirectTX * kDirectTY>(part, t.partials + (size_t)blk * kPartialWidth);
+    }
+}
+
+// Deterministic second pass of the residual: sums (or maxima) over the workgroup partials in a
+// fixed order, then the pseudo-loop control of the tank.
+template <bool NORM_MAX>
+__global__ void __launch_bounds__(256) finalize_kernel(TankDev t, Scheme sc, int n_blocks)
+{
+    Status *st = t.status;
+    if (st->done) return;
+    double acc[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < n_blocks; b += 256)
+        for (int k = 0; k < kPartialWidth; ++k) {
+            const double x = t.partials[(size_t)b * kPartialWidth + k];
+            acc[k] = (NORM_MAX && k < 4) ? combine<true>(acc[k], x) : acc[k] + x;
+        }
+    __shared__ double red[256][kPartialWidth];
+    for (int k = 0; k < kPartialWidth; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < kPartialWidth; ++k) {
+                const double y = red[threadIdx.x + s][k];
+                red[threadIdx.x][k] = (NORM_MAX && k < 4) ? combine<true>(red[threadIdx.x][k], y)
+                                                          : red[threadIdx.x][k] + y;
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double norms[4];
+        bool finite = true, below = true;
+        for (int k = 0; k < 4; ++k) {
+            norms[k] = NORM_MAX ? red[0][k] : sqrt(red[0][k] / (double)(t.n_fluid > 0 ? t.n_fluid : 1));
+            if (!(norms[k] < INFINITY)) finite = false;  // NaN or Inf
+            if (!(norms[k] < st->tol)) below = false;
+            st->norms[k] = norms[k];
+        }
+        const int iters = st->iters + 1;
+        const bool bad = !finite || red[0][4] > 0.0;
+        st->iters = iters;
+        st->cur = next_cur(st->cur, sc.smax);
+        if (bad) st->diverged = 1;
+        const bool converged = st->tol > 0.0 && below;
+        st->done = (bad || converged || iters >= st->max_pseudo) ? 1 : 0;
+    }
+}
+
+// Start of a real-time step (Algorithm 1): level n-1 <- level n (BDF2), level n <- current
+// state, the step's BDF coefficients, and a fresh pseudo-loop status.
+__global__ void __launch_bounds__(256)
+    begin_step_kernel(TankDev t, StepParams sp, int max_pseudo, double tol, int use_history)
+{
+    Status *st = t.status;
+    const double *q = t.state[st->cur];
+    const size_t plane = t.plane;
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < plane;
+         c += (size_t)gridDim.x * 256) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (use_history) t.level_nm1[k * plane + c] = t.level_n[k * plane + c];
+            t.level_n[k * plane + c] = q[k * plane + c];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *const_cast<StepParams *>(t.step) = sp;
+        st->iters = 0;
+        st->diverged = 0;
+        st->max_pseudo = max_pseudo;
+        st->tol = tol;
+        st->done = (max_pseudo <= 0) ? 1 : 0;
+    }
+}
+
+}  // namespace
+
+int stage_blocks(const TankDev &t, int, int)
+{
+    return ((t.nx + kDirectTX - 1) / kDirectTX) * ((t.ny + kDirectTY - 1) / kDirectTY);
+}
+
+int launch_begin_step(const TankDev &t, const Scheme &sc, double dt, int max_pseudo, double tol,
+                      int use_history, void *stream)
+{
+    StepParams sp;
+    sp.inv_dt = 1.0 / dt;
+    if (sc.bdf2 && use_history) {
+        sp.b0 = 1.5;
+        sp.b1 = -2.0;
+        sp.b2 = 0.5;
+    } else {
+        sp.b0 = 1.0;
+        sp.b1 = -1.0;
+        sp.b2 = 0.0;
+    }
+    size_t blocks = (t.plane + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(begin_step_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       (hipStream_t)stream, t, sp, max_pseudo, tol, use_history);
+    return (int)hipGetLastError();
+}
+
+int launch_stage_f64(const TankDev &t, const Scheme &sc, int stage, int, int, void *stream)
+{
+    dim3 grid((t.nx + kDirectTX - 1) / kDirectTX, (t.ny + kDirectTY - 1) / kDirectTY);
+    dim3 block(kDirectTX, kDirectTY);
+    if (sc.norm_max)
+        hipLaunchKernelGGL(stage_direct_f64<true>, grid, block, 0, (hipStream_t)stream, t, sc, stage);
+    else
+        hipLaunchKernelGGL(stage_direct_f64<false>, grid, block, 0, (hipStream_t)stream, t, sc, stage);
+    return (int)hipGetLastError();
+}
+
+int launch_finalize(const TankDev &t, const Scheme &sc, int n_blocks, void *stream)
+{
+    if (sc.norm_max)
+        hipLaunchKernelGGL(finalize_kernel<true>, dim3(1), dim3(256), 0, (hipStream_t)stream, t, sc,
+                           n_blocks);
+    else
+        hipLaunchKernelGGL(finalize_kernel<false>, dim3(1), dim3(256), 0, (hipStream_t)stream, t, sc,
+                           n_blocks);
+    return (int)hipGetLastError();
+}
+
+}  // namespace vdac

@@ -1,0 +1,556 @@
+// vdac_api.cpp -- host side of libvdac: argument checking, device memory layout, the real-time
+// step driver (Algorithm 1) and the C ABI declared in include/vdac.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vdac.h"
+#include "vdac_internal.h"
+
+using namespace vdac;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(VDAC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct TankLayout {
+    size_t state[3], level_n, level_nm1, flags, partials, status, step, end;
+};
+
+struct TankHost {
+    vdac_tank desc;
+    std::vector<uint8_t> flags;
+    TankDev dev;
+    int n_blocks;
+    int hist_ok;  // level n-1 holds a real-time level (BDF2 may be used)
+};
+
+}  // namespace
+
+struct vdac_grid {
+    std::vector<TankHost> tanks;
+    vdac_options opt;
+    Scheme sc;
+    hipStream_t stream;
+    char *ws;
+    bool own_ws;
+    size_t ws_bytes;
+    // stage-kernel timing (measurement only)
+    bool timing;
+    std::vector<hipEvent_t> ev_pool;
+    struct PendingTiming {
+        int start, stop;  // indices into ev_pool
+        int tank, iter;   // tank and pseudo-iteration (within the step) of the launch
+    };
+    std::vector<PendingTiming> ev_pending;
+    double t_ms;
+    int64_t t_launches;
+    double t_cell_stages;
+};
+
+namespace {
+
+int check_options(const vdac_options *o)
+{
+    if (o->precision != VDAC_FP64)
+        return fail(VDAC_E_INVALID, "precision %d is not available", o->precision);
+    if (o->rk_stages < 1 || o->rk_stages > 8)
+        return fail(VDAC_E_INVALID, "rk_stages must be 1..8 (got %d)", o->rk_stages);
+    for (int s = 0; s < o->rk_stages; ++s)
+        if (!(o->rk_alpha[s] > 0.0) || !std::isfinite(o->rk_alpha[s]))
+            return fail(VDAC_E_INVALID, "rk_alpha[%d] must be finite and > 0", s);
+    if (o->rk_alpha[o->rk_stages - 1] != 1.0)
+        return fail(VDAC_E_INVALID, "the last Runge-Kutta coefficient must be 1");
+    if (!(o->cfl_tau > 0.0) || !std::isfinite(o->cfl_tau))
+        return fail(VDAC_E_INVALID, "cfl_tau must be finite and > 0");
+    if (!(o->limiter_k >= 1.0 && o->limiter_k <= 2.0))
+        return fail(VDAC_E_INVALID, "limiter_k must lie in [1, 2]");
+    if (o->local_dtau != 1)
+        return fail(VDAC_E_INVALID, "only local pseudo-time steps are available (local_dtau = 1)");
+    if (o->bdf_order != 1 && o->bdf_order != 2)
+        return fail(VDAC_E_INVALID, "bdf_order must be 1 or 2");
+    if (o->norm != VDAC_NORM_RMS && o->norm != VDAC_NORM_MAX)
+        return fail(VDAC_E_INVALID, "norm must be VDAC_NORM_RMS or VDAC_NORM_MAX");
+    if (o->wall_slip != 0 && o->wall_slip != 1)
+        return fail(VDAC_E_INVALID, "wall_slip must be 0 or 1");
+    if (o->tile_x < 0 || o->tile_y < 0)
+        return fail(VDAC_E_INVALID, "tile sizes must be >= 0");
+    return VDAC_OK;
+}
+
+int check_tank(const vdac_tank *t, int idx)
+{
+    if (t->nx < 1 || t->ny < 1)
+        return fail(VDAC_E_INVALID, "tank %d: nx and ny must be >= 1", idx);
+    if ((long long)t->nx * (long long)t->ny > (1LL << 30))
+        return fail(VDAC_E_INVALID, "tank %d: more than 2^30 cells", idx);
+    if (!(t->lx > 0.0) || !(t->ly > 0.0) || !std::isfinite(t->lx) || !std::isfinite(t->ly))
+        return fail(VDAC_E_INVALID, "tank %d: lx and ly must be finite and > 0", idx);
+    if (!(t->beta > 0.0) || !std::isfinite(t->beta))
+        return fail(VDAC_E_INVALID, "tank %d: beta must be finite and > 0", idx);
+    if (!std::isfinite(t->gx) || !std::isfinite(t->gy))
+        return fail(VDAC_E_INVALID, "tank %d: gravity must be finite", idx);
+    for (int s = 0; s < 4; ++s)
+        if (t->bc[s] != VDAC_BC_WALL && t->bc[s] != VDAC_BC_PERIODIC)
+            return fail(VDAC_E_INVALID, "tank %d: bc[%d] must be VDAC_BC_WALL or VDAC_BC_PERIODIC", idx, s);
+    if ((t->bc[0] == VDAC_BC_PERIODIC) != (t->bc[1] == VDAC_BC_PERIODIC) ||
+        (t->bc[2] == VDAC_BC_PERIODIC) != (t->bc[3] == VDAC_BC_PERIODIC))
+        return fail(VDAC_E_INVALID, "tank %d: periodic sides must come in pairs", idx);
+    return VDAC_OK;
+}
+
+TankLayout layout_of(const vdac_tank *t, const vdac_options *o, int n_blocks)
+{
+    const size_t plane = (size_t)t->nx * (size_t)t->ny;
+    TankLayout L;
+    size_t off = 0;
+    for (int b = 0; b < 3; ++b) {
+        L.state[b] = off;
+        off += align256(4 * plane * sizeof(double));
+    }
+    L.level_n = off;
+    off += align256(3 * plane * sizeof(double));
+    L.level_nm1 = off;
+    if (o->bdf_order == 2) off += align256(3 * plane * sizeof(double));
+    L.flags = off;
+    off += align256(plane);
+    L.partials = off;
+    off += align256((size_t)n_blocks * kPartialWidth * sizeof(double));
+    L.status = off;
+    off += align256(sizeof(Status));
+    L.step = off;
+    off += align256(sizeof(StepParams));
+    L.end = off;
+    return L;
+}
+
+int blocks_for(const vdac_tank *t)
+{
+    TankDev d;
+    d.nx = t->nx;
+    d.ny = t->ny;
+    return stage_blocks(d, 0, 0);
+}
+
+void build_flags(const vdac_tank *t, std::vector<uint8_t> &flags, int *n_fluid)
+{
+    const int nx = t->nx, ny = t->ny;
+    const bool px = t->bc[0] == VDAC_BC_PERIODIC, py = t->bc[2] == VDAC_BC_PERIODIC;
+    flags.assign((size_t)nx * ny, 0);
+    auto solid = [&](int i, int j) { return t->solid != nullptr && t->solid[(size_t)j * nx + i] != 0; };
+    // a face is a wall if the neighbour lies outside a non-periodic side or is solid
+    auto wall = [&](int i, int j, int di, int dj) {
+        int ni = i + di, nj = j + dj;
+        if (ni < 0 || ni >= nx) {
+            if (!px) return true;
+            ni = (ni + nx) % nx;
+        }
+        if (nj < 0 || nj >= ny) {
+            if (!py) return true;
+            nj = (nj + ny) % ny;
+        }
+        return solid(ni, nj);
+    };
+    int nf = 0;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            uint8_t f = 0;
+            if (solid(i, j)) {
+                f = FLAG_SOLID;
+            } else {
+                ++nf;
+                if (wall(i, j, -1, 0)) f |= FLAG_WALL_XM;
+                if (wall(i, j, +1, 0)) f |= FLAG_WALL_XP;
+                if (wall(i, j, 0, -1)) f |= FLAG_WALL_YM;
+                if (wall(i, j, 0, +1)) f |= FLAG_WALL_YP;
+            }
+            flags[(size_t)j * nx + i] = f;
+        }
+    *n_fluid = nf;
+}
+
+int read_status(const vdac_grid *g, int tank, Status *st)
+{
+    hipError_t e = hipMemcpyAsync(st, g->tanks[tank].dev.status, sizeof(Status), hipMemcpyDeviceToHost,
+                                  g->stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the tank status");
+    e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "synchronising the stream");
+    return VDAC_OK;
+}
+
+hipEvent_t pool_event(vdac_grid *g, size_t idx)
+{
+    while (g->ev_pool.size() <= idx) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g->ev_pool.push_back(e);
+    }
+    return g->ev_pool[idx];
+}
+
+// Collects the elapsed time of every bracketed stage launch of the finished step.
+int collect_timing(vdac_grid *g, const std::vector<int> &iters_before, const std::vector<int> &iters_after)
+{
+    for (auto &pr : g->ev_pending) {
+        // launches after the tank stopped returned at once: they count neither time nor cells
+        if (pr.iter >= iters_after[pr.tank] - iters_before[pr.tank]) continue;
+        hipError_t e = hipEventSynchronize(g->ev_pool[pr.stop]);
+        if (e != hipSuccess) return hip_fail(e, "stage timing");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, g->ev_pool[pr.start], g->ev_pool[pr.stop]);
+        if (e != hipSuccess) return hip_fail(e, "stage timing");
+        g->t_ms += ms;
+    }
+    g->ev_pending.clear();
+    for (size_t t = 0; t < g->tanks.size(); ++t) {
+        const int n = iters_after[t] - iters_before[t];
+        g->t_launches += (int64_t)n * g->sc.smax;
+        g->t_cell_stages += (double)n * g->sc.smax * g->tanks[t].dev.n_fluid;
+    }
+    return VDAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void vdac_default_options(vdac_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->precision = VDAC_FP64;
+    o->rk_stages = 3;
+    o->rk_alpha[0] = 1.0 / 3.0;
+    o->rk_alpha[1] = 0.5;
+    o->rk_alpha[2] = 1.0;
+    o->cfl_tau = 0.48;
+    o->limiter_k = 1.0;
+    o->local_dtau = 1;
+    o->bdf_order = 1;
+    o->norm = VDAC_NORM_RMS;
+    o->wall_slip = 0;
+}
+
+size_t workspace_bytes(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o)
+{
+    vdac_options def;
+    if (!o) {
+        vdac_default_options(&def);
+        o = &def;
+    }
+    if (!tanks || n_tanks < 1 || check_options(o) != VDAC_OK) return 0;
+    size_t total = 0;
+    for (int t = 0; t < n_tanks; ++t) {
+        if (check_tank(&tanks[t], t) != VDAC_OK) return 0;
+        total += layout_of(&tanks[t], o, blocks_for(&tanks[t])).end;
+    }
+    return total;
+}
+
+int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
+                void *device_workspace, size_t ws_bytes, void *hip_stream, vdac_grid **out)
+{
+    g_error.clear();
+    if (!out) return fail(VDAC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!tanks || n_tanks < 1) return fail(VDAC_E_INVALID, "need at least one tank");
+    vdac_options def;
+    if (!o) {
+        vdac_default_options(&def);
+        o = &def;
+    }
+    int rc = check_options(o);
+    if (rc != VDAC_OK) return rc;
+    for (int t = 0; t < n_tanks; ++t)
+        if ((rc = check_tank(&tanks[t], t)) != VDAC_OK) return rc;
+    const size_t need = workspace_bytes(tanks, n_tanks, o);
+
+    vdac_grid *g = new (std::nothrow) vdac_grid();
+    if (!g) return fail(VDAC_E_NOMEM, "host allocation failed");
+    g->opt = *o;
+    g->stream = (hipStream_t)hip_stream;
+    if (device_workspace) {
+        if (ws_bytes < need) {
+            delete g;
+            return fail(VDAC_E_NOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+        }
+        if (((uintptr_t)device_workspace & 255) != 0) {
+            delete g;
+            return fail(VDAC_E_INVALID, "device_workspace must be 256-byte aligned");
+        }
+        g->ws = (char *)device_workspace;
+        g->own_ws = false;
+    } else {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, need);
+        if (e != hipSuccess) {
+            delete g;
+            return fail(VDAC_E_NOMEM, "hipMalloc of %zu bytes failed: %s", need, hipGetErrorString(e));
+        }
+        g->ws = (char *)p;
+        g->own_ws = true;
+    }
+    g->ws_bytes = need;
+
+    Scheme &sc = g->sc;
+    std::memset(&sc, 0, sizeof sc);
+    sc.smax = o->rk_stages;
+    for (int s = 0; s < 8; ++s) sc.alpha[s] = (s < o->rk_stages) ? o->rk_alpha[s] : 0.0;
+    sc.k = o->limiter_k;
+    sc.slip = o->wall_slip;
+    sc.norm_max = (o->norm == VDAC_NORM_MAX);
+    sc.bdf2 = (o->bdf_order == 2);
+
+    g->tanks.resize(n_tanks);
+    size_t base = 0;
+    for (int t = 0; t < n_tanks; ++t) {
+        TankHost &th = g->tanks[t];
+        th.desc = tanks[t];
+        th.desc.solid = nullptr;
+        th.n_blocks = blocks_for(&tanks[t]);
+        th.hist_ok = 0;
+        int n_fluid = 0;
+        build_flags(&tanks[t], th.flags, &n_fluid);
+        const TankLayout L = layout_of(&tanks[t], o, th.n_blocks);
+        TankDev &d = th.dev;
+        std::memset(&d, 0, sizeof d);
+        d.nx = tanks[t].nx;
+        d.ny = tanks[t].ny;
+        d.per_x = tanks[t].bc[0] == VDAC_BC_PERIODIC;
+        d.per_y = tanks[t].bc[2] == VDAC_BC_PERIODIC;
+        d.dx = tanks[t].lx / tanks[t].nx;
+        d.dy = tanks[t].ly / tanks[t].ny;
+        d.inv_dx = 1.0 / d.dx;
+        d.inv_dy = 1.0 / d.dy;
+        d.half_dx = 0.5 * d.dx;
+        d.half_dy = 0.5 * d.dy;
+        d.gx = tanks[t].gx;
+        d.gy = tanks[t].gy;
+        d.beta = tanks[t].beta;
+        d.inv_beta = 1.0 / tanks[t].beta;
+        d.cfl = o->cfl_tau;
+        d.plane = (size_t)d.nx * d.ny;
+        for (int b = 0; b < 3; ++b) d.state[b] = (double *)(g->ws + base + L.state[b]);
+        d.level_n = (double *)(g->ws + base + L.level_n);
+        d.level_nm1 = sc.bdf2 ? (double *)(g->ws + base + L.level_nm1) : nullptr;
+        d.flags = (const uint8_t *)(g->ws + base + L.flags);
+        d.partials = (double *)(g->ws + base + L.partials);
+        d.status = (Status *)(g->ws + base + L.status);
+        d.step = (const StepParams *)(g->ws + base + L.step);
+        d.n_fluid = n_fluid;
+        base += L.end;
+
+        hipError_t e = hipMemcpyAsync((void *)d.flags, th.flags.data(), th.flags.size(),
+                                      hipMemcpyHostToDevice, g->stream);
+        if (e != hipSuccess) {
+            destroy_grid(g);
+            return hip_fail(e, "uploading the cell flags");
+        }
+        // initial state: rho = 1, at rest, p = 0
+        std::vector<double> q(4 * d.plane, 0.0);
+        std::fill(q.begin(), q.begin() + d.plane, 1.0);
+        for (int b = 0; b < 3; ++b) {
+            e = hipMemcpyAsync(d.state[b], q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice,
+                               g->stream);
+            if (e != hipSuccess) break;
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d.level_n, q.data(), 3 * d.plane * sizeof(double), hipMemcpyHostToDevice,
+                               g->stream);
+        Status st;
+        std::memset(&st, 0, sizeof st);
+        st.done = 1;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d.status, &st, sizeof st, hipMemcpyHostToDevice, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) {
+            destroy_grid(g);
+            return hip_fail(e, "initialising the tank");
+        }
+    }
+    *out = g;
+    return VDAC_OK;
+}
+
+int set_state(vdac_grid *g, int32_t tank, const double *q)
+{
+    g_error.clear();
+    if (!g || !q) return fail(VDAC_E_INVALID, "grid or q is NULL");
+    if (tank < 0 || tank >= (int)g->tanks.size()) return fail(VDAC_E_INVALID, "no tank %d", tank);
+    TankHost &th = g->tanks[tank];
+    const TankDev &d = th.dev;
+    for (size_t c = 0; c < d.plane; ++c) {
+        if (th.flags[c] & FLAG_SOLID) continue;
+        if (!(q[c] > 0.0) || !std::isfinite(q[c]))
+            return fail(VDAC_E_INVALID, "tank %d: rho must be finite and > 0 (cell %zu)", tank, c);
+        for (int k = 1; k < 4; ++k)
+            if (!std::isfinite(q[k * d.plane + c]))
+                return fail(VDAC_E_INVALID, "tank %d: non-finite value in field %d (cell %zu)", tank, k, c);
+    }
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < 3 && e == hipSuccess; ++b)
+        e = hipMemcpyAsync(d.state[b], q, 4 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d.level_n, q, 3 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
+    Status st;
+    std::memset(&st, 0, sizeof st);
+    st.done = 1;
+    if (e == hipSuccess) e = hipMemcpyAsync(d.status, &st, sizeof st, hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "set_state");
+    th.hist_ok = 0;
+    return VDAC_OK;
+}
+
+int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int32_t *pseudo_done)
+{
+    g_error.clear();
+    if (!g) return fail(VDAC_E_INVALID, "grid is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(VDAC_E_INVALID, "dt must be finite and > 0");
+    if (max_pseudo < 0) return fail(VDAC_E_INVALID, "max_pseudo must be >= 0");
+    if (std::isnan(tol)) return fail(VDAC_E_INVALID, "tol is NaN");
+    const int nt = (int)g->tanks.size();
+    int rc;
+    for (int t = 0; t < nt; ++t) {
+        TankHost &th = g->tanks[t];
+        rc = launch_begin_step(th.dev, g->sc, dt, max_pseudo, tol, g->sc.bdf2 && th.hist_ok, g->stream);
+        if (rc != 0) return hip_fail((hipError_t)rc, "begin_step launch");
+    }
+    const int poll = (tol > 0.0) ? 8 : max_pseudo;
+    size_t ev_next = 0;
+    for (int m = 0; m < max_pseudo;) {
+        const int chunk = (max_pseudo - m < poll) ? (max_pseudo - m) : poll;
+        for (int it = 0; it < chunk; ++it)
+            for (int t = 0; t < nt; ++t) {
+                const TankHost &th = g->tanks[t];
+                for (int s = 1; s <= g->sc.smax; ++s) {
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    if (g->timing) {
+                        e0 = pool_event(g, ev_next);
+                        e1 = pool_event(g, ev_next + 1);
+                        if (!e0 || !e1) return fail(VDAC_E_DEVICE, "creating timing events failed");
+                        g->ev_pending.push_back({(int)ev_next, (int)ev_next + 1, t, m + it});
+                        ev_next += 2;
+                        (void)hipEventRecord(e0, g->stream);
+                    }
+                    rc = launch_stage_f64(th.dev, g->sc, s, g->opt.tile_x, g->opt.tile_y, g->stream);
+                    if (rc != 0) return hip_fail((hipError_t)rc, "stage launch");
+                    if (g->timing) (void)hipEventRecord(e1, g->stream);
+                }
+                rc = launch_finalize(th.dev, g->sc, th.n_blocks, g->stream);
+                if (rc != 0) return hip_fail((hipError_t)rc, "finalize launch");
+            }
+        m += chunk;
+        if (m < max_pseudo) {
+            bool all_done = true;
+            for (int t = 0; t < nt && all_done; ++t) {
+                Status st;
+                if ((rc = read_status(g, t, &st)) != VDAC_OK) return rc;
+                all_done = st.done != 0;
+            }
+            if (all_done) break;
+        }
+    }
+    int status = VDAC_OK;
+    std::vector<int> before(nt, 0), after(nt, 0);
+    for (int t = 0; t < nt; ++t) {
+        Status st;
+        if ((rc = read_status(g, t, &st)) != VDAC_OK) return rc;
+        after[t] = st.iters;
+        if (pseudo_done) pseudo_done[t] = st.iters;
+        if (st.diverged && status == VDAC_OK)
+            status = fail(VDAC_E_DIVERGED, "tank %d diverged at pseudo-iteration %d", t, st.iters);
+        g->tanks[t].hist_ok = 1;
+    }
+    if (g->timing && (rc = collect_timing(g, before, after)) != VDAC_OK) return rc;
+    return status;
+}
+
+int stage_timing(vdac_grid *g, int32_t enable)
+{
+    g_error.clear();
+    if (!g) return fail(VDAC_E_INVALID, "grid is NULL");
+    g->timing = enable != 0;
+    g->ev_pending.clear();
+    g->t_ms = 0.0;
+    g->t_launches = 0;
+    g->t_cell_stages = 0.0;
+    return VDAC_OK;
+}
+
+int stage_timing_read(const vdac_grid *g, double *kernel_ms, int64_t *launches, double *cell_stages)
+{
+    g_error.clear();
+    if (!g) return fail(VDAC_E_INVALID, "grid is NULL");
+    if (kernel_ms) *kernel_ms = g->t_ms;
+    if (launches) *launches = g->t_launches;
+    if (cell_stages) *cell_stages = g->t_cell_stages;
+    return VDAC_OK;
+}
+
+int residual_norm(const vdac_grid *g, int32_t tank, double out[4])
+{
+    g_error.clear();
+    if (!g || !out) return fail(VDAC_E_INVALID, "grid or out is NULL");
+    if (tank < 0 || tank >= (int)g->tanks.size()) return fail(VDAC_E_INVALID, "no tank %d", tank);
+    Status st;
+    int rc = read_status(g, tank, &st);
+    if (rc != VDAC_OK) return rc;
+    for (int k = 0; k < 4; ++k) out[k] = st.norms[k];
+    return VDAC_OK;
+}
+
+int get_state(const vdac_grid *g, int32_t tank, double *q)
+{
+    g_error.clear();
+    if (!g || !q) return fail(VDAC_E_INVALID, "grid or q is NULL");
+    if (tank < 0 || tank >= (int)g->tanks.size()) return fail(VDAC_E_INVALID, "no tank %d", tank);
+    Status st;
+    int rc = read_status(g, tank, &st);
+    if (rc != VDAC_OK) return rc;
+    const TankDev &d = g->tanks[tank].dev;
+    hipError_t e = hipMemcpyAsync(q, d.state[st.cur], 4 * d.plane * sizeof(double), hipMemcpyDeviceToHost,
+                                  g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "get_state");
+    return VDAC_OK;
+}
+
+void destroy_grid(vdac_grid *g)
+{
+    if (!g) return;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    else (void)hipDeviceSynchronize();
+    for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
+    if (g->own_ws && g->ws) (void)hipFree(g->ws);
+    delete g;
+}
+
+const char *last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// vdac_device.h -- per-point pieces of the scheme as device functions, templated on the
+// arithmetic type T (double for the FP64 path, float for the reconstruction and flux of the
+// mixed path).
+//
+// Face states carry primitives W = (rho, u, v, p); fluxes are returned for the conserved
+// vector (rho, rho u, rho v, p/beta) of the compact form (Sec. 2.1.2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace vdac {
+
+template <typename T>
+struct Prim {
+    T r, u, v, p;
+};
+
+// Derivatives of rho, u, v along one axis.
+template <typename T>
+struct Slope {
+    T r, u, v;
+};
+
+// k-limiter G(a, b) = s max(0, min(k|b|, s a), min(|b|, k s a)), s = sgn(b), sgn(0) = 0
+// (Sec. 2.3.1).  k = 1 is minmod, k = 2 superbee.
+template <typename T>
+__device__ __forceinline__ T limiter(T a, T b, T k)
+{
+    T s = (b > T(0)) ? T(1) : ((b < T(0)) ? T(-1) : T(0));
+    T ab = fabs(b);
+    T sa = s * a;
+    T t1 = fmin(k * ab, sa);
+    T t2 = fmin(ab, k * sa);
+    return s * fmax(T(0), fmax(t1, t2));
+}
+
+// Limited one-sided slopes of rho, u, v at a cell from its two neighbours along one axis:
+// G((W_{i+1} - W_i)/h, (W_i - W_{i-1})/h).
+template <typename T>
+__device__ __forceinline__ Slope<T> slopes(const Prim<T> &m, const Prim<T> &c, const Prim<T> &p,
+                                           T inv_h, T k)
+{
+    Slope<T> g;
+    g.r = limiter((p.r - c.r) * inv_h, (c.r - m.r) * inv_h, k);
+    g.u = limiter((p.u - c.u) * inv_h, (c.u - m.u) * inv_h, k);
+    g.v = limiter((p.v - c.v) * inv_h, (c.v - m.v) * inv_h, k);
+    return g;
+}
+
+// Mirror image across a wall whose normal lies along `axis` (0 = x, 1 = y): rho and p keep
+// their value (zero gradient); the velocity is negated, both components for no-slip walls and the
+// normal one only for free slip (Sec. 2.5).
+template <typename T>
+__device__ __forceinline__ Prim<T> mirror(Prim<T> w, int axis, bool slip)
+{
+    if (!slip || axis == 0) w.u = -w.u;
+    if (!slip || axis == 1) w.v = -w.v;
+    return w;
+}
+
+// New pressure gradient (Sec. 2.3.2): the rearranged x-momentum equation
+//   dp/dx = -d(rho u)/dt - d(rho u^2)/dx - d(rho u v)/dy + rho g_x
+// with the products expanded by the product rule and every derivative taken from the limited
+// slopes; d(rho u)/dt is the frozen real-time source and rho g_x the frozen body force.  The
+// y-component exchanges the roles of x and y.
+template <typename T>
+__device__ __forceinline__ T gradp_x(const Prim<T> &w, const Slope<T> &gx, const Slope<T> &gy,
+                                     T d_ru, T body_x)
+{
+    return -d_ru - (w.u * w.u * gx.r + T(2) * w.r * w.u * gx.u)
+           - (w.u * w.v * gy.r + w.r * w.u * gy.v + w.r * w.v * gy.u) + body_x;
+}
+
+template <typename T>
+__device__ __forceinline__ T gradp_y(const Prim<T> &w, const Slope<T> &gx, const Slope<T> &gy,
+                                     T d_rv, T body_y)
+{
+    return -d_rv - (w.u * w.v * gx.r + w.r * w.u * gx.v + w.r * w.v * gx.u)
+           - (w.v * w.v * gy.r + T(2) * w.r * w.v * gy.v) + body_y;
+}
+
+// Osher-Dumbser-Toro flux for the x-split problem (Sec. 2.4.3):
+//   F = (F(Q_L) + F(Q_R))/2 - (1/2) sum_j (w_j/2) |A(Q_j)| (Q_R - Q_L),
+// Q_j = Q_L + t_j (Q_R - Q_L) on the straight path in conserved variables, t_j = (1 + xi_j)/2 with
+// the three-point Gauss-Legendre nodes xi = (-sqrt(3/5), 0, sqrt(3/5)), w = (5, 8, 5)/9.
+//
+// |A| = R |Lambda| L of Sec. 2.1.3 is applied in closed form: with lambda_{1,2} = u,
+// lambda_4 = (u + c)/2 > 0 > lambda_5 = (u - c)/2 and sum_k r_k l_k^T = I,
+//   |A| dQ = |u| dQ + (lambda_4 - |u|)(l_4 . dQ) r_4 + (-lambda_5 - |u|)(l_5 . dQ) r_5,
+// where, with a = (d(rho u) - u d(rho))/beta and dq = d(p/beta),
+//   l_4 . dQ =  (rho/c)(lambda_4 a + dq),   l_5 . dQ = -(rho/c)(lambda_5 a + dq),
+//   r_4 = (lambda_4, u lambda_4 + beta/rho, v lambda_4, -lambda_5/rho),
+//   r_5 = (lambda_5, u lambda_5 + beta/rho, v lambda_5, -lambda_4/rho).
+template <typename T>
+__device__ __forceinline__ void osher_x(const Prim<T> &L, const Prim<T> &R, T beta, T inv_beta,
+                                        T F[4])
+{
+    const T mL = L.r * L.u, nL = L.r * L.v;
+    const T mR = R.r * R.u, nR = R.r * R.v;
+    const T dr = R.r - L.r, dm = mR - mL, dn = nR - nL;
+    const T dq = (R.p - L.p) * inv_beta;
+
+    // Gauss-Legendre nodes on [0, 1] and half weights
+    const T t0 = T(0.11270166537925831148207346002176);  // (1 - sqrt(3/5))/2
+    const T t2 = T(0.88729833462074168851792653997824);  // (1 + sqrt(3/5))/2
+    const T w0 = T(5.0) / T(18.0), w1 = T(8.0) / T(18.0);
+
+    T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const T t = (j == 0) ? t0 : ((j == 1) ? T(0.5) : t2);
+        const T wj = (j == 1) ? w1 : w0;
+        const T rho = L.r + dr * t;
+        const T m = mL + dm * t;
+        const T n = nL + dn * t;
+        const T ir = T(1) / rho;
+        const T u = m * ir, v = n * ir;
+        const T c = sqrt(u * u + T(4) * beta * ir);
+        const T rc = rho / c;
+        const T l4 = T(0.5) * (u + c), l5 = T(0.5) * (u - c);
+        const T au = fabs(u);
+        const T a = (dm - u * dr) * inv_beta;
+        const T k4 = (l4 - au) * rc * (l4 * a + dq);
+        const T k5 = (l5 + au) * rc * (l5 * a + dq);
+        const T s = k4 * l4 + k5 * l5;
+        acc0 += wj * (au * dr + s);
+        acc1 += wj * (au * dm + u * s + beta * ir * (k4 + k5));
+        acc2 += wj * (au * dn + v * s);
+        acc3 += wj * (au * dq - (k4 * l5 + k5 * l4) * ir);
+    }
+    F[0] = T(0.5) * (mL + mR - acc0);
+    F[1] = T(0.5) * (mL * L.u + L.p + mR * R.u + R.p - acc1);
+    F[2] = T(0.5) * (mL * L.v + mR * R.v - acc2);
+    F[3] = T(0.5) * (L.u + R.u - acc3);
+}
+
+// Face flux with normal +y: Algorithm 2 gives t1 = (1, 0, 0) for n = (0, 1, 0), so the rotated
+// problem is the x-split one with u and v exchanged, and R^T exchanges the momentum components of
+// the result back (Sec. 2.4).
+template <typename T>
+__device__ __forceinline__ void osher_y(const Prim<T> &L, const Prim<T> &R, T beta, T inv_beta,
+                                        T F[4])
+{
+    Prim<T> Ls = {L.r, L.v, L.u, L.p};
+    Prim<T> Rs = {R.r, R.v, R.u, R.p};
+    T G[4];
+    osher_x(Ls, Rs, beta, inv_beta, G);
+    F[0] = G[0];
+    F[1] = G[2];
+    F[2] = G[1];
+    F[3] = G[3];
+}
+
+}  // namespace vdac

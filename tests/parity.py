@@ -1,0 +1,88 @@
+"""Helpers for the GPU-versus-oracle parity tests: run the same seeded workload through the HIP
+library (via the C ABI) and through the oracle, and compare field by field."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_2108_08769_amd import vdac
+from paper_2108_08769_amd import workloads as wl
+
+
+def gpu_options(wk: wl.Workload, precision=None, norm=0, wall_slip=False, tile=(0, 0)):
+    return vdac.make_options(precision=precision or wk.precision, stages=wk.stages,
+                             alpha=wk.alpha, cfl=wk.cfl, k=wk.k, bdf=wk.bdf, norm=norm,
+                             wall_slip=wall_slip, tile=tile)
+
+
+def oracle_problem(t: wl.Tank, wk: wl.Workload, wall_slip=False):
+    return oracle.Problem(t.nx, t.ny, t.lx, t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
+                          solid=t.solid, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl, k=wk.k,
+                          local_dtau=wk.local_dtau, bdf=wk.bdf, wall_slip=wall_slip)
+
+
+def run_gpu(wk: wl.Workload, steps: int, max_pseudo: int, tol: float = 0.0, norm=0,
+            wall_slip=False, precision=None, tile=(0, 0)):
+    """Returns (states per tank, iterations [steps, tanks], norms [tanks, 4], status codes)."""
+    tanks = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
+                  solid=t.solid) for t in wk.tanks]
+    grid = vdac.Grid(tanks, gpu_options(wk, precision, norm, wall_slip, tile))
+    try:
+        for i, t in enumerate(wk.tanks):
+            grid.set_state(i, t.q)
+        iters, codes = [], []
+        for _ in range(steps):
+            rc, done = grid.step(wk.dt, max_pseudo, tol, check=False)
+            codes.append(rc)
+            iters.append(done)
+        states = [grid.get_state(i) for i in range(len(wk.tanks))]
+        norms = np.array([grid.residual_norm(i) for i in range(len(wk.tanks))])
+    finally:
+        grid.close()
+    return states, np.array(iters), norms, codes
+
+
+def run_oracle(wk: wl.Workload, steps: int, max_pseudo: int, tol: float = 0.0, norm=0,
+               wall_slip=False):
+    states, iters, norms, codes = [], [], [], []
+    per_tank_iters = [[] for _ in wk.tanks]
+    for ti, t in enumerate(wk.tanks):
+        pb = oracle_problem(t, wk, wall_slip)
+        q, prev = t.q.copy(), None
+        for _ in range(steps):
+            qnew, it, res, rc = oracle.step(pb, q, wk.dt, max_pseudo, tol, norm,
+                                            qnm1=prev if wk.bdf == 2 else None)
+            prev, q = q, qnew
+            per_tank_iters[ti].append(it)
+            codes.append(rc)
+        states.append(q)
+        norms.append(res)
+    iters = np.array(per_tank_iters).T
+    return states, iters, np.array(norms), codes
+
+
+def field_scales(t: wl.Tank) -> np.ndarray:
+    """Physical magnitude of each field for a gravity-driven tank: rho_max, rho_max U and
+    rho_max |g| L for the momenta and the pressure, with U = sqrt(|g| L) the gravity-wave speed
+    over the tank's larger side L (or the initial speed if larger)."""
+    L = max(t.lx, t.ly)
+    g = float(np.hypot(t.gx, t.gy))
+    rho = float(t.q[0].max())
+    u0 = float(np.abs(t.q[1:3] / t.q[0]).max())
+    U = max(np.sqrt(g * L), u0)
+    return np.array([rho, rho * U, rho * U, rho * g * L])
+
+
+def field_errors(a: np.ndarray, b: np.ndarray, solid=None, scales=None) -> np.ndarray:
+    """Per-field max |a - b| / max(max |b|, scale) over fluid cells.  The scale floor only matters
+    where a field is nearly zero compared with its physical magnitude (a tank close to rest),
+    where the field-relative error is dominated by cancellation between large balanced terms."""
+    mask = np.ones(a.shape[1:], bool) if solid is None else solid == 0
+    out = np.zeros(4)
+    for k in range(4):
+        d = np.abs(a[k][mask] - b[k][mask]).max()
+        s = np.abs(b[k][mask]).max()
+        if scales is not None:
+            s = max(s, scales[k])
+        out[k] = d / s if s > 0 else d
+    return out

@@ -1,0 +1,94 @@
+"""The C-ABI library loads, exports every entry point its header declares, and rejects bad
+arguments before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2108_08769_amd import vdac
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "vdac.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, re.M)
+    return sorted(set(n for n in names if n not in ("sizeof",)))
+
+
+def test_header_lists_the_boundary():
+    assert set(vdac.EXPORTS) == set(declared_functions())
+
+
+def test_library_exports_every_declared_symbol():
+    lib = vdac.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", vdac.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    for name in declared_functions():
+        assert name in exported, name
+
+
+def test_default_options():
+    o = vdac.default_options()
+    assert o.precision == vdac.FP64 and o.rk_stages == 3
+    assert list(o.rk_alpha)[:3] == [1.0 / 3.0, 0.5, 1.0]
+    assert o.cfl_tau == 0.48 and o.limiter_k == 1.0 and o.local_dtau == 1
+    assert o.bdf_order == 1 and o.norm == vdac.NORM_RMS and o.wall_slip == 0
+
+
+def test_workspace_bytes():
+    o = vdac.default_options()
+    t, _ = vdac.make_tank(64, 32, 2.0, 1.0)
+    n = vdac.workspace_bytes([t], o)
+    plane = 64 * 32 * 8
+    assert n >= 3 * 4 * plane + 3 * plane + 64 * 32
+    t2, _ = vdac.make_tank(16, 16, 1.0, 1.0)
+    assert vdac.workspace_bytes([t, t2], o) == n + vdac.workspace_bytes([t2], o)
+    bad, _ = vdac.make_tank(0, 32, 2.0, 1.0)
+    assert vdac.workspace_bytes([bad], o) == 0
+
+
+def _create(tanks, opt):
+    arr = (vdac.Tank * len(tanks))(*tanks)
+    h = ctypes.c_void_p()
+    rc = vdac.lib().create_grid(arr, len(tanks), ctypes.byref(opt), None, 0, None, ctypes.byref(h))
+    return rc, vdac.lib().last_error().decode()
+
+
+@pytest.mark.parametrize("change,needle", [
+    (lambda t, o: setattr(t, "nx", 0), "nx and ny"),
+    (lambda t, o: setattr(t, "beta", -1.0), "beta"),
+    (lambda t, o: setattr(t, "lx", float("nan")), "lx and ly"),
+    (lambda t, o: t.bc.__setitem__(0, 1), "pairs"),
+    (lambda t, o: t.bc.__setitem__(2, 7), "bc[2]"),
+    (lambda t, o: setattr(o, "rk_stages", 0), "rk_stages"),
+    (lambda t, o: o.rk_alpha.__setitem__(2, 0.9), "last Runge-Kutta"),
+    (lambda t, o: setattr(o, "cfl_tau", 0.0), "cfl_tau"),
+    (lambda t, o: setattr(o, "limiter_k", 3.0), "limiter_k"),
+    (lambda t, o: setattr(o, "bdf_order", 3), "bdf_order"),
+    (lambda t, o: setattr(o, "norm", 5), "norm"),
+    (lambda t, o: setattr(o, "local_dtau", 0), "local"),
+])
+def test_create_grid_rejects_bad_arguments(change, needle):
+    t, _ = vdac.make_tank(8, 8, 1.0, 1.0)
+    o = vdac.default_options()
+    change(t, o)
+    rc, msg = _create([t], o)
+    assert rc == vdac.VDAC_E_INVALID
+    assert needle in msg
+
+
+def test_null_handles_are_rejected():
+    L = vdac.lib()
+    q = (ctypes.c_double * 4)()
+    assert L.set_state(None, 0, q) == vdac.VDAC_E_INVALID
+    assert L.step_dual_time(None, 1e-3, 1, 0.0, None) == vdac.VDAC_E_INVALID
+    assert L.get_state(None, 0, q) == vdac.VDAC_E_INVALID
+    assert L.residual_norm(None, 0, q) == vdac.VDAC_E_INVALID
+    L.destroy_grid(None)

@@ -1,0 +1,191 @@
+"""GPU FP64 path against the oracle, element by element, through the C ABI.
+
+Bar: per-field max |gpu - oracle| / max(max |oracle|, physical scale of the field) <= 1e-12
+over fluid cells (the FP64 target; the scale floor, rho_max sqrt(|g| L) for momentum and
+rho_max |g| L for pressure, only matters for a tank close to rest); iteration counts equal.  Cases span several workgroup tiles and ragged tails, the paper's
+boundary kinds, solid obstacles, the options, and full-size grids of the benchmark workloads on
+truncated runs.
+"""
+import numpy as np
+import pytest
+
+from paper_2108_08769_amd import vdac
+from paper_2108_08769_amd import workloads as wl
+from parity import run_gpu, run_oracle, field_errors, field_scales
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def check(wk, steps, pseudo, tol=0.0, bar=TOL, **kw):
+    print(f"[parity] {wk.name} tanks={len(wk.tanks)} steps={steps} pseudo={pseudo} tol={tol} {kw}",
+          flush=True)
+    g_states, g_it, g_norms, g_codes = run_gpu(wk, steps, pseudo, tol, **kw)
+    o_states, o_it, o_norms, o_codes = run_oracle(wk, steps, pseudo, tol,
+                                                 **{k: v for k, v in kw.items() if k in ("norm", "wall_slip")})
+    assert all(c == 0 for c in g_codes) and all(c == 0 for c in o_codes), (g_codes, o_codes)
+    np.testing.assert_array_equal(g_it, o_it)
+    worst = 0.0
+    for t, a, b in zip(wk.tanks, g_states, o_states):
+        err = field_errors(a, b, t.solid, field_scales(t))
+        worst = max(worst, err.max())
+        assert np.all(err <= bar), (t.nx, t.ny, err)
+        if t.solid is not None:
+            np.testing.assert_array_equal(a[:, t.solid == 1], t.q[:, t.solid == 1])
+    for a, b in zip(g_norms, o_norms):
+        np.testing.assert_allclose(a, b, rtol=1e-7, atol=1e-12)
+    print(f"[parity]   worst field error {worst:.3e}", flush=True)
+    return worst
+
+
+def small_dam(nx, ny, lx=4.0, ly=2.0):
+    xc = (np.arange(nx) + 0.5) * lx / nx
+    yc = (np.arange(ny) + 0.5) * ly / ny
+    rho = np.where((xc[None, :] < 1.0) & (yc[:, None] < 1.0), 1000.0, 1.0)
+    q = np.zeros((4, ny, nx))
+    q[0] = rho
+    return wl.Workload(f"dam_{nx}x{ny}", [wl.Tank(nx, ny, lx, ly, q, gy=-9.81, beta=1100.0)],
+                       dt=1e-3, steps=1, max_pseudo=1)
+
+
+def test_hydrostatic_tank():
+    wk = wl.hydrostatic()
+    check(wk, steps=2, pseudo=100)
+
+
+def test_dam_break_ragged():
+    check(small_dam(37, 23), steps=3, pseudo=20)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 7), (7, 1), (2, 2), (3, 3), (16, 16), (17, 15),
+                                   (33, 2)])
+def test_tiny_and_ragged_tanks(nx, ny):
+    q = wl.random_state(nx, ny, seed=nx * 100 + ny, rho_range=(1.0, 3.0), vel=0.2, p_scale=5.0)
+    wk = wl.Workload("tiny", [wl.Tank(nx, ny, 0.1 * nx, 0.13 * ny, q, gx=0.3, gy=-9.81, beta=300.0)],
+                     dt=1e-3, steps=1, max_pseudo=1)
+    check(wk, steps=2, pseudo=4)
+
+
+def test_rayleigh_taylor_periodic():
+    wk = wl.rayleigh_taylor(nx=32, ny=96, precision="f64")
+    check(wk, steps=3, pseudo=15)
+
+
+def test_obstacle_dam_break():
+    wk = wl.obstacle_dam_break(n=64)
+    assert wk.tanks[0].solid.sum() > 0
+    check(wk, steps=2, pseudo=20)
+
+
+@pytest.mark.parametrize("opt", ["slip", "superbee", "bdf2", "two_stage", "max_norm", "cfl"])
+def test_options(opt):
+    wk = small_dam(40, 20)
+    kw = {}
+    if opt == "slip":
+        kw["wall_slip"] = True
+    elif opt == "superbee":
+        wk.k = 2.0
+    elif opt == "bdf2":
+        wk.bdf = 2
+    elif opt == "two_stage":
+        wk.stages, wk.alpha = 2, (0.5, 1.0)
+    elif opt == "max_norm":
+        kw["norm"] = 1
+    elif opt == "cfl":
+        wk.cfl = 0.3
+    check(wk, steps=3, pseudo=12, **kw)
+
+
+def perturbed_hydrostatic(nx=16, ny=16, seed=0):
+    dy = 1.0 / ny
+    yc = (np.arange(ny) + 0.5) * dy
+    rho = np.where(yc < 0.5, 1000.0, 1.0)
+    p = np.zeros(ny)
+    for j in range(ny - 1):
+        p[j + 1] = p[j] - 9.81 * dy * (rho[j] + rho[j + 1]) / 2
+    q = np.zeros((4, ny, nx))
+    q[0] = rho[:, None]
+    q[3] = p[:, None] + np.random.default_rng(seed).uniform(-5.0, 5.0, (ny, nx))
+    return wl.Workload("perturbed_hydrostatic", [wl.Tank(nx, ny, 1.0, 1.0, q, gy=-9.81, beta=1000.0)],
+                       dt=1e-2, steps=1, max_pseudo=1)
+
+
+def test_tolerance_stopping():
+    """Pseudo-iterations stop at the first iteration whose residual norms are all below the
+    tolerance; GPU and oracle stop at the same iteration (about 400 here)."""
+    wk = perturbed_hydrostatic()
+    g_states, g_it, _, _ = run_gpu(wk, 1, 20000, tol=1e-2)
+    assert 100 < g_it[0, 0] < 20000
+    check(wk, steps=2, pseudo=20000, tol=1e-2)
+
+
+def test_multi_tank_grid():
+    tanks = []
+    for i, (nx, ny) in enumerate([(24, 16), (9, 31), (40, 8)]):
+        q = wl.random_state(nx, ny, seed=7 + i, rho_range=(1.0, 3.0), vel=0.2, p_scale=5.0)
+        tanks.append(wl.Tank(nx, ny, 0.05 * nx, 0.05 * ny, q, gy=-9.81, beta=200.0 + 50 * i,
+                             bc=(1, 1, 0, 0) if i == 1 else (0, 0, 0, 0)))
+    wk = wl.Workload("multi", tanks, dt=1e-3, steps=1, max_pseudo=1)
+    check(wk, steps=2, pseudo=6)
+
+
+def test_full_size_dam_break_512x256():
+    """The benchmark workload at its full size, truncated to a few pseudo-iterations."""
+    check(wl.dam_break(), steps=1, pseudo=4)
+
+
+def test_full_size_rayleigh_taylor_256x1024():
+    check(wl.rayleigh_taylor(precision="f64"), steps=1, pseudo=2)
+
+
+def test_deterministic_repeat():
+    wk = small_dam(64, 32)
+    a = run_gpu(wk, 2, 10)
+    b = run_gpu(wk, 2, 10)
+    np.testing.assert_array_equal(a[0][0], b[0][0])
+    np.testing.assert_array_equal(a[2], b[2])
+
+
+def test_hydrostatic_equilibrium_held_on_gpu():
+    """The exact discrete hydrostatic state stays put on the GPU too."""
+    nx = ny = 64
+    dy = 1.0 / ny
+    yc = (np.arange(ny) + 0.5) * dy
+    rho = np.where(yc < 0.5, 1000.0, 1.0)
+    p = np.zeros(ny)
+    for j in range(ny - 1):
+        p[j + 1] = p[j] - 9.81 * dy * (rho[j] + rho[j + 1]) / 2
+    q = np.zeros((4, ny, nx))
+    q[0] = rho[:, None]
+    q[3] = (p + 50.0)[:, None]
+    wk = wl.Workload("hydro_eq", [wl.Tank(nx, ny, 1.0, 1.0, q, gy=-9.81, beta=1000.0)], dt=1e-3,
+                     steps=1, max_pseudo=1)
+    states, _, norms, codes = run_gpu(wk, 2, 50)
+    assert codes == [0, 0]
+    assert np.abs(states[0][1:3]).max() <= 1e-9
+    assert np.abs(states[0][3] - q[3]).max() <= 1e-12 * np.abs(q[3]).max()
+    assert norms[0].max() <= 1e-8
+
+
+def test_divergence_is_reported():
+    """An oversized pseudo-time Courant number blows the iteration up; the step reports it and
+    the kernels still finish normally."""
+    wk = small_dam(32, 16)
+    wk.cfl = 40.0
+    states, iters, norms, codes = run_gpu(wk, 1, 50)
+    assert codes == [vdac.VDAC_E_DIVERGED]
+    assert iters[0, 0] < 50
+
+
+def test_set_state_rejects_bad_density():
+    grid = vdac.Grid([dict(nx=4, ny=4, lx=1.0, ly=1.0)])
+    try:
+        q = np.zeros((4, 4, 4))
+        q[0] = 1.0
+        q[0, 1, 1] = -1.0
+        with pytest.raises(vdac.VdacError) as e:
+            grid.set_state(0, q)
+        assert e.value.code == vdac.VDAC_E_INVALID
+    finally:
+        grid.close()
