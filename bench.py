@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--no-stage-timing", action="store_true")
+    ap.add_argument("--tile", default="0x0", help="stage kernel tile, e.g. 32x8 (0x0 = automatic)")
+    ap.add_argument("--max-pseudo", type=int, default=0,
+                    help="override the workload's pseudo-iteration cap (short profiled runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -91,10 +94,13 @@ def main():
     from paper_2108_08769_amd import vdac
 
     wk = build_workload(args.workload, args.precision)
+    if args.max_pseudo > 0:
+        wk.max_pseudo = args.max_pseudo
     tanks = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
                   solid=t.solid) for t in wk.tanks]
+    tile = tuple(int(v) for v in args.tile.lower().split("x"))
     opts = vdac.make_options(precision=wk.precision, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl,
-                             k=wk.k, bdf=wk.bdf)
+                             k=wk.k, bdf=wk.bdf, tile=tile)
     torch.cuda.set_device(0)
     grid = vdac.Grid(tanks, opts)
     for i, t in enumerate(wk.tanks):
@@ -149,7 +155,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if wk.precision == "f64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": wk.name, "cells": fluid, "precision": wk.precision,
+        "config": {"workload": wk.name, "cells": fluid, "precision": wk.precision, "tile": args.tile,
                    "dt": wk.dt, "max_pseudo": wk.max_pseudo, "tol": wk.tol,
                    "rk_stages": wk.stages, "pseudo_iterations": iters},
         "roofline": roofline,

@@ -7,32 +7,11 @@
 // sides agree bit for bit and the scheme stays conservative).
 #include <hip/hip_runtime.h>
 
-#include "vdac_device.h"
-#include "vdac_internal.h"
+#include "stage_common.h"
 
 namespace vdac {
 
 namespace {
-
-__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-
-__device__ __forceinline__ Prim<double> load_prim(const double *q, size_t plane, size_t c)
-{
-    Prim<double> w;
-    w.r = q[c];
-    w.u = q[plane + c] / w.r;
-    w.v = q[2 * plane + c] / w.r;
-    w.p = q[3 * plane + c];
-    return w;
-}
-
-// A fluid cell as the reconstruction sees it: W, limited slopes along x and y, and the stage-0
-// sources (real-time term of rho, rho u, rho v and rho^0 for the body force).
-struct CellRec {
-    Prim<double> w;
-    Slope<double> gx, gy;
-    double d_r, d_ru, d_rv, rho0;
-};
 
 __device__ __forceinline__ void reconstruct(const TankDev &t, const Scheme &sc,
                                             const StepParams &sp, const double *qprev,
@@ -66,111 +45,6 @@ __device__ __forceinline__ void reconstruct(const TankDev &t, const Scheme &sc,
     rec.d_ru = num[1] * sp.inv_dt;
     rec.d_rv = num[2] * sp.inv_dt;
     rec.rho0 = q0[c];
-}
-
-// State of a reconstructed cell at its face on side sd (+1 / -1) of axis (0 = x, 1 = y):
-// W + grad W . (x_f - x_i), with the new pressure gradient for p.
-__device__ __forceinline__ Prim<double> own_state(const TankDev &t, const CellRec &c, int axis,
-                                                  int sd)
-{
-    Prim<double> s;
-    if (axis == 0) {
-        const double h = sd > 0 ? t.half_dx : -t.half_dx;
-        const double px = gradp_x(c.w, c.gx, c.gy, c.d_ru, c.rho0 * t.gx);
-        s.r = c.w.r + c.gx.r * h;
-        s.u = c.w.u + c.gx.u * h;
-        s.v = c.w.v + c.gx.v * h;
-        s.p = c.w.p + px * h;
-    } else {
-        const double h = sd > 0 ? t.half_dy : -t.half_dy;
-        const double py = gradp_y(c.w, c.gx, c.gy, c.d_rv, c.rho0 * t.gy);
-        s.r = c.w.r + c.gy.r * h;
-        s.u = c.w.u + c.gy.u * h;
-        s.v = c.w.v + c.gy.v * h;
-        s.p = c.w.p + py * h;
-    }
-    return s;
-}
-
-// State of the wall ghost on side sd of axis, at the face it shares with cell c.  The ghost
-// mirrors c and its stencil mirrors c's stencil, so (limiter symmetric and odd) its slope normal
-// to the wall equals c's and its tangential slopes are c's with the mirror's signs; its sources
-// are mirrored and gravity is reversed in it (Sec. 2.5).
-__device__ __forceinline__ Prim<double> ghost_state(const TankDev &t, const CellRec &c, int axis,
-                                                    int sd, bool slip)
-{
-    const double su = (!slip || axis == 0) ? -1.0 : 1.0;  // mirror sign of u
-    const double sv = (!slip || axis == 1) ? -1.0 : 1.0;  // mirror sign of v
-    Prim<double> w = {c.w.r, su * c.w.u, sv * c.w.v, c.w.p};
-    Prim<double> s;
-    if (axis == 0) {
-        Slope<double> gx = c.gx;
-        Slope<double> gy = {c.gy.r, su * c.gy.u, sv * c.gy.v};
-        const double px = gradp_x(w, gx, gy, su * c.d_ru, -(c.rho0 * t.gx));
-        const double h = sd > 0 ? -t.half_dx : t.half_dx;  // ghost's face toward c
-        s.r = w.r + gx.r * h;
-        s.u = w.u + gx.u * h;
-        s.v = w.v + gx.v * h;
-        s.p = w.p + px * h;
-    } else {
-        Slope<double> gy = c.gy;
-        Slope<double> gx = {c.gx.r, su * c.gx.u, sv * c.gx.v};
-        const double py = gradp_y(w, gx, gy, sv * c.d_rv, -(c.rho0 * t.gy));
-        const double h = sd > 0 ? -t.half_dy : t.half_dy;
-        s.r = w.r + gy.r * h;
-        s.u = w.u + gy.u * h;
-        s.v = w.v + gy.v * h;
-        s.p = w.p + py * h;
-    }
-    return s;
-}
-
-// Pseudo-time step of Sec. 2.2.3 in 2D: CFL dx dy / ((|u| + c_x) dy/2 + (|v| + c_y) dx/2).
-__device__ __forceinline__ double local_dtau(const TankDev &t, double cfl, double rho, double u,
-                                             double v)
-{
-    const double cx = sqrt(u * u + 4.0 * t.beta / rho);
-    const double cy = sqrt(v * v + 4.0 * t.beta / rho);
-    const double lx = 0.5 * (fabs(u) + cx) * t.dy;
-    const double ly = 0.5 * (fabs(v) + cy) * t.dx;
-    return cfl * (t.dx * t.dy) / (lx + ly);
-}
-
-template <bool NORM_MAX>
-__device__ __forceinline__ double combine(double a, double b)
-{
-    return NORM_MAX ? (a > b || a != a ? a : b) : a + b;
-}
-
-// Workgroup reduction of the residual partials (fixed order: deterministic).
-template <bool NORM_MAX, int NT>
-__device__ __forceinline__ void block_reduce_store(double v[kPartialWidth], double *out)
-{
-#pragma unroll
-    for (int k = 0; k < kPartialWidth; ++k) {
-        double x = v[k];
-        const bool mx = NORM_MAX && k < 4;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double y = __shfl_xor(x, off, 64);
-            x = mx ? combine<true>(x, y) : x + y;
-        }
-        v[k] = x;
-    }
-    __shared__ double red[NT / 64][kPartialWidth];
-    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    if (lane == 0)
-        for (int k = 0; k < kPartialWidth; ++k) red[wave][k] = v[k];
-    __syncthreads();
-    if (tid == 0) {
-        for (int k = 0; k < kPartialWidth; ++k) {
-            double x = red[0][k];
-            for (int w = 1; w < NT / 64; ++w)
-                x = (NORM_MAX && k < 4) ? combine<true>(x, red[w][k]) : x + red[w][k];
-            out[k] = x;
-        }
-    }
 }
 
 constexpr int kDirectTX = 16, kDirectTY = 16;
@@ -245,7 +119,7 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
             // bracket of eq. RK2 and the point-implicit update (eq. point_implicit)
             const double r0 = q0[c], m0 = q0[plane + c], n0 = q0[2 * plane + c];
             const double p0 = q0[3 * plane + c];
-            const double dtau = local_dtau(t, t.cfl, r0, m0 / r0, n0 / r0);
+            const double dtau = local_dtau(t, t.cfl, r0, m0, n0);
             const double src[3] = {-me.d_r, -me.d_ru + r0 * t.gx, -me.d_rv + r0 * t.gy};
             const double base[3] = {r0, m0, n0};
             const double ad = alpha * dtau;
@@ -356,9 +230,23 @@ __global__ void __launch_bounds__(256)
 
 }  // namespace
 
-int stage_blocks(const TankDev &t, int, int)
+int direct_blocks(const TankDev &t)
 {
     return ((t.nx + kDirectTX - 1) / kDirectTX) * ((t.ny + kDirectTY - 1) / kDirectTY);
+}
+
+int stage_blocks(const TankDev &t, int tile_x, int tile_y)
+{
+    if (tile_x == 1 && tile_y == 1) return direct_blocks(t);
+    if (tile_x == -1) return march_units(t, tile_y);
+    return tile_count(t, tile_x, tile_y);
+}
+
+int launch_stage(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y, void *stream)
+{
+    if (tile_x == 1 && tile_y == 1) return launch_stage_direct_f64(t, sc, stage, stream);
+    if (tile_x == -1) return launch_stage_march_f64(t, sc, stage, tile_y, stream);
+    return launch_stage_tile_f64(t, sc, stage, tile_x, tile_y, stream);
 }
 
 int launch_begin_step(const TankDev &t, const Scheme &sc, double dt, int max_pseudo, double tol,
@@ -382,7 +270,7 @@ int launch_begin_step(const TankDev &t, const Scheme &sc, double dt, int max_pse
     return (int)hipGetLastError();
 }
 
-int launch_stage_f64(const TankDev &t, const Scheme &sc, int stage, int, int, void *stream)
+int launch_stage_direct_f64(const TankDev &t, const Scheme &sc, int stage, void *stream)
 {
     dim3 grid((t.nx + kDirectTX - 1) / kDirectTX, (t.ny + kDirectTY - 1) / kDirectTY);
     dim3 block(kDirectTX, kDirectTY);

@@ -1,0 +1,329 @@
+// stage_tile.hip -- the Runge-Kutta stage kernel for gfx950 in its tiled form.
+//
+// One 256-thread workgroup updates one TX x TY tile of cells in four phases separated by
+// workgroup barriers:
+//   1. the stage input Q^{s-1} of the tile and a two-cell halo is loaded once from memory and
+//      kept in LDS as primitives (rho, u, v, p), with the cell flags of the tile and a one-cell
+//      ring;
+//   2. every fluid cell of the tile and of the ring is reconstructed once: limited slopes of
+//      rho, u, v (Sec. 2.3.1), the stage-0 sources from Q^0 and level n, and the new pressure
+//      gradient (Sec. 2.3.2).  The cell writes its own state at each of its faces that belong to
+//      the tile into that face's LDS slot; across a wall face (domain wall or solid neighbour) it
+//      also writes the ghost's state into the opposite slot (Sec. 2.5).  Each slot therefore has
+//      exactly one writer;
+//   3. every face of the tile is evaluated once with the Osher-Dumbser-Toro flux (Sec. 2.4.3);
+//      the flux overwrites the face's left/lower state slot;
+//   4. each tile cell forms the flux divergence, adds the frozen sources and applies the
+//      point-implicit update (eq. RK2), and the last stage accumulates the residual.
+// Periodic sides are handled by wrapping halo indices; cells outside a non-periodic side read
+// as non-fluid.
+#include <hip/hip_runtime.h>
+
+#include "stage_common.h"
+
+namespace vdac {
+
+namespace {
+
+constexpr int kNT = 256;
+
+// Index along one axis of a tile-relative position: wraps across a periodic side, or reports
+// the position outside the tank.
+__device__ __forceinline__ bool locate(int g, int n, int periodic, int &out)
+{
+    if (g < 0 || g >= n) {
+        if (!periodic) return false;
+        while (g < 0) g += n;
+        while (g >= n) g -= n;
+    }
+    out = g;
+    return true;
+}
+
+template <int TX, int TY, bool NORM_MAX>
+__global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int stage, int tiles_x,
+                                                      int n_tiles)
+{
+    constexpr int RX = TX + 4, RY = TY + 4, NR2 = RX * RY;  // primitives: tile + 2-cell halo
+    constexpr int SX = TX + 2, SY = TY + 2, NR1 = SX * SY;  // flags: tile + 1-cell ring
+    constexpr int NC = TX * TY;
+    static_assert(NC == kNT, "one tile cell per thread");
+    constexpr int NRING = 2 * (TX + TY);                    // ring positions without corners
+    constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
+
+    __shared__ double sW[4][NR2];
+    __shared__ uint8_t sF[NR1];
+    __shared__ double sXL[4][NFX], sXR[4][NFX];  // x-face states (then fluxes in sXL)
+    __shared__ double sYL[4][NFY], sYU[4][NFY];  // y-face states (then fluxes in sYL)
+
+    const Status *st = t.status;
+    if (st->done) return;
+
+    // XCD-aware tile order: the hardware hands block b to XCD b % 8; each XCD gets a contiguous
+    // run of tiles so that neighbouring tiles, which share halo cells, share an L2.
+    const int per = (n_tiles + 7) >> 3;
+    const int tile = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+    if (tile >= n_tiles) return;
+    const int x0 = (tile % tiles_x) * TX;
+    const int y0 = (tile / tiles_x) * TY;
+    const int tid = threadIdx.x;
+
+    const int cur = st->cur;
+    const StageBuffers bufs = stage_buffers(cur, stage);
+    const double *qprev = t.state[bufs.in];
+    const double *q0 = t.state[cur];
+    double *qout = t.state[bufs.out];
+    const StepParams sp = *t.step;
+    const size_t plane = t.plane;
+    const bool slip = sc.slip != 0;
+    const double k = sc.k;
+
+    // ---- phase 1: stage input and flags into LDS -------------------------------------------
+    for (int r = tid; r < NR2; r += kNT) {
+        const int ri = r % RX, rj = r / RX;
+        int gi, gj;
+        Prim<double> w = {1.0, 0.0, 0.0, 0.0};
+        if (locate(x0 - 2 + ri, t.nx, t.per_x, gi) && locate(y0 - 2 + rj, t.ny, t.per_y, gj))
+            w = load_prim(qprev, plane, (size_t)gj * t.nx + gi);
+        sW[0][r] = w.r;
+        sW[1][r] = w.u;
+        sW[2][r] = w.v;
+        sW[3][r] = w.p;
+    }
+    for (int r = tid; r < NR1; r += kNT) {
+        const int ri = r % SX, rj = r / SX;
+        int gi, gj;
+        uint8_t f = FLAG_SOLID;  // outside a non-periodic side: not a fluid cell
+        if (locate(x0 - 1 + ri, t.nx, t.per_x, gi) && locate(y0 - 1 + rj, t.ny, t.per_y, gj))
+            f = t.flags[(size_t)gj * t.nx + gi];
+        sF[r] = f;
+    }
+    __syncthreads();
+
+    // ---- phase 2: reconstruction of the tile and ring cells --------------------------------
+    // The tile cell of this thread keeps its stage-0 data for phase 4.
+    double own_q0[3] = {1.0, 0.0, 0.0}, own_d[3] = {0.0, 0.0, 0.0};
+
+    for (int pidx = tid; pidx < NC + NRING; pidx += kNT) {
+        int i, j;
+        if (pidx < NC) {
+            i = pidx % TX;
+            j = pidx / TX;
+        } else {
+            const int q = pidx - NC;
+            if (q < TX) {
+                i = q;
+                j = -1;
+            } else if (q < 2 * TX) {
+                i = q - TX;
+                j = TY;
+            } else if (q < 2 * TX + TY) {
+                i = -1;
+                j = q - 2 * TX;
+            } else {
+                i = TX;
+                j = q - 2 * TX - TY;
+            }
+        }
+        const uint8_t f = sF[(j + 1) * SX + (i + 1)];
+        if (f & FLAG_SOLID) continue;
+        const int r = (j + 2) * RX + (i + 2);
+        CellRec rec;
+        rec.w = {sW[0][r], sW[1][r], sW[2][r], sW[3][r]};
+        // a wall face shows the cell its own mirror image (Sec. 2.5)
+        const Prim<double> xm = (f & FLAG_WALL_XM) ? mirror(rec.w, 0, slip)
+                                                   : Prim<double>{sW[0][r - 1], sW[1][r - 1], sW[2][r - 1], 0.0};
+        const Prim<double> xp = (f & FLAG_WALL_XP) ? mirror(rec.w, 0, slip)
+                                                   : Prim<double>{sW[0][r + 1], sW[1][r + 1], sW[2][r + 1], 0.0};
+        const Prim<double> ym = (f & FLAG_WALL_YM) ? mirror(rec.w, 1, slip)
+                                                   : Prim<double>{sW[0][r - RX], sW[1][r - RX], sW[2][r - RX], 0.0};
+        const Prim<double> yp = (f & FLAG_WALL_YP) ? mirror(rec.w, 1, slip)
+                                                   : Prim<double>{sW[0][r + RX], sW[1][r + RX], sW[2][r + RX], 0.0};
+        rec.gx = slopes(xm, rec.w, xp, t.inv_dx, k);
+        rec.gy = slopes(ym, rec.w, yp, t.inv_dy, k);
+
+        // stage-0 sources: real-time term (B0 Q^0 + B1 Q^n + B2 Q^{n-1})/dt and rho^0
+        int gi, gj;
+        locate(x0 + i, t.nx, t.per_x, gi);
+        locate(y0 + j, t.ny, t.per_y, gj);
+        const size_t c = (size_t)gj * t.nx + gi;
+        double qa[3], num[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            qa[m] = q0[m * plane + c];
+            num[m] = sp.b0 * qa[m] + sp.b1 * t.level_n[m * plane + c];
+            if (sp.b2 != 0.0) num[m] += sp.b2 * t.level_nm1[m * plane + c];
+        }
+        rec.d_r = num[0] * sp.inv_dt;
+        rec.d_ru = num[1] * sp.inv_dt;
+        rec.d_rv = num[2] * sp.inv_dt;
+        rec.rho0 = qa[0];
+        if (pidx < NC) {
+            own_q0[0] = qa[0];
+            own_q0[1] = qa[1];
+            own_q0[2] = qa[2];
+            own_d[0] = rec.d_r;
+            own_d[1] = rec.d_ru;
+            own_d[2] = rec.d_rv;
+        }
+
+        const FaceStates fs = face_states(t, rec);
+        const bool row_in = (j >= 0 && j < TY), col_in = (i >= 0 && i < TX);
+        if (row_in) {
+            if (i >= 0) {  // left face i of the tile's x-faces
+                const int fi = j * (TX + 1) + i;
+                const Prim<double> s = fs.xl;
+                sXR[0][fi] = s.r; sXR[1][fi] = s.u; sXR[2][fi] = s.v; sXR[3][fi] = s.p;
+                if (f & FLAG_WALL_XM) {
+                    const Prim<double> gs = ghost_state(t, rec, 0, -1, slip);
+                    sXL[0][fi] = gs.r; sXL[1][fi] = gs.u; sXL[2][fi] = gs.v; sXL[3][fi] = gs.p;
+                }
+            }
+            if (i < TX) {  // right face i + 1
+                const int fi = j * (TX + 1) + i + 1;
+                const Prim<double> s = fs.xr;
+                sXL[0][fi] = s.r; sXL[1][fi] = s.u; sXL[2][fi] = s.v; sXL[3][fi] = s.p;
+                if (f & FLAG_WALL_XP) {
+                    const Prim<double> gs = ghost_state(t, rec, 0, +1, slip);
+                    sXR[0][fi] = gs.r; sXR[1][fi] = gs.u; sXR[2][fi] = gs.v; sXR[3][fi] = gs.p;
+                }
+            }
+        }
+        if (col_in) {
+            if (j >= 0) {  // lower face j of the tile's y-faces
+                const int fi = j * TX + i;
+                const Prim<double> s = fs.yb;
+                sYU[0][fi] = s.r; sYU[1][fi] = s.u; sYU[2][fi] = s.v; sYU[3][fi] = s.p;
+                if (f & FLAG_WALL_YM) {
+                    const Prim<double> gs = ghost_state(t, rec, 1, -1, slip);
+                    sYL[0][fi] = gs.r; sYL[1][fi] = gs.u; sYL[2][fi] = gs.v; sYL[3][fi] = gs.p;
+                }
+            }
+            if (j < TY) {  // upper face j + 1
+                const int fi = (j + 1) * TX + i;
+                const Prim<double> s = fs.yt;
+                sYL[0][fi] = s.r; sYL[1][fi] = s.u; sYL[2][fi] = s.v; sYL[3][fi] = s.p;
+                if (f & FLAG_WALL_YP) {
+                    const Prim<double> gs = ghost_state(t, rec, 1, +1, slip);
+                    sYU[0][fi] = gs.r; sYU[1][fi] = gs.u; sYU[2][fi] = gs.v; sYU[3][fi] = gs.p;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 3: one Osher flux per face --------------------------------------------------
+    for (int fidx = tid; fidx < NFX + NFY; fidx += kNT) {
+        if (fidx < NFX) {
+            const int fi = fidx % (TX + 1), j = fidx / (TX + 1);
+            const uint8_t fl = sF[(j + 1) * SX + fi], fr = sF[(j + 1) * SX + fi + 1];
+            if ((fl & FLAG_SOLID) && (fr & FLAG_SOLID)) continue;
+            const Prim<double> L = {sXL[0][fidx], sXL[1][fidx], sXL[2][fidx], sXL[3][fidx]};
+            const Prim<double> R = {sXR[0][fidx], sXR[1][fidx], sXR[2][fidx], sXR[3][fidx]};
+            double F[4];
+            osher_x(L, R, t.beta, t.inv_beta, F);
+            sXL[0][fidx] = F[0]; sXL[1][fidx] = F[1]; sXL[2][fidx] = F[2]; sXL[3][fidx] = F[3];
+        } else {
+            const int q = fidx - NFX;
+            const int i = q % TX, g = q / TX;
+            const uint8_t fl = sF[g * SX + i + 1], fu = sF[(g + 1) * SX + i + 1];
+            if ((fl & FLAG_SOLID) && (fu & FLAG_SOLID)) continue;
+            const Prim<double> L = {sYL[0][q], sYL[1][q], sYL[2][q], sYL[3][q]};
+            const Prim<double> U = {sYU[0][q], sYU[1][q], sYU[2][q], sYU[3][q]};
+            double F[4];
+            osher_y(L, U, t.beta, t.inv_beta, F);
+            sYL[0][q] = F[0]; sYL[1][q] = F[1]; sYL[2][q] = F[2]; sYL[3][q] = F[3];
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 4: divergence, sources and the point-implicit update ------------------------
+    const double alpha = sc.alpha[stage - 1];
+    const bool last = (stage == sc.smax);
+    double part[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    {
+        const int i = tid % TX, j = tid / TX;
+        const int gi = x0 + i, gj = y0 + j;
+        const uint8_t f = sF[(j + 1) * SX + (i + 1)];
+        if (gi < t.nx && gj < t.ny && !(f & FLAG_SOLID)) {
+            const size_t c = (size_t)gj * t.nx + gi;
+            const int xm = j * (TX + 1) + i, ym = j * TX + i;
+            double R4[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const double div = (sXL[m][xm + 1] - sXL[m][xm]) * t.inv_dx
+                                   + (sYL[m][ym + TX] - sYL[m][ym]) * t.inv_dy;
+                R4[m] = -div;
+            }
+            const double r0 = own_q0[0], m0 = own_q0[1], n0 = own_q0[2];
+            R4[0] += -own_d[0];
+            R4[1] += -own_d[1] + r0 * t.gx;
+            R4[2] += -own_d[2] + r0 * t.gy;
+            const double p0 = q0[3 * plane + c];
+            const double dtau = local_dtau(t, t.cfl, r0, m0, n0);
+            const double ad = alpha * dtau;
+            const double api = 1.0 + sp.b0 * ad * sp.inv_dt;
+            const double fac = ad / api;
+            qout[c] = r0 + fac * R4[0];
+            qout[plane + c] = m0 + fac * R4[1];
+            qout[2 * plane + c] = n0 + fac * R4[2];
+            qout[3 * plane + c] = p0 + t.beta * (ad * R4[3]);
+            if (last) {
+                const double rp = t.beta * R4[3];
+                if (NORM_MAX) {
+                    part[0] = fabs(R4[0]);
+                    part[1] = fabs(R4[1]);
+                    part[2] = fabs(R4[2]);
+                    part[3] = fabs(rp);
+                } else {
+                    part[0] = R4[0] * R4[0];
+                    part[1] = R4[1] * R4[1];
+                    part[2] = R4[2] * R4[2];
+                    part[3] = rp * rp;
+                }
+                const double rn = r0 + fac * R4[0];
+                part[4] = (rn > 0.0 && rn < INFINITY) ? 0.0 : 1.0;
+            }
+        }
+    }
+    if (last) block_reduce_store<NORM_MAX, kNT>(part, t.partials + (size_t)tile * kPartialWidth);
+}
+
+template <int TX, int TY>
+int launch_tile(const TankDev &t, const Scheme &sc, int stage, void *stream)
+{
+    const int tiles_x = (t.nx + TX - 1) / TX, tiles_y = (t.ny + TY - 1) / TY;
+    const int n_tiles = tiles_x * tiles_y;
+    const int blocks = ((n_tiles + 7) / 8) * 8;
+    if (sc.norm_max)
+        hipLaunchKernelGGL((stage_tile_f64<TX, TY, true>), dim3(blocks), dim3(kNT), 0,
+                           (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles);
+    else
+        hipLaunchKernelGGL((stage_tile_f64<TX, TY, false>), dim3(blocks), dim3(kNT), 0,
+                           (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles);
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+bool tile_supported(int tile_x, int tile_y)
+{
+    return (tile_x == 32 && tile_y == 8) || (tile_x == 16 && tile_y == 16) ||
+           (tile_x == 64 && tile_y == 4);
+}
+
+int tile_count(const TankDev &t, int tile_x, int tile_y)
+{
+    return ((t.nx + tile_x - 1) / tile_x) * ((t.ny + tile_y - 1) / tile_y);
+}
+
+int launch_stage_tile_f64(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
+                          void *stream)
+{
+    if (tile_x == 32 && tile_y == 8) return launch_tile<32, 8>(t, sc, stage, stream);
+    if (tile_x == 16 && tile_y == 16) return launch_tile<16, 16>(t, sc, stage, stream);
+    if (tile_x == 64 && tile_y == 4) return launch_tile<64, 4>(t, sc, stage, stream);
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace vdac

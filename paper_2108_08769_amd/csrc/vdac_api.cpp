@@ -45,7 +45,8 @@ struct TankHost {
     vdac_tank desc;
     std::vector<uint8_t> flags;
     TankDev dev;
-    int n_blocks;
+    int tile_x, tile_y;  // stage kernel tile of this tank
+    int n_blocks;        // residual partials per stage launch
     int hist_ok;  // level n-1 holds a real-time level (BDF2 may be used)
 };
 
@@ -97,8 +98,13 @@ int check_options(const vdac_options *o)
         return fail(VDAC_E_INVALID, "norm must be VDAC_NORM_RMS or VDAC_NORM_MAX");
     if (o->wall_slip != 0 && o->wall_slip != 1)
         return fail(VDAC_E_INVALID, "wall_slip must be 0 or 1");
-    if (o->tile_x < 0 || o->tile_y < 0)
-        return fail(VDAC_E_INVALID, "tile sizes must be >= 0");
+    const bool auto_tile = o->tile_x == 0 && o->tile_y == 0;
+    const bool direct = o->tile_x == 1 && o->tile_y == 1;
+    const bool march = o->tile_x == -1 && o->tile_y >= 1 && o->tile_y <= 4096;
+    if (!auto_tile && !direct && !march && !tile_supported(o->tile_x, o->tile_y))
+        return fail(VDAC_E_INVALID, "tile %d x %d is not available (0 x 0 = automatic, 1 x 1 = "
+                    "one thread per cell, -1 x L = row marching in chunks of L rows, or 32 x 8, "
+                    "16 x 16, 64 x 4)", o->tile_x, o->tile_y);
     return VDAC_OK;
 }
 
@@ -148,12 +154,25 @@ TankLayout layout_of(const vdac_tank *t, const vdac_options *o, int n_blocks)
     return L;
 }
 
-int blocks_for(const vdac_tank *t)
+void tile_for(const vdac_tank *, const vdac_options *o, int *tx, int *ty)
+{
+    if (o->tile_x == 0 && o->tile_y == 0) {
+        *tx = kDefaultTileX;
+        *ty = kDefaultTileY;
+    } else {
+        *tx = o->tile_x;
+        *ty = o->tile_y;
+    }
+}
+
+int blocks_for(const vdac_tank *t, const vdac_options *o)
 {
     TankDev d;
     d.nx = t->nx;
     d.ny = t->ny;
-    return stage_blocks(d, 0, 0);
+    int tx, ty;
+    tile_for(t, o, &tx, &ty);
+    return stage_blocks(d, tx, ty);
 }
 
 void build_flags(const vdac_tank *t, std::vector<uint8_t> &flags, int *n_fluid)
@@ -267,7 +286,7 @@ size_t workspace_bytes(const vdac_tank *tanks, int32_t n_tanks, const vdac_optio
     size_t total = 0;
     for (int t = 0; t < n_tanks; ++t) {
         if (check_tank(&tanks[t], t) != VDAC_OK) return 0;
-        total += layout_of(&tanks[t], o, blocks_for(&tanks[t])).end;
+        total += layout_of(&tanks[t], o, blocks_for(&tanks[t], o)).end;
     }
     return total;
 }
@@ -332,7 +351,8 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         TankHost &th = g->tanks[t];
         th.desc = tanks[t];
         th.desc.solid = nullptr;
-        th.n_blocks = blocks_for(&tanks[t]);
+        tile_for(&tanks[t], o, &th.tile_x, &th.tile_y);
+        th.n_blocks = blocks_for(&tanks[t], o);
         th.hist_ok = 0;
         int n_fluid = 0;
         build_flags(&tanks[t], th.flags, &n_fluid);
@@ -458,7 +478,7 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
                         ev_next += 2;
                         (void)hipEventRecord(e0, g->stream);
                     }
-                    rc = launch_stage_f64(th.dev, g->sc, s, g->opt.tile_x, g->opt.tile_y, g->stream);
+                    rc = launch_stage(th.dev, g->sc, s, th.tile_x, th.tile_y, g->stream);
                     if (rc != 0) return hip_fail((hipError_t)rc, "stage launch");
                     if (g->timing) (void)hipEventRecord(e1, g->stream);
                 }

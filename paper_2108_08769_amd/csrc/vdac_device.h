@@ -21,6 +21,32 @@ struct Slope {
     T r, u, v;
 };
 
+// Reciprocal and reciprocal square root of a positive, finite, normal FP64 argument: the
+// hardware estimates (v_rcp_f64, v_rsq_f64) refined by two Newton steps, which leaves an error of
+// about one unit in the last place.  Used where an IEEE division or square root would cost about
+// ten instructions more.
+__device__ __forceinline__ double rcp_pos(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+__device__ __forceinline__ double rsqrt_pos(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    // y <- y + y (1 - x y^2) / 2, twice
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+__device__ __forceinline__ float rcp_pos(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsqrt_pos(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // k-limiter G(a, b) = s max(0, min(k|b|, s a), min(|b|, k s a)), s = sgn(b), sgn(0) = 0
 // (Sec. 2.3.1).  k = 1 is minmod, k = 2 superbee.
 template <typename T>
@@ -34,6 +60,15 @@ __device__ __forceinline__ T limiter(T a, T b, T k)
     return s * fmax(T(0), fmax(t1, t2));
 }
 
+// k = 1: minmod(a, b) = sgn(b) min(|a|, |b|) when a and b share a sign, else 0 -- the same value
+// as limiter(a, b, 1) (up to the sign of a zero result).
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b)
+{
+    const T m = fmin(fabs(a), fabs(b));
+    return (a * b > T(0)) ? copysign(m, b) : T(0);
+}
+
 // Limited one-sided slopes of rho, u, v at a cell from its two neighbours along one axis:
 // G((W_{i+1} - W_i)/h, (W_i - W_{i-1})/h).
 template <typename T>
@@ -41,9 +76,15 @@ __device__ __forceinline__ Slope<T> slopes(const Prim<T> &m, const Prim<T> &c, c
                                            T inv_h, T k)
 {
     Slope<T> g;
-    g.r = limiter((p.r - c.r) * inv_h, (c.r - m.r) * inv_h, k);
-    g.u = limiter((p.u - c.u) * inv_h, (c.u - m.u) * inv_h, k);
-    g.v = limiter((p.v - c.v) * inv_h, (c.v - m.v) * inv_h, k);
+    if (k == T(1)) {
+        g.r = minmod((p.r - c.r) * inv_h, (c.r - m.r) * inv_h);
+        g.u = minmod((p.u - c.u) * inv_h, (c.u - m.u) * inv_h);
+        g.v = minmod((p.v - c.v) * inv_h, (c.v - m.v) * inv_h);
+    } else {
+        g.r = limiter((p.r - c.r) * inv_h, (c.r - m.r) * inv_h, k);
+        g.u = limiter((p.u - c.u) * inv_h, (c.u - m.u) * inv_h, k);
+        g.v = limiter((p.v - c.v) * inv_h, (c.v - m.v) * inv_h, k);
+    }
     return g;
 }
 
@@ -99,39 +140,46 @@ __device__ __forceinline__ void osher_x(const Prim<T> &L, const Prim<T> &R, T be
     const T mR = R.r * R.u, nR = R.r * R.v;
     const T dr = R.r - L.r, dm = mR - mL, dn = nR - nL;
     const T dq = (R.p - L.p) * inv_beta;
+    const T four_beta = T(4) * beta;
 
     // Gauss-Legendre nodes on [0, 1] and half weights
     const T t0 = T(0.11270166537925831148207346002176);  // (1 - sqrt(3/5))/2
     const T t2 = T(0.88729833462074168851792653997824);  // (1 + sqrt(3/5))/2
     const T w0 = T(5.0) / T(18.0), w1 = T(8.0) / T(18.0);
 
-    T acc0 = T(0), acc1 = T(0), acc2 = T(0), acc3 = T(0);
+    // sum_j (w_j/2) |A_j| dQ = (sum_j (w_j/2)|u_j|) dQ + sum_j [k4 r4 + k5 r5]_j, with the weight
+    // folded into k4 and k5
+    T sau = T(0), a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const T t = (j == 0) ? t0 : ((j == 1) ? T(0.5) : t2);
         const T wj = (j == 1) ? w1 : w0;
-        const T rho = L.r + dr * t;
-        const T m = mL + dm * t;
-        const T n = nL + dn * t;
-        const T ir = T(1) / rho;
+        const T rho = fma(dr, t, L.r);
+        const T m = fma(dm, t, mL);
+        const T n = fma(dn, t, nL);
+        const T ir = rcp_pos(rho);
         const T u = m * ir, v = n * ir;
-        const T c = sqrt(u * u + T(4) * beta * ir);
-        const T rc = rho / c;
-        const T l4 = T(0.5) * (u + c), l5 = T(0.5) * (u - c);
+        const T c2 = fma(u, u, four_beta * ir);
+        const T y = rsqrt_pos(c2);          // 1/c
+        const T c = c2 * y;
+        const T rcw = wj * rho * y;         // (w_j/2) rho / c
+        const T hu = T(0.5) * u, hc = T(0.5) * c;
+        const T l4 = hu + hc, l5 = hu - hc;
         const T au = fabs(u);
-        const T a = (dm - u * dr) * inv_beta;
-        const T k4 = (l4 - au) * rc * (l4 * a + dq);
-        const T k5 = (l5 + au) * rc * (l5 * a + dq);
-        const T s = k4 * l4 + k5 * l5;
-        acc0 += wj * (au * dr + s);
-        acc1 += wj * (au * dm + u * s + beta * ir * (k4 + k5));
-        acc2 += wj * (au * dn + v * s);
-        acc3 += wj * (au * dq - (k4 * l5 + k5 * l4) * ir);
+        sau = fma(wj, au, sau);
+        const T a = fma(-u, dr, dm) * inv_beta;
+        const T k4 = (l4 - au) * rcw * fma(l4, a, dq);
+        const T k5 = (l5 + au) * rcw * fma(l5, a, dq);
+        const T s = fma(k4, l4, k5 * l5);
+        a0 += s;
+        a1 += fma(u, s, beta * ir * (k4 + k5));
+        a2 = fma(v, s, a2);
+        a3 -= fma(k4, l5, k5 * l4) * ir;
     }
-    F[0] = T(0.5) * (mL + mR - acc0);
-    F[1] = T(0.5) * (mL * L.u + L.p + mR * R.u + R.p - acc1);
-    F[2] = T(0.5) * (mL * L.v + mR * R.v - acc2);
-    F[3] = T(0.5) * (L.u + R.u - acc3);
+    F[0] = T(0.5) * (mL + mR - fma(sau, dr, a0));
+    F[1] = T(0.5) * (fma(mL, L.u, L.p) + fma(mR, R.u, R.p) - fma(sau, dm, a1));
+    F[2] = T(0.5) * (mL * L.v + mR * R.v - fma(sau, dn, a2));
+    F[3] = T(0.5) * (L.u + R.u - fma(sau, dq, a3));
 }
 
 // Face flux with normal +y: Algorithm 2 gives t1 = (1, 0, 0) for n = (0, 1, 0), so the rotated

@@ -93,12 +93,27 @@ struct Scheme {
     int32_t bdf2;    // the grid keeps a level n-1 history
 };
 
-// Launch wrappers (kernels_f64.hip).  All return hipError_t cast to int.
+// Launch wrappers.  All return hipError_t cast to int.  A stage launch with tile (1, 1) runs the
+// plain one-thread-per-cell kernel (kernels_f64.hip); tile (-1, L) runs the row-marching kernel
+// (stage_march.hip) on 64-column strips swept in chunks of L rows; the supported 2D tiles run
+// the tiled kernel (stage_tile.hip).  stage_blocks() is the number of residual partials a stage
+// launch writes.
 int launch_begin_step(const TankDev &t, const Scheme &sc, double dt, int max_pseudo, double tol,
                       int use_history, void *stream);
-int launch_stage_f64(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
-                     void *stream);
+int launch_stage(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
+                 void *stream);
+int launch_stage_direct_f64(const TankDev &t, const Scheme &sc, int stage, void *stream);
+int launch_stage_tile_f64(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
+                          void *stream);
 int launch_finalize(const TankDev &t, const Scheme &sc, int n_blocks, void *stream);
+int launch_stage_march_f64(const TankDev &t, const Scheme &sc, int stage, int chunk, void *stream);
+int march_units(const TankDev &t, int chunk);
 int stage_blocks(const TankDev &t, int tile_x, int tile_y);
+int direct_blocks(const TankDev &t);
+int tile_count(const TankDev &t, int tile_x, int tile_y);
+bool tile_supported(int tile_x, int tile_y);
+
+// Tile used when the options leave the choice open.
+constexpr int kDefaultTileX = 32, kDefaultTileY = 8;
 
 }  // namespace vdac

@@ -43,7 +43,7 @@ def run_gpu(wk: wl.Workload, steps: int, max_pseudo: int, tol: float = 0.0, norm
 
 
 def run_oracle(wk: wl.Workload, steps: int, max_pseudo: int, tol: float = 0.0, norm=0,
-               wall_slip=False):
+               wall_slip=False, **_ignored):
     states, iters, norms, codes = [], [], [], []
     per_tank_iters = [[] for _ in wk.tanks]
     for ti, t in enumerate(wk.tanks):
