@@ -72,7 +72,8 @@ typedef struct {
     int32_t norm;        /* VDAC_NORM_RMS or VDAC_NORM_MAX over fluid cells */
     int32_t wall_slip;   /* 0: no-slip wall ghosts as in Sec. 2.5; 1: free-slip ghosts */
     int32_t tile_x, tile_y; /* stage-kernel shape: 0 x 0 automatic; 1 x 1 one thread per cell;
-                               -1 x L row marching over 64-column strips in chunks of L rows;
+                               -W x L row marching over 64-column strips in chunks of L rows,
+                               W = 3 for a 3-waves-per-SIMD register budget, 1 or 2 otherwise;
                                32 x 8, 16 x 16 or 64 x 4 two-dimensional LDS tiles */
 } vdac_options;
 

@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
         if (!(f & FLAG_SOLID)) {
             CellRec me;
             reconstruct(t, sc, sp, qprev, q0, i, j, me);
-            double Fxm[4], Fxp[4], Fym[4], Fyp[4];
+            Vec4<double> Fxm, Fxp, Fym, Fyp;
             {
                 Prim<double> L, R;
                 R = own_state(t, me, 0, -1);
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
                     reconstruct(t, sc, sp, qprev, q0, wrap(i - 1, t.nx), j, nb);
                     L = own_state(t, nb, 0, +1);
                 }
-                osher_x(L, R, t.beta, t.inv_beta, Fxm);
+                Fxm = osher_x(L, R, t.beta, t.inv_beta);
                 L = own_state(t, me, 0, +1);
                 if (f & FLAG_WALL_XP) {
                     R = ghost_state(t, me, 0, +1, slip);
@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
                     reconstruct(t, sc, sp, qprev, q0, wrap(i + 1, t.nx), j, nb);
                     R = own_state(t, nb, 0, -1);
                 }
-                osher_x(L, R, t.beta, t.inv_beta, Fxp);
+                Fxp = osher_x(L, R, t.beta, t.inv_beta);
                 R = own_state(t, me, 1, -1);
                 if (f & FLAG_WALL_YM) {
                     L = ghost_state(t, me, 1, -1, slip);
@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
                     reconstruct(t, sc, sp, qprev, q0, i, wrap(j - 1, t.ny), nb);
                     L = own_state(t, nb, 1, +1);
                 }
-                osher_y(L, R, t.beta, t.inv_beta, Fym);
+                Fym = osher_y(L, R, t.beta, t.inv_beta);
                 L = own_state(t, me, 1, +1);
                 if (f & FLAG_WALL_YP) {
                     R = ghost_state(t, me, 1, +1, slip);
@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
                     reconstruct(t, sc, sp, qprev, q0, i, wrap(j + 1, t.ny), nb);
                     R = own_state(t, nb, 1, -1);
                 }
-                osher_y(L, R, t.beta, t.inv_beta, Fyp);
+                Fyp = osher_y(L, R, t.beta, t.inv_beta);
             }
             // bracket of eq. RK2 and the point-implicit update (eq. point_implicit)
             const double r0 = q0[c], m0 = q0[plane + c], n0 = q0[2 * plane + c];
@@ -238,14 +238,14 @@ int direct_blocks(const TankDev &t)
 int stage_blocks(const TankDev &t, int tile_x, int tile_y)
 {
     if (tile_x == 1 && tile_y == 1) return direct_blocks(t);
-    if (tile_x == -1) return march_units(t, tile_y);
+    if (tile_x < 0) return march_units(t, tile_y);
     return tile_count(t, tile_x, tile_y);
 }
 
 int launch_stage(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y, void *stream)
 {
     if (tile_x == 1 && tile_y == 1) return launch_stage_direct_f64(t, sc, stage, stream);
-    if (tile_x == -1) return launch_stage_march_f64(t, sc, stage, tile_y, stream);
+    if (tile_x < 0) return launch_stage_march_f64(t, sc, stage, tile_y, -tile_x, stream);
     return launch_stage_tile_f64(t, sc, stage, tile_x, tile_y, stream);
 }
 

@@ -27,7 +27,6 @@ namespace {
 constexpr int kLanes = 64;
 constexpr int kOut = 60;            // output columns per strip (lanes 2..61)
 constexpr int kWavesPerBlock = 4;
-constexpr int kMinWavesPerSimd = 2;  // register budget: at most 256 VGPRs per lane
 
 __device__ __forceinline__ bool locate_axis(int g, int n, int periodic, int &out)
 {
@@ -56,66 +55,72 @@ __device__ __forceinline__ Prim<double> prim_from_right(const Prim<double> &w)
 // ahead (it is the upper neighbour of the next row), the stage-0 state, level n (and level
 // n-1) and the flags one row ahead.
 struct InputLoad {
-    double q[4];     // stage input Q^{s-1}: rho, rho u, rho v, p
+    double r, m, n, p;   // stage input Q^{s-1}: rho, rho u, rho v, p
 };
 struct SourceLoad {
-    double z[4];     // stage-0 state Q^0: rho, rho u, rho v, p
-    double n[3];     // level n
-    double m[3];     // level n-1 (BDF2 only)
-    uint8_t f;       // cell flags (FLAG_SOLID if outside the tank)
+    double z0, z1, z2, z3;  // stage-0 state Q^0: rho, rho u, rho v, p
+    double n0, n1, n2;      // level n
+    double m0, m1, m2;      // level n-1 (BDF2 only)
+    uint8_t f;              // cell flags (FLAG_SOLID if outside the tank)
 };
 
-__device__ __forceinline__ void load_input(const TankDev &t, const double *qprev, bool have_col,
-                                           int gi, int r, InputLoad &L)
+__device__ __forceinline__ InputLoad load_input(const TankDev &t, const double *qprev,
+                                                bool have_col, int gi, int r)
 {
     int gj;
+    InputLoad L = {1.0, 0.0, 0.0, 0.0};
     if (have_col && locate_axis(r, t.ny, t.per_y, gj)) {
         const size_t c = (size_t)gj * t.nx + gi;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) L.q[k] = qprev[k * t.plane + c];
-    } else {
-        L.q[0] = 1.0;
-        L.q[1] = L.q[2] = L.q[3] = 0.0;
+        L.r = qprev[c];
+        L.m = qprev[t.plane + c];
+        L.n = qprev[2 * t.plane + c];
+        L.p = qprev[3 * t.plane + c];
     }
+    return L;
 }
 
 template <bool BDF2>
-__device__ __forceinline__ void load_sources(const TankDev &t, const double *q0, bool have_col,
-                                             int gi, int r, SourceLoad &L)
+__device__ __forceinline__ SourceLoad load_sources(const TankDev &t, const double *q0,
+                                                   bool have_col, int gi, int r)
 {
     int gj;
-    L.f = FLAG_SOLID;
+    SourceLoad L = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0, FLAG_SOLID};
     if (have_col && locate_axis(r, t.ny, t.per_y, gj)) {
         const size_t plane = t.plane;
         const size_t c = (size_t)gj * t.nx + gi;
         L.f = t.flags[c];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) L.z[k] = q0[k * plane + c];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) L.n[k] = t.level_n[k * plane + c];
+        L.z0 = q0[c];
+        L.z1 = q0[plane + c];
+        L.z2 = q0[2 * plane + c];
+        L.z3 = q0[3 * plane + c];
+        L.n0 = t.level_n[c];
+        L.n1 = t.level_n[plane + c];
+        L.n2 = t.level_n[2 * plane + c];
         if (BDF2) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) L.m[k] = t.level_nm1[k * plane + c];
-        }
-    } else {
-        L.z[0] = 1.0;
-        L.z[1] = L.z[2] = L.z[3] = 0.0;
-        L.n[0] = 1.0;
-        L.n[1] = L.n[2] = 0.0;
-        if (BDF2) {
-            L.m[0] = 1.0;
-            L.m[1] = L.m[2] = 0.0;
+            L.m0 = t.level_nm1[c];
+            L.m1 = t.level_nm1[plane + c];
+            L.m2 = t.level_nm1[2 * plane + c];
         }
     }
+    return L;
 }
 
 __device__ __forceinline__ Prim<double> to_prim(const InputLoad &L)
 {
-    return {L.q[0], L.q[1] / L.q[0], L.q[2] / L.q[0], L.q[3]};
+    const double ir = rcp_pos(L.r);
+    return {L.r, L.m * ir, L.n * ir, L.p};
 }
 
-template <bool NORM_MAX, bool BDF2>
-__global__ void __launch_bounds__(kLanes *kWavesPerBlock, kMinWavesPerSimd)
+// States of a reconstructed cell at one face: W +- grad W h, with the new pressure gradient.
+__device__ __forceinline__ Prim<double> state_at(const Prim<double> &w, const Slope<double> &g,
+                                                 double gp, double h)
+{
+    return {fma(g.r, h, w.r), fma(g.u, h, w.u), fma(g.v, h, w.v), fma(gp, h, w.p)};
+}
+
+// WAVES: the register budget as waves per SIMD (2: up to 256 VGPRs per lane, 3: up to 168).
+template <bool NORM_MAX, bool BDF2, bool LAST, int WAVES>
+__global__ void __launch_bounds__(kLanes *kWavesPerBlock, WAVES)
     stage_march_f64(TankDev t, Scheme sc, int stage, int chunk, int n_strips, int n_units)
 {
     const Status *st = t.status;
@@ -147,57 +152,54 @@ __global__ void __launch_bounds__(kLanes *kWavesPerBlock, kMinWavesPerSimd)
     const bool slip = sc.slip != 0;
     const double kl = sc.k;
     const double alpha = sc.alpha[stage - 1];
-    const bool last = (stage == sc.smax);
     const size_t plane = t.plane;
 
-    // window of primitives: rows r-1 (lo), r (mid), r+1 (hi)
-    InputLoad in_ld;
-    SourceLoad src_ld;
-    load_input(t, qprev, have_col, gi, j0 - 2, in_ld);
-    Prim<double> lo = to_prim(in_ld);
-    load_input(t, qprev, have_col, gi, j0 - 1, in_ld);
-    Prim<double> mid = to_prim(in_ld);
-    load_input(t, qprev, have_col, gi, j0, in_ld);
-    Prim<double> hi = to_prim(in_ld);
-    load_input(t, qprev, have_col, gi, j0 + 1, in_ld);          // row r+2
-    load_sources<BDF2>(t, q0, have_col, gi, j0 - 1, src_ld);    // row r
+    // window of primitives: rows r-1 (lo), r (mid), r+1 (hi); loads for later rows in flight
+    Prim<double> lo = to_prim(load_input(t, qprev, have_col, gi, j0 - 2));
+    Prim<double> mid = to_prim(load_input(t, qprev, have_col, gi, j0 - 1));
+    Prim<double> hi = to_prim(load_input(t, qprev, have_col, gi, j0));
+    InputLoad in_ld = load_input(t, qprev, have_col, gi, j0 + 1);           // row r+2
+    SourceLoad src_ld = load_sources<BDF2>(t, q0, have_col, gi, j0 - 1);    // row r
 
-    // carries from row r-1
-    Prim<double> top_state = {1.0, 0.0, 0.0, 0.0};  // its state at the face above it
-    double g_wall[4] = {0.0, 0.0, 0.0, 0.0};        // flux above it when that face is a wall
-    double rpart[4] = {0.0, 0.0, 0.0, 0.0};         // its residual without the flux above it
-    double base[4] = {0.0, 0.0, 0.0, 0.0};          // its stage-0 state
-    double fac = 0.0, adt = 0.0;                    // its update factors
+    // carries from row r-1:
+    //  below      its state at its upper face, or, if that face is a wall, the face's flux
+    //  pre/base   its update without the flux above it: non-final stages carry
+    //             pre = Q^0 + fac R_partial; the final stage keeps Q^0 and R_partial apart for
+    //             the residual norm
+    Vec4<double> below = {1.0, 0.0, 0.0, 0.0};
+    Vec4<double> pre = zero4<double>();
+    Vec4<double> rpart = zero4<double>();
+    double fac = 0.0, adt = 0.0;
     bool fluid_lo = false;
-    double part[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double part0 = 0.0, part1 = 0.0, part2 = 0.0, part3 = 0.0, part4 = 0.0;
 
     for (int r = j0 - 1; r <= j1; ++r) {
         // sources of row r (loaded one step ahead), then the next loads
         const uint8_t f = src_ld.f;
         const bool fluid = !(f & FLAG_SOLID);
-        double z[4], d[3];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) z[k] = src_ld.z[k];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            double num = sp.b0 * src_ld.z[k] + sp.b1 * src_ld.n[k];
-            if (BDF2) num += sp.b2 * src_ld.m[k];
-            d[k] = num * sp.inv_dt;
+        const Vec4<double> z = {src_ld.z0, src_ld.z1, src_ld.z2, src_ld.z3};
+        double num0 = fma(sp.b0, src_ld.z0, sp.b1 * src_ld.n0);
+        double num1 = fma(sp.b0, src_ld.z1, sp.b1 * src_ld.n1);
+        double num2 = fma(sp.b0, src_ld.z2, sp.b1 * src_ld.n2);
+        if (BDF2) {
+            num0 = fma(sp.b2, src_ld.m0, num0);
+            num1 = fma(sp.b2, src_ld.m1, num1);
+            num2 = fma(sp.b2, src_ld.m2, num2);
         }
         const Prim<double> next_hi = to_prim(in_ld);
-        load_input(t, qprev, have_col, gi, r + 3, in_ld);
-        load_sources<BDF2>(t, q0, have_col, gi, r + 1, src_ld);
+        in_ld = load_input(t, qprev, have_col, gi, r + 3);
+        src_ld = load_sources<BDF2>(t, q0, have_col, gi, r + 1);
 
         // ---- reconstruction of row r ------------------------------------------------------
         const Prim<double> wl = prim_from_left(mid);
         const Prim<double> wr = prim_from_right(mid);
         CellRec rec;
         rec.w = mid;
-        rec.d_r = d[0];
-        rec.d_ru = d[1];
-        rec.d_rv = d[2];
-        rec.rho0 = z[0];
-        Prim<double> sxl = mid, sxr = mid, syb = mid, syt = mid;
+        rec.d_r = num0 * sp.inv_dt;
+        rec.d_ru = num1 * sp.inv_dt;
+        rec.d_rv = num2 * sp.inv_dt;
+        rec.rho0 = z.a;
+        double px = 0.0, py = 0.0;
         if (fluid) {
             const Prim<double> xm = (f & FLAG_WALL_XM) ? mirror(mid, 0, slip) : wl;
             const Prim<double> xp = (f & FLAG_WALL_XP) ? mirror(mid, 0, slip) : wr;
@@ -205,27 +207,22 @@ __global__ void __launch_bounds__(kLanes *kWavesPerBlock, kMinWavesPerSimd)
             const Prim<double> yp = (f & FLAG_WALL_YP) ? mirror(mid, 1, slip) : hi;
             rec.gx = slopes(xm, mid, xp, t.inv_dx, kl);
             rec.gy = slopes(ym, mid, yp, t.inv_dy, kl);
-            const double px = gradp_x(mid, rec.gx, rec.gy, rec.d_ru, rec.rho0 * t.gx);
-            const double py = gradp_y(mid, rec.gx, rec.gy, rec.d_rv, rec.rho0 * t.gy);
-            sxl = {mid.r - rec.gx.r * t.half_dx, mid.u - rec.gx.u * t.half_dx,
-                   mid.v - rec.gx.v * t.half_dx, mid.p - px * t.half_dx};
-            sxr = {mid.r + rec.gx.r * t.half_dx, mid.u + rec.gx.u * t.half_dx,
-                   mid.v + rec.gx.v * t.half_dx, mid.p + px * t.half_dx};
-            syb = {mid.r - rec.gy.r * t.half_dy, mid.u - rec.gy.u * t.half_dy,
-                   mid.v - rec.gy.v * t.half_dy, mid.p - py * t.half_dy};
-            syt = {mid.r + rec.gy.r * t.half_dy, mid.u + rec.gy.u * t.half_dy,
-                   mid.v + rec.gy.v * t.half_dy, mid.p + py * t.half_dy};
+            px = gradp_x(mid, rec.gx, rec.gy, rec.d_ru, rec.rho0 * t.gx);
+            py = gradp_y(mid, rec.gx, rec.gy, rec.d_rv, rec.rho0 * t.gy);
+        } else {
+            rec.gx = {0.0, 0.0, 0.0};
+            rec.gy = {0.0, 0.0, 0.0};
         }
 
         // ---- y-face between rows r-1 and r ------------------------------------------------
-        double gb[4] = {0.0, 0.0, 0.0, 0.0};
+        Vec4<double> gb = zero4<double>();
         if (r >= j0) {
             if (fluid) {
-                const Prim<double> L = fluid_lo ? top_state : ghost_state(t, rec, 1, -1, slip);
-                osher_y(L, syb, t.beta, t.inv_beta, gb);
+                const Prim<double> L = fluid_lo ? Prim<double>{below.a, below.b, below.c, below.d}
+                                                : ghost_state(t, rec, 1, -1, slip);
+                gb = osher_y(L, state_at(mid, rec.gy, py, -t.half_dy), t.beta, t.inv_beta);
             } else if (fluid_lo) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) gb[k] = g_wall[k];
+                gb = below;  // evaluated with row r-1's ghost
             }
         }
 
@@ -234,83 +231,89 @@ __global__ void __launch_bounds__(kLanes *kWavesPerBlock, kMinWavesPerSimd)
             int gj;
             locate_axis(r - 1, t.ny, t.per_y, gj);
             const size_t c = (size_t)gj * t.nx + gi;
-            double R4[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) R4[k] = rpart[k] - gb[k] * t.inv_dy;
-            const double rn = base[0] + fac * R4[0];
-            qout[c] = rn;
-            qout[plane + c] = base[1] + fac * R4[1];
-            qout[2 * plane + c] = base[2] + fac * R4[2];
-            qout[3 * plane + c] = base[3] + t.beta * (adt * R4[3]);
-            if (last) {
-                const double rp = t.beta * R4[3];
+            if (LAST) {
+                const double R0 = fma(-gb.a, t.inv_dy, rpart.a);
+                const double R1 = fma(-gb.b, t.inv_dy, rpart.b);
+                const double R2 = fma(-gb.c, t.inv_dy, rpart.c);
+                const double R3 = fma(-gb.d, t.inv_dy, rpart.d);
+                const double rn = fma(fac, R0, pre.a);
+                qout[c] = rn;
+                qout[plane + c] = fma(fac, R1, pre.b);
+                qout[2 * plane + c] = fma(fac, R2, pre.c);
+                qout[3 * plane + c] = fma(t.beta, adt * R3, pre.d);
+                const double rp = t.beta * R3;
                 if (NORM_MAX) {
-                    part[0] = combine<true>(part[0], fabs(R4[0]));
-                    part[1] = combine<true>(part[1], fabs(R4[1]));
-                    part[2] = combine<true>(part[2], fabs(R4[2]));
-                    part[3] = combine<true>(part[3], fabs(rp));
+                    part0 = combine<true>(part0, fabs(R0));
+                    part1 = combine<true>(part1, fabs(R1));
+                    part2 = combine<true>(part2, fabs(R2));
+                    part3 = combine<true>(part3, fabs(rp));
                 } else {
-                    part[0] += R4[0] * R4[0];
-                    part[1] += R4[1] * R4[1];
-                    part[2] += R4[2] * R4[2];
-                    part[3] += rp * rp;
+                    part0 = fma(R0, R0, part0);
+                    part1 = fma(R1, R1, part1);
+                    part2 = fma(R2, R2, part2);
+                    part3 = fma(rp, rp, part3);
                 }
-                part[4] += (rn > 0.0 && rn < INFINITY) ? 0.0 : 1.0;
+                part4 += (rn > 0.0 && rn < INFINITY) ? 0.0 : 1.0;
+            } else {
+                // fac and adt already carry 1/dy here
+                qout[c] = fma(-fac, gb.a, pre.a);
+                qout[plane + c] = fma(-fac, gb.b, pre.b);
+                qout[2 * plane + c] = fma(-fac, gb.c, pre.c);
+                qout[3 * plane + c] = fma(-adt, gb.d, pre.d);
             }
         }
 
-        // ---- x-faces of row r and its partial residual -----------------------------------
-        double rp4[4] = {0.0, 0.0, 0.0, 0.0};
+        // ---- x-faces of row r and its residual without the upper y-face ------------------
+        Vec4<double> rp4 = zero4<double>();
         if (r >= j0 && r < j1) {
+            const Prim<double> sxl = state_at(mid, rec.gx, px, -t.half_dx);
             const Prim<double> partner = prim_from_right(sxl);  // right neighbour's left state
-            double fr[4] = {0.0, 0.0, 0.0, 0.0};
+            Vec4<double> fr = zero4<double>();
             if (fluid) {
                 const Prim<double> R = (f & FLAG_WALL_XP) ? ghost_state(t, rec, 0, +1, slip) : partner;
-                osher_x(sxr, R, t.beta, t.inv_beta, fr);
+                fr = osher_x(state_at(mid, rec.gx, px, t.half_dx), R, t.beta, t.inv_beta);
             }
-            double fl[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) fl[k] = from_left(fr[k]);
-            if (fluid && (f & FLAG_WALL_XM)) {
-                const Prim<double> Lg = ghost_state(t, rec, 0, -1, slip);
-                osher_x(Lg, sxl, t.beta, t.inv_beta, fl);
-            }
-            // residual of row r without its upper y-face: -(x-divergence) + lower flux / dy
-            // - real-time term + body force
-#pragma unroll
-            for (int k = 0; k < 4; ++k) rp4[k] = -((fr[k] - fl[k]) * t.inv_dx) + gb[k] * t.inv_dy;
-            rp4[0] += -d[0];
-            rp4[1] += -d[1] + z[0] * t.gx;
-            rp4[2] += -d[2] + z[0] * t.gy;
-        }
-        // a wall above row r: evaluate that face now, from row r's ghost
-        double gw[4] = {0.0, 0.0, 0.0, 0.0};
-        if (fluid && (f & FLAG_WALL_YP) && r < j1) {
-            const Prim<double> U = ghost_state(t, rec, 1, +1, slip);
-            osher_y(syt, U, t.beta, t.inv_beta, gw);
+            Vec4<double> fl = {from_left(fr.a), from_left(fr.b), from_left(fr.c), from_left(fr.d)};
+            if (fluid && (f & FLAG_WALL_XM))
+                fl = osher_x(ghost_state(t, rec, 0, -1, slip), sxl, t.beta, t.inv_beta);
+            // -(x-divergence) + lower flux / dy - real-time term + body force
+            rp4.a = fma(gb.a, t.inv_dy, -((fr.a - fl.a) * t.inv_dx)) - rec.d_r;
+            rp4.b = fma(gb.b, t.inv_dy, -((fr.b - fl.b) * t.inv_dx)) + fma(z.a, t.gx, -rec.d_ru);
+            rp4.c = fma(gb.c, t.inv_dy, -((fr.c - fl.c) * t.inv_dx)) + fma(z.a, t.gy, -rec.d_rv);
+            rp4.d = fma(gb.d, t.inv_dy, -((fr.d - fl.d) * t.inv_dx));
         }
 
-        // ---- carry row r to the next step -------------------------------------------------
+        // ---- carries of row r -------------------------------------------------------------
+        const Prim<double> syt = state_at(mid, rec.gy, py, t.half_dy);
+        if (fluid && (f & FLAG_WALL_YP) && r < j1)  // a wall above row r: that face's flux now
+            below = osher_y(syt, ghost_state(t, rec, 1, +1, slip), t.beta, t.inv_beta);
+        else
+            below = {syt.r, syt.u, syt.v, syt.p};
         if (fluid && r >= j0 && r < j1) {
-            const double dtau = local_dtau(t, t.cfl, z[0], z[1], z[2]);
-            adt = alpha * dtau;
-            fac = adt / (1.0 + sp.b0 * adt * sp.inv_dt);
+            const double dtau = local_dtau(t, t.cfl, z.a, z.b, z.c);
+            const double ad = alpha * dtau;
+            const double fc = ad / (1.0 + sp.b0 * ad * sp.inv_dt);
+            if (LAST) {
+                pre = z;
+                rpart = rp4;
+                fac = fc;
+                adt = ad;
+            } else {
+                pre = {fma(fc, rp4.a, z.a), fma(fc, rp4.b, z.b), fma(fc, rp4.c, z.c),
+                       fma(t.beta * ad, rp4.d, z.d)};
+                fac = fc * t.inv_dy;
+                adt = t.beta * ad * t.inv_dy;
+            }
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            rpart[k] = rp4[k];
-            base[k] = z[k];
-            g_wall[k] = gw[k];
-        }
-        top_state = syt;
         fluid_lo = fluid;
         lo = mid;
         mid = hi;
         hi = next_hi;
     }
 
-    if (last) {
+    if (LAST) {
         // wave reduction (fixed order) and one partial per strip chunk
+        const double part[kPartialWidth] = {part0, part1, part2, part3, part4};
 #pragma unroll
         for (int k = 0; k < kPartialWidth; ++k) {
             double x = part[k];
@@ -333,7 +336,8 @@ int march_units(const TankDev &t, int chunk)
     return n_strips * n_chunks;
 }
 
-int launch_stage_march_f64(const TankDev &t, const Scheme &sc, int stage, int chunk, void *stream)
+int launch_stage_march_f64(const TankDev &t, const Scheme &sc, int stage, int chunk, int waves,
+                           void *stream)
 {
     const int n_strips = (t.nx + kOut - 1) / kOut;
     const int n_units = march_units(t, chunk);
@@ -342,13 +346,29 @@ int launch_stage_march_f64(const TankDev &t, const Scheme &sc, int stage, int ch
     const dim3 g(grid), b(kLanes * kWavesPerBlock);
     hipStream_t s = (hipStream_t)stream;
     const bool bdf2 = t.level_nm1 != nullptr;
-    if (sc.norm_max) {
-        if (bdf2) hipLaunchKernelGGL((stage_march_f64<true, true>), g, b, 0, s, t, sc, stage, chunk, n_strips, n_units);
-        else hipLaunchKernelGGL((stage_march_f64<true, false>), g, b, 0, s, t, sc, stage, chunk, n_strips, n_units);
+    const bool last = stage == sc.smax;
+#define VDAC_MARCH(NM, B2, LS)                                                                       \
+    do {                                                                                             \
+        if (waves == 3)                                                                              \
+            hipLaunchKernelGGL((stage_march_f64<NM, B2, LS, 3>), g, b, 0, s, t, sc, stage, chunk,    \
+                               n_strips, n_units);                                                   \
+        else                                                                                         \
+            hipLaunchKernelGGL((stage_march_f64<NM, B2, LS, 2>), g, b, 0, s, t, sc, stage, chunk,    \
+                               n_strips, n_units);                                                   \
+    } while (0)
+    if (last) {
+        if (sc.norm_max) {
+            if (bdf2) VDAC_MARCH(true, true, true);
+            else VDAC_MARCH(true, false, true);
+        } else {
+            if (bdf2) VDAC_MARCH(false, true, true);
+            else VDAC_MARCH(false, false, true);
+        }
     } else {
-        if (bdf2) hipLaunchKernelGGL((stage_march_f64<false, true>), g, b, 0, s, t, sc, stage, chunk, n_strips, n_units);
-        else hipLaunchKernelGGL((stage_march_f64<false, false>), g, b, 0, s, t, sc, stage, chunk, n_strips, n_units);
+        if (bdf2) VDAC_MARCH(false, true, false);
+        else VDAC_MARCH(false, false, false);
     }
+#undef VDAC_MARCH
     return (int)hipGetLastError();
 }
 

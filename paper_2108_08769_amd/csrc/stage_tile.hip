@@ -220,9 +220,8 @@ __global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int 
             if ((fl & FLAG_SOLID) && (fr & FLAG_SOLID)) continue;
             const Prim<double> L = {sXL[0][fidx], sXL[1][fidx], sXL[2][fidx], sXL[3][fidx]};
             const Prim<double> R = {sXR[0][fidx], sXR[1][fidx], sXR[2][fidx], sXR[3][fidx]};
-            double F[4];
-            osher_x(L, R, t.beta, t.inv_beta, F);
-            sXL[0][fidx] = F[0]; sXL[1][fidx] = F[1]; sXL[2][fidx] = F[2]; sXL[3][fidx] = F[3];
+            const Vec4<double> F = osher_x(L, R, t.beta, t.inv_beta);
+            sXL[0][fidx] = F.a; sXL[1][fidx] = F.b; sXL[2][fidx] = F.c; sXL[3][fidx] = F.d;
         } else {
             const int q = fidx - NFX;
             const int i = q % TX, g = q / TX;
@@ -230,9 +229,8 @@ __global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int 
             if ((fl & FLAG_SOLID) && (fu & FLAG_SOLID)) continue;
             const Prim<double> L = {sYL[0][q], sYL[1][q], sYL[2][q], sYL[3][q]};
             const Prim<double> U = {sYU[0][q], sYU[1][q], sYU[2][q], sYU[3][q]};
-            double F[4];
-            osher_y(L, U, t.beta, t.inv_beta, F);
-            sYL[0][q] = F[0]; sYL[1][q] = F[1]; sYL[2][q] = F[2]; sYL[3][q] = F[3];
+            const Vec4<double> F = osher_y(L, U, t.beta, t.inv_beta);
+            sYL[0][q] = F.a; sYL[1][q] = F.b; sYL[2][q] = F.c; sYL[3][q] = F.d;
         }
     }
     __syncthreads();

@@ -100,10 +100,10 @@ int check_options(const vdac_options *o)
         return fail(VDAC_E_INVALID, "wall_slip must be 0 or 1");
     const bool auto_tile = o->tile_x == 0 && o->tile_y == 0;
     const bool direct = o->tile_x == 1 && o->tile_y == 1;
-    const bool march = o->tile_x == -1 && o->tile_y >= 1 && o->tile_y <= 4096;
+    const bool march = o->tile_x >= -3 && o->tile_x <= -1 && o->tile_y >= 1 && o->tile_y <= 4096;
     if (!auto_tile && !direct && !march && !tile_supported(o->tile_x, o->tile_y))
         return fail(VDAC_E_INVALID, "tile %d x %d is not available (0 x 0 = automatic, 1 x 1 = "
-                    "one thread per cell, -1 x L = row marching in chunks of L rows, or 32 x 8, "
+                    "one thread per cell, -W x L (W = 1..3) = row marching in chunks of L rows, or 32 x 8, "
                     "16 x 16, 64 x 4)", o->tile_x, o->tile_y);
     return VDAC_OK;
 }

@@ -15,6 +15,22 @@ struct Prim {
     T r, u, v, p;
 };
 
+// Four components of a flux or a residual: rho, rho u, rho v, p/beta.
+template <typename T>
+struct Vec4 {
+    T a, b, c, d;
+    __device__ __forceinline__ T operator[](int k) const
+    {
+        return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ Vec4<T> zero4()
+{
+    return {T(0), T(0), T(0), T(0)};
+}
+
 // Derivatives of rho, u, v along one axis.
 template <typename T>
 struct Slope {
@@ -133,8 +149,7 @@ __device__ __forceinline__ T gradp_y(const Prim<T> &w, const Slope<T> &gx, const
 //   r_4 = (lambda_4, u lambda_4 + beta/rho, v lambda_4, -lambda_5/rho),
 //   r_5 = (lambda_5, u lambda_5 + beta/rho, v lambda_5, -lambda_4/rho).
 template <typename T>
-__device__ __forceinline__ void osher_x(const Prim<T> &L, const Prim<T> &R, T beta, T inv_beta,
-                                        T F[4])
+__device__ __forceinline__ Vec4<T> osher_x(const Prim<T> &L, const Prim<T> &R, T beta, T inv_beta)
 {
     const T mL = L.r * L.u, nL = L.r * L.v;
     const T mR = R.r * R.u, nR = R.r * R.v;
@@ -176,27 +191,24 @@ __device__ __forceinline__ void osher_x(const Prim<T> &L, const Prim<T> &R, T be
         a2 = fma(v, s, a2);
         a3 -= fma(k4, l5, k5 * l4) * ir;
     }
-    F[0] = T(0.5) * (mL + mR - fma(sau, dr, a0));
-    F[1] = T(0.5) * (fma(mL, L.u, L.p) + fma(mR, R.u, R.p) - fma(sau, dm, a1));
-    F[2] = T(0.5) * (mL * L.v + mR * R.v - fma(sau, dn, a2));
-    F[3] = T(0.5) * (L.u + R.u - fma(sau, dq, a3));
+    Vec4<T> F;
+    F.a = T(0.5) * (mL + mR - fma(sau, dr, a0));
+    F.b = T(0.5) * (fma(mL, L.u, L.p) + fma(mR, R.u, R.p) - fma(sau, dm, a1));
+    F.c = T(0.5) * (mL * L.v + mR * R.v - fma(sau, dn, a2));
+    F.d = T(0.5) * (L.u + R.u - fma(sau, dq, a3));
+    return F;
 }
 
 // Face flux with normal +y: Algorithm 2 gives t1 = (1, 0, 0) for n = (0, 1, 0), so the rotated
 // problem is the x-split one with u and v exchanged, and R^T exchanges the momentum components of
 // the result back (Sec. 2.4).
 template <typename T>
-__device__ __forceinline__ void osher_y(const Prim<T> &L, const Prim<T> &R, T beta, T inv_beta,
-                                        T F[4])
+__device__ __forceinline__ Vec4<T> osher_y(const Prim<T> &L, const Prim<T> &R, T beta, T inv_beta)
 {
-    Prim<T> Ls = {L.r, L.v, L.u, L.p};
-    Prim<T> Rs = {R.r, R.v, R.u, R.p};
-    T G[4];
-    osher_x(Ls, Rs, beta, inv_beta, G);
-    F[0] = G[0];
-    F[1] = G[2];
-    F[2] = G[1];
-    F[3] = G[3];
+    const Prim<T> Ls = {L.r, L.v, L.u, L.p};
+    const Prim<T> Rs = {R.r, R.v, R.u, R.p};
+    const Vec4<T> G = osher_x(Ls, Rs, beta, inv_beta);
+    return {G.a, G.c, G.b, G.d};
 }
 
 }  // namespace vdac

@@ -94,8 +94,9 @@ struct Scheme {
 };
 
 // Launch wrappers.  All return hipError_t cast to int.  A stage launch with tile (1, 1) runs the
-// plain one-thread-per-cell kernel (kernels_f64.hip); tile (-1, L) runs the row-marching kernel
-// (stage_march.hip) on 64-column strips swept in chunks of L rows; the supported 2D tiles run
+// plain one-thread-per-cell kernel (kernels_f64.hip); tile (-W, L) with W = 1, 2 or 3 runs the
+// row-marching kernel (stage_march.hip) on 64-column strips swept in chunks of L rows, compiled
+// for W = 3 waves per SIMD (tighter register budget) or 2 otherwise; the supported 2D tiles run
 // the tiled kernel (stage_tile.hip).  stage_blocks() is the number of residual partials a stage
 // launch writes.
 int launch_begin_step(const TankDev &t, const Scheme &sc, double dt, int max_pseudo, double tol,
@@ -106,7 +107,8 @@ int launch_stage_direct_f64(const TankDev &t, const Scheme &sc, int stage, void 
 int launch_stage_tile_f64(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
                           void *stream);
 int launch_finalize(const TankDev &t, const Scheme &sc, int n_blocks, void *stream);
-int launch_stage_march_f64(const TankDev &t, const Scheme &sc, int stage, int chunk, void *stream);
+int launch_stage_march_f64(const TankDev &t, const Scheme &sc, int stage, int chunk, int waves,
+                           void *stream);
 int march_units(const TankDev &t, int chunk);
 int stage_blocks(const TankDev &t, int tile_x, int tile_y);
 int direct_blocks(const TankDev &t);

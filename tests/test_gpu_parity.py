@@ -129,7 +129,7 @@ def test_multi_tank_grid():
     check(wk, steps=2, pseudo=6)
 
 
-TILES = [(1, 1), (32, 8), (16, 16), (64, 4), (-1, 16), (-1, 7), (-1, 64)]
+TILES = [(1, 1), (32, 8), (16, 16), (64, 4), (-1, 16), (-1, 7), (-3, 64), (-3, 5)]
 
 
 @pytest.mark.parametrize("tile", TILES)
