@@ -75,10 +75,12 @@ typedef struct {
                                -W x L row marching over 64-column strips in chunks of L rows,
                                W = 3 for a 3-waves-per-SIMD register budget, 1 or 2 otherwise;
                                32 x 8, 16 x 16 or 64 x 4 two-dimensional LDS tiles */
+    int32_t graph_iters; /* pseudo-iterations captured per HIP graph and replayed on the stream:
+                            0 automatic, K > 0 exactly K, -1 launch kernels one by one */
 } vdac_options;
 
 /* Fills o with the defaults: FP64, 3 stages alpha = (1/3, 1/2, 1), CFL_tau 0.48, minmod,
- * local dtau, backward Euler, RMS norm, no-slip walls, automatic tiles. */
+ * local dtau, backward Euler, RMS norm, no-slip walls, automatic tiles, automatic graphs. */
 void vdac_default_options(vdac_options *o);
 
 /* Device bytes create_grid needs for these tanks and options (0 on invalid arguments). */

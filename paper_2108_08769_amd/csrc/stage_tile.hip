@@ -25,8 +25,6 @@ namespace vdac {
 
 namespace {
 
-constexpr int kNT = 256;
-
 // Index along one axis of a tile-relative position: wraps across a periodic side, or reports
 // the position outside the tank.
 __device__ __forceinline__ bool locate(int g, int n, int periodic, int &out)
@@ -40,15 +38,71 @@ __device__ __forceinline__ bool locate(int g, int n, int periodic, int &out)
     return true;
 }
 
-template <int TX, int TY, bool NORM_MAX>
-__global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int stage, int tiles_x,
-                                                      int n_tiles)
+// Tile position of the pidx-th cell that phase 2 reconstructs: the tile cells first, then the
+// ring around the tile without its corners (below, above, left, right).
+template <int TX, int TY>
+__device__ __forceinline__ void ring_position(int pidx, int &i, int &j)
+{
+    constexpr int NC = TX * TY;
+    if (pidx < NC) {
+        i = pidx % TX;
+        j = pidx / TX;
+        return;
+    }
+    const int q = pidx - NC;
+    if (q < TX) {
+        i = q;
+        j = -1;
+    } else if (q < 2 * TX) {
+        i = q - TX;
+        j = TY;
+    } else if (q < 2 * TX + TY) {
+        i = -1;
+        j = q - 2 * TX;
+    } else {
+        i = TX;
+        j = q - 2 * TX - TY;
+    }
+}
+
+// Stage-0 data of one cell: Q^0 (rho, rho u, rho v), level n and level n-1.
+struct SourceData {
+    double z0, z1, z2, n0, n1, n2, m0, m1, m2;
+};
+
+__device__ __forceinline__ SourceData load_source(const TankDev &t, const double *q0, size_t c,
+                                                  bool bdf2)
+{
+    const size_t plane = t.plane;
+    SourceData s;
+    s.z0 = q0[c];
+    s.z1 = q0[plane + c];
+    s.z2 = q0[2 * plane + c];
+    s.n0 = t.level_n[c];
+    s.n1 = t.level_n[plane + c];
+    s.n2 = t.level_n[2 * plane + c];
+    if (bdf2) {
+        s.m0 = t.level_nm1[c];
+        s.m1 = t.level_nm1[plane + c];
+        s.m2 = t.level_nm1[2 * plane + c];
+    } else {
+        s.m0 = s.m1 = s.m2 = 0.0;
+    }
+    return s;
+}
+
+// NT threads per tile: 256 (one per tile cell) or 512 (every phase finishes in at most two
+// rounds, which shortens the critical path of small grids).
+template <int TX, int TY, int NT, bool NORM_MAX>
+__global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int stage, int tiles_x,
+                                                     int n_tiles)
 {
     constexpr int RX = TX + 4, RY = TY + 4, NR2 = RX * RY;  // primitives: tile + 2-cell halo
     constexpr int SX = TX + 2, SY = TY + 2, NR1 = SX * SY;  // flags: tile + 1-cell ring
     constexpr int NC = TX * TY;
-    static_assert(NC == kNT, "one tile cell per thread");
+    static_assert(NC <= NT, "at most one tile cell per thread");
     constexpr int NRING = 2 * (TX + TY);                    // ring positions without corners
+    constexpr int NPOS = NC + NRING;
     constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
 
     __shared__ double sW[4][NR2];
@@ -76,10 +130,11 @@ __global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int 
     const StepParams sp = *t.step;
     const size_t plane = t.plane;
     const bool slip = sc.slip != 0;
+    const bool bdf2 = sp.b2 != 0.0;
     const double k = sc.k;
 
-    // ---- phase 1: stage input and flags into LDS -------------------------------------------
-    for (int r = tid; r < NR2; r += kNT) {
+    // ---- phase 1: every global load of the stage is issued here --------------------------
+    for (int r = tid; r < NR2; r += NT) {
         const int ri = r % RX, rj = r / RX;
         int gi, gj;
         Prim<double> w = {1.0, 0.0, 0.0, 0.0};
@@ -90,7 +145,7 @@ __global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int 
         sW[2][r] = w.v;
         sW[3][r] = w.p;
     }
-    for (int r = tid; r < NR1; r += kNT) {
+    for (int r = tid; r < NR1; r += NT) {
         const int ri = r % SX, rj = r / SX;
         int gi, gj;
         uint8_t f = FLAG_SOLID;  // outside a non-periodic side: not a fluid cell
@@ -98,33 +153,27 @@ __global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int 
             f = t.flags[(size_t)gj * t.nx + gi];
         sF[r] = f;
     }
+    // stage-0 data of this thread's first phase-2 cell, and Q^0's pressure of its tile cell
+    SourceData src0 = {1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+    double own_p0 = 0.0;
+    if (tid < NPOS) {
+        int i, j, gi, gj;
+        ring_position<TX, TY>(tid, i, j);
+        if (locate(x0 + i, t.nx, t.per_x, gi) && locate(y0 + j, t.ny, t.per_y, gj)) {
+            const size_t c = (size_t)gj * t.nx + gi;
+            src0 = load_source(t, q0, c, bdf2);
+            if (tid < NC) own_p0 = q0[3 * plane + c];
+        }
+    }
     __syncthreads();
 
     // ---- phase 2: reconstruction of the tile and ring cells --------------------------------
     // The tile cell of this thread keeps its stage-0 data for phase 4.
     double own_q0[3] = {1.0, 0.0, 0.0}, own_d[3] = {0.0, 0.0, 0.0};
 
-    for (int pidx = tid; pidx < NC + NRING; pidx += kNT) {
+    for (int pidx = tid; pidx < NPOS; pidx += NT) {
         int i, j;
-        if (pidx < NC) {
-            i = pidx % TX;
-            j = pidx / TX;
-        } else {
-            const int q = pidx - NC;
-            if (q < TX) {
-                i = q;
-                j = -1;
-            } else if (q < 2 * TX) {
-                i = q - TX;
-                j = TY;
-            } else if (q < 2 * TX + TY) {
-                i = -1;
-                j = q - 2 * TX;
-            } else {
-                i = TX;
-                j = q - 2 * TX - TY;
-            }
-        }
+        ring_position<TX, TY>(pidx, i, j);
         const uint8_t f = sF[(j + 1) * SX + (i + 1)];
         if (f & FLAG_SOLID) continue;
         const int r = (j + 2) * RX + (i + 2);
@@ -143,25 +192,29 @@ __global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int 
         rec.gy = slopes(ym, rec.w, yp, t.inv_dy, k);
 
         // stage-0 sources: real-time term (B0 Q^0 + B1 Q^n + B2 Q^{n-1})/dt and rho^0
-        int gi, gj;
-        locate(x0 + i, t.nx, t.per_x, gi);
-        locate(y0 + j, t.ny, t.per_y, gj);
-        const size_t c = (size_t)gj * t.nx + gi;
-        double qa[3], num[3];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            qa[m] = q0[m * plane + c];
-            num[m] = sp.b0 * qa[m] + sp.b1 * t.level_n[m * plane + c];
-            if (sp.b2 != 0.0) num[m] += sp.b2 * t.level_nm1[m * plane + c];
+        SourceData sd = src0;
+        if (pidx != tid) {  // later rounds (256-thread tiles) load here
+            int gi, gj;
+            locate(x0 + i, t.nx, t.per_x, gi);
+            locate(y0 + j, t.ny, t.per_y, gj);
+            sd = load_source(t, q0, (size_t)gj * t.nx + gi, bdf2);
         }
-        rec.d_r = num[0] * sp.inv_dt;
-        rec.d_ru = num[1] * sp.inv_dt;
-        rec.d_rv = num[2] * sp.inv_dt;
-        rec.rho0 = qa[0];
+        double num0 = fma(sp.b0, sd.z0, sp.b1 * sd.n0);
+        double num1 = fma(sp.b0, sd.z1, sp.b1 * sd.n1);
+        double num2 = fma(sp.b0, sd.z2, sp.b1 * sd.n2);
+        if (bdf2) {
+            num0 = fma(sp.b2, sd.m0, num0);
+            num1 = fma(sp.b2, sd.m1, num1);
+            num2 = fma(sp.b2, sd.m2, num2);
+        }
+        rec.d_r = num0 * sp.inv_dt;
+        rec.d_ru = num1 * sp.inv_dt;
+        rec.d_rv = num2 * sp.inv_dt;
+        rec.rho0 = sd.z0;
         if (pidx < NC) {
-            own_q0[0] = qa[0];
-            own_q0[1] = qa[1];
-            own_q0[2] = qa[2];
+            own_q0[0] = sd.z0;
+            own_q0[1] = sd.z1;
+            own_q0[2] = sd.z2;
             own_d[0] = rec.d_r;
             own_d[1] = rec.d_ru;
             own_d[2] = rec.d_rv;
@@ -213,7 +266,7 @@ __global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int 
     __syncthreads();
 
     // ---- phase 3: one Osher flux per face --------------------------------------------------
-    for (int fidx = tid; fidx < NFX + NFY; fidx += kNT) {
+    for (int fidx = tid; fidx < NFX + NFY; fidx += NT) {
         if (fidx < NFX) {
             const int fi = fidx % (TX + 1), j = fidx / (TX + 1);
             const uint8_t fl = sF[(j + 1) * SX + fi], fr = sF[(j + 1) * SX + fi + 1];
@@ -239,7 +292,7 @@ __global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int 
     const double alpha = sc.alpha[stage - 1];
     const bool last = (stage == sc.smax);
     double part[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    {
+    if (tid < NC) {
         const int i = tid % TX, j = tid / TX;
         const int gi = x0 + i, gj = y0 + j;
         const uint8_t f = sF[(j + 1) * SX + (i + 1)];
@@ -257,7 +310,6 @@ __global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int 
             R4[0] += -own_d[0];
             R4[1] += -own_d[1] + r0 * t.gx;
             R4[2] += -own_d[2] + r0 * t.gy;
-            const double p0 = q0[3 * plane + c];
             const double dtau = local_dtau(t, t.cfl, r0, m0, n0);
             const double ad = alpha * dtau;
             const double api = 1.0 + sp.b0 * ad * sp.inv_dt;
@@ -265,7 +317,7 @@ __global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int 
             qout[c] = r0 + fac * R4[0];
             qout[plane + c] = m0 + fac * R4[1];
             qout[2 * plane + c] = n0 + fac * R4[2];
-            qout[3 * plane + c] = p0 + t.beta * (ad * R4[3]);
+            qout[3 * plane + c] = own_p0 + t.beta * (ad * R4[3]);
             if (last) {
                 const double rp = t.beta * R4[3];
                 if (NORM_MAX) {
@@ -284,43 +336,50 @@ __global__ void __launch_bounds__(kNT) stage_tile_f64(TankDev t, Scheme sc, int 
             }
         }
     }
-    if (last) block_reduce_store<NORM_MAX, kNT>(part, t.partials + (size_t)tile * kPartialWidth);
+    if (last) block_reduce_store<NORM_MAX, NT>(part, t.partials + (size_t)tile * kPartialWidth);
 }
 
-template <int TX, int TY>
+template <int TX, int TY, int NT>
 int launch_tile(const TankDev &t, const Scheme &sc, int stage, void *stream)
 {
     const int tiles_x = (t.nx + TX - 1) / TX, tiles_y = (t.ny + TY - 1) / TY;
     const int n_tiles = tiles_x * tiles_y;
     const int blocks = ((n_tiles + 7) / 8) * 8;
     if (sc.norm_max)
-        hipLaunchKernelGGL((stage_tile_f64<TX, TY, true>), dim3(blocks), dim3(kNT), 0,
+        hipLaunchKernelGGL((stage_tile_f64<TX, TY, NT, true>), dim3(blocks), dim3(NT), 0,
                            (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles);
     else
-        hipLaunchKernelGGL((stage_tile_f64<TX, TY, false>), dim3(blocks), dim3(kNT), 0,
+        hipLaunchKernelGGL((stage_tile_f64<TX, TY, NT, false>), dim3(blocks), dim3(NT), 0,
                            (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles);
     return (int)hipGetLastError();
 }
 
 }  // namespace
 
+// 32 x 8, 16 x 16 and 64 x 4 tiles run with 256 threads; 3208 and 1616 name the 32 x 8 and
+// 16 x 16 tiles run with 512 threads.
 bool tile_supported(int tile_x, int tile_y)
 {
     return (tile_x == 32 && tile_y == 8) || (tile_x == 16 && tile_y == 16) ||
-           (tile_x == 64 && tile_y == 4);
+           (tile_x == 64 && tile_y == 4) || (tile_x == 3208 && tile_y == 2) ||
+           (tile_x == 1616 && tile_y == 2);
 }
 
 int tile_count(const TankDev &t, int tile_x, int tile_y)
 {
+    if (tile_x == 3208) tile_x = 32, tile_y = 8;
+    if (tile_x == 1616) tile_x = 16, tile_y = 16;
     return ((t.nx + tile_x - 1) / tile_x) * ((t.ny + tile_y - 1) / tile_y);
 }
 
 int launch_stage_tile_f64(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
                           void *stream)
 {
-    if (tile_x == 32 && tile_y == 8) return launch_tile<32, 8>(t, sc, stage, stream);
-    if (tile_x == 16 && tile_y == 16) return launch_tile<16, 16>(t, sc, stage, stream);
-    if (tile_x == 64 && tile_y == 4) return launch_tile<64, 4>(t, sc, stage, stream);
+    if (tile_x == 32 && tile_y == 8) return launch_tile<32, 8, 256>(t, sc, stage, stream);
+    if (tile_x == 16 && tile_y == 16) return launch_tile<16, 16, 256>(t, sc, stage, stream);
+    if (tile_x == 64 && tile_y == 4) return launch_tile<64, 4, 256>(t, sc, stage, stream);
+    if (tile_x == 3208 && tile_y == 2) return launch_tile<32, 8, 512>(t, sc, stage, stream);
+    if (tile_x == 1616 && tile_y == 2) return launch_tile<16, 16, 512>(t, sc, stage, stream);
     return (int)hipErrorInvalidValue;
 }
 

@@ -38,7 +38,7 @@ int hip_fail(hipError_t e, const char *what)
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct TankLayout {
-    size_t state[3], level_n, level_nm1, flags, partials, status, step, end;
+    size_t state[3], level_n, level_nm1, flags, partials, end;
 };
 
 struct TankHost {
@@ -60,12 +60,18 @@ struct vdac_grid {
     char *ws;
     bool own_ws;
     size_t ws_bytes;
+    Status *status_dev;                 // [n_tanks], contiguous
+    StepParams *step_dev;
+    std::vector<Status> status_host;
+    // captured pseudo-iterations, keyed by the number of iterations per graph
+    hipStream_t cap_stream;
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;
     // stage-kernel timing (measurement only)
     bool timing;
     std::vector<hipEvent_t> ev_pool;
     struct PendingTiming {
-        int start, stop;  // indices into ev_pool
-        int tank, iter;   // tank and pseudo-iteration (within the step) of the launch
+        int start, stop;  // indices into ev_pool, around one iteration's stage launches
+        int tank, iter;   // tank and pseudo-iteration (within the step)
     };
     std::vector<PendingTiming> ev_pending;
     double t_ms;
@@ -98,6 +104,8 @@ int check_options(const vdac_options *o)
         return fail(VDAC_E_INVALID, "norm must be VDAC_NORM_RMS or VDAC_NORM_MAX");
     if (o->wall_slip != 0 && o->wall_slip != 1)
         return fail(VDAC_E_INVALID, "wall_slip must be 0 or 1");
+    if (o->graph_iters < -1 || o->graph_iters > 1000)
+        return fail(VDAC_E_INVALID, "graph_iters must lie in [-1, 1000]");
     const bool auto_tile = o->tile_x == 0 && o->tile_y == 0;
     const bool direct = o->tile_x == 1 && o->tile_y == 1;
     const bool march = o->tile_x >= -3 && o->tile_x <= -1 && o->tile_y >= 1 && o->tile_y <= 4096;
@@ -146,12 +154,15 @@ TankLayout layout_of(const vdac_tank *t, const vdac_options *o, int n_blocks)
     off += align256(plane);
     L.partials = off;
     off += align256((size_t)n_blocks * kPartialWidth * sizeof(double));
-    L.status = off;
-    off += align256(sizeof(Status));
-    L.step = off;
-    off += align256(sizeof(StepParams));
     L.end = off;
     return L;
+}
+
+// Grid-level block after the tanks: every tank's Status (contiguous, so one copy reads them all)
+// and the shared StepParams.
+size_t grid_block_bytes(int n_tanks)
+{
+    return align256((size_t)n_tanks * sizeof(Status)) + align256(sizeof(StepParams));
 }
 
 void tile_for(const vdac_tank *, const vdac_options *o, int *tx, int *ty)
@@ -212,6 +223,18 @@ void build_flags(const vdac_tank *t, std::vector<uint8_t> &flags, int *n_fluid)
     *n_fluid = nf;
 }
 
+// Copies every tank's Status to g->status_host (one copy, one synchronisation).
+int read_statuses(vdac_grid *g)
+{
+    const size_t n = g->tanks.size();
+    hipError_t e = hipMemcpyAsync(g->status_host.data(), g->status_dev, n * sizeof(Status),
+                                  hipMemcpyDeviceToHost, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the tank status");
+    e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "synchronising the stream");
+    return VDAC_OK;
+}
+
 int read_status(const vdac_grid *g, int tank, Status *st)
 {
     hipError_t e = hipMemcpyAsync(st, g->tanks[tank].dev.status, sizeof(Status), hipMemcpyDeviceToHost,
@@ -220,6 +243,12 @@ int read_status(const vdac_grid *g, int tank, Status *st)
     e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "synchronising the stream");
     return VDAC_OK;
+}
+
+void drop_graphs(vdac_grid *g)
+{
+    for (auto &kv : g->graphs) (void)hipGraphExecDestroy(kv.second);
+    g->graphs.clear();
 }
 
 hipEvent_t pool_event(vdac_grid *g, size_t idx)
@@ -236,14 +265,14 @@ hipEvent_t pool_event(vdac_grid *g, size_t idx)
 int collect_timing(vdac_grid *g, const std::vector<int> &iters_before, const std::vector<int> &iters_after)
 {
     for (auto &pr : g->ev_pending) {
-        // launches after the tank stopped returned at once: they count neither time nor cells
+        // iterations after the tank stopped returned at once: they count neither time nor cells
         if (pr.iter >= iters_after[pr.tank] - iters_before[pr.tank]) continue;
         hipError_t e = hipEventSynchronize(g->ev_pool[pr.stop]);
         if (e != hipSuccess) return hip_fail(e, "stage timing");
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, g->ev_pool[pr.start], g->ev_pool[pr.stop]);
         if (e != hipSuccess) return hip_fail(e, "stage timing");
-        g->t_ms += ms;
+        g->t_ms += ms;  // s_max back-to-back stage launches
     }
     g->ev_pending.clear();
     for (size_t t = 0; t < g->tanks.size(); ++t) {
@@ -273,6 +302,7 @@ void vdac_default_options(vdac_options *o)
     o->bdf_order = 1;
     o->norm = VDAC_NORM_RMS;
     o->wall_slip = 0;
+    o->graph_iters = 0;
 }
 
 size_t workspace_bytes(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o)
@@ -288,7 +318,7 @@ size_t workspace_bytes(const vdac_tank *tanks, int32_t n_tanks, const vdac_optio
         if (check_tank(&tanks[t], t) != VDAC_OK) return 0;
         total += layout_of(&tanks[t], o, blocks_for(&tanks[t], o)).end;
     }
-    return total;
+    return total + grid_block_bytes(n_tanks);
 }
 
 int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
@@ -346,7 +376,17 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
     sc.bdf2 = (o->bdf_order == 2);
 
     g->tanks.resize(n_tanks);
+    g->status_host.assign(n_tanks, Status());
+    g->cap_stream = nullptr;
+    g->timing = false;
+    g->t_ms = 0.0;
+    g->t_launches = 0;
+    g->t_cell_stages = 0.0;
     size_t base = 0;
+    for (int t = 0; t < n_tanks; ++t) base += layout_of(&tanks[t], o, blocks_for(&tanks[t], o)).end;
+    g->status_dev = (Status *)(g->ws + base);
+    g->step_dev = (StepParams *)(g->ws + base + align256((size_t)n_tanks * sizeof(Status)));
+    base = 0;
     for (int t = 0; t < n_tanks; ++t) {
         TankHost &th = g->tanks[t];
         th.desc = tanks[t];
@@ -380,8 +420,8 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         d.level_nm1 = sc.bdf2 ? (double *)(g->ws + base + L.level_nm1) : nullptr;
         d.flags = (const uint8_t *)(g->ws + base + L.flags);
         d.partials = (double *)(g->ws + base + L.partials);
-        d.status = (Status *)(g->ws + base + L.status);
-        d.step = (const StepParams *)(g->ws + base + L.step);
+        d.status = g->status_dev + t;
+        d.step = g->step_dev;
         d.n_fluid = n_fluid;
         base += L.end;
 
@@ -412,6 +452,12 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
             destroy_grid(g);
             return hip_fail(e, "initialising the tank");
         }
+    }
+    hipError_t ec = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
+    if (ec != hipSuccess) {
+        g->cap_stream = nullptr;
+        destroy_grid(g);
+        return hip_fail(ec, "creating the capture stream");
     }
     *out = g;
     return VDAC_OK;
@@ -447,6 +493,66 @@ int set_state(vdac_grid *g, int32_t tank, const double *q)
     return VDAC_OK;
 }
 
+namespace {
+
+// One pseudo-iteration of every tank: s_max stage launches and the residual finalize.  With
+// timing on, an event pair brackets each tank's back-to-back stage launches.
+int launch_iterations(vdac_grid *g, hipStream_t stream, int n_iter, int first_iter, size_t *ev_next)
+{
+    const int nt = (int)g->tanks.size();
+    int rc;
+    for (int it = 0; it < n_iter; ++it)
+        for (int t = 0; t < nt; ++t) {
+            const TankHost &th = g->tanks[t];
+            hipEvent_t e1 = nullptr;
+            if (ev_next) {
+                hipEvent_t e0 = pool_event(g, *ev_next);
+                e1 = pool_event(g, *ev_next + 1);
+                if (!e0 || !e1) return fail(VDAC_E_DEVICE, "creating timing events failed");
+                g->ev_pending.push_back({(int)*ev_next, (int)*ev_next + 1, t, first_iter + it});
+                *ev_next += 2;
+                (void)hipEventRecord(e0, stream);
+            }
+            for (int s = 1; s <= g->sc.smax; ++s) {
+                rc = launch_stage(th.dev, g->sc, s, th.tile_x, th.tile_y, stream);
+                if (rc != 0) return hip_fail((hipError_t)rc, "stage launch");
+            }
+            if (e1) (void)hipEventRecord(e1, stream);
+            rc = launch_finalize(th.dev, g->sc, th.n_blocks, stream);
+            if (rc != 0) return hip_fail((hipError_t)rc, "finalize launch");
+        }
+    return VDAC_OK;
+}
+
+// The graph of k pseudo-iterations of every tank, captured on the private stream once.
+int graph_for(vdac_grid *g, int k, hipGraphExec_t *exec)
+{
+    for (auto &kv : g->graphs)
+        if (kv.first == k) {
+            *exec = kv.second;
+            return VDAC_OK;
+        }
+    hipError_t e = hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "beginning graph capture");
+    int rc = launch_iterations(g, g->cap_stream, k, 0, nullptr);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(g->cap_stream, &graph);
+    if (rc != VDAC_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "ending graph capture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "instantiating the pseudo-iteration graph");
+    g->graphs.push_back({k, ge});
+    *exec = ge;
+    return VDAC_OK;
+}
+
+}  // namespace
+
 int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int32_t *pseudo_done)
 {
     g_error.clear();
@@ -461,46 +567,43 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
         rc = launch_begin_step(th.dev, g->sc, dt, max_pseudo, tol, g->sc.bdf2 && th.hist_ok, g->stream);
         if (rc != 0) return hip_fail((hipError_t)rc, "begin_step launch");
     }
-    const int poll = (tol > 0.0) ? 8 : max_pseudo;
+    std::vector<int> before(nt, 0);
+    // iterations per launch group: with a tolerance, the host checks the stop flags after each
+    // group (the kernels of stopped tanks return at once); without, groups cover max_pseudo.
+    int group;
+    if (tol > 0.0) {
+        group = max_pseudo < 10 ? max_pseudo : 10;
+    } else {
+        const int n_groups = (max_pseudo + 19) / 20;
+        group = n_groups > 0 ? (max_pseudo + n_groups - 1) / n_groups : 0;
+    }
+    const bool use_graph = g->opt.graph_iters >= 0 && !g->timing;
+    if (use_graph && g->opt.graph_iters > 0) group = g->opt.graph_iters;
     size_t ev_next = 0;
-    for (int m = 0; m < max_pseudo;) {
-        const int chunk = (max_pseudo - m < poll) ? (max_pseudo - m) : poll;
-        for (int it = 0; it < chunk; ++it)
-            for (int t = 0; t < nt; ++t) {
-                const TankHost &th = g->tanks[t];
-                for (int s = 1; s <= g->sc.smax; ++s) {
-                    hipEvent_t e0 = nullptr, e1 = nullptr;
-                    if (g->timing) {
-                        e0 = pool_event(g, ev_next);
-                        e1 = pool_event(g, ev_next + 1);
-                        if (!e0 || !e1) return fail(VDAC_E_DEVICE, "creating timing events failed");
-                        g->ev_pending.push_back({(int)ev_next, (int)ev_next + 1, t, m + it});
-                        ev_next += 2;
-                        (void)hipEventRecord(e0, g->stream);
-                    }
-                    rc = launch_stage(th.dev, g->sc, s, th.tile_x, th.tile_y, g->stream);
-                    if (rc != 0) return hip_fail((hipError_t)rc, "stage launch");
-                    if (g->timing) (void)hipEventRecord(e1, g->stream);
-                }
-                rc = launch_finalize(th.dev, g->sc, th.n_blocks, g->stream);
-                if (rc != 0) return hip_fail((hipError_t)rc, "finalize launch");
-            }
-        m += chunk;
-        if (m < max_pseudo) {
+    for (int m = 0; m < max_pseudo && group > 0;) {
+        if (use_graph) {
+            hipGraphExec_t exec;
+            if ((rc = graph_for(g, group, &exec)) != VDAC_OK) return rc;
+            hipError_t e = hipGraphLaunch(exec, g->stream);
+            if (e != hipSuccess) return hip_fail(e, "graph launch");
+        } else {
+            const int n = (max_pseudo - m < group) ? (max_pseudo - m) : group;
+            if ((rc = launch_iterations(g, g->stream, n, m, g->timing ? &ev_next : nullptr)) != VDAC_OK)
+                return rc;
+        }
+        m += group;
+        if (m < max_pseudo && tol > 0.0) {
+            if ((rc = read_statuses(g)) != VDAC_OK) return rc;
             bool all_done = true;
-            for (int t = 0; t < nt && all_done; ++t) {
-                Status st;
-                if ((rc = read_status(g, t, &st)) != VDAC_OK) return rc;
-                all_done = st.done != 0;
-            }
+            for (int t = 0; t < nt && all_done; ++t) all_done = g->status_host[t].done != 0;
             if (all_done) break;
         }
     }
+    if ((rc = read_statuses(g)) != VDAC_OK) return rc;
     int status = VDAC_OK;
-    std::vector<int> before(nt, 0), after(nt, 0);
+    std::vector<int> after(nt, 0);
     for (int t = 0; t < nt; ++t) {
-        Status st;
-        if ((rc = read_status(g, t, &st)) != VDAC_OK) return rc;
+        const Status &st = g->status_host[t];
         after[t] = st.iters;
         if (pseudo_done) pseudo_done[t] = st.iters;
         if (st.diverged && status == VDAC_OK)
@@ -567,6 +670,8 @@ void destroy_grid(vdac_grid *g)
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     else (void)hipDeviceSynchronize();
     for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
+    drop_graphs(g);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     if (g->own_ws && g->ws) (void)hipFree(g->ws);
     delete g;
 }

@@ -54,6 +54,7 @@ class Options(ctypes.Structure):
         ("wall_slip", ctypes.c_int32),
         ("tile_x", ctypes.c_int32),
         ("tile_y", ctypes.c_int32),
+        ("graph_iters", ctypes.c_int32),
     ]
 
 
@@ -115,7 +116,7 @@ def default_options() -> Options:
 
 
 def make_options(precision="f64", stages=3, alpha=(1.0 / 3.0, 0.5, 1.0), cfl=0.48, k=1.0,
-                 bdf=1, norm=NORM_RMS, wall_slip=False, tile=(0, 0)) -> Options:
+                 bdf=1, norm=NORM_RMS, wall_slip=False, tile=(0, 0), graph_iters=0) -> Options:
     o = default_options()
     o.precision = {"f64": FP64, "mixed": FP32_MIXED}[precision] if isinstance(precision, str) \
         else int(precision)
@@ -128,6 +129,7 @@ def make_options(precision="f64", stages=3, alpha=(1.0 / 3.0, 0.5, 1.0), cfl=0.4
     o.norm = int(norm)
     o.wall_slip = int(bool(wall_slip))
     o.tile_x, o.tile_y = int(tile[0]), int(tile[1])
+    o.graph_iters = int(graph_iters)
     return o
 
 

@@ -9,10 +9,11 @@ from paper_2108_08769_amd import vdac
 from paper_2108_08769_amd import workloads as wl
 
 
-def gpu_options(wk: wl.Workload, precision=None, norm=0, wall_slip=False, tile=(0, 0)):
+def gpu_options(wk: wl.Workload, precision=None, norm=0, wall_slip=False, tile=(0, 0),
+                graph_iters=0):
     return vdac.make_options(precision=precision or wk.precision, stages=wk.stages,
                              alpha=wk.alpha, cfl=wk.cfl, k=wk.k, bdf=wk.bdf, norm=norm,
-                             wall_slip=wall_slip, tile=tile)
+                             wall_slip=wall_slip, tile=tile, graph_iters=graph_iters)
 
 
 def oracle_problem(t: wl.Tank, wk: wl.Workload, wall_slip=False):
@@ -22,11 +23,11 @@ def oracle_problem(t: wl.Tank, wk: wl.Workload, wall_slip=False):
 
 
 def run_gpu(wk: wl.Workload, steps: int, max_pseudo: int, tol: float = 0.0, norm=0,
-            wall_slip=False, precision=None, tile=(0, 0)):
+            wall_slip=False, precision=None, tile=(0, 0), graph_iters=0):
     """Returns (states per tank, iterations [steps, tanks], norms [tanks, 4], status codes)."""
     tanks = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
                   solid=t.solid) for t in wk.tanks]
-    grid = vdac.Grid(tanks, gpu_options(wk, precision, norm, wall_slip, tile))
+    grid = vdac.Grid(tanks, gpu_options(wk, precision, norm, wall_slip, tile, graph_iters))
     try:
         for i, t in enumerate(wk.tanks):
             grid.set_state(i, t.q)

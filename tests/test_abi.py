@@ -49,7 +49,8 @@ def test_workspace_bytes():
     plane = 64 * 32 * 8
     assert n >= 3 * 4 * plane + 3 * plane + 64 * 32
     t2, _ = vdac.make_tank(16, 16, 1.0, 1.0)
-    assert vdac.workspace_bytes([t, t2], o) == n + vdac.workspace_bytes([t2], o)
+    both = vdac.workspace_bytes([t, t2], o)
+    assert n < both <= n + vdac.workspace_bytes([t2], o)
     bad, _ = vdac.make_tank(0, 32, 2.0, 1.0)
     assert vdac.workspace_bytes([bad], o) == 0
 

@@ -129,7 +129,7 @@ def test_multi_tank_grid():
     check(wk, steps=2, pseudo=6)
 
 
-TILES = [(1, 1), (32, 8), (16, 16), (64, 4), (-1, 16), (-1, 7), (-3, 64), (-3, 5)]
+TILES = [(1, 1), (32, 8), (16, 16), (64, 4), (3208, 2), (1616, 2), (-1, 16), (-1, 7), (-3, 64), (-3, 5)]
 
 
 @pytest.mark.parametrize("tile", TILES)
@@ -153,6 +153,30 @@ def test_tile_variants_agree():
     for tile in TILES[1:]:
         got = run_gpu(wk, 2, 20, tile=tile)[0][0]
         assert np.all(field_errors(got, ref, None, field_scales(wk.tanks[0])) <= 1e-13)
+
+
+@pytest.mark.parametrize("case", ["fixed", "tolerance", "multi_tank"])
+def test_graph_replay_matches_eager_launches(case):
+    """Pseudo-iterations captured in HIP graphs and replayed (several replays per step, host
+    synchronisations and state reads between steps) give bit-identical states, iteration
+    counts and norms to launching every kernel from the host."""
+    if case == "fixed":
+        wk, steps, pseudo, tol = small_dam(70, 33), 3, 23, 0.0
+    elif case == "tolerance":
+        wk, steps, pseudo, tol = perturbed_hydrostatic(), 2, 2000, 1e-2
+    else:
+        tanks = [wl.Tank(nx, ny, 0.05 * nx, 0.05 * ny,
+                         wl.random_state(nx, ny, seed=nx, rho_range=(1.0, 3.0), vel=0.2, p_scale=5.0),
+                         gy=-9.81, beta=300.0) for nx, ny in [(20, 12), (7, 30), (33, 5)]]
+        wk, steps, pseudo, tol = wl.Workload("multi", tanks, dt=1e-3, steps=1, max_pseudo=1), 2, 9, 0.0
+    ref = run_gpu(wk, steps, pseudo, tol, graph_iters=-1)
+    for gi in (0, 4):
+        got = run_gpu(wk, steps, pseudo, tol, graph_iters=gi)
+        for a, b in zip(got[0], ref[0]):
+            np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(got[1], ref[1])
+        np.testing.assert_array_equal(got[2], ref[2])
+        assert got[3] == ref[3]
 
 
 def test_full_size_dam_break_512x256():
