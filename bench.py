@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_CELL_STAGE = {       # algorithmic bytes per fluid cell per stage, three-stage mean
-    "f64": (88.0 + 120.0 + 120.0) / 3.0,
+    "f64": (88.0 + 120.0 + 120.0) / 3.0,      # Q^{s-1} 32 + Q^0 32 + level n 24 + out 32
+    "mixed": (64.0 + 80.0 + 80.0) / 3.0,      # deviations 16 + 16, level n 32, out 16
 }
 
 
@@ -85,6 +86,9 @@ def main():
                     help="override the workload's pseudo-iteration cap (short profiled runs)")
     ap.add_argument("--graph-iters", type=int, default=0,
                     help="pseudo-iterations per captured HIP graph (0 automatic, -1 no graphs)")
+    ap.add_argument("--unbatched", action="store_true",
+                    help="one grid per tank, stepped one after the other (the baseline of the "
+                         "batched form)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -92,6 +96,7 @@ def main():
               f"(asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2108_08769_amd import vdac
 
@@ -104,24 +109,38 @@ def main():
     opts = vdac.make_options(precision=wk.precision, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl,
                              k=wk.k, bdf=wk.bdf, tile=tile, graph_iters=args.graph_iters)
     torch.cuda.set_device(0)
-    grid = vdac.Grid(tanks, opts)
-    for i, t in enumerate(wk.tanks):
-        grid.set_state(i, t.q)
+    if args.unbatched:
+        grids = [vdac.Grid([td], opts) for td in tanks]
+        for g, t in zip(grids, wk.tanks):
+            g.set_state(0, t.q)
+    else:
+        grids = [vdac.Grid(tanks, opts)]
+        for i, t in enumerate(wk.tanks):
+            grids[0].set_state(i, t.q)
+    fluid_per_grid = [np.array([t.fluid_cells for t in wk.tanks], dtype=np.float64)] \
+        if not args.unbatched else [np.array([t.fluid_cells], dtype=np.float64) for t in wk.tanks]
+
+    def step_all():
+        iters, cs = 0, 0.0
+        for g, fl in zip(grids, fluid_per_grid):
+            _, done = g.step(wk.dt, wk.max_pseudo, wk.tol)
+            iters += int(done.sum())
+            cs += float((fl * done).sum()) * wk.stages
+        return iters, cs
+
     for _ in range(args.warmup):
-        grid.step(wk.dt, wk.max_pseudo, wk.tol)
+        step_all()
     torch.cuda.synchronize()
 
     # timed region: exactly K steps, kernels replayed from captured graphs, no instrumentation
-    import numpy as np
-    fluid_per_tank = np.array([t.fluid_cells for t in wk.tanks], dtype=np.float64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = 0
     cell_stages = 0.0
     for _ in range(args.steps):
-        _, done = grid.step(wk.dt, wk.max_pseudo, wk.tol)
-        iters += int(done.sum())
-        cell_stages += float((fluid_per_tank * done).sum()) * wk.stages
+        it, cs = step_all()
+        iters += it
+        cell_stages += cs
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     fluid = wk.fluid_cells
@@ -130,11 +149,15 @@ def main():
     # pair around each pseudo-iteration's back-to-back stage kernels on the library's stream
     roofline = None
     if not args.no_stage_timing:
-        grid.stage_timing(True)
+        for g in grids:
+            g.stage_timing(True)
         for _ in range(args.steps):
-            grid.step(wk.dt, wk.max_pseudo, wk.tol)
-        kms, launches, kcs = grid.stage_timing_read()
-        grid.stage_timing(False)
+            step_all()
+        kms, launches, kcs = 0.0, 0, 0.0
+        for g in grids:
+            a, b, c = g.stage_timing_read()
+            kms, launches, kcs = kms + a, launches + b, kcs + c
+            g.stage_timing(False)
         if launches > 0 and kms > 0:
             bpc = BYTES_PER_CELL_STAGE[wk.precision]
             avg_s = kms / 1e3 / launches
@@ -145,7 +168,8 @@ def main():
                         "kernel": "stage", "avg_launch_us": round(avg_s * 1e6, 3),
                         "launches": launches, "bytes_per_launch": bytes_per_launch}
     value = cell_stages / elapsed
-    grid.close()
+    for g in grids:
+        g.close()
 
     line = {
         "metric": "cell-updates/s per pseudo-time stage",
@@ -161,6 +185,7 @@ def main():
         "dtype": "f64" if wk.precision == "f64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": wk.name, "cells": fluid, "precision": wk.precision, "tile": args.tile,
+                   "tanks": len(wk.tanks), "batched": not args.unbatched,
                    "graph_iters": args.graph_iters,
                    "dt": wk.dt, "max_pseudo": wk.max_pseudo, "tol": wk.tol,
                    "rk_stages": wk.stages, "pseudo_iterations": iters},

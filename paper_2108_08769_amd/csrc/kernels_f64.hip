@@ -1,5 +1,6 @@
-// kernels_f64.hip -- FP64 kernels of one real-time step on gfx950: begin-of-step bookkeeping,
-// the Runge-Kutta stage and the deterministic residual finalize.
+// kernels_f64.hip -- kernels of one real-time step on gfx950 other than the row-marching stage:
+// begin-of-step bookkeeping and the deterministic residual finalize (all tanks in one launch),
+// the conversions of the mixed-precision storage, and the plain FP64 stage kernel.
 //
 // stage_direct_f64 is the plain form of a stage: one thread per cell, which reconstructs itself
 // and its four neighbours and evaluates all four of its faces.  Every face is therefore computed
@@ -57,9 +58,9 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
     if (st->done) return;
     const int cur = st->cur;
     const StageBuffers b = stage_buffers(cur, stage);
-    const double *qprev = t.state[b.in];
-    const double *q0 = t.state[cur];
-    double *qout = t.state[b.out];
+    const double *qprev = (const double *)t.state[b.in];
+    const double *q0 = (const double *)t.state[cur];
+    double *qout = (double *)t.state[b.out];
     const StepParams sp = *t.step;
     const double alpha = sc.alpha[stage - 1];
     const bool last = (stage == sc.smax);
@@ -158,13 +159,15 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
     }
 }
 
-// Deterministic second pass of the residual: sums (or maxima) over the workgroup partials in a
-// fixed order, then the pseudo-loop control of the tank.
+// Deterministic second pass of the residual: sums (or maxima) over the partials of one tank
+// in a fixed order, then the pseudo-loop control of the tank.  Workgroup b serves tank b.
 template <bool NORM_MAX>
-__global__ void __launch_bounds__(256) finalize_kernel(TankDev t, Scheme sc, int n_blocks)
+__global__ void __launch_bounds__(256) finalize_kernel(const TankDev *__restrict__ tanks, Scheme sc)
 {
+    const TankDev &t = tanks[blockIdx.x];
     Status *st = t.status;
     if (st->done) return;
+    const int n_blocks = t.n_partials;
     double acc[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < n_blocks; b += 256)
         for (int k = 0; k < kPartialWidth; ++k) {
@@ -202,30 +205,91 @@ __global__ void __launch_bounds__(256) finalize_kernel(TankDev t, Scheme sc, int
     }
 }
 
-// Start of a real-time step (Algorithm 1): level n-1 <- level n (BDF2), level n <- current
-// state, the step's BDF coefficients, and a fresh pseudo-loop status.
+// Start of a real-time step (Algorithm 1) for tank blockIdx.y: level n-1 <- level n (BDF2 with
+// history) or <- the new level n (BDF2 without), level n <- current state, and a fresh
+// pseudo-loop status; workgroup (0, 0) also stores the step's BDF coefficients.  In the mixed
+// form the new level n is level n plus the current deviation, which then becomes zero.
 __global__ void __launch_bounds__(256)
-    begin_step_kernel(TankDev t, StepParams sp, int max_pseudo, double tol, int use_history)
+    begin_step_kernel(const TankDev *__restrict__ tanks, StepParams sp, int max_pseudo, double tol,
+                      int use_history, int mixed)
 {
+    const TankDev &t = tanks[blockIdx.y];
     Status *st = t.status;
-    const double *q = t.state[st->cur];
+    const int cur = st->cur;
     const size_t plane = t.plane;
     for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < plane;
          c += (size_t)gridDim.x * 256) {
+        if (mixed) {
+            float *d = (float *)t.state[cur];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (use_history) t.level_nm1[k * plane + c] = t.level_n[k * plane + c];
-            t.level_n[k * plane + c] = q[k * plane + c];
+            for (int k = 0; k < 4; ++k) {
+                const double old = t.level_n[k * plane + c];
+                const double nw = old + (double)d[k * plane + c];
+                if (k < 3 && t.level_nm1) t.level_nm1[k * plane + c] = use_history ? old : nw;
+                t.level_n[k * plane + c] = nw;
+                d[k * plane + c] = 0.0f;
+            }
+        } else {
+            const double *q = (const double *)t.state[cur];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double nw = q[k * plane + c];
+                if (t.level_nm1) t.level_nm1[k * plane + c] = use_history ? t.level_n[k * plane + c] : nw;
+                t.level_n[k * plane + c] = nw;
+            }
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *const_cast<StepParams *>(t.step) = sp;
+        if (blockIdx.y == 0) *const_cast<StepParams *>(t.step) = sp;
         st->iters = 0;
         st->diverged = 0;
         st->max_pseudo = max_pseudo;
         st->tol = tol;
         st->done = (max_pseudo <= 0) ? 1 : 0;
     }
+}
+
+// Mixed form: the caller's FP64 state q [4][plane] (rho, rho u, rho v, p) becomes level n (and
+// n-1 for the first three fields) and zero deviations in all three state buffers.
+__global__ void __launch_bounds__(256) import_mixed_kernel(TankDev t, const double *__restrict__ q)
+{
+    const size_t plane = t.plane;
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < plane;
+         c += (size_t)gridDim.x * 256) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double v = q[k * plane + c];
+            t.level_n[k * plane + c] = v;
+            if (k < 3 && t.level_nm1) t.level_nm1[k * plane + c] = v;
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            float *d = (float *)t.state[b];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d[k * plane + c] = 0.0f;
+        }
+    }
+}
+
+// Mixed form: q [4][plane] <- level n + deviation of buffer cur, in FP64.
+__global__ void __launch_bounds__(256)
+    export_mixed_kernel(TankDev t, int cur, double *__restrict__ q)
+{
+    const size_t plane = t.plane;
+    const float *d = (const float *)t.state[cur];
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < plane;
+         c += (size_t)gridDim.x * 256) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k * plane + c] = t.level_n[k * plane + c] + (double)d[k * plane + c];
+    }
+}
+
+unsigned cell_blocks(size_t plane)
+{
+    size_t blocks = (plane + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    return (unsigned)blocks;
 }
 
 }  // namespace
@@ -235,38 +299,27 @@ int direct_blocks(const TankDev &t)
     return ((t.nx + kDirectTX - 1) / kDirectTX) * ((t.ny + kDirectTY - 1) / kDirectTY);
 }
 
-int stage_blocks(const TankDev &t, int tile_x, int tile_y)
+int launch_begin_step_all(const TankDev *tanks_dev, int n_tanks, size_t max_plane, const Scheme &sc,
+                          const StepParams &sp, int max_pseudo, double tol, int use_history,
+                          void *stream)
 {
-    if (tile_x == 1 && tile_y == 1) return direct_blocks(t);
-    if (tile_x < 0) return march_units(t, tile_y);
-    return tile_count(t, tile_x, tile_y);
+    const dim3 grid(cell_blocks(max_plane), (unsigned)n_tanks);
+    hipLaunchKernelGGL(begin_step_kernel, grid, dim3(256), 0, (hipStream_t)stream, tanks_dev, sp,
+                       max_pseudo, tol, use_history, sc.mixed);
+    return (int)hipGetLastError();
 }
 
-int launch_stage(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y, void *stream)
+int launch_import_mixed(const TankDev &t, const double *q, void *stream)
 {
-    if (tile_x == 1 && tile_y == 1) return launch_stage_direct_f64(t, sc, stage, stream);
-    if (tile_x < 0) return launch_stage_march_f64(t, sc, stage, tile_y, -tile_x, stream);
-    return launch_stage_tile_f64(t, sc, stage, tile_x, tile_y, stream);
+    hipLaunchKernelGGL(import_mixed_kernel, dim3(cell_blocks(t.plane)), dim3(256), 0,
+                       (hipStream_t)stream, t, q);
+    return (int)hipGetLastError();
 }
 
-int launch_begin_step(const TankDev &t, const Scheme &sc, double dt, int max_pseudo, double tol,
-                      int use_history, void *stream)
+int launch_export_mixed(const TankDev &t, int cur, double *q, void *stream)
 {
-    StepParams sp;
-    sp.inv_dt = 1.0 / dt;
-    if (sc.bdf2 && use_history) {
-        sp.b0 = 1.5;
-        sp.b1 = -2.0;
-        sp.b2 = 0.5;
-    } else {
-        sp.b0 = 1.0;
-        sp.b1 = -1.0;
-        sp.b2 = 0.0;
-    }
-    size_t blocks = (t.plane + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(begin_step_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                       (hipStream_t)stream, t, sp, max_pseudo, tol, use_history);
+    hipLaunchKernelGGL(export_mixed_kernel, dim3(cell_blocks(t.plane)), dim3(256), 0,
+                       (hipStream_t)stream, t, cur, q);
     return (int)hipGetLastError();
 }
 
@@ -281,14 +334,14 @@ int launch_stage_direct_f64(const TankDev &t, const Scheme &sc, int stage, void 
     return (int)hipGetLastError();
 }
 
-int launch_finalize(const TankDev &t, const Scheme &sc, int n_blocks, void *stream)
+int launch_finalize_all(const TankDev *tanks_dev, int n_tanks, const Scheme &sc, void *stream)
 {
     if (sc.norm_max)
-        hipLaunchKernelGGL(finalize_kernel<true>, dim3(1), dim3(256), 0, (hipStream_t)stream, t, sc,
-                           n_blocks);
+        hipLaunchKernelGGL(finalize_kernel<true>, dim3((unsigned)n_tanks), dim3(256), 0,
+                           (hipStream_t)stream, tanks_dev, sc);
     else
-        hipLaunchKernelGGL(finalize_kernel<false>, dim3(1), dim3(256), 0, (hipStream_t)stream, t, sc,
-                           n_blocks);
+        hipLaunchKernelGGL(finalize_kernel<false>, dim3((unsigned)n_tanks), dim3(256), 0,
+                           (hipStream_t)stream, tanks_dev, sc);
     return (int)hipGetLastError();
 }
 

@@ -9,6 +9,63 @@
 
 namespace vdac {
 
+// Wave-uniform copies (readfirstlane) of values every lane of a wave holds alike, so that they
+// live in scalar registers.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni(uint64_t v)
+{
+    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+__device__ __forceinline__ double uni(double v) { return __builtin_bit_cast(double, uni(__builtin_bit_cast(uint64_t, v))); }
+template <typename T>
+__device__ __forceinline__ T *uni(T *p)
+{
+    return (T *)uni((uint64_t)(uintptr_t)p);
+}
+
+// The descriptor of a tank read from the device table into scalar registers, field by field (a
+// struct copy would go through private memory); the state buffers come from state_buf.
+__device__ __forceinline__ TankDev load_tank(const TankDev *__restrict__ p)
+{
+    TankDev t;
+    t.nx = uni(p->nx);
+    t.ny = uni(p->ny);
+    t.per_x = uni(p->per_x);
+    t.per_y = uni(p->per_y);
+    t.dx = uni(p->dx);
+    t.dy = uni(p->dy);
+    t.inv_dx = uni(p->inv_dx);
+    t.inv_dy = uni(p->inv_dy);
+    t.half_dx = uni(p->half_dx);
+    t.half_dy = uni(p->half_dy);
+    t.gx = uni(p->gx);
+    t.gy = uni(p->gy);
+    t.beta = uni(p->beta);
+    t.inv_beta = uni(p->inv_beta);
+    t.cfl = uni(p->cfl);
+    t.plane = (size_t)uni((uint64_t)p->plane);
+    t.state[0] = t.state[1] = t.state[2] = nullptr;  // see state_buf
+    t.level_n = uni(p->level_n);
+    t.level_nm1 = uni(p->level_nm1);
+    t.flags = uni(p->flags);
+    t.partials = uni(p->partials);
+    t.status = uni(p->status);
+    t.step = uni(p->step);
+    t.n_fluid = uni(p->n_fluid);
+    t.n_partials = uni(p->n_partials);
+    t.n_strips = uni(p->n_strips);
+    t.chunk = uni(p->chunk);
+    return t;
+}
+
+// State buffer b (0..2) of a tank, read from the device table (indexing the array of a local
+// copy would force the copy into private memory).
+__device__ __forceinline__ void *state_buf(const TankDev *__restrict__ p, int b)
+{
+    return uni(p->state[b]);
+}
+
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 __device__ __forceinline__ Prim<double> load_prim(const double *q, size_t plane, size_t c)
@@ -74,31 +131,186 @@ __device__ __forceinline__ void block_reduce_store(double v[kPartialWidth], doub
     }
 }
 
-// A fluid cell as the reconstruction sees it: W, limited slopes along x and y, and the stage-0
-// sources (real-time term of rho, rho u, rho v and rho^0 for the body force).
-struct CellRec {
-    Prim<double> w;
-    Slope<double> gx, gy;
-    double d_r, d_ru, d_rv, rho0;
+// ------------------------------------------------------------------------------------------
+// Precision policies.  FP64: the state is stored as (rho, rho u, rho v, p) in FP64 and every step
+// runs in FP64.  Mixed: the state is stored in FP32 as the deviation from real-time level n
+// (rho - rho^n, rho u - (rho u)^n, rho v - (rho v)^n) plus the absolute pressure, level n (and
+// n-1) stay in FP64; reconstruction and Riemann fluxes run in FP32 on pressures taken relative to
+// the face's left (lower) cell, and the divergence, sources, update and norm run in FP64.
+// ------------------------------------------------------------------------------------------
+struct PrecF64 {
+    using Real = double;   // reconstruction and flux arithmetic
+    using Store = double;  // state storage
+    static constexpr bool kMixed = false;
+};
+struct PrecMixed {
+    using Real = float;
+    using Store = float;
+    static constexpr bool kMixed = true;
 };
 
-// States of a reconstructed cell at its four faces (left, right, lower, upper):
-// W + grad W . (x_f - x_i), with the new pressure gradient for p, evaluated once.
-struct FaceStates {
-    Prim<double> xl, xr, yb, yt;
+// Absolute state (rho, rho u, rho v, p) of cell c of a state buffer.
+template <class P>
+__device__ __forceinline__ void load_state(const TankDev &t, const void *buf, size_t c, double &r,
+                                           double &m, double &n, double &p)
+{
+    const size_t plane = t.plane;
+    const typename P::Store *q = (const typename P::Store *)buf;
+    if (P::kMixed) {
+        r = t.level_n[c] + (double)q[c];
+        m = t.level_n[plane + c] + (double)q[plane + c];
+        n = t.level_n[2 * plane + c] + (double)q[2 * plane + c];
+    } else {
+        r = (double)q[c];
+        m = (double)q[plane + c];
+        n = (double)q[2 * plane + c];
+    }
+    p = (double)q[3 * plane + c];
+}
+
+// Primitives of cell c of a state buffer in the reconstruction precision.
+template <class P>
+__device__ __forceinline__ Prim<typename P::Real> load_prim_p(const TankDev &t, const void *buf,
+                                                              size_t c)
+{
+    using R = typename P::Real;
+    double r, m, n, p;
+    load_state<P>(t, buf, c, r, m, n, p);
+    const double ir = rcp_pos(r);
+    return {(R)r, (R)(m * ir), (R)(n * ir), (R)p};
+}
+
+// Stores the absolute state (rho, rho u, rho v, p) of cell c; the mixed form stores deviations
+// from level n given in ln0..ln2.
+template <class P>
+__device__ __forceinline__ void store_state(const TankDev &t, void *buf, size_t c, double r, double m,
+                                            double n, double p, double ln0, double ln1, double ln2)
+{
+    const size_t plane = t.plane;
+    typename P::Store *q = (typename P::Store *)buf;
+    if (P::kMixed) {
+        q[c] = (float)(r - ln0);
+        q[plane + c] = (float)(m - ln1);
+        q[2 * plane + c] = (float)(n - ln2);
+    } else {
+        q[c] = r;
+        q[plane + c] = m;
+        q[2 * plane + c] = n;
+    }
+    q[3 * plane + c] = (typename P::Store)p;
+}
+
+// Stage-0 data of one cell: Q^0 (rho, rho u, rho v, p), level n, and the real-time term
+// (B0 Q^0 + B1 Q^n + B2 Q^{n-1})/dt of eq. bdf on rho, rho u, rho v.  The mixed form keeps the
+// stored deviations d = Q^0 - Q^n and, since B0 + B1 + B2 = 0, forms the term as
+// (B0 d + B2 (Q^{n-1} - Q^n))/dt without cancellation.
+struct Stage0 {
+    double z0, z1, z2, z3;  // Q^0
+    double n0, n1, n2;      // level n
+    double d0, d1, d2;      // real-time term
 };
+
+template <class P, bool BDF2>
+__device__ __forceinline__ Stage0 load_stage0(const TankDev &t, const void *q0buf, size_t c,
+                                              const StepParams &sp)
+{
+    const size_t plane = t.plane;
+    const typename P::Store *q = (const typename P::Store *)q0buf;
+    Stage0 s;
+    s.n0 = t.level_n[c];
+    s.n1 = t.level_n[plane + c];
+    s.n2 = t.level_n[2 * plane + c];
+    s.z3 = (double)q[3 * plane + c];
+    if (P::kMixed) {
+        const double e0 = q[c], e1 = q[plane + c], e2 = q[2 * plane + c];
+        s.z0 = s.n0 + e0;
+        s.z1 = s.n1 + e1;
+        s.z2 = s.n2 + e2;
+        double a0 = sp.b0 * e0, a1 = sp.b0 * e1, a2 = sp.b0 * e2;
+        if (BDF2) {
+            a0 = fma(sp.b2, t.level_nm1[c] - s.n0, a0);
+            a1 = fma(sp.b2, t.level_nm1[plane + c] - s.n1, a1);
+            a2 = fma(sp.b2, t.level_nm1[2 * plane + c] - s.n2, a2);
+        }
+        s.d0 = a0 * sp.inv_dt;
+        s.d1 = a1 * sp.inv_dt;
+        s.d2 = a2 * sp.inv_dt;
+    } else {
+        s.z0 = q[c];
+        s.z1 = q[plane + c];
+        s.z2 = q[2 * plane + c];
+        double a0 = fma(sp.b0, s.z0, sp.b1 * s.n0);
+        double a1 = fma(sp.b0, s.z1, sp.b1 * s.n1);
+        double a2 = fma(sp.b0, s.z2, sp.b1 * s.n2);
+        if (BDF2) {
+            a0 = fma(sp.b2, t.level_nm1[c], a0);
+            a1 = fma(sp.b2, t.level_nm1[plane + c], a1);
+            a2 = fma(sp.b2, t.level_nm1[2 * plane + c], a2);
+        }
+        s.d0 = a0 * sp.inv_dt;
+        s.d1 = a1 * sp.inv_dt;
+        s.d2 = a2 * sp.inv_dt;
+    }
+    return s;
+}
+
+// A fluid cell as the reconstruction sees it: W, limited slopes along x and y, and the stage-0
+// sources (real-time term of rho u, rho v and rho^0 for the body force).
+template <typename R>
+struct CellRecT {
+    Prim<R> w;
+    Slope<R> gx, gy;
+    R d_r, d_ru, d_rv, rho0;
+};
+using CellRec = CellRecT<double>;
+
+// State of a reconstructed cell at one face: W +- grad W h, with the new pressure gradient gp
+// for p; pbase is the pressure the state is expressed from (the cell's own pressure for the
+// absolute form, its difference to the face's reference pressure for the compensated form).
+template <typename R>
+__device__ __forceinline__ Prim<R> state_at(const Prim<R> &w, const Slope<R> &g, R gp, R h, R pbase)
+{
+    return {fma(g.r, h, w.r), fma(g.u, h, w.u), fma(g.v, h, w.v), fma(gp, h, pbase)};
+}
+
+// New pressure gradient of a reconstructed cell (Sec. 2.3.2).
+template <typename R>
+__device__ __forceinline__ R cell_gradp_x(const TankDev &t, const CellRecT<R> &c)
+{
+    return gradp_x(c.w, c.gx, c.gy, c.d_ru, c.rho0 * (R)t.gx);
+}
+template <typename R>
+__device__ __forceinline__ R cell_gradp_y(const TankDev &t, const CellRecT<R> &c)
+{
+    return gradp_y(c.w, c.gx, c.gy, c.d_rv, c.rho0 * (R)t.gy);
+}
+
+// States of a reconstructed cell at its four faces (left, right, lower, upper), with the
+// pressure gradient evaluated once and p expressed from pbase.
+template <typename R>
+struct FaceStatesT {
+    Prim<R> xl, xr, yb, yt;
+};
+using FaceStates = FaceStatesT<double>;
+
+template <typename R>
+__device__ __forceinline__ FaceStatesT<R> face_states(const TankDev &t, const CellRecT<R> &c,
+                                                      R pb_xl, R pb_xr, R pb_yb, R pb_yt)
+{
+    const R px = cell_gradp_x(t, c);
+    const R py = cell_gradp_y(t, c);
+    const R hx = (R)t.half_dx, hy = (R)t.half_dy;
+    FaceStatesT<R> s;
+    s.xl = state_at(c.w, c.gx, px, -hx, pb_xl);
+    s.xr = state_at(c.w, c.gx, px, hx, pb_xr);
+    s.yb = state_at(c.w, c.gy, py, -hy, pb_yb);
+    s.yt = state_at(c.w, c.gy, py, hy, pb_yt);
+    return s;
+}
 
 __device__ __forceinline__ FaceStates face_states(const TankDev &t, const CellRec &c)
 {
-    const double px = gradp_x(c.w, c.gx, c.gy, c.d_ru, c.rho0 * t.gx);
-    const double py = gradp_y(c.w, c.gx, c.gy, c.d_rv, c.rho0 * t.gy);
-    const double hx = t.half_dx, hy = t.half_dy;
-    FaceStates s;
-    s.xl = {fma(-c.gx.r, hx, c.w.r), fma(-c.gx.u, hx, c.w.u), fma(-c.gx.v, hx, c.w.v), fma(-px, hx, c.w.p)};
-    s.xr = {fma(c.gx.r, hx, c.w.r), fma(c.gx.u, hx, c.w.u), fma(c.gx.v, hx, c.w.v), fma(px, hx, c.w.p)};
-    s.yb = {fma(-c.gy.r, hy, c.w.r), fma(-c.gy.u, hy, c.w.u), fma(-c.gy.v, hy, c.w.v), fma(-py, hy, c.w.p)};
-    s.yt = {fma(c.gy.r, hy, c.w.r), fma(c.gy.u, hy, c.w.u), fma(c.gy.v, hy, c.w.v), fma(py, hy, c.w.p)};
-    return s;
+    return face_states<double>(t, c, c.w.p, c.w.p, c.w.p, c.w.p);
 }
 
 // State of a reconstructed cell at its face on side sd (+1 / -1) of axis (0 = x, 1 = y):
@@ -106,56 +318,44 @@ __device__ __forceinline__ FaceStates face_states(const TankDev &t, const CellRe
 __device__ __forceinline__ Prim<double> own_state(const TankDev &t, const CellRec &c, int axis,
                                                   int sd)
 {
-    Prim<double> s;
     if (axis == 0) {
         const double h = sd > 0 ? t.half_dx : -t.half_dx;
-        const double px = gradp_x(c.w, c.gx, c.gy, c.d_ru, c.rho0 * t.gx);
-        s.r = c.w.r + c.gx.r * h;
-        s.u = c.w.u + c.gx.u * h;
-        s.v = c.w.v + c.gx.v * h;
-        s.p = c.w.p + px * h;
-    } else {
-        const double h = sd > 0 ? t.half_dy : -t.half_dy;
-        const double py = gradp_y(c.w, c.gx, c.gy, c.d_rv, c.rho0 * t.gy);
-        s.r = c.w.r + c.gy.r * h;
-        s.u = c.w.u + c.gy.u * h;
-        s.v = c.w.v + c.gy.v * h;
-        s.p = c.w.p + py * h;
+        return state_at(c.w, c.gx, cell_gradp_x(t, c), h, c.w.p);
     }
-    return s;
+    const double h = sd > 0 ? t.half_dy : -t.half_dy;
+    return state_at(c.w, c.gy, cell_gradp_y(t, c), h, c.w.p);
 }
 
 // State of the wall ghost on side sd of axis, at the face it shares with cell c.  The ghost
 // mirrors c and its stencil mirrors c's stencil, so (limiter symmetric and odd) its slope normal
 // to the wall equals c's and its tangential slopes are c's with the mirror's signs; its sources
-// are mirrored and gravity is reversed in it (Sec. 2.5).
+// are mirrored and gravity is reversed in it (Sec. 2.5).  Its pressure equals c's; pbase is that
+// pressure in the form the face uses.
+template <typename R>
+__device__ __forceinline__ Prim<R> ghost_state(const TankDev &t, const CellRecT<R> &c, int axis,
+                                               int sd, bool slip, R pbase)
+{
+    const R su = (!slip || axis == 0) ? R(-1) : R(1);  // mirror sign of u
+    const R sv = (!slip || axis == 1) ? R(-1) : R(1);  // mirror sign of v
+    const Prim<R> w = {c.w.r, su * c.w.u, sv * c.w.v, c.w.p};
+    if (axis == 0) {
+        const Slope<R> gx = c.gx;
+        const Slope<R> gy = {c.gy.r, su * c.gy.u, sv * c.gy.v};
+        const R px = gradp_x(w, gx, gy, su * c.d_ru, -(c.rho0 * (R)t.gx));
+        const R h = sd > 0 ? -(R)t.half_dx : (R)t.half_dx;  // ghost's face toward c
+        return state_at(w, gx, px, h, pbase);
+    }
+    const Slope<R> gy = c.gy;
+    const Slope<R> gx = {c.gx.r, su * c.gx.u, sv * c.gx.v};
+    const R py = gradp_y(w, gx, gy, sv * c.d_rv, -(c.rho0 * (R)t.gy));
+    const R h = sd > 0 ? -(R)t.half_dy : (R)t.half_dy;
+    return state_at(w, gy, py, h, pbase);
+}
+
 __device__ __forceinline__ Prim<double> ghost_state(const TankDev &t, const CellRec &c, int axis,
                                                     int sd, bool slip)
 {
-    const double su = (!slip || axis == 0) ? -1.0 : 1.0;  // mirror sign of u
-    const double sv = (!slip || axis == 1) ? -1.0 : 1.0;  // mirror sign of v
-    Prim<double> w = {c.w.r, su * c.w.u, sv * c.w.v, c.w.p};
-    Prim<double> s;
-    if (axis == 0) {
-        Slope<double> gx = c.gx;
-        Slope<double> gy = {c.gy.r, su * c.gy.u, sv * c.gy.v};
-        const double px = gradp_x(w, gx, gy, su * c.d_ru, -(c.rho0 * t.gx));
-        const double h = sd > 0 ? -t.half_dx : t.half_dx;  // ghost's face toward c
-        s.r = w.r + gx.r * h;
-        s.u = w.u + gx.u * h;
-        s.v = w.v + gx.v * h;
-        s.p = w.p + px * h;
-    } else {
-        Slope<double> gy = c.gy;
-        Slope<double> gx = {c.gx.r, su * c.gx.u, sv * c.gx.v};
-        const double py = gradp_y(w, gx, gy, sv * c.d_rv, -(c.rho0 * t.gy));
-        const double h = sd > 0 ? -t.half_dy : t.half_dy;
-        s.r = w.r + gy.r * h;
-        s.u = w.u + gy.u * h;
-        s.v = w.v + gy.v * h;
-        s.p = w.p + py * h;
-    }
-    return s;
+    return ghost_state<double>(t, c, axis, sd, slip, c.w.p);
 }
 
 }  // namespace vdac

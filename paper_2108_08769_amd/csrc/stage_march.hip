@@ -1,8 +1,14 @@
-// stage_march.hip -- the Runge-Kutta stage kernel for gfx950 in its row-marching form.
+// stage_march.hip -- the Runge-Kutta stage kernel for gfx950 in its row-marching form, for the
+// FP64 and the mixed-precision storage, over any number of tanks in one launch.
+//
+// Work comes from a unit table: entry e of the table is the work of wave e % W of workgroup
+// e / W (W waves per workgroup), one chunk of rows of one 64-column strip of one tank.  The host
+// orders the table so that workgroup b, which the dispatcher places on XCD b % 8, gets a unit
+// next to the other units of that XCD (one L2 per XCD).
 //
 // Each 64-lane wave owns a strip of 64 consecutive columns (lanes 2..61 produce output, lanes
-// 0-1 and 62-63 are the halo the reconstruction and the x-faces need) and sweeps a chunk of rows
-// upward.  The three rows the limited slopes need stay in registers, x-neighbours come from
+// 0-1 and 62-63 are the halo the reconstruction and the x-faces need) and sweeps its chunk of
+// rows upward.  The three rows the limited slopes need stay in registers, x-neighbours come from
 // cross-lane shuffles, and the loads of the next row are issued a full row ahead of their use.
 // No LDS, no workgroup barrier.  Per row r the wave
 //   1. reconstructs row r once per lane: limited slopes (Sec. 2.3.1), the stage-0 sources from
@@ -16,6 +22,16 @@
 //      on the last stage the residual partial.
 // Each face is evaluated once.  Periodic sides wrap indices; cells outside a non-periodic side
 // read as non-fluid.
+//
+// Mixed form: all four fields are stored as FP32 deviations from the FP64 level n, so the
+// absolute state is known to FP64 accuracy up to the FP32 rounding of the (small) deviations.
+// The reconstruction and the fluxes run in FP32 on pressures measured from the pressure of the
+// face's lower-index cell (the ghost's, equal to the cell's own, on a wall).  The Osher flux
+// depends on p only through the p term of the normal momentum flux and through p differences, so
+// the shift is exact: the divergence adds back p_i - p_ref of the lower face in FP64.  This keeps
+// the hydrostatic pressure differences, which are small against p itself, to FP32 precision of
+// the differences.  Sources, divergence, update and norm run in FP64; the update is formed on
+// the deviation from level n, then rounded to FP32.
 #include <hip/hip_runtime.h>
 
 #include "stage_common.h"
@@ -26,7 +42,7 @@ namespace {
 
 constexpr int kLanes = 64;
 constexpr int kOut = 60;            // output columns per strip (lanes 2..61)
-constexpr int kWavesPerBlock = 4;
+constexpr int kMaxWavesPerBlock = 4;
 
 __device__ __forceinline__ bool locate_axis(int g, int n, int periodic, int &out)
 {
@@ -39,52 +55,86 @@ __device__ __forceinline__ bool locate_axis(int g, int n, int periodic, int &out
     return true;
 }
 
-__device__ __forceinline__ double from_left(double v) { return __shfl_up(v, 1, kLanes); }
-__device__ __forceinline__ double from_right(double v) { return __shfl_down(v, 1, kLanes); }
+template <typename T>
+__device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, kLanes); }
+template <typename T>
+__device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, kLanes); }
 
-__device__ __forceinline__ Prim<double> prim_from_left(const Prim<double> &w)
+template <typename T>
+__device__ __forceinline__ Prim<T> prim_from_left(const Prim<T> &w)
 {
     return {from_left(w.r), from_left(w.u), from_left(w.v), from_left(w.p)};
 }
-__device__ __forceinline__ Prim<double> prim_from_right(const Prim<double> &w)
+template <typename T>
+__device__ __forceinline__ Prim<T> prim_from_right(const Prim<T> &w)
 {
     return {from_right(w.r), from_right(w.u), from_right(w.v), from_right(w.p)};
+}
+
+template <typename T, typename U>
+__device__ __forceinline__ Vec4<T> cast4(const Vec4<U> &a)
+{
+    return {(T)a.a, (T)a.b, (T)a.c, (T)a.d};
 }
 
 // Loads of one row, issued one step ahead of their use: the stage input is fetched two rows
 // ahead (it is the upper neighbour of the next row), the stage-0 state, level n (and level
 // n-1) and the flags one row ahead.
+template <class P>
 struct InputLoad {
-    double r, m, n, p;   // stage input Q^{s-1}: rho, rho u, rho v, p
+    typename P::Store r, m, n, p;  // stage input Q^{s-1} (mixed: deviations from level n)
+    double lr, lm, ln, lp;         // level n of rho, rho u, rho v, p (mixed form only)
 };
+template <class P>
 struct SourceLoad {
-    double z0, z1, z2, z3;  // stage-0 state Q^0: rho, rho u, rho v, p
-    double n0, n1, n2;      // level n
-    double m0, m1, m2;      // level n-1 (BDF2 only)
-    uint8_t f;              // cell flags (FLAG_SOLID if outside the tank)
+    typename P::Store z0, z1, z2, z3;  // stage-0 state Q^0 (mixed: deviations from level n)
+    double n0, n1, n2;                 // level n
+    double m0, m1, m2;                 // level n-1 (BDF2 only)
+    uint8_t f;                         // cell flags (FLAG_SOLID if outside the tank)
 };
 
-__device__ __forceinline__ InputLoad load_input(const TankDev &t, const double *qprev,
-                                                bool have_col, int gi, int r)
+template <class P>
+__device__ __forceinline__ InputLoad<P> load_input(const TankDev &t,
+                                                   const typename P::Store *__restrict__ qprev,
+                                                   bool have_col, int gi, int r)
 {
+    using S = typename P::Store;
     int gj;
-    InputLoad L = {1.0, 0.0, 0.0, 0.0};
+    InputLoad<P> L;
+    L.r = P::kMixed ? S(0) : S(1);
+    L.m = L.n = L.p = S(0);
+    L.lr = 1.0;
+    L.lm = L.ln = L.lp = 0.0;
     if (have_col && locate_axis(r, t.ny, t.per_y, gj)) {
+        const size_t plane = t.plane;
         const size_t c = (size_t)gj * t.nx + gi;
         L.r = qprev[c];
-        L.m = qprev[t.plane + c];
-        L.n = qprev[2 * t.plane + c];
-        L.p = qprev[3 * t.plane + c];
+        L.m = qprev[plane + c];
+        L.n = qprev[2 * plane + c];
+        L.p = qprev[3 * plane + c];
+        if (P::kMixed) {
+            L.lr = t.level_n[c];
+            L.lm = t.level_n[plane + c];
+            L.ln = t.level_n[2 * plane + c];
+            L.lp = t.level_n[3 * plane + c];
+        }
     }
     return L;
 }
 
-template <bool BDF2>
-__device__ __forceinline__ SourceLoad load_sources(const TankDev &t, const double *q0,
-                                                   bool have_col, int gi, int r)
+template <class P, bool BDF2>
+__device__ __forceinline__ SourceLoad<P> load_sources(const TankDev &t,
+                                                      const typename P::Store *__restrict__ q0,
+                                                      bool have_col, int gi, int r)
 {
+    using S = typename P::Store;
     int gj;
-    SourceLoad L = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0, FLAG_SOLID};
+    SourceLoad<P> L;
+    L.z0 = P::kMixed ? S(0) : S(1);
+    L.z1 = L.z2 = L.z3 = S(0);
+    L.n0 = L.m0 = 1.0;
+    L.n1 = L.n2 = L.m1 = L.m2 = 0.0;
+    L.f = FLAG_SOLID;
     if (have_col && locate_axis(r, t.ny, t.per_y, gj)) {
         const size_t plane = t.plane;
         const size_t c = (size_t)gj * t.nx + gi;
@@ -105,71 +155,96 @@ __device__ __forceinline__ SourceLoad load_sources(const TankDev &t, const doubl
     return L;
 }
 
-__device__ __forceinline__ Prim<double> to_prim(const InputLoad &L)
+// Primitives of a loaded cell in the reconstruction precision.  In the mixed form p is left at
+// zero: the face pressures come from the FP64 pressure (abs_p) through differences.
+template <class P>
+__device__ __forceinline__ Prim<typename P::Real> to_prim(const InputLoad<P> &L)
 {
-    const double ir = rcp_pos(L.r);
-    return {L.r, L.m * ir, L.n * ir, L.p};
+    if constexpr (P::kMixed) {
+        const float r = (float)(L.lr + (double)L.r);
+        const float m = (float)(L.lm + (double)L.m);
+        const float n = (float)(L.ln + (double)L.n);
+        const float ir = rcp_pos(r);
+        return {r, m * ir, n * ir, 0.0f};
+    } else {
+        const double ir = rcp_pos(L.r);
+        return {L.r, L.m * ir, L.n * ir, L.p};
+    }
 }
 
-// States of a reconstructed cell at one face: W +- grad W h, with the new pressure gradient.
-__device__ __forceinline__ Prim<double> state_at(const Prim<double> &w, const Slope<double> &g,
-                                                 double gp, double h)
+// Absolute pressure of a loaded cell in FP64.
+template <class P>
+__device__ __forceinline__ double abs_p(const InputLoad<P> &L)
 {
-    return {fma(g.r, h, w.r), fma(g.u, h, w.u), fma(g.v, h, w.v), fma(gp, h, w.p)};
+    return P::kMixed ? L.lp + (double)L.p : (double)L.p;
 }
 
 // WAVES: the register budget as waves per SIMD (2: up to 256 VGPRs per lane, 3: up to 168).
-template <bool NORM_MAX, bool BDF2, bool LAST, int WAVES>
-__global__ void __launch_bounds__(kLanes *kWavesPerBlock, WAVES)
-    stage_march_f64(TankDev t, Scheme sc, int stage, int chunk, int n_strips, int n_units)
+template <class P, bool NORM_MAX, bool BDF2, bool LAST, int WAVES>
+__global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
+    stage_march(const TankDev *__restrict__ tanks, const MarchUnit *__restrict__ units, Scheme sc,
+                int stage)
 {
+    using R = typename P::Real;
+    using S = typename P::Store;
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    const int lane = threadIdx.x % kLanes;
+    const MarchUnit un = units[blockIdx.x * (blockDim.x / kLanes) + wave];
+    if (un.tank < 0) return;  // padding (uniform per wave)
+    const TankDev t = load_tank(tanks + un.tank);
     const Status *st = t.status;
     if (st->done) return;
 
-    // XCD-aware order: block b runs on XCD b % 8; each XCD gets a contiguous run of units, and
-    // consecutive units are neighbouring strips of the same row chunk.
-    const int n_blocks = (n_units + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int per = (n_blocks + 7) >> 3;
-    const int blk = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
-    const int wave = threadIdx.x / kLanes, lane = threadIdx.x % kLanes;
-    const int unit = blk * kWavesPerBlock + wave;
-    if (blk >= n_blocks || unit >= n_units) return;  // uniform per wave
-
-    const int strip = unit % n_strips, ch = unit / n_strips;
+    const int strip = un.local % t.n_strips, ch = un.local / t.n_strips;
     const int col = strip * kOut - 2 + lane;  // this lane's column (may lie outside the tank)
     int gi = 0;
     const bool have_col = locate_axis(col, t.nx, t.per_x, gi);
     const bool out_lane = lane >= 2 && lane < 2 + kOut && col >= 0 && col < t.nx;
-    const int j0 = ch * chunk;
-    const int j1 = min(j0 + chunk, t.ny);
+    const int j0 = ch * t.chunk;
+    const int j1 = min(j0 + t.chunk, t.ny);
 
     const int cur = st->cur;
     const StageBuffers bufs = stage_buffers(cur, stage);
-    const double *qprev = t.state[bufs.in];
-    const double *q0 = t.state[cur];
-    double *qout = t.state[bufs.out];
+    const S *__restrict__ qprev = (const S *)state_buf(tanks + un.tank, bufs.in);
+    const S *__restrict__ q0 = (const S *)state_buf(tanks + un.tank, cur);
+    S *__restrict__ qout = (S *)state_buf(tanks + un.tank, bufs.out);
     const StepParams sp = *t.step;
     const bool slip = sc.slip != 0;
-    const double kl = sc.k;
+    const R kl = (R)sc.k;
     const double alpha = sc.alpha[stage - 1];
     const size_t plane = t.plane;
+    const R hx = (R)t.half_dx, hy = (R)t.half_dy;
+    const R beta = (R)t.beta, inv_beta = (R)t.inv_beta;
 
     // window of primitives: rows r-1 (lo), r (mid), r+1 (hi); loads for later rows in flight
-    Prim<double> lo = to_prim(load_input(t, qprev, have_col, gi, j0 - 2));
-    Prim<double> mid = to_prim(load_input(t, qprev, have_col, gi, j0 - 1));
-    Prim<double> hi = to_prim(load_input(t, qprev, have_col, gi, j0));
-    InputLoad in_ld = load_input(t, qprev, have_col, gi, j0 + 1);           // row r+2
-    SourceLoad src_ld = load_sources<BDF2>(t, q0, have_col, gi, j0 - 1);    // row r
+    // (plo, pmid, phi: their absolute pressures in FP64)
+    Prim<R> lo, mid, hi;
+    double plo, pmid, phi;
+    {
+        const InputLoad<P> a = load_input<P>(t, qprev, have_col, gi, j0 - 2);
+        const InputLoad<P> b = load_input<P>(t, qprev, have_col, gi, j0 - 1);
+        const InputLoad<P> c = load_input<P>(t, qprev, have_col, gi, j0);
+        lo = to_prim(a);
+        mid = to_prim(b);
+        hi = to_prim(c);
+        plo = abs_p(a);
+        pmid = abs_p(b);
+        phi = abs_p(c);
+    }
+    InputLoad<P> in_ld = load_input<P>(t, qprev, have_col, gi, j0 + 1);             // row r+2
+    SourceLoad<P> src_ld = load_sources<P, BDF2>(t, q0, have_col, gi, j0 - 1);       // row r
 
     // carries from row r-1:
     //  below      its state at its upper face, or, if that face is a wall, the face's flux
-    //  pre/base   its update without the flux above it: non-final stages carry
+    //  pre        its update without the flux above it: non-final stages carry
     //             pre = Q^0 + fac R_partial; the final stage keeps Q^0 and R_partial apart for
-    //             the residual norm
-    Vec4<double> below = {1.0, 0.0, 0.0, 0.0};
+    //             the residual norm (mixed form: deviations from level n in place of Q)
+    //  lvl        final stage, mixed form: its level-n density (for the positivity check)
+    Vec4<R> below = {R(1), R(0), R(0), R(0)};
     Vec4<double> pre = zero4<double>();
     Vec4<double> rpart = zero4<double>();
-    double fac = 0.0, adt = 0.0;
+    double fac = 0.0, adt = 0.0, lvl = 0.0;
     bool fluid_lo = false;
     double part0 = 0.0, part1 = 0.0, part2 = 0.0, part3 = 0.0, part4 = 0.0;
 
@@ -177,54 +252,92 @@ __global__ void __launch_bounds__(kLanes *kWavesPerBlock, WAVES)
         // sources of row r (loaded one step ahead), then the next loads
         const uint8_t f = src_ld.f;
         const bool fluid = !(f & FLAG_SOLID);
-        const Vec4<double> z = {src_ld.z0, src_ld.z1, src_ld.z2, src_ld.z3};
-        double num0 = fma(sp.b0, src_ld.z0, sp.b1 * src_ld.n0);
-        double num1 = fma(sp.b0, src_ld.z1, sp.b1 * src_ld.n1);
-        double num2 = fma(sp.b0, src_ld.z2, sp.b1 * src_ld.n2);
-        if (BDF2) {
-            num0 = fma(sp.b2, src_ld.m0, num0);
-            num1 = fma(sp.b2, src_ld.m1, num1);
-            num2 = fma(sp.b2, src_ld.m2, num2);
+        // z: the base of the update (Q^0, or its deviation and p^0); a0..a2: absolute Q^0
+        const Vec4<double> z = {(double)src_ld.z0, (double)src_ld.z1, (double)src_ld.z2,
+                                (double)src_ld.z3};
+        double a0, a1, a2, num0, num1, num2;
+        if constexpr (P::kMixed) {
+            // (B0 Q^0 + B1 Q^n + B2 Q^{n-1}) = B0 (Q^0 - Q^n) + B2 (Q^{n-1} - Q^n): B0+B1+B2 = 0
+            a0 = src_ld.n0 + z.a;
+            a1 = src_ld.n1 + z.b;
+            a2 = src_ld.n2 + z.c;
+            num0 = sp.b0 * z.a;
+            num1 = sp.b0 * z.b;
+            num2 = sp.b0 * z.c;
+            if (BDF2) {
+                num0 = fma(sp.b2, src_ld.m0 - src_ld.n0, num0);
+                num1 = fma(sp.b2, src_ld.m1 - src_ld.n1, num1);
+                num2 = fma(sp.b2, src_ld.m2 - src_ld.n2, num2);
+            }
+        } else {
+            a0 = z.a;
+            a1 = z.b;
+            a2 = z.c;
+            num0 = fma(sp.b0, z.a, sp.b1 * src_ld.n0);
+            num1 = fma(sp.b0, z.b, sp.b1 * src_ld.n1);
+            num2 = fma(sp.b0, z.c, sp.b1 * src_ld.n2);
+            if (BDF2) {
+                num0 = fma(sp.b2, src_ld.m0, num0);
+                num1 = fma(sp.b2, src_ld.m1, num1);
+                num2 = fma(sp.b2, src_ld.m2, num2);
+            }
         }
-        const Prim<double> next_hi = to_prim(in_ld);
-        in_ld = load_input(t, qprev, have_col, gi, r + 3);
-        src_ld = load_sources<BDF2>(t, q0, have_col, gi, r + 1);
+        const double lvl_r = src_ld.n0;
+        const double d_r = num0 * sp.inv_dt, d_ru = num1 * sp.inv_dt, d_rv = num2 * sp.inv_dt;
+        const Prim<R> next_hi = to_prim(in_ld);
+        const double next_phi = abs_p(in_ld);
+        in_ld = load_input<P>(t, qprev, have_col, gi, r + 3);
+        src_ld = load_sources<P, BDF2>(t, q0, have_col, gi, r + 1);
 
         // ---- reconstruction of row r ------------------------------------------------------
-        const Prim<double> wl = prim_from_left(mid);
-        const Prim<double> wr = prim_from_right(mid);
-        CellRec rec;
+        const Prim<R> wl = prim_from_left(mid);
+        const Prim<R> wr = prim_from_right(mid);
+        CellRecT<R> rec;
         rec.w = mid;
-        rec.d_r = num0 * sp.inv_dt;
-        rec.d_ru = num1 * sp.inv_dt;
-        rec.d_rv = num2 * sp.inv_dt;
-        rec.rho0 = z.a;
-        double px = 0.0, py = 0.0;
+        rec.d_r = (R)d_r;
+        rec.d_ru = (R)d_ru;
+        rec.d_rv = (R)d_rv;
+        rec.rho0 = (R)a0;
+        R px = R(0), py = R(0);
         if (fluid) {
-            const Prim<double> xm = (f & FLAG_WALL_XM) ? mirror(mid, 0, slip) : wl;
-            const Prim<double> xp = (f & FLAG_WALL_XP) ? mirror(mid, 0, slip) : wr;
-            const Prim<double> ym = (f & FLAG_WALL_YM) ? mirror(mid, 1, slip) : lo;
-            const Prim<double> yp = (f & FLAG_WALL_YP) ? mirror(mid, 1, slip) : hi;
-            rec.gx = slopes(xm, mid, xp, t.inv_dx, kl);
-            rec.gy = slopes(ym, mid, yp, t.inv_dy, kl);
-            px = gradp_x(mid, rec.gx, rec.gy, rec.d_ru, rec.rho0 * t.gx);
-            py = gradp_y(mid, rec.gx, rec.gy, rec.d_rv, rec.rho0 * t.gy);
+            const Prim<R> xm = (f & FLAG_WALL_XM) ? mirror(mid, 0, slip) : wl;
+            const Prim<R> xp = (f & FLAG_WALL_XP) ? mirror(mid, 0, slip) : wr;
+            const Prim<R> ym = (f & FLAG_WALL_YM) ? mirror(mid, 1, slip) : lo;
+            const Prim<R> yp = (f & FLAG_WALL_YP) ? mirror(mid, 1, slip) : hi;
+            rec.gx = slopes(xm, mid, xp, (R)t.inv_dx, kl);
+            rec.gy = slopes(ym, mid, yp, (R)t.inv_dy, kl);
+            px = cell_gradp_x(t, rec);
+            py = cell_gradp_y(t, rec);
         } else {
-            rec.gx = {0.0, 0.0, 0.0};
-            rec.gy = {0.0, 0.0, 0.0};
+            rec.gx = {R(0), R(0), R(0)};
+            rec.gy = {R(0), R(0), R(0)};
+        }
+        // pressure each face state is expressed from: the absolute p (FP64 form), or p minus
+        // the pressure of the face's lower-index cell (mixed form); sx, sy add that reference
+        // back at the lower faces in FP64
+        R pb_own = mid.p, pb_xl = mid.p, pb_yb = mid.p;
+        double sx = 0.0, sy = 0.0;
+        if constexpr (P::kMixed) {
+            const double pleft = from_left(pmid);  // a shuffle: every lane takes part
+            sx = (f & FLAG_WALL_XM) ? 0.0 : pmid - pleft;
+            sy = (f & FLAG_WALL_YM) ? 0.0 : pmid - plo;
+            pb_own = R(0);
+            pb_xl = (R)sx;
+            pb_yb = (R)sy;
         }
 
         // ---- y-face between rows r-1 and r ------------------------------------------------
-        Vec4<double> gb = zero4<double>();
+        Vec4<R> gb = zero4<R>();
         if (r >= j0) {
             if (fluid) {
-                const Prim<double> L = fluid_lo ? Prim<double>{below.a, below.b, below.c, below.d}
-                                                : ghost_state(t, rec, 1, -1, slip);
-                gb = osher_y(L, state_at(mid, rec.gy, py, -t.half_dy), t.beta, t.inv_beta);
+                const Prim<R> L = fluid_lo ? Prim<R>{below.a, below.b, below.c, below.d}
+                                           : ghost_state(t, rec, 1, -1, slip, pb_own);
+                gb = osher_y(L, state_at(mid, rec.gy, py, -hy, pb_yb), beta, inv_beta);
             } else if (fluid_lo) {
                 gb = below;  // evaluated with row r-1's ghost
             }
         }
+        const Vec4<double> gbd = cast4<double>(gb);
 
         // ---- update of row r-1 ------------------------------------------------------------
         if (r - 1 >= j0 && out_lane && fluid_lo) {
@@ -232,15 +345,15 @@ __global__ void __launch_bounds__(kLanes *kWavesPerBlock, WAVES)
             locate_axis(r - 1, t.ny, t.per_y, gj);
             const size_t c = (size_t)gj * t.nx + gi;
             if (LAST) {
-                const double R0 = fma(-gb.a, t.inv_dy, rpart.a);
-                const double R1 = fma(-gb.b, t.inv_dy, rpart.b);
-                const double R2 = fma(-gb.c, t.inv_dy, rpart.c);
-                const double R3 = fma(-gb.d, t.inv_dy, rpart.d);
+                const double R0 = fma(-gbd.a, t.inv_dy, rpart.a);
+                const double R1 = fma(-gbd.b, t.inv_dy, rpart.b);
+                const double R2 = fma(-gbd.c, t.inv_dy, rpart.c);
+                const double R3 = fma(-gbd.d, t.inv_dy, rpart.d);
                 const double rn = fma(fac, R0, pre.a);
-                qout[c] = rn;
-                qout[plane + c] = fma(fac, R1, pre.b);
-                qout[2 * plane + c] = fma(fac, R2, pre.c);
-                qout[3 * plane + c] = fma(t.beta, adt * R3, pre.d);
+                qout[c] = (S)rn;
+                qout[plane + c] = (S)fma(fac, R1, pre.b);
+                qout[2 * plane + c] = (S)fma(fac, R2, pre.c);
+                qout[3 * plane + c] = (S)fma(t.beta, adt * R3, pre.d);
                 const double rp = t.beta * R3;
                 if (NORM_MAX) {
                     part0 = combine<true>(part0, fabs(R0));
@@ -253,44 +366,51 @@ __global__ void __launch_bounds__(kLanes *kWavesPerBlock, WAVES)
                     part2 = fma(R2, R2, part2);
                     part3 = fma(rp, rp, part3);
                 }
-                part4 += (rn > 0.0 && rn < INFINITY) ? 0.0 : 1.0;
+                const double rho_new = P::kMixed ? lvl + rn : rn;
+                part4 += (rho_new > 0.0 && rho_new < INFINITY) ? 0.0 : 1.0;
             } else {
                 // fac and adt already carry 1/dy here
-                qout[c] = fma(-fac, gb.a, pre.a);
-                qout[plane + c] = fma(-fac, gb.b, pre.b);
-                qout[2 * plane + c] = fma(-fac, gb.c, pre.c);
-                qout[3 * plane + c] = fma(-adt, gb.d, pre.d);
+                qout[c] = (S)fma(-fac, gbd.a, pre.a);
+                qout[plane + c] = (S)fma(-fac, gbd.b, pre.b);
+                qout[2 * plane + c] = (S)fma(-fac, gbd.c, pre.c);
+                qout[3 * plane + c] = (S)fma(-adt, gbd.d, pre.d);
             }
         }
 
         // ---- x-faces of row r and its residual without the upper y-face ------------------
         Vec4<double> rp4 = zero4<double>();
         if (r >= j0 && r < j1) {
-            const Prim<double> sxl = state_at(mid, rec.gx, px, -t.half_dx);
-            const Prim<double> partner = prim_from_right(sxl);  // right neighbour's left state
-            Vec4<double> fr = zero4<double>();
+            const Prim<R> sxl = state_at(mid, rec.gx, px, -hx, pb_xl);
+            const Prim<R> partner = prim_from_right(sxl);  // right neighbour's left state
+            Vec4<R> fr = zero4<R>();
             if (fluid) {
-                const Prim<double> R = (f & FLAG_WALL_XP) ? ghost_state(t, rec, 0, +1, slip) : partner;
-                fr = osher_x(state_at(mid, rec.gx, px, t.half_dx), R, t.beta, t.inv_beta);
+                const Prim<R> Rs = (f & FLAG_WALL_XP) ? ghost_state(t, rec, 0, +1, slip, pb_own)
+                                                      : partner;
+                fr = osher_x(state_at(mid, rec.gx, px, hx, pb_own), Rs, beta, inv_beta);
             }
-            Vec4<double> fl = {from_left(fr.a), from_left(fr.b), from_left(fr.c), from_left(fr.d)};
+            Vec4<R> fl = {from_left(fr.a), from_left(fr.b), from_left(fr.c), from_left(fr.d)};
             if (fluid && (f & FLAG_WALL_XM))
-                fl = osher_x(ghost_state(t, rec, 0, -1, slip), sxl, t.beta, t.inv_beta);
+                fl = osher_x(ghost_state(t, rec, 0, -1, slip, pb_own), sxl, beta, inv_beta);
+            const Vec4<double> frd = cast4<double>(fr), fld = cast4<double>(fl);
             // -(x-divergence) + lower flux / dy - real-time term + body force
-            rp4.a = fma(gb.a, t.inv_dy, -((fr.a - fl.a) * t.inv_dx)) - rec.d_r;
-            rp4.b = fma(gb.b, t.inv_dy, -((fr.b - fl.b) * t.inv_dx)) + fma(z.a, t.gx, -rec.d_ru);
-            rp4.c = fma(gb.c, t.inv_dy, -((fr.c - fl.c) * t.inv_dx)) + fma(z.a, t.gy, -rec.d_rv);
-            rp4.d = fma(gb.d, t.inv_dy, -((fr.d - fl.d) * t.inv_dx));
+            rp4.a = fma(gbd.a, t.inv_dy, -((frd.a - fld.a) * t.inv_dx)) - d_r;
+            rp4.b = fma(gbd.b, t.inv_dy, -((frd.b - fld.b) * t.inv_dx)) + fma(a0, t.gx, -d_ru);
+            rp4.c = fma(gbd.c, t.inv_dy, -((frd.c - fld.c) * t.inv_dx)) + fma(a0, t.gy, -d_rv);
+            rp4.d = fma(gbd.d, t.inv_dy, -((frd.d - fld.d) * t.inv_dx));
+            if constexpr (P::kMixed) {
+                rp4.b = fma(-sx, t.inv_dx, rp4.b);
+                rp4.c = fma(-sy, t.inv_dy, rp4.c);
+            }
         }
 
         // ---- carries of row r -------------------------------------------------------------
-        const Prim<double> syt = state_at(mid, rec.gy, py, t.half_dy);
+        const Prim<R> syt = state_at(mid, rec.gy, py, hy, pb_own);
         if (fluid && (f & FLAG_WALL_YP) && r < j1)  // a wall above row r: that face's flux now
-            below = osher_y(syt, ghost_state(t, rec, 1, +1, slip), t.beta, t.inv_beta);
+            below = osher_y(syt, ghost_state(t, rec, 1, +1, slip, pb_own), beta, inv_beta);
         else
             below = {syt.r, syt.u, syt.v, syt.p};
         if (fluid && r >= j0 && r < j1) {
-            const double dtau = local_dtau(t, t.cfl, z.a, z.b, z.c);
+            const double dtau = local_dtau(t, t.cfl, a0, a1, a2);
             const double ad = alpha * dtau;
             const double fc = ad / (1.0 + sp.b0 * ad * sp.inv_dt);
             if (LAST) {
@@ -298,6 +418,7 @@ __global__ void __launch_bounds__(kLanes *kWavesPerBlock, WAVES)
                 rpart = rp4;
                 fac = fc;
                 adt = ad;
+                lvl = lvl_r;
             } else {
                 pre = {fma(fc, rp4.a, z.a), fma(fc, rp4.b, z.b), fma(fc, rp4.c, z.c),
                        fma(t.beta * ad, rp4.d, z.d)};
@@ -309,10 +430,13 @@ __global__ void __launch_bounds__(kLanes *kWavesPerBlock, WAVES)
         lo = mid;
         mid = hi;
         hi = next_hi;
+        plo = pmid;
+        pmid = phi;
+        phi = next_phi;
     }
 
     if (LAST) {
-        // wave reduction (fixed order) and one partial per strip chunk
+        // wave reduction (fixed order) and one partial per unit
         const double part[kPartialWidth] = {part0, part1, part2, part3, part4};
 #pragma unroll
         for (int k = 0; k < kPartialWidth; ++k) {
@@ -322,53 +446,57 @@ __global__ void __launch_bounds__(kLanes *kWavesPerBlock, WAVES)
                 const double y = __shfl_xor(x, off, kLanes);
                 x = (NORM_MAX && k < 4) ? combine<true>(x, y) : x + y;
             }
-            if (lane == 0) t.partials[(size_t)unit * kPartialWidth + k] = x;
+            if (lane == 0) t.partials[(size_t)un.local * kPartialWidth + k] = x;
         }
+    }
+}
+
+template <class P, bool NM, bool B2, bool LS>
+void launch_march_t(const TankDev *tanks, const MarchUnit *units, dim3 g, dim3 b, int waves_simd,
+                    const Scheme &sc, int stage, hipStream_t s)
+{
+    if (waves_simd == 3)
+        hipLaunchKernelGGL((stage_march<P, NM, B2, LS, 3>), g, b, 0, s, tanks, units, sc, stage);
+    else
+        hipLaunchKernelGGL((stage_march<P, NM, B2, LS, 2>), g, b, 0, s, tanks, units, sc, stage);
+}
+
+template <class P>
+void launch_march_p(const TankDev *tanks, const MarchUnit *units, dim3 g, dim3 b, int waves_simd,
+                    const Scheme &sc, int stage, hipStream_t s)
+{
+    const bool last = stage == sc.smax;
+    const bool bdf2 = sc.bdf2 != 0;
+    if (last) {
+        if (sc.norm_max) {
+            if (bdf2) launch_march_t<P, true, true, true>(tanks, units, g, b, waves_simd, sc, stage, s);
+            else launch_march_t<P, true, false, true>(tanks, units, g, b, waves_simd, sc, stage, s);
+        } else {
+            if (bdf2) launch_march_t<P, false, true, true>(tanks, units, g, b, waves_simd, sc, stage, s);
+            else launch_march_t<P, false, false, true>(tanks, units, g, b, waves_simd, sc, stage, s);
+        }
+    } else {
+        if (bdf2) launch_march_t<P, false, true, false>(tanks, units, g, b, waves_simd, sc, stage, s);
+        else launch_march_t<P, false, false, false>(tanks, units, g, b, waves_simd, sc, stage, s);
     }
 }
 
 }  // namespace
 
-int march_units(const TankDev &t, int chunk)
-{
-    const int n_strips = (t.nx + kOut - 1) / kOut;
-    const int n_chunks = (t.ny + chunk - 1) / chunk;
-    return n_strips * n_chunks;
-}
+int march_strips(int nx) { return (nx + kOut - 1) / kOut; }
 
-int launch_stage_march_f64(const TankDev &t, const Scheme &sc, int stage, int chunk, int waves,
-                           void *stream)
+int launch_stage_march(const TankDev *tanks_dev, const MarchUnit *units, int n_entries,
+                       int waves_per_block, const Scheme &sc, int stage, int waves_simd,
+                       void *stream)
 {
-    const int n_strips = (t.nx + kOut - 1) / kOut;
-    const int n_units = march_units(t, chunk);
-    const int n_blocks = (n_units + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int grid = ((n_blocks + 7) / 8) * 8;
-    const dim3 g(grid), b(kLanes * kWavesPerBlock);
+    if (waves_per_block < 1 || waves_per_block > kMaxWavesPerBlock || n_entries % waves_per_block)
+        return (int)hipErrorInvalidValue;
+    const dim3 g(n_entries / waves_per_block), b(kLanes * waves_per_block);
     hipStream_t s = (hipStream_t)stream;
-    const bool bdf2 = t.level_nm1 != nullptr;
-    const bool last = stage == sc.smax;
-#define VDAC_MARCH(NM, B2, LS)                                                                       \
-    do {                                                                                             \
-        if (waves == 3)                                                                              \
-            hipLaunchKernelGGL((stage_march_f64<NM, B2, LS, 3>), g, b, 0, s, t, sc, stage, chunk,    \
-                               n_strips, n_units);                                                   \
-        else                                                                                         \
-            hipLaunchKernelGGL((stage_march_f64<NM, B2, LS, 2>), g, b, 0, s, t, sc, stage, chunk,    \
-                               n_strips, n_units);                                                   \
-    } while (0)
-    if (last) {
-        if (sc.norm_max) {
-            if (bdf2) VDAC_MARCH(true, true, true);
-            else VDAC_MARCH(true, false, true);
-        } else {
-            if (bdf2) VDAC_MARCH(false, true, true);
-            else VDAC_MARCH(false, false, true);
-        }
-    } else {
-        if (bdf2) VDAC_MARCH(false, true, false);
-        else VDAC_MARCH(false, false, false);
-    }
-#undef VDAC_MARCH
+    if (sc.mixed)
+        launch_march_p<PrecMixed>(tanks_dev, units, g, b, waves_simd, sc, stage, s);
+    else
+        launch_march_p<PrecF64>(tanks_dev, units, g, b, waves_simd, sc, stage, s);
     return (int)hipGetLastError();
 }
 

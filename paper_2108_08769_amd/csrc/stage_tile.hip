@@ -124,9 +124,9 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
 
     const int cur = st->cur;
     const StageBuffers bufs = stage_buffers(cur, stage);
-    const double *qprev = t.state[bufs.in];
-    const double *q0 = t.state[cur];
-    double *qout = t.state[bufs.out];
+    const double *qprev = (const double *)t.state[bufs.in];
+    const double *q0 = (const double *)t.state[cur];
+    double *qout = (double *)t.state[bufs.out];
     const StepParams sp = *t.step;
     const size_t plane = t.plane;
     const bool slip = sc.slip != 0;

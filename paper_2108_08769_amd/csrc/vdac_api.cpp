@@ -2,6 +2,7 @@
 // step driver (Algorithm 1) and the C ABI declared in include/vdac.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -41,13 +42,24 @@ struct TankLayout {
     size_t state[3], level_n, level_nm1, flags, partials, end;
 };
 
+enum Kind { KIND_DIRECT, KIND_TILE, KIND_MARCH };
+
+// Which stage kernel runs and how the work is cut, decided from the tanks and the options.
+struct Plan {
+    int kind;
+    int tile_x, tile_y;          // KIND_TILE
+    int waves_simd;              // KIND_MARCH: register budget, 2 or 3 waves per SIMD
+    int wpb;                     // KIND_MARCH: waves (table entries) per workgroup
+    int n_entries;               // KIND_MARCH: unit-table entries, padding included
+    std::vector<int> chunk;      // per tank, KIND_MARCH: rows per work unit
+    std::vector<int> n_partials; // per tank: residual partials per stage launch
+    size_t max_plane;
+};
+
 struct TankHost {
     vdac_tank desc;
     std::vector<uint8_t> flags;
     TankDev dev;
-    int tile_x, tile_y;  // stage kernel tile of this tank
-    int n_blocks;        // residual partials per stage launch
-    int hist_ok;  // level n-1 holds a real-time level (BDF2 may be used)
 };
 
 }  // namespace
@@ -56,13 +68,18 @@ struct vdac_grid {
     std::vector<TankHost> tanks;
     vdac_options opt;
     Scheme sc;
+    Plan plan;
     hipStream_t stream;
     char *ws;
     bool own_ws;
     size_t ws_bytes;
     Status *status_dev;                 // [n_tanks], contiguous
     StepParams *step_dev;
+    TankDev *tanks_dev;                 // [n_tanks]
+    MarchUnit *units_dev;               // [plan.n_entries] (row marching only)
+    double *staging;                    // [4][max_plane] (mixed form only)
     std::vector<Status> status_host;
+    int hist_ok;                        // every tank's level n-1 holds a real-time level
     // captured pseudo-iterations, keyed by the number of iterations per graph
     hipStream_t cap_stream;
     std::vector<std::pair<int, hipGraphExec_t>> graphs;
@@ -71,7 +88,7 @@ struct vdac_grid {
     std::vector<hipEvent_t> ev_pool;
     struct PendingTiming {
         int start, stop;  // indices into ev_pool, around one iteration's stage launches
-        int tank, iter;   // tank and pseudo-iteration (within the step)
+        int iter;         // pseudo-iteration (within the step)
     };
     std::vector<PendingTiming> ev_pending;
     double t_ms;
@@ -83,8 +100,8 @@ namespace {
 
 int check_options(const vdac_options *o)
 {
-    if (o->precision != VDAC_FP64)
-        return fail(VDAC_E_INVALID, "precision %d is not available", o->precision);
+    if (o->precision != VDAC_FP64 && o->precision != VDAC_FP32_MIXED)
+        return fail(VDAC_E_INVALID, "precision must be VDAC_FP64 or VDAC_FP32_MIXED (got %d)", o->precision);
     if (o->rk_stages < 1 || o->rk_stages > 8)
         return fail(VDAC_E_INVALID, "rk_stages must be 1..8 (got %d)", o->rk_stages);
     for (int s = 0; s < o->rk_stages; ++s)
@@ -113,6 +130,9 @@ int check_options(const vdac_options *o)
         return fail(VDAC_E_INVALID, "tile %d x %d is not available (0 x 0 = automatic, 1 x 1 = "
                     "one thread per cell, -W x L (W = 1..3) = row marching in chunks of L rows, or 32 x 8, "
                     "16 x 16, 64 x 4)", o->tile_x, o->tile_y);
+    if (o->precision == VDAC_FP32_MIXED && !auto_tile && !march)
+        return fail(VDAC_E_INVALID, "the mixed precision form runs the row-marching kernel only "
+                    "(tile 0 x 0 or -W x L)");
     return VDAC_OK;
 }
 
@@ -137,53 +157,137 @@ int check_tank(const vdac_tank *t, int idx)
     return VDAC_OK;
 }
 
-TankLayout layout_of(const vdac_tank *t, const vdac_options *o, int n_blocks)
+// Wave slots of the chip for the row-marching kernel: 256 CUs x 4 SIMDs x 2 waves.
+constexpr long kWaveSlots = 2048;
+
+Plan plan_for(const vdac_tank *tanks, int n_tanks, const vdac_options *o)
+{
+    Plan p;
+    p.tile_x = p.tile_y = 0;
+    p.waves_simd = 2;
+    p.wpb = 1;
+    p.n_entries = 0;
+    p.max_plane = 0;
+    for (int t = 0; t < n_tanks; ++t)
+        p.max_plane = std::max(p.max_plane, (size_t)tanks[t].nx * (size_t)tanks[t].ny);
+    p.chunk.assign(n_tanks, 0);
+    p.n_partials.assign(n_tanks, 0);
+    const bool auto_tile = o->tile_x == 0 && o->tile_y == 0;
+    if (o->tile_x == 1 && o->tile_y == 1) {
+        p.kind = KIND_DIRECT;
+        for (int t = 0; t < n_tanks; ++t) {
+            TankDev d;
+            d.nx = tanks[t].nx;
+            d.ny = tanks[t].ny;
+            p.n_partials[t] = direct_blocks(d);
+        }
+        return p;
+    }
+    if (o->tile_x > 0) {
+        p.kind = KIND_TILE;
+        p.tile_x = o->tile_x;
+        p.tile_y = o->tile_y;
+        for (int t = 0; t < n_tanks; ++t) {
+            TankDev d;
+            d.nx = tanks[t].nx;
+            d.ny = tanks[t].ny;
+            p.n_partials[t] = tile_count(d, o->tile_x, o->tile_y);
+        }
+        return p;
+    }
+    p.kind = KIND_MARCH;
+    int chunk;
+    if (auto_tile) {
+        // smallest chunk (at least 2 rows, at most 32) whose units fit the wave slots once
+        long strip_rows = 0;
+        for (int t = 0; t < n_tanks; ++t) strip_rows += (long)march_strips(tanks[t].nx) * tanks[t].ny;
+        long c = (strip_rows + kWaveSlots - 1) / kWaveSlots;
+        chunk = (int)std::min(32L, std::max(2L, c));
+    } else {
+        chunk = o->tile_y;
+        p.waves_simd = (o->tile_x == -3) ? 3 : 2;
+    }
+    long units = 0;
+    for (int t = 0; t < n_tanks; ++t) {
+        p.chunk[t] = std::min(chunk, tanks[t].ny);
+        const int n_chunks = (tanks[t].ny + p.chunk[t] - 1) / p.chunk[t];
+        p.n_partials[t] = march_strips(tanks[t].nx) * n_chunks;
+        units += p.n_partials[t];
+    }
+    p.wpb = units >= 2 * kWaveSlots ? 4 : 1;
+    const long blocks = (units + p.wpb - 1) / p.wpb;
+    p.n_entries = (int)(((blocks + 7) / 8) * 8 * p.wpb);
+    return p;
+}
+
+// Unit table of the row-marching kernel: workgroup b runs on XCD b % 8; XCD x receives the x-th
+// eighth of the units in their natural order (tank, row chunk, strip), so that neighbouring
+// strips and chunks share an L2.
+std::vector<MarchUnit> unit_table(const Plan &p, const vdac_tank *tanks, int n_tanks)
+{
+    std::vector<MarchUnit> nat;
+    for (int t = 0; t < n_tanks; ++t)
+        for (int l = 0; l < p.n_partials[t]; ++l) nat.push_back({t, l});
+    std::vector<MarchUnit> tab(p.n_entries, MarchUnit{-1, 0});
+    const int nb = p.n_entries / p.wpb;
+    const int per = nb / 8;  // workgroups per XCD
+    for (int b = 0; b < nb; ++b) {
+        const int x = b % 8, k = b / 8;
+        for (int w = 0; w < p.wpb; ++w) {
+            const size_t u = (size_t)x * per * p.wpb + (size_t)k * p.wpb + w;
+            if (u < nat.size()) tab[(size_t)b * p.wpb + w] = nat[u];
+        }
+    }
+    (void)tanks;
+    return tab;
+}
+
+size_t elem_bytes(const vdac_options *o) { return o->precision == VDAC_FP32_MIXED ? 4 : 8; }
+
+TankLayout layout_of(const vdac_tank *t, const vdac_options *o, int n_partials)
 {
     const size_t plane = (size_t)t->nx * (size_t)t->ny;
     TankLayout L;
     size_t off = 0;
     for (int b = 0; b < 3; ++b) {
         L.state[b] = off;
-        off += align256(4 * plane * sizeof(double));
+        off += align256(4 * plane * elem_bytes(o));
     }
     L.level_n = off;
-    off += align256(3 * plane * sizeof(double));
+    off += align256((o->precision == VDAC_FP32_MIXED ? 4 : 3) * plane * sizeof(double));
     L.level_nm1 = off;
     if (o->bdf_order == 2) off += align256(3 * plane * sizeof(double));
     L.flags = off;
     off += align256(plane);
     L.partials = off;
-    off += align256((size_t)n_blocks * kPartialWidth * sizeof(double));
+    off += align256((size_t)n_partials * kPartialWidth * sizeof(double));
     L.end = off;
     return L;
 }
 
-// Grid-level block after the tanks: every tank's Status (contiguous, so one copy reads them all)
-// and the shared StepParams.
-size_t grid_block_bytes(int n_tanks)
-{
-    return align256((size_t)n_tanks * sizeof(Status)) + align256(sizeof(StepParams));
-}
+// Grid-level block after the tanks: every tank's Status (contiguous, so one copy reads them all),
+// the shared StepParams, the device copy of the tank descriptors, the unit table, and the
+// staging buffer of the mixed form's state conversions.
+struct GridBlock {
+    size_t status, step, tanks, units, staging, end;
+};
 
-void tile_for(const vdac_tank *, const vdac_options *o, int *tx, int *ty)
+GridBlock grid_block(int n_tanks, const Plan &p, const vdac_options *o)
 {
-    if (o->tile_x == 0 && o->tile_y == 0) {
-        *tx = kDefaultTileX;
-        *ty = kDefaultTileY;
-    } else {
-        *tx = o->tile_x;
-        *ty = o->tile_y;
-    }
-}
-
-int blocks_for(const vdac_tank *t, const vdac_options *o)
-{
-    TankDev d;
-    d.nx = t->nx;
-    d.ny = t->ny;
-    int tx, ty;
-    tile_for(t, o, &tx, &ty);
-    return stage_blocks(d, tx, ty);
+    GridBlock B;
+    size_t off = 0;
+    B.status = off;
+    off += align256((size_t)n_tanks * sizeof(Status));
+    B.step = off;
+    off += align256(sizeof(StepParams));
+    B.tanks = off;
+    off += align256((size_t)n_tanks * sizeof(TankDev));
+    B.units = off;
+    off += align256((size_t)p.n_entries * sizeof(MarchUnit));
+    B.staging = off;
+    if (o->precision == VDAC_FP32_MIXED) off += align256(4 * p.max_plane * sizeof(double));
+    B.end = off;
+    return B;
 }
 
 void build_flags(const vdac_tank *t, std::vector<uint8_t> &flags, int *n_fluid)
@@ -261,25 +365,57 @@ hipEvent_t pool_event(vdac_grid *g, size_t idx)
     return g->ev_pool[idx];
 }
 
-// Collects the elapsed time of every bracketed stage launch of the finished step.
+// Collects the elapsed time of every bracketed pseudo-iteration of the finished step.  An
+// iteration counts if some tank was still running in it; its launches and cell-stages count the
+// tanks that were.
 int collect_timing(vdac_grid *g, const std::vector<int> &iters_before, const std::vector<int> &iters_after)
 {
+    const size_t nt = g->tanks.size();
     for (auto &pr : g->ev_pending) {
-        // iterations after the tank stopped returned at once: they count neither time nor cells
-        if (pr.iter >= iters_after[pr.tank] - iters_before[pr.tank]) continue;
+        int active = 0;
+        double cells = 0.0;
+        for (size_t t = 0; t < nt; ++t)
+            if (pr.iter < iters_after[t] - iters_before[t]) {
+                ++active;
+                cells += g->tanks[t].dev.n_fluid;
+            }
+        if (active == 0) continue;
         hipError_t e = hipEventSynchronize(g->ev_pool[pr.stop]);
         if (e != hipSuccess) return hip_fail(e, "stage timing");
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, g->ev_pool[pr.start], g->ev_pool[pr.stop]);
         if (e != hipSuccess) return hip_fail(e, "stage timing");
         g->t_ms += ms;  // s_max back-to-back stage launches
+        g->t_launches += (int64_t)g->sc.smax * (g->plan.kind == KIND_MARCH ? 1 : active);
+        g->t_cell_stages += cells * g->sc.smax;
     }
     g->ev_pending.clear();
-    for (size_t t = 0; t < g->tanks.size(); ++t) {
-        const int n = iters_after[t] - iters_before[t];
-        g->t_launches += (int64_t)n * g->sc.smax;
-        g->t_cell_stages += (double)n * g->sc.smax * g->tanks[t].dev.n_fluid;
+    return VDAC_OK;
+}
+
+// Uploads an FP64 state [4][plane] into tank t: plain copies into the three state buffers and
+// level n (FP64 form), or through the staging buffer and the import kernel (mixed form).
+int upload_state(vdac_grid *g, int t, const double *q)
+{
+    const TankDev &d = g->tanks[t].dev;
+    hipError_t e = hipSuccess;
+    if (g->sc.mixed) {
+        e = hipMemcpyAsync(g->staging, q, 4 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
+        if (e == hipSuccess) e = (hipError_t)launch_import_mixed(d, g->staging, g->stream);
+    } else {
+        for (int b = 0; b < 3 && e == hipSuccess; ++b)
+            e = hipMemcpyAsync(d.state[b], q, 4 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d.level_n, q, 3 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
+        if (e == hipSuccess && d.level_nm1)
+            e = hipMemcpyAsync(d.level_nm1, q, 3 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
     }
+    Status st;
+    std::memset(&st, 0, sizeof st);
+    st.done = 1;  // cur = 0
+    if (e == hipSuccess) e = hipMemcpyAsync(d.status, &st, sizeof st, hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "uploading the state");
     return VDAC_OK;
 }
 
@@ -313,12 +449,12 @@ size_t workspace_bytes(const vdac_tank *tanks, int32_t n_tanks, const vdac_optio
         o = &def;
     }
     if (!tanks || n_tanks < 1 || check_options(o) != VDAC_OK) return 0;
-    size_t total = 0;
-    for (int t = 0; t < n_tanks; ++t) {
+    for (int t = 0; t < n_tanks; ++t)
         if (check_tank(&tanks[t], t) != VDAC_OK) return 0;
-        total += layout_of(&tanks[t], o, blocks_for(&tanks[t], o)).end;
-    }
-    return total + grid_block_bytes(n_tanks);
+    const Plan p = plan_for(tanks, n_tanks, o);
+    size_t total = 0;
+    for (int t = 0; t < n_tanks; ++t) total += layout_of(&tanks[t], o, p.n_partials[t]).end;
+    return total + grid_block(n_tanks, p, o).end;
 }
 
 int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
@@ -342,7 +478,9 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
     vdac_grid *g = new (std::nothrow) vdac_grid();
     if (!g) return fail(VDAC_E_NOMEM, "host allocation failed");
     g->opt = *o;
+    g->plan = plan_for(tanks, n_tanks, o);
     g->stream = (hipStream_t)hip_stream;
+    g->cap_stream = nullptr;
     if (device_workspace) {
         if (ws_bytes < need) {
             delete g;
@@ -374,29 +512,33 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
     sc.slip = o->wall_slip;
     sc.norm_max = (o->norm == VDAC_NORM_MAX);
     sc.bdf2 = (o->bdf_order == 2);
+    sc.mixed = (o->precision == VDAC_FP32_MIXED);
 
+    const Plan &pl = g->plan;
     g->tanks.resize(n_tanks);
     g->status_host.assign(n_tanks, Status());
-    g->cap_stream = nullptr;
+    g->hist_ok = 0;
     g->timing = false;
     g->t_ms = 0.0;
     g->t_launches = 0;
     g->t_cell_stages = 0.0;
     size_t base = 0;
-    for (int t = 0; t < n_tanks; ++t) base += layout_of(&tanks[t], o, blocks_for(&tanks[t], o)).end;
-    g->status_dev = (Status *)(g->ws + base);
-    g->step_dev = (StepParams *)(g->ws + base + align256((size_t)n_tanks * sizeof(Status)));
+    for (int t = 0; t < n_tanks; ++t) base += layout_of(&tanks[t], o, pl.n_partials[t]).end;
+    const GridBlock B = grid_block(n_tanks, pl, o);
+    g->status_dev = (Status *)(g->ws + base + B.status);
+    g->step_dev = (StepParams *)(g->ws + base + B.step);
+    g->tanks_dev = (TankDev *)(g->ws + base + B.tanks);
+    g->units_dev = (MarchUnit *)(g->ws + base + B.units);
+    g->staging = sc.mixed ? (double *)(g->ws + base + B.staging) : nullptr;
     base = 0;
+    std::vector<TankDev> devs(n_tanks);
     for (int t = 0; t < n_tanks; ++t) {
         TankHost &th = g->tanks[t];
         th.desc = tanks[t];
         th.desc.solid = nullptr;
-        tile_for(&tanks[t], o, &th.tile_x, &th.tile_y);
-        th.n_blocks = blocks_for(&tanks[t], o);
-        th.hist_ok = 0;
         int n_fluid = 0;
         build_flags(&tanks[t], th.flags, &n_fluid);
-        const TankLayout L = layout_of(&tanks[t], o, th.n_blocks);
+        const TankLayout L = layout_of(&tanks[t], o, pl.n_partials[t]);
         TankDev &d = th.dev;
         std::memset(&d, 0, sizeof d);
         d.nx = tanks[t].nx;
@@ -415,7 +557,7 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         d.inv_beta = 1.0 / tanks[t].beta;
         d.cfl = o->cfl_tau;
         d.plane = (size_t)d.nx * d.ny;
-        for (int b = 0; b < 3; ++b) d.state[b] = (double *)(g->ws + base + L.state[b]);
+        for (int b = 0; b < 3; ++b) d.state[b] = (void *)(g->ws + base + L.state[b]);
         d.level_n = (double *)(g->ws + base + L.level_n);
         d.level_nm1 = sc.bdf2 ? (double *)(g->ws + base + L.level_nm1) : nullptr;
         d.flags = (const uint8_t *)(g->ws + base + L.flags);
@@ -423,34 +565,39 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         d.status = g->status_dev + t;
         d.step = g->step_dev;
         d.n_fluid = n_fluid;
+        d.n_partials = pl.n_partials[t];
+        d.n_strips = march_strips(d.nx);
+        d.chunk = pl.chunk[t] > 0 ? pl.chunk[t] : 1;
+        devs[t] = d;
         base += L.end;
-
-        hipError_t e = hipMemcpyAsync((void *)d.flags, th.flags.data(), th.flags.size(),
-                                      hipMemcpyHostToDevice, g->stream);
+    }
+    hipError_t e = hipMemcpyAsync(g->tanks_dev, devs.data(), devs.size() * sizeof(TankDev),
+                                  hipMemcpyHostToDevice, g->stream);
+    std::vector<MarchUnit> tab;
+    if (e == hipSuccess && pl.kind == KIND_MARCH) {
+        tab = unit_table(pl, tanks, n_tanks);
+        e = hipMemcpyAsync(g->units_dev, tab.data(), tab.size() * sizeof(MarchUnit),
+                           hipMemcpyHostToDevice, g->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) {
+        destroy_grid(g);
+        return hip_fail(e, "uploading the tank descriptors");
+    }
+    for (int t = 0; t < n_tanks; ++t) {
+        TankHost &th = g->tanks[t];
+        e = hipMemcpyAsync((void *)th.dev.flags, th.flags.data(), th.flags.size(), hipMemcpyHostToDevice,
+                           g->stream);
         if (e != hipSuccess) {
             destroy_grid(g);
             return hip_fail(e, "uploading the cell flags");
         }
         // initial state: rho = 1, at rest, p = 0
-        std::vector<double> q(4 * d.plane, 0.0);
-        std::fill(q.begin(), q.begin() + d.plane, 1.0);
-        for (int b = 0; b < 3; ++b) {
-            e = hipMemcpyAsync(d.state[b], q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice,
-                               g->stream);
-            if (e != hipSuccess) break;
-        }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d.level_n, q.data(), 3 * d.plane * sizeof(double), hipMemcpyHostToDevice,
-                               g->stream);
-        Status st;
-        std::memset(&st, 0, sizeof st);
-        st.done = 1;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d.status, &st, sizeof st, hipMemcpyHostToDevice, g->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-        if (e != hipSuccess) {
+        std::vector<double> q(4 * th.dev.plane, 0.0);
+        std::fill(q.begin(), q.begin() + th.dev.plane, 1.0);
+        if ((rc = upload_state(g, t, q.data())) != VDAC_OK) {
             destroy_grid(g);
-            return hip_fail(e, "initialising the tank");
+            return rc;
         }
     }
     hipError_t ec = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
@@ -478,49 +625,50 @@ int set_state(vdac_grid *g, int32_t tank, const double *q)
             if (!std::isfinite(q[k * d.plane + c]))
                 return fail(VDAC_E_INVALID, "tank %d: non-finite value in field %d (cell %zu)", tank, k, c);
     }
-    hipError_t e = hipSuccess;
-    for (int b = 0; b < 3 && e == hipSuccess; ++b)
-        e = hipMemcpyAsync(d.state[b], q, 4 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d.level_n, q, 3 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
-    Status st;
-    std::memset(&st, 0, sizeof st);
-    st.done = 1;
-    if (e == hipSuccess) e = hipMemcpyAsync(d.status, &st, sizeof st, hipMemcpyHostToDevice, g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    if (e != hipSuccess) return hip_fail(e, "set_state");
-    th.hist_ok = 0;
+    const int rc = upload_state(g, tank, q);
+    if (rc != VDAC_OK) return rc;
+    g->hist_ok = 0;
     return VDAC_OK;
 }
 
 namespace {
 
-// One pseudo-iteration of every tank: s_max stage launches and the residual finalize.  With
-// timing on, an event pair brackets each tank's back-to-back stage launches.
+// One pseudo-iteration of every tank: s_max stage launches (one per stage for the whole grid
+// with the row-marching kernel, one per stage and tank otherwise) and the residual finalize of
+// all tanks.  With timing on, an event pair brackets each iteration's stage launches.
 int launch_iterations(vdac_grid *g, hipStream_t stream, int n_iter, int first_iter, size_t *ev_next)
 {
     const int nt = (int)g->tanks.size();
+    const Plan &pl = g->plan;
     int rc;
-    for (int it = 0; it < n_iter; ++it)
-        for (int t = 0; t < nt; ++t) {
-            const TankHost &th = g->tanks[t];
-            hipEvent_t e1 = nullptr;
-            if (ev_next) {
-                hipEvent_t e0 = pool_event(g, *ev_next);
-                e1 = pool_event(g, *ev_next + 1);
-                if (!e0 || !e1) return fail(VDAC_E_DEVICE, "creating timing events failed");
-                g->ev_pending.push_back({(int)*ev_next, (int)*ev_next + 1, t, first_iter + it});
-                *ev_next += 2;
-                (void)hipEventRecord(e0, stream);
+    for (int it = 0; it < n_iter; ++it) {
+        hipEvent_t e1 = nullptr;
+        if (ev_next) {
+            hipEvent_t e0 = pool_event(g, *ev_next);
+            e1 = pool_event(g, *ev_next + 1);
+            if (!e0 || !e1) return fail(VDAC_E_DEVICE, "creating timing events failed");
+            g->ev_pending.push_back({(int)*ev_next, (int)*ev_next + 1, first_iter + it});
+            *ev_next += 2;
+            (void)hipEventRecord(e0, stream);
+        }
+        for (int s = 1; s <= g->sc.smax; ++s) {
+            if (pl.kind == KIND_MARCH) {
+                rc = launch_stage_march(g->tanks_dev, g->units_dev, pl.n_entries, pl.wpb, g->sc, s,
+                                        pl.waves_simd, stream);
+                if (rc != 0) return hip_fail((hipError_t)rc, "stage launch");
+                continue;
             }
-            for (int s = 1; s <= g->sc.smax; ++s) {
-                rc = launch_stage(th.dev, g->sc, s, th.tile_x, th.tile_y, stream);
+            for (int t = 0; t < nt; ++t) {
+                const TankDev &d = g->tanks[t].dev;
+                rc = pl.kind == KIND_DIRECT ? launch_stage_direct_f64(d, g->sc, s, stream)
+                                            : launch_stage_tile_f64(d, g->sc, s, pl.tile_x, pl.tile_y, stream);
                 if (rc != 0) return hip_fail((hipError_t)rc, "stage launch");
             }
-            if (e1) (void)hipEventRecord(e1, stream);
-            rc = launch_finalize(th.dev, g->sc, th.n_blocks, stream);
-            if (rc != 0) return hip_fail((hipError_t)rc, "finalize launch");
         }
+        if (e1) (void)hipEventRecord(e1, stream);
+        rc = launch_finalize_all(g->tanks_dev, nt, g->sc, stream);
+        if (rc != 0) return hip_fail((hipError_t)rc, "finalize launch");
+    }
     return VDAC_OK;
 }
 
@@ -562,11 +710,16 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
     if (std::isnan(tol)) return fail(VDAC_E_INVALID, "tol is NaN");
     const int nt = (int)g->tanks.size();
     int rc;
-    for (int t = 0; t < nt; ++t) {
-        TankHost &th = g->tanks[t];
-        rc = launch_begin_step(th.dev, g->sc, dt, max_pseudo, tol, g->sc.bdf2 && th.hist_ok, g->stream);
-        if (rc != 0) return hip_fail((hipError_t)rc, "begin_step launch");
-    }
+    // Table 1: backward Euler, or BDF2 once level n-1 holds a real-time level
+    const int use_history = g->sc.bdf2 && g->hist_ok;
+    StepParams sp;
+    sp.inv_dt = 1.0 / dt;
+    sp.b0 = use_history ? 1.5 : 1.0;
+    sp.b1 = use_history ? -2.0 : -1.0;
+    sp.b2 = use_history ? 0.5 : 0.0;
+    rc = launch_begin_step_all(g->tanks_dev, nt, g->plan.max_plane, g->sc, sp, max_pseudo, tol,
+                               use_history, g->stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "begin_step launch");
     std::vector<int> before(nt, 0);
     // iterations per launch group: with a tolerance, the host checks the stop flags after each
     // group (the kernels of stopped tanks return at once); without, groups cover max_pseudo.
@@ -608,8 +761,8 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
         if (pseudo_done) pseudo_done[t] = st.iters;
         if (st.diverged && status == VDAC_OK)
             status = fail(VDAC_E_DIVERGED, "tank %d diverged at pseudo-iteration %d", t, st.iters);
-        g->tanks[t].hist_ok = 1;
     }
+    g->hist_ok = 1;
     if (g->timing && (rc = collect_timing(g, before, after)) != VDAC_OK) return rc;
     return status;
 }
@@ -657,8 +810,15 @@ int get_state(const vdac_grid *g, int32_t tank, double *q)
     int rc = read_status(g, tank, &st);
     if (rc != VDAC_OK) return rc;
     const TankDev &d = g->tanks[tank].dev;
-    hipError_t e = hipMemcpyAsync(q, d.state[st.cur], 4 * d.plane * sizeof(double), hipMemcpyDeviceToHost,
-                                  g->stream);
+    hipError_t e;
+    if (g->sc.mixed) {
+        e = (hipError_t)launch_export_mixed(d, st.cur, g->staging, g->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(q, g->staging, 4 * d.plane * sizeof(double), hipMemcpyDeviceToHost, g->stream);
+    } else {
+        e = hipMemcpyAsync(q, d.state[st.cur], 4 * d.plane * sizeof(double), hipMemcpyDeviceToHost,
+                           g->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "get_state");
     return VDAC_OK;

@@ -1,13 +1,16 @@
 // vdac_internal.h -- structures shared by the host driver and the HIP kernels of libvdac.
 //
 // Device memory of one tank (all planes x-fastest, 256-byte aligned):
-//   state[3]   three rotating state buffers, 4 planes each: rho, rho*u, rho*v, p.  The current
-//              state, the stage-0 state of the running pseudo-iteration and the stage outputs
-//              rotate among them (see stage_buffers below), so no state is ever copied.
-//   level_n    3 planes (rho, rho*u, rho*v) of real-time level n; level_nm1 the same for BDF2.
+//   state[3]   three rotating state buffers, 4 planes each.  FP64 form: rho, rho*u, rho*v, p in
+//              FP64.  Mixed form: FP32 deviations rho - rho^n, rho*u - (rho*u)^n,
+//              rho*v - (rho*v)^n, p - p^n from real-time level n.  The current state, the
+//              stage-0 state of the running pseudo-iteration and the stage outputs rotate among
+//              them (see stage_buffers below), so no state is ever copied.
+//   level_n    real-time level n in FP64: 3 planes (rho, rho*u, rho*v) in the FP64 form, 4 (and
+//              p) in the mixed form; level_nm1 3 planes for BDF2.
 //   flags      one byte per cell: which faces are walls (domain wall or solid neighbour) and
 //              whether the cell itself is solid.
-//   partials   per-workgroup residual partial sums of the last Runge-Kutta stage.
+//   partials   per-work-unit residual partial sums of the last Runge-Kutta stage.
 //   status     pseudo-loop control of the tank (iteration count, stop flags, norms).
 #pragma once
 
@@ -73,14 +76,24 @@ struct TankDev {
     double beta, inv_beta;
     double cfl;
     size_t plane;             // nx*ny
-    double *state[3];         // 4 planes each
-    double *level_n;          // 3 planes
+    void *state[3];           // 4 planes each (double, or float in the mixed form)
+    double *level_n;          // 3 planes (4 in the mixed form)
     double *level_nm1;        // 3 planes (BDF2) or nullptr
     const uint8_t *flags;
-    double *partials;         // [n_blocks][kPartialWidth]
+    double *partials;         // [n_partials][kPartialWidth]
     Status *status;
     const StepParams *step;
     int32_t n_fluid;
+    int32_t n_partials;       // residual partials one stage launch writes for this tank
+    int32_t n_strips;         // row-marching kernel: 64-column strips across the tank
+    int32_t chunk;            // row-marching kernel: rows per work unit
+};
+
+// One wave's work in the row-marching kernel: rows [chunk*c, chunk*(c+1)) of strip s of a tank,
+// with local = c * n_strips + s.  tank < 0 marks padding.
+struct MarchUnit {
+    int32_t tank;
+    int32_t local;
 };
 
 // Scheme settings common to all tanks of a grid.
@@ -91,26 +104,34 @@ struct Scheme {
     int32_t slip;    // free-slip wall ghosts
     int32_t norm_max;
     int32_t bdf2;    // the grid keeps a level n-1 history
+    int32_t mixed;   // FP32 deviation storage and FP32 reconstruction / flux
 };
 
-// Launch wrappers.  All return hipError_t cast to int.  A stage launch with tile (1, 1) runs the
-// plain one-thread-per-cell kernel (kernels_f64.hip); tile (-W, L) with W = 1, 2 or 3 runs the
-// row-marching kernel (stage_march.hip) on 64-column strips swept in chunks of L rows, compiled
-// for W = 3 waves per SIMD (tighter register budget) or 2 otherwise; the supported 2D tiles run
-// the tiled kernel (stage_tile.hip).  stage_blocks() is the number of residual partials a stage
-// launch writes.
-int launch_begin_step(const TankDev &t, const Scheme &sc, double dt, int max_pseudo, double tol,
-                      int use_history, void *stream);
-int launch_stage(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
-                 void *stream);
+// Launch wrappers.  All return hipError_t cast to int.
+//
+// Per-tank launches (FP64 only): tile (1, 1) runs the plain one-thread-per-cell kernel
+// (kernels_f64.hip), the supported 2D tiles the LDS-tiled kernel (stage_tile.hip).  Grid-wide
+// launches: the row-marching kernel (stage_march.hip) runs every work unit of every tank from
+// the device unit table in one launch per stage, with `waves_per_block` table entries per
+// workgroup and a register budget of `waves_simd` (2 or 3) waves per SIMD; begin_step and
+// finalize cover all tanks in one launch each.
+// begin_step: use_history = 1 moves level n to level n-1 (BDF2 after a completed step); 0 sets
+// level n-1 (if kept) to the new level n.
+int launch_begin_step_all(const TankDev *tanks_dev, int n_tanks, size_t max_plane, const Scheme &sc,
+                          const StepParams &sp, int max_pseudo, double tol, int use_history,
+                          void *stream);
+int launch_finalize_all(const TankDev *tanks_dev, int n_tanks, const Scheme &sc, void *stream);
 int launch_stage_direct_f64(const TankDev &t, const Scheme &sc, int stage, void *stream);
 int launch_stage_tile_f64(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
                           void *stream);
-int launch_finalize(const TankDev &t, const Scheme &sc, int n_blocks, void *stream);
-int launch_stage_march_f64(const TankDev &t, const Scheme &sc, int stage, int chunk, int waves,
-                           void *stream);
-int march_units(const TankDev &t, int chunk);
-int stage_blocks(const TankDev &t, int tile_x, int tile_y);
+int launch_stage_march(const TankDev *tanks_dev, const MarchUnit *units, int n_entries,
+                       int waves_per_block, const Scheme &sc, int stage, int waves_simd,
+                       void *stream);
+// Conversions between the caller's FP64 conserved state [4][ny][nx] (rho, rho u, rho v, p) in
+// device memory and the mixed form's storage (cur = 0 after import).
+int launch_import_mixed(const TankDev &t, const double *q, void *stream);
+int launch_export_mixed(const TankDev &t, int cur, double *q, void *stream);
+int march_strips(int nx);
 int direct_blocks(const TankDev &t);
 int tile_count(const TankDev &t, int tile_x, int tile_y);
 bool tile_supported(int tile_x, int tile_y);

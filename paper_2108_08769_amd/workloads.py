@@ -119,11 +119,12 @@ SLOSH_SIDES = tuple(range(32, 257, 16))   # 32, 48, ..., 256 (15 values)
 
 def sloshing_ensemble(n_tanks: int = 512, seed: int = 4, h: float = 1.0 / 128.0,
                       precision: str = "mixed") -> Workload:
-    """Batched sloshing: independent tanks with sides drawn from {32, 48, ..., 256} (x first,
-    then y), density ratio log-uniform in [1.1, 1000], fill level uniform in [0.3, 0.7] and a
-    uniform initial horizontal velocity in [-0.5, 0.5]; cell size h, light rho = 1, heavy
-    rho = ratio below fill * height; beta = 1100, g = -9.81, dt = 1e-3, 10 steps x 50
-    pseudo-iterations."""
+    """Batched sloshing: independent closed tanks at rest with a tilted interface.  Per tank,
+    drawn in this order: sides nx, ny from {32, 48, ..., 256}, density ratio log-uniform in
+    [1.1, 1000], mean fill level uniform in [0.3, 0.7] of the height, and a tilt a uniform in
+    [-0.5, 0.5]: the heavy fluid (rho = ratio) lies below y = ly (fill + 0.2 a (2 x / lx - 1)),
+    the light fluid (rho = 1) above, so the interface is displaced by up to 0.1 ly at the side
+    walls.  Cell size h, beta = 1100, g = -9.81, dt = 1e-3, 10 steps x 50 pseudo-iterations."""
     rng = np.random.default_rng(seed)
     tanks = []
     for _ in range(n_tanks):
@@ -131,12 +132,12 @@ def sloshing_ensemble(n_tanks: int = 512, seed: int = 4, h: float = 1.0 / 128.0,
         ny = int(rng.choice(SLOSH_SIDES))
         ratio = float(math.exp(rng.uniform(math.log(1.1), math.log(1000.0))))
         fill = float(rng.uniform(0.3, 0.7))
-        u0 = float(rng.uniform(-0.5, 0.5))
+        tilt = float(rng.uniform(-0.5, 0.5))
         lx, ly = nx * h, ny * h
-        yc = _centres(ny, ly)
-        rho = np.where(yc < fill * ly, ratio, 1.0)[:, None] * np.ones((1, nx))
-        tanks.append(Tank(nx, ny, lx, ly, _state(rho, u=np.full((ny, nx), u0)), gy=-9.81,
-                          beta=1100.0))
+        xc, yc = _centres(nx, lx), _centres(ny, ly)
+        surface = ly * (fill + 0.2 * tilt * (2.0 * xc / lx - 1.0))
+        rho = np.where(yc[:, None] < surface[None, :], ratio, 1.0)
+        tanks.append(Tank(nx, ny, lx, ly, _state(rho), gy=-9.81, beta=1100.0))
     return Workload(f"sloshing_ensemble_{n_tanks}", tanks, dt=1e-3, steps=10, max_pseudo=50,
                     precision=precision)
 
