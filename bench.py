@@ -1,19 +1,29 @@
 """Benchmark: cell-updates per second per pseudo-time stage of the dual-time Godunov solver.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dam_break] [--precision f64]
+                    [--tile autotune|0x0|-WxL|TXxTY] [--unbatched] [--cpu-budget S]
 
 A step is one real-time step (Algorithm 1): level n <- state, then pseudo-iterations of
 s_max Runge-Kutta stages until the RMS residual is below the workload's tolerance or the
 iteration cap is reached.  The default workload is the 512 x 256 dam break (water column
 x < 1, y < 1 in a 4 x 2 walled tank, beta = 1100, dt = 1e-4, up to 100 pseudo-iterations to an
-RMS residual of 1e-6) in FP64, synthetic initial data.  The state stays resident in HBM for the
-whole timed region; nothing crosses PCIe inside it except the per-step status read.
+RMS residual of 1e-6) in FP64, synthetic initial data; other workloads: hydrostatic,
+rayleigh_taylor, obstacle_dam_break (4096 x 4096), sloshing_ensemble (512 tanks).  The
+stage-kernel shape comes from the library's autotuner (untimed, before the warmup).  The state
+stays resident in HBM for the whole timed region; nothing crosses PCIe inside it except the
+per-step status read.
 
-value = fluid cells x stages executed / seconds over exactly K timed steps.  The roofline entry
-is the Runge-Kutta stage kernel: algorithmic bytes per launch (109.3 B per fluid cell for FP64,
-the mean of 88 B at stage 1 and 120 B at later stages of a three-stage scheme) divided by its
-mean launch duration, measured with HIP events on the library's stream during the timed region.
-cpu_baseline times the serial FP64 oracle on a bounded sample of the same workload.
+value = fluid cells x stages executed / seconds over exactly K timed steps (kernels replayed
+from captured HIP graphs).  The roofline entry is the Runge-Kutta stage kernel: algorithmic
+bytes per launch (per fluid cell-stage 109.3 B for FP64, the mean of 88 B at stage 1 and 120 B
+at later stages of a three-stage scheme; 74.7 B for the mixed form, 64 and 80 B) divided by its
+mean launch duration.  That duration is measured live with HIP events on the library's stream,
+in a measurement pass of K further steps right after the timed region (kernels launched one by
+one, an event pair around each pseudo-iteration's s_max stage launches, so it includes the
+dispatch gaps between them).  traffic is the copy-calibrated FETCH_SIZE + WRITE_SIZE bytes per
+launch from the committed counter summaries in profiles/, reported only while the kernel
+sources still hash to what was profiled.  cpu_baseline times the serial FP64 oracle on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -31,6 +41,36 @@ BYTES_PER_CELL_STAGE = {       # algorithmic bytes per fluid cell per stage, thr
     "f64": (88.0 + 120.0 + 120.0) / 3.0,      # Q^{s-1} 32 + Q^0 32 + level n 24 + out 32
     "mixed": (64.0 + 80.0 + 80.0) / 3.0,      # deviations 16 + 16, level n 32, out 16
 }
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP/C++ sources of the library (the kernels a profile was taken of)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2108_08769_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: str, precision: str, tile: str):
+    """HBM bytes per stage launch from the committed counter summaries (profiles/*.md, copy-
+    calibrated FETCH_SIZE + WRITE_SIZE), or None if no summary covers this workload, precision and
+    tile or the kernel sources changed since it was taken."""
+    import glob
+    src = kernel_source_hash()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(f) as fh:
+            for line in fh:
+                if not line.startswith("traffic:"):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if (kv.get("workload") == workload and kv.get("precision") == precision
+                        and kv.get("tile") == tile and kv.get("source") == src):
+                    return float(kv["bytes_per_launch"])
+    return None
 
 
 def build_workload(name: str, precision: str):
@@ -81,7 +121,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--no-stage-timing", action="store_true")
-    ap.add_argument("--tile", default="0x0", help="stage kernel tile, e.g. 32x8 (0x0 = automatic)")
+    ap.add_argument("--tile", default="autotune",
+                    help="stage kernel shape: autotune (the library's autotuner), 0x0 (built-in "
+                         "heuristic), -WxL (row marching), or a 2D tile such as 3208x2")
     ap.add_argument("--max-pseudo", type=int, default=0,
                     help="override the workload's pseudo-iteration cap (short profiled runs)")
     ap.add_argument("--graph-iters", type=int, default=0,
@@ -89,6 +131,9 @@ def main():
     ap.add_argument("--unbatched", action="store_true",
                     help="one grid per tank, stepped one after the other (the baseline of the "
                          "batched form)")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only copy this many MiB device to device 20 times and print the rate "
+                         "(calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -100,15 +145,35 @@ def main():
     import torch
     from paper_2108_08769_amd import vdac
 
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * 2 ** 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"copy_probe_bytes_each_way": 4 * n, "copies": 20,
+                          "GB_per_s_read_plus_write": 2 * 4 * n * 20 / dt / 1e9}), flush=True)
+        return
+
     wk = build_workload(args.workload, args.precision)
     if args.max_pseudo > 0:
         wk.max_pseudo = args.max_pseudo
     tanks = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
                   solid=t.solid) for t in wk.tanks]
-    tile = tuple(int(v) for v in args.tile.lower().split("x"))
+    torch.cuda.set_device(0)
+    tune = args.tile == "autotune"
+    tile = (0, 0) if tune else tuple(int(v) for v in args.tile.lower().split("x"))
     opts = vdac.make_options(precision=wk.precision, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl,
                              k=wk.k, bdf=wk.bdf, tile=tile, graph_iters=args.graph_iters)
-    torch.cuda.set_device(0)
+    if tune and not args.unbatched:
+        # untimed: the tuner times each candidate shape on scratch grids of the same tanks
+        opts = vdac.autotune(tanks, opts, iters=5)
+    chosen = f"{opts.tile_x}x{opts.tile_y}"
     if args.unbatched:
         grids = [vdac.Grid([td], opts) for td in tanks]
         for g, t in zip(grids, wk.tanks):
@@ -163,8 +228,11 @@ def main():
             avg_s = kms / 1e3 / launches
             bytes_per_launch = bpc * kcs / launches
             achieved = bytes_per_launch / avg_s / 1e9
+            traffic = profiled_traffic(wk.name, wk.precision, chosen)
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": None if traffic is None else round(traffic / 1e9, 6),
+                        "traffic_unit": "GB per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)",
                         "kernel": "stage", "avg_launch_us": round(avg_s * 1e6, 3),
                         "launches": launches, "bytes_per_launch": bytes_per_launch}
     value = cell_stages / elapsed
@@ -184,7 +252,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if wk.precision == "f64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": wk.name, "cells": fluid, "precision": wk.precision, "tile": args.tile,
+        "config": {"workload": wk.name, "cells": fluid, "precision": wk.precision,
+                   "tile": chosen + (" (autotuned)" if tune and not args.unbatched else ""),
                    "tanks": len(wk.tanks), "batched": not args.unbatched,
                    "graph_iters": args.graph_iters,
                    "dt": wk.dt, "max_pseudo": wk.max_pseudo, "tol": wk.tol,

@@ -114,17 +114,30 @@ int residual_norm(const vdac_grid *g, int32_t tank, double out[4]);
 /* Copies one tank's state to the host array q [4][ny][nx] (rho, rho*u, rho*v, p). */
 int get_state(const vdac_grid *g, int32_t tank, double *q);
 
-/* Measurement: while enabled, step_dual_time brackets every Runge-Kutta stage kernel it
- * launches with a pair of HIP events on the grid's stream and accumulates their elapsed times;
- * enabling resets the totals.  The events add a marker on each side of each stage launch and
- * nothing else. */
+/* Measurement: while enabled, step_dual_time launches kernels one by one (no graphs) and
+ * brackets the s_max back-to-back Runge-Kutta stage launches of every pseudo-iteration with a
+ * pair of HIP events on the grid's stream, accumulating their elapsed times; enabling resets the
+ * totals.  The events add a marker before the first and after the last stage launch of each
+ * pseudo-iteration and nothing else. */
 int stage_timing(vdac_grid *g, int32_t enable);
 
 /* Totals since stage timing was enabled: summed stage-kernel milliseconds, number of stage
- * launches, and fluid cell-stages those launches updated (launches of tanks that had already
- * stopped count neither time nor cells).  Any output pointer may be NULL. */
+ * launches (a launch of the row-marching kernel covers every tank of the grid), and fluid
+ * cell-stages those launches updated (pseudo-iterations in which every tank had already stopped
+ * count neither time nor cells).  Any output pointer may be NULL. */
 int stage_timing_read(const vdac_grid *g, double *kernel_ms, int64_t *launches,
                       double *cell_stages);
+
+/* Autotuner of the stage-kernel shape.  For the tanks and options given (o's tile fields are
+ * ignored on input), builds a scratch grid per candidate shape -- row marching with chunks of
+ * 1..64 rows under a 2- and a 3-waves-per-SIMD register budget, and for a single FP64 tank also
+ * the 2D LDS tiles -- runs one untimed and one timed real step of `iters` pseudo-iterations
+ * (1..1000) from the initial rest state, and writes the shape with the least stage-kernel time
+ * into o->tile_x, o->tile_y.  The result is cached for the life of the process, keyed by
+ * precision, scheme and tank shapes, so later calls with the same key return at once.  Allocates
+ * and frees device memory and runs on hip_stream; the kernel time does not depend on the state. */
+int autotune_tile(const vdac_tank *tanks, int32_t n_tanks, vdac_options *o, void *hip_stream,
+                  int32_t iters);
 
 /* Frees the grid (and the device memory it allocated).  NULL is ignored. */
 void destroy_grid(vdac_grid *g);

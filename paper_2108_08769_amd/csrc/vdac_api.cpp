@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -821,6 +823,89 @@ int get_state(const vdac_grid *g, int32_t tank, double *q)
     }
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "get_state");
+    return VDAC_OK;
+}
+
+namespace {
+
+std::mutex g_tune_mutex;
+std::map<std::string, std::pair<int, int>> g_tune_cache;
+
+std::string tune_key(const vdac_tank *tanks, int n_tanks, const vdac_options *o)
+{
+    std::string k = std::to_string(o->precision) + "/" + std::to_string(o->rk_stages) + "/" +
+                    std::to_string(o->bdf_order) + "/" + std::to_string(o->norm) + "/" +
+                    std::to_string((int)o->limiter_k);
+    for (int t = 0; t < n_tanks; ++t)
+        k += ":" + std::to_string(tanks[t].nx) + "x" + std::to_string(tanks[t].ny) +
+             (tanks[t].bc[0] == VDAC_BC_PERIODIC ? "p" : "w") + (tanks[t].bc[2] == VDAC_BC_PERIODIC ? "p" : "w");
+    return k;
+}
+
+}  // namespace
+
+int autotune_tile(const vdac_tank *tanks, int32_t n_tanks, vdac_options *o, void *hip_stream,
+                  int32_t iters)
+{
+    g_error.clear();
+    if (!tanks || n_tanks < 1 || !o) return fail(VDAC_E_INVALID, "tanks or options missing");
+    if (iters < 1 || iters > 1000) return fail(VDAC_E_INVALID, "iters must lie in [1, 1000]");
+    vdac_options base = *o;
+    base.tile_x = base.tile_y = 0;
+    int rc = check_options(&base);
+    if (rc != VDAC_OK) return rc;
+    for (int t = 0; t < n_tanks; ++t)
+        if ((rc = check_tank(&tanks[t], t)) != VDAC_OK) return rc;
+    const std::string key = tune_key(tanks, n_tanks, &base);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            o->tile_x = it->second.first;
+            o->tile_y = it->second.second;
+            return VDAC_OK;
+        }
+    }
+    int max_ny = 1;
+    for (int t = 0; t < n_tanks; ++t) max_ny = std::max(max_ny, tanks[t].ny);
+    std::vector<std::pair<int, int>> cand;
+    const int chunks[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+    for (int w : {2, 3})
+        for (int c : chunks)
+            if (c == 1 || c / 2 < max_ny) cand.push_back({-w, c});
+    if (base.precision == VDAC_FP64 && n_tanks == 1)
+        for (auto tl : {std::pair<int, int>{3208, 2}, {1616, 2}, {32, 8}, {16, 16}}) cand.push_back(tl);
+
+    double best_ms = 0.0;
+    std::pair<int, int> best = {0, 0};
+    for (auto tl : cand) {
+        vdac_options oc = base;
+        oc.tile_x = tl.first;
+        oc.tile_y = tl.second;
+        oc.graph_iters = -1;
+        vdac_grid *g = nullptr;
+        rc = create_grid(tanks, n_tanks, &oc, nullptr, 0, hip_stream, &g);
+        if (rc != VDAC_OK) return rc;
+        // one untimed step (code load, caches), then one timed step of the stage kernels
+        rc = step_dual_time(g, 1e-3, iters, 0.0, nullptr);
+        if (rc == VDAC_OK) rc = stage_timing(g, 1);
+        if (rc == VDAC_OK) rc = step_dual_time(g, 1e-3, iters, 0.0, nullptr);
+        double ms = 0.0;
+        if (rc == VDAC_OK) rc = stage_timing_read(g, &ms, nullptr, nullptr);
+        destroy_grid(g);
+        if (rc != VDAC_OK) return rc;
+        if (best.first == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = tl;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        g_tune_cache[key] = best;
+    }
+    o->tile_x = best.first;
+    o->tile_y = best.second;
+    g_error.clear();
     return VDAC_OK;
 }
 

@@ -21,7 +21,7 @@ NORM_RMS, NORM_MAX = 0, 1
 
 EXPORTS = ("vdac_default_options", "workspace_bytes", "create_grid", "set_state",
            "step_dual_time", "residual_norm", "get_state", "stage_timing", "stage_timing_read",
-           "destroy_grid", "last_error")
+           "autotune_tile", "destroy_grid", "last_error")
 
 
 class VdacError(RuntimeError):
@@ -96,6 +96,9 @@ def lib():
         L.stage_timing.restype = ctypes.c_int
         L.stage_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp]
         L.stage_timing_read.restype = ctypes.c_int
+        L.autotune_tile.argtypes = [ctypes.POINTER(Tank), ctypes.c_int32, ctypes.POINTER(Options),
+                                    vp, ctypes.c_int32]
+        L.autotune_tile.restype = ctypes.c_int
         L.destroy_grid.argtypes = [vp]
         L.destroy_grid.restype = None
         L.last_error.argtypes = []
@@ -150,6 +153,27 @@ def make_tank(nx, ny, lx, ly, gx=0.0, gy=-9.81, beta=1000.0, bc=(0, 0, 0, 0), so
 def workspace_bytes(tanks, options: Options | None = None) -> int:
     arr = (Tank * len(tanks))(*tanks)
     return int(lib().workspace_bytes(arr, len(tanks), ctypes.byref(options) if options else None))
+
+
+def autotune(tanks, options: Options, iters: int = 5, device="cuda", stream=None) -> Options:
+    """Runs the library's tile autotuner for these tanks and options and returns a copy of the
+    options with the fastest stage-kernel shape filled in."""
+    import torch  # stream only
+    structs, keep = [], []
+    for t in tanks:
+        if isinstance(t, Tank):
+            structs.append(t)
+        else:
+            s, k = make_tank(**t)
+            structs.append(s)
+            keep.append(k)
+    arr = (Tank * len(structs))(*structs)
+    out = Options()
+    ctypes.pointer(out)[0] = options
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    _check(lib().autotune_tile(arr, len(structs), ctypes.byref(out), ctypes.c_void_p(st.cuda_stream),
+                               int(iters)))
+    return out
 
 
 class Grid:
