@@ -9,7 +9,7 @@
 // Each 64-lane wave owns a strip of 64 consecutive columns (lanes 2..61 produce output, lanes
 // 0-1 and 62-63 are the halo the reconstruction and the x-faces need) and sweeps its chunk of
 // rows upward.  The three rows the limited slopes need stay in registers, x-neighbours come from
-// cross-lane shuffles, and the loads of the next row are issued a full row ahead of their use.
+// cross-lane DPP moves, and the loads of the next row are issued a full row ahead of their use.
 // No LDS, no workgroup barrier.  Per row r the wave
 //   1. reconstructs row r once per lane: limited slopes (Sec. 2.3.1), the stage-0 sources from
 //      Q^0 and level n, the new pressure gradient (Sec. 2.3.2), and the states at the four faces;
@@ -55,10 +55,33 @@ __device__ __forceinline__ bool locate_axis(int g, int n, int periodic, int &out
     return true;
 }
 
-template <typename T>
-__device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, kLanes); }
-template <typename T>
-__device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, kLanes); }
+// Neighbour exchange across the wave with DPP moves (wave_shr:1 / wave_shl:1 shift a value one
+// lane up / down the whole 64-lane wave in one VALU instruction); the lane without a source
+// (lane 0, resp. 63, a halo lane) reads zero.
+constexpr int kDppWaveShr1 = 0x138, kDppWaveShl1 = 0x130;
+
+__device__ __forceinline__ float from_left(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kDppWaveShr1, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_right(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kDppWaveShl1, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double from_left(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, kDppWaveShr1, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), kDppWaveShr1, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double from_right(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, kDppWaveShl1, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), kDppWaveShl1, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 
 template <typename T>
 __device__ __forceinline__ Prim<T> prim_from_left(const Prim<T> &w)
@@ -88,7 +111,7 @@ struct InputLoad {
 template <class P>
 struct SourceLoad {
     typename P::Store z0, z1, z2, z3;  // stage-0 state Q^0 (mixed: deviations from level n)
-    double n0, n1, n2;                 // level n
+    double n0, n1, n2;                 // level n (FP64 form only)
     double m0, m1, m2;                 // level n-1 (BDF2 only)
     uint8_t f;                         // cell flags (FLAG_SOLID if outside the tank)
 };
@@ -143,9 +166,11 @@ __device__ __forceinline__ SourceLoad<P> load_sources(const TankDev &t,
         L.z1 = q0[plane + c];
         L.z2 = q0[2 * plane + c];
         L.z3 = q0[3 * plane + c];
-        L.n0 = t.level_n[c];
-        L.n1 = t.level_n[plane + c];
-        L.n2 = t.level_n[2 * plane + c];
+        if (!P::kMixed) {  // the mixed form takes level n from the input row (it carries it)
+            L.n0 = t.level_n[c];
+            L.n1 = t.level_n[plane + c];
+            L.n2 = t.level_n[2 * plane + c];
+        }
         if (BDF2) {
             L.m0 = t.level_nm1[c];
             L.m1 = t.level_nm1[plane + c];
@@ -219,8 +244,11 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
 
     // window of primitives: rows r-1 (lo), r (mid), r+1 (hi); loads for later rows in flight
     // (plo, pmid, phi: their absolute pressures in FP64)
+    // (mixed form: lvl_mid, lvl_hi carry level n of rho, rho u, rho v of rows r and r+1, which
+    // the input loads fetched, so that the sources need not fetch it again)
     Prim<R> lo, mid, hi;
     double plo, pmid, phi;
+    Vec4<double> lvl_mid = zero4<double>(), lvl_hi = zero4<double>();
     {
         const InputLoad<P> a = load_input<P>(t, qprev, have_col, gi, j0 - 2);
         const InputLoad<P> b = load_input<P>(t, qprev, have_col, gi, j0 - 1);
@@ -231,6 +259,10 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         plo = abs_p(a);
         pmid = abs_p(b);
         phi = abs_p(c);
+        if constexpr (P::kMixed) {
+            lvl_mid = {b.lr, b.lm, b.ln, 0.0};
+            lvl_hi = {c.lr, c.lm, c.ln, 0.0};
+        }
     }
     InputLoad<P> in_ld = load_input<P>(t, qprev, have_col, gi, j0 + 1);             // row r+2
     SourceLoad<P> src_ld = load_sources<P, BDF2>(t, q0, have_col, gi, j0 - 1);       // row r
@@ -256,19 +288,21 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         const Vec4<double> z = {(double)src_ld.z0, (double)src_ld.z1, (double)src_ld.z2,
                                 (double)src_ld.z3};
         double a0, a1, a2, num0, num1, num2;
+        double lvl_r;  // level-n density of row r
         if constexpr (P::kMixed) {
             // (B0 Q^0 + B1 Q^n + B2 Q^{n-1}) = B0 (Q^0 - Q^n) + B2 (Q^{n-1} - Q^n): B0+B1+B2 = 0
-            a0 = src_ld.n0 + z.a;
-            a1 = src_ld.n1 + z.b;
-            a2 = src_ld.n2 + z.c;
+            a0 = lvl_mid.a + z.a;
+            a1 = lvl_mid.b + z.b;
+            a2 = lvl_mid.c + z.c;
             num0 = sp.b0 * z.a;
             num1 = sp.b0 * z.b;
             num2 = sp.b0 * z.c;
             if (BDF2) {
-                num0 = fma(sp.b2, src_ld.m0 - src_ld.n0, num0);
-                num1 = fma(sp.b2, src_ld.m1 - src_ld.n1, num1);
-                num2 = fma(sp.b2, src_ld.m2 - src_ld.n2, num2);
+                num0 = fma(sp.b2, src_ld.m0 - lvl_mid.a, num0);
+                num1 = fma(sp.b2, src_ld.m1 - lvl_mid.b, num1);
+                num2 = fma(sp.b2, src_ld.m2 - lvl_mid.c, num2);
             }
+            lvl_r = lvl_mid.a;
         } else {
             a0 = z.a;
             a1 = z.b;
@@ -281,11 +315,12 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
                 num1 = fma(sp.b2, src_ld.m1, num1);
                 num2 = fma(sp.b2, src_ld.m2, num2);
             }
+            lvl_r = src_ld.n0;
         }
-        const double lvl_r = src_ld.n0;
         const double d_r = num0 * sp.inv_dt, d_ru = num1 * sp.inv_dt, d_rv = num2 * sp.inv_dt;
         const Prim<R> next_hi = to_prim(in_ld);
         const double next_phi = abs_p(in_ld);
+        const Vec4<double> next_lvl = {in_ld.lr, in_ld.lm, in_ld.ln, 0.0};
         in_ld = load_input<P>(t, qprev, have_col, gi, r + 3);
         src_ld = load_sources<P, BDF2>(t, q0, have_col, gi, r + 1);
 
@@ -433,6 +468,10 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         plo = pmid;
         pmid = phi;
         phi = next_phi;
+        if constexpr (P::kMixed) {
+            lvl_mid = lvl_hi;
+            lvl_hi = next_lvl;
+        }
     }
 
     if (LAST) {
