@@ -131,8 +131,9 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
                 const double div = (Fxp[k] - Fxm[k]) * t.inv_dx + (Fyp[k] - Fym[k]) * t.inv_dy;
                 R4[k] = -div + (k < 3 ? src[k] : 0.0);
             }
+            const double fac = ad * rcp_pos(api);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) qout[k * plane + c] = base[k] + (ad / api) * R4[k];
+            for (int k = 0; k < 3; ++k) qout[k * plane + c] = base[k] + fac * R4[k];
             const double pnew = p0 + t.beta * (ad * R4[3]);
             qout[3 * plane + c] = pnew;
             if (last) {

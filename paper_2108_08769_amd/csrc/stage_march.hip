@@ -447,7 +447,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         if (fluid && r >= j0 && r < j1) {
             const double dtau = local_dtau(t, t.cfl, a0, a1, a2);
             const double ad = alpha * dtau;
-            const double fc = ad / (1.0 + sp.b0 * ad * sp.inv_dt);
+            const double fc = ad * rcp_pos(fma(sp.b0 * ad, sp.inv_dt, 1.0));
             if (LAST) {
                 pre = z;
                 rpart = rp4;

@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
             const double dtau = local_dtau(t, t.cfl, r0, m0, n0);
             const double ad = alpha * dtau;
             const double api = 1.0 + sp.b0 * ad * sp.inv_dt;
-            const double fac = ad / api;
+            const double fac = ad * rcp_pos(api);
             qout[c] = r0 + fac * R4[0];
             qout[plane + c] = m0 + fac * R4[1];
             qout[2 * plane + c] = n0 + fac * R4[2];

@@ -38,26 +38,23 @@ struct Slope {
 };
 
 // Reciprocal and reciprocal square root of a positive, finite, normal FP64 argument: the
-// hardware estimates (v_rcp_f64, v_rsq_f64) refined by two Newton steps, which leaves an error of
-// about one unit in the last place.  Used where an IEEE division or square root would cost about
-// ten instructions more.
+// hardware estimates (v_rcp_f64, v_rsq_f64, relative error about 5e-8) refined by one
+// third-order step, which leaves an error of about one unit in the last place:
+//   1/x      = y (1 + e + e^2 + ...),             e = 1 - x y,
+//   1/sqrt x = y (1 + e/2 + 3 e^2/8 + ...),       e = 1 - x y^2.
+// Used where an IEEE division or square root would cost about ten instructions more.
 __device__ __forceinline__ double rcp_pos(double x)
 {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, y, 1.0);
+    return fma(y, fma(e, e, e), y);
 }
 
 __device__ __forceinline__ double rsqrt_pos(double x)
 {
-    double y = __builtin_amdgcn_rsq(x);
-    // y <- y + y (1 - x y^2) / 2, twice
-    double e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-x * y, y, 1.0);
-    return fma(0.5 * y, e, y);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y, e * fma(e, 0.375, 0.5), y);
 }
 
 __device__ __forceinline__ float rcp_pos(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -154,21 +151,25 @@ __device__ __forceinline__ Vec4<T> osher_x(const Prim<T> &L, const Prim<T> &R, T
     const T mL = L.r * L.u, nL = L.r * L.v;
     const T mR = R.r * R.u, nR = R.r * R.v;
     const T dr = R.r - L.r, dm = mR - mL, dn = nR - nL;
-    const T dq = (R.p - L.p) * inv_beta;
+    const T dp = R.p - L.p;
     const T four_beta = T(4) * beta;
 
-    // Gauss-Legendre nodes on [0, 1] and half weights
+    // Gauss-Legendre nodes on [0, 1], half weights, and half weights over beta
     const T t0 = T(0.11270166537925831148207346002176);  // (1 - sqrt(3/5))/2
     const T t2 = T(0.88729833462074168851792653997824);  // (1 + sqrt(3/5))/2
     const T w0 = T(5.0) / T(18.0), w1 = T(8.0) / T(18.0);
+    const T w0b = w0 * inv_beta, w1b = w1 * inv_beta;
 
-    // sum_j (w_j/2) |A_j| dQ = (sum_j (w_j/2)|u_j|) dQ + sum_j [k4 r4 + k5 r5]_j, with the weight
-    // folded into k4 and k5
-    T sau = T(0), a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+    // sum_j (w_j/2) |A_j| dQ = (sum_j (w_j/2)|u_j|) dQ + sum_j [k4 r4 + k5 r5]_j with the weight
+    // folded into k4 and k5.  With a' = d(rho u) - u d(rho) = beta a and dp = beta dq,
+    //   k4 = (lambda_4 - |u|)(w/2)(rho/c)(lambda_4 a + dq) = (lambda_4 - |u|)(w/(2 beta))(rho/c)(lambda_4 a' + dp)
+    // and alike for k5; component 1 is accumulated as sum u s + beta sum (k4 + k5)/rho.
+    T sau = T(0), a0 = T(0), a1u = T(0), a1b = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const T t = (j == 0) ? t0 : ((j == 1) ? T(0.5) : t2);
         const T wj = (j == 1) ? w1 : w0;
+        const T wjb = (j == 1) ? w1b : w0b;
         const T rho = fma(dr, t, L.r);
         const T m = fma(dm, t, mL);
         const T n = fma(dn, t, nL);
@@ -176,26 +177,27 @@ __device__ __forceinline__ Vec4<T> osher_x(const Prim<T> &L, const Prim<T> &R, T
         const T u = m * ir, v = n * ir;
         const T c2 = fma(u, u, four_beta * ir);
         const T y = rsqrt_pos(c2);          // 1/c
-        const T c = c2 * y;
-        const T rcw = wj * rho * y;         // (w_j/2) rho / c
-        const T hu = T(0.5) * u, hc = T(0.5) * c;
-        const T l4 = hu + hc, l5 = hu - hc;
+        const T hc = T(0.5) * (c2 * y);     // c/2
+        const T rcw = wjb * rho * y;        // (w_j/2) rho / (beta c)
+        const T l4 = fma(T(0.5), u, hc), l5 = fma(T(0.5), u, -hc);
         const T au = fabs(u);
         sau = fma(wj, au, sau);
-        const T a = fma(-u, dr, dm) * inv_beta;
-        const T k4 = (l4 - au) * rcw * fma(l4, a, dq);
-        const T k5 = (l5 + au) * rcw * fma(l5, a, dq);
+        const T a = fma(-u, dr, dm);
+        const T k4 = (l4 - au) * rcw * fma(l4, a, dp);
+        const T k5 = (l5 + au) * rcw * fma(l5, a, dp);
         const T s = fma(k4, l4, k5 * l5);
         a0 += s;
-        a1 += fma(u, s, beta * ir * (k4 + k5));
+        a1u = fma(u, s, a1u);
+        a1b = fma(ir, k4 + k5, a1b);
         a2 = fma(v, s, a2);
-        a3 -= fma(k4, l5, k5 * l4) * ir;
+        a3 = fma(-ir, fma(k4, l5, k5 * l4), a3);
     }
+    const T a1 = fma(beta, a1b, a1u);
     Vec4<T> F;
     F.a = T(0.5) * (mL + mR - fma(sau, dr, a0));
     F.b = T(0.5) * (fma(mL, L.u, L.p) + fma(mR, R.u, R.p) - fma(sau, dm, a1));
     F.c = T(0.5) * (mL * L.v + mR * R.v - fma(sau, dn, a2));
-    F.d = T(0.5) * (L.u + R.u - fma(sau, dq, a3));
+    F.d = T(0.5) * (L.u + R.u - fma(sau, dp * inv_beta, a3));
     return F;
 }
 
