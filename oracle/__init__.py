@@ -23,6 +23,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 BC_WALL = 0
 BC_PERIODIC = 1
+BC_TRANSMISSIVE = 2
+FLUX_OSHER, FLUX_ROE, FLUX_BASSI = 0, 1, 2
+PGRAD_NEW, PGRAD_LIMITER, PGRAD_SPLIT = 0, 1, 2
 
 
 def build() -> str:
@@ -50,6 +53,9 @@ class _Problem(ctypes.Structure):
         ("local_dtau", ctypes.c_int),
         ("bdf", ctypes.c_int),
         ("wall_slip", ctypes.c_int),
+        ("flux", ctypes.c_int),
+        ("pgrad", ctypes.c_int),
+        ("pk", ctypes.c_double),
     ]
 
 
@@ -75,12 +81,20 @@ def lib():
         L.orc_eigen.argtypes = [dp, ctypes.c_double, dp, dp, dp]
         L.orc_abs_jacobian.argtypes = [dp, ctypes.c_double, dp]
         L.orc_osher_x.argtypes = [dp, dp, ctypes.c_double, dp]
+        L.orc_roe_x.argtypes = [dp, dp, ctypes.c_double, dp]
+        L.orc_bassi_x.argtypes = [dp, dp, ctypes.c_double, dp]
+        L.orc_bassi_star.argtypes = [dp, dp, ctypes.c_double, dp]
+        L.orc_exact_sample.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, dp]
         L.orc_face_flux.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_face_flux_kind.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, dp]
+        L.orc_realtime_dt.restype = ctypes.c_double
+        L.orc_realtime_dt.argtypes = [ctypes.POINTER(_Problem), dp, ctypes.c_double]
         L.orc_stage.restype = ctypes.c_int
-        L.orc_stage.argtypes = [ctypes.POINTER(_Problem), dp, dp, dp, dp, ctypes.c_double,
+        L.orc_stage.argtypes = [ctypes.POINTER(_Problem), dp, dp, dp, dp, dp, ctypes.c_double,
                                 ctypes.c_int, dp, ctypes.POINTER(_Detail)]
         L.orc_step.restype = ctypes.c_int
-        L.orc_step.argtypes = [ctypes.POINTER(_Problem), dp, dp, ctypes.c_double, ctypes.c_int,
+        L.orc_step.argtypes = [ctypes.POINTER(_Problem), dp, dp, dp, ctypes.c_double, ctypes.c_int,
                                ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
         _lib = L
     return _lib
@@ -112,6 +126,9 @@ class Problem:
     local_dtau: bool = True
     bdf: int = 1
     wall_slip: bool = False
+    flux: int = FLUX_OSHER
+    pgrad: int = PGRAD_NEW
+    pk: float = 1.0
     _keep: list = field(default_factory=list, repr=False)
 
     def c_struct(self) -> _Problem:
@@ -132,6 +149,7 @@ class Problem:
         p.local_dtau = int(bool(self.local_dtau))
         p.bdf = self.bdf
         p.wall_slip = int(bool(self.wall_slip))
+        p.flux, p.pgrad, p.pk = int(self.flux), int(self.pgrad), float(self.pk)
         return p
 
 
@@ -168,19 +186,59 @@ def osher_x(ql, qr, beta):
     return f
 
 
-def face_flux(qa, qb, normal, beta):
-    qa = np.ascontiguousarray(qa, dtype=np.float64)
-    qb = np.ascontiguousarray(qb, dtype=np.float64)
+def _flux2(name, ql, qr, beta):
+    ql = np.ascontiguousarray(ql, dtype=np.float64)
+    qr = np.ascontiguousarray(qr, dtype=np.float64)
     f = np.zeros(4)
-    lib().orc_face_flux(_ptr(qa), _ptr(qb), float(normal[0]), float(normal[1]), beta, _ptr(f))
+    getattr(lib(), name)(_ptr(ql), _ptr(qr), beta, _ptr(f))
     return f
 
 
-def stage(pb: Problem, qprev, q0, qn, dt, s, qnm1=None):
+def roe_x(ql, qr, beta):
+    return _flux2("orc_roe_x", ql, qr, beta)
+
+
+def bassi_x(ql, qr, beta):
+    return _flux2("orc_bassi_x", ql, qr, beta)
+
+
+def bassi_star(ql, qr, beta):
+    """(S_L, S_R, u*, p*, rho*L, rho*R) of the exact Riemann solution."""
+    ql = np.ascontiguousarray(ql, dtype=np.float64)
+    qr = np.ascontiguousarray(qr, dtype=np.float64)
+    st = np.zeros(6)
+    lib().orc_bassi_star(_ptr(ql), _ptr(qr), beta, _ptr(st))
+    return st
+
+
+def exact_sample(ql, qr, beta, xi):
+    ql = np.ascontiguousarray(ql, dtype=np.float64)
+    qr = np.ascontiguousarray(qr, dtype=np.float64)
+    q = np.zeros(4)
+    lib().orc_exact_sample(_ptr(ql), _ptr(qr), beta, float(xi), _ptr(q))
+    return q
+
+
+def face_flux(qa, qb, normal, beta, kind=FLUX_OSHER):
+    qa = np.ascontiguousarray(qa, dtype=np.float64)
+    qb = np.ascontiguousarray(qb, dtype=np.float64)
+    f = np.zeros(4)
+    lib().orc_face_flux_kind(_ptr(qa), _ptr(qb), float(normal[0]), float(normal[1]), beta,
+                             int(kind), _ptr(f))
+    return f
+
+
+def realtime_dt(pb: Problem, q, cfl_t: float) -> float:
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    st = pb.c_struct()
+    return lib().orc_realtime_dt(ctypes.byref(st), _ptr(q), float(cfl_t))
+
+
+def stage(pb: Problem, qprev, q0, qn, dt, s, qnm1=None, qnm2=None):
     """One Runge-Kutta stage; returns (q_out, detail dict)."""
     ny, nx = pb.ny, pb.nx
     arrs = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
-            for a in (qprev, q0, qn, qnm1)]
+            for a in (qprev, q0, qn, qnm1, qnm2)]
     out = np.zeros((4, ny, nx))
     det = {"prim": np.zeros((4, ny, nx)), "grad": np.zeros((8, ny, nx)),
            "fx": np.zeros((4, ny, nx + 1)), "fy": np.zeros((4, ny + 1, nx)),
@@ -188,22 +246,23 @@ def stage(pb: Problem, qprev, q0, qn, dt, s, qnm1=None):
     d = _Detail(*[_ptr(det[k]) for k in ("prim", "grad", "fx", "fy", "resid", "dtau")])
     st = pb.c_struct()
     rc = lib().orc_stage(ctypes.byref(st), _ptr(arrs[0]), _ptr(arrs[1]), _ptr(arrs[2]),
-                         _ptr(arrs[3]), dt, s, _ptr(out), ctypes.byref(d))
+                         _ptr(arrs[3]), _ptr(arrs[4]), dt, s, _ptr(out), ctypes.byref(d))
     if rc != 0:
         raise ValueError(f"orc_stage returned {rc}")
     return out, det
 
 
-def step(pb: Problem, q, dt, max_pseudo, tol=0.0, norm=0, qnm1=None):
+def step(pb: Problem, q, dt, max_pseudo, tol=0.0, norm=0, qnm1=None, qnm2=None):
     """One real-time step.  Returns (q_new, iterations, norms[4], status)."""
     q = np.array(q, dtype=np.float64, order="C", copy=True)
     assert q.shape == (4, pb.ny, pb.nx)
     qm = None if qnm1 is None else np.ascontiguousarray(qnm1, dtype=np.float64)
+    qm2 = None if qnm2 is None else np.ascontiguousarray(qnm2, dtype=np.float64)
     it = ctypes.c_int(0)
     res = np.zeros(4)
     st = pb.c_struct()
-    rc = lib().orc_step(ctypes.byref(st), _ptr(q), _ptr(qm), dt, int(max_pseudo), float(tol),
-                        int(norm), ctypes.byref(it), _ptr(res))
+    rc = lib().orc_step(ctypes.byref(st), _ptr(q), _ptr(qm), _ptr(qm2), dt, int(max_pseudo),
+                        float(tol), int(norm), ctypes.byref(it), _ptr(res))
     if rc == -1:
         raise ValueError("orc_step: invalid arguments")
     return q, it.value, res, rc

@@ -45,6 +45,15 @@
  *       Converged when every field is below the tolerance.
  *   R11 The y-direction spectral radius uses c_y = sqrt(v^2 + 4 beta/rho).
  *   R12 Gauss-Legendre on [0,1]: the integral of |A| dQ is (1/2) sum_j w_j |A(Q_j)| (Q_R - Q_L).
+ *   R13 Zero-gradient (transmissive) sides: the ghosts mirror the interior like wall ghosts but
+ *       keep every variable's sign, and gravity is not reversed in them; the normal derivative of
+ *       every variable then vanishes at the boundary face.
+ *   R14 The pressure-gradient variants of Sec. 2.3.2 use the same stencils as rho, u, v: the
+ *       k-limiter applied to p, or the split limiter whose hydrostatic parts use the stencil's
+ *       densities and the gravity of the cell (reversed in wall ghosts).
+ *   R15 Roe averages of rho, u, v only: p does not enter the eigenstructure (Sec. 2.4.2).
+ *   R16 BDF order: the smallest of the order asked for and the real-time levels available
+ *       (the first step is backward Euler, the second at most BDF2; Table 1).
  */
 #include "vdac_oracle.h"
 
@@ -151,10 +160,89 @@ void orc_osher_x(const double ql[4], const double qr[4], double beta, double f[4
     for (int k = 0; k < 4; ++k) f[k] = 0.5 * (fr[k] + fl[k] - integral[k]);
 }
 
+/* Sec. 2.4.2: F = (F(Q_R) + F(Q_L) - |A~| (Q_R - Q_L)) / 2 with |A~| = R |Lambda| L at the Roe
+ * average rho~ = sqrt(rho_L rho_R), u~ = (sqrt(rho_L) u_L + sqrt(rho_R) u_R)/(sqrt(rho_L) +
+ * sqrt(rho_R)), v~ alike (R15). */
+void orc_roe_x(const double ql[4], const double qr[4], double beta, double f[4])
+{
+    double rl = ql[0], rr = qr[0];
+    double ul = ql[1] / rl, ur = qr[1] / rr;
+    double vl = ql[2] / rl, vr = qr[2] / rr;
+    double sl = sqrt(rl), sr = sqrt(rr);
+    double rt = sqrt(rl * rr);
+    double ut = (sl * ul + sr * ur) / (sl + sr);
+    double vt = (sl * vl + sr * vr) / (sl + sr);
+    double qt[4] = {rt, rt * ut, rt * vt, 0.0};
+    double A[16], fl[4], fr[4];
+    orc_abs_jacobian(qt, beta, A);
+    orc_flux_phys(ql, beta, fl);
+    orc_flux_phys(qr, beta, fr);
+    for (int r = 0; r < 4; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < 4; ++c) s += A[r * 4 + c] * (qr[c] - ql[c]);
+        f[r] = 0.5 * (fr[r] + fl[r] - s);
+    }
+}
+
+/* Sec. 2.4.1: acoustic speeds S_L = (u_L - c_L)/2 = lambda_5,L and S_R = (u_R + c_R)/2 =
+ * lambda_4,R; the star velocity, pressure and densities as printed. */
+void orc_bassi_star(const double ql[4], const double qr[4], double beta, double star[6])
+{
+    double rl = ql[0], rr = qr[0];
+    double ul = ql[1] / rl, ur = qr[1] / rr;
+    double pl = beta * ql[3], pr = beta * qr[3];
+    double cl = sqrt(ul * ul + 4.0 * beta / rl);
+    double cr = sqrt(ur * ur + 4.0 * beta / rr);
+    double l4l = 0.5 * (ul + cl), l5l = 0.5 * (ul - cl);
+    double l4r = 0.5 * (ur + cr), l5r = 0.5 * (ur - cr);
+    double us = (pr - pl + rr * ur * l5r - rl * ul * l4l) / (rr * l5r - rl * l4l);
+    double ps = pr + rr * l5r * (ur - us);
+    star[0] = l5l;
+    star[1] = l4r;
+    star[2] = us;
+    star[3] = ps;
+    star[4] = rl * l4l / (us - l5l);
+    star[5] = rr * l5r / (us - l4r);
+}
+
+/* Sec. 2.4.1: the tangential velocity changes only across the contact; the exact solution at
+ * xi = x/tau is Q_L left of the acoustic fan, Q_R right of it, and inside it the left or right
+ * star state by the side of the contact.  (If the contact leaves the fan, the solver's
+ * assumption fails; the sampler still returns Q_L and Q_R outside the fan.) */
+void orc_exact_sample(const double ql[4], const double qr[4], double beta, double xi, double q[4])
+{
+    double st[6];
+    orc_bassi_star(ql, qr, beta, st);
+    if (xi < st[0]) {
+        for (int k = 0; k < 4; ++k) q[k] = ql[k];
+    } else if (xi >= st[1]) {
+        for (int k = 0; k < 4; ++k) q[k] = qr[k];
+    } else if (xi < st[2]) {
+        double v = ql[2] / ql[0];
+        q[0] = st[4];
+        q[1] = st[4] * st[2];
+        q[2] = st[4] * v;
+        q[3] = st[3] / beta;
+    } else {
+        double v = qr[2] / qr[0];
+        q[0] = st[5];
+        q[1] = st[5] * st[2];
+        q[2] = st[5] * v;
+        q[3] = st[3] / beta;
+    }
+}
+
+void orc_bassi_x(const double ql[4], const double qr[4], double beta, double f[4])
+{
+    double q[4];
+    orc_exact_sample(ql, qr, beta, 0.0, q);
+    orc_flux_phys(q, beta, f);
+}
+
 /* Sec. 2.4: rotate to an x-split problem with R(n), built from n by Algorithm 2, then rotate the
  * flux back with R^T.  In 2D the state is (rho, rho u, rho v, p/beta) and only n and t1 enter. */
-void orc_face_flux(const double qa[4], const double qb[4], double nx, double ny, double beta,
-                   double f[4])
+void orc_face_flux_kind(const double qa[4], const double qb[4], double nx, double ny, double beta,
+                        int kind, double f[4])
 {
     double t1x, t1y;
     if (nx == 0.0) {
@@ -183,11 +271,22 @@ void orc_face_flux(const double qa[4], const double qb[4], double nx, double ny,
             qr[r] += Rm[r * 4 + c] * qb[c];
         }
     }
-    orc_osher_x(ql, qr, beta, fx);
+    if (kind == ORC_FLUX_ROE)
+        orc_roe_x(ql, qr, beta, fx);
+    else if (kind == ORC_FLUX_BASSI)
+        orc_bassi_x(ql, qr, beta, fx);
+    else
+        orc_osher_x(ql, qr, beta, fx);
     for (int r = 0; r < 4; ++r) {
         f[r] = 0.0;
         for (int c = 0; c < 4; ++c) f[r] += Rm[c * 4 + r] * fx[c];
     }
+}
+
+void orc_face_flux(const double qa[4], const double qb[4], double nx, double ny, double beta,
+                   double f[4])
+{
+    orc_face_flux_kind(qa, qb, nx, ny, beta, ORC_FLUX_OSHER, f);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -231,39 +330,58 @@ static prim mirror_axis(prim w, int axis)
     return w;
 }
 
-/* Neighbour of cell (i,j) in direction (di,dj): returns 1 and its index if it is a fluid cell
- * (after periodic wrapping), 0 if the face between them is a wall (domain wall or solid). */
-static int neighbour(const geom *g, int i, int j, int di, int dj, size_t *idx)
+/* What lies across the face of cell (i,j) in direction (di,dj): a fluid cell (after periodic
+ * wrapping; its index in *idx), a wall (domain wall or solid cell) or a zero-gradient side. */
+enum { SIDE_FLUID = 0, SIDE_WALL = 1, SIDE_OPEN = 2 };
+
+static int side_of(const geom *g, int s)
+{
+    return g->pb->bc[s] == ORC_BC_TRANSMISSIVE ? SIDE_OPEN : SIDE_WALL;
+}
+
+static int neighbour_kind(const geom *g, int i, int j, int di, int dj, size_t *idx)
 {
     int ni = i + di, nj = j + dj;
     if (ni < 0) {
-        if (g->pb->bc[0] != ORC_BC_PERIODIC) return 0;
+        if (g->pb->bc[0] != ORC_BC_PERIODIC) return side_of(g, 0);
         ni += g->nx;
     }
     if (ni >= g->nx) {
-        if (g->pb->bc[1] != ORC_BC_PERIODIC) return 0;
+        if (g->pb->bc[1] != ORC_BC_PERIODIC) return side_of(g, 1);
         ni -= g->nx;
     }
     if (nj < 0) {
-        if (g->pb->bc[2] != ORC_BC_PERIODIC) return 0;
+        if (g->pb->bc[2] != ORC_BC_PERIODIC) return side_of(g, 2);
         nj += g->ny;
     }
     if (nj >= g->ny) {
-        if (g->pb->bc[3] != ORC_BC_PERIODIC) return 0;
+        if (g->pb->bc[3] != ORC_BC_PERIODIC) return side_of(g, 3);
         nj -= g->ny;
     }
-    if (is_solid(g, ni, nj)) return 0;
+    if (is_solid(g, ni, nj)) return SIDE_WALL;
     *idx = at(g, ni, nj);
-    return 1;
+    return SIDE_FLUID;
+}
+
+static int neighbour(const geom *g, int i, int j, int di, int dj, size_t *idx)
+{
+    return neighbour_kind(g, i, j, di, dj, idx) == SIDE_FLUID;
+}
+
+/* Image across a wall (R8) or a zero-gradient side (R13). */
+static prim reflect(prim w, int axis, int kind)
+{
+    return kind == SIDE_WALL ? mirror_axis(w, axis) : w;
 }
 
 /* The value fluid cell (i,j) sees at its neighbour (i+di, j+dj): the neighbour's W, or across a
- * wall the ghost, which mirrors cell (i,j) itself (R8, R9). */
+ * wall or zero-gradient side the ghost, which reflects cell (i,j) itself (R8, R9, R13). */
 static prim seen(const geom *g, const prim *W, int i, int j, int di, int dj)
 {
     size_t nb;
-    if (neighbour(g, i, j, di, dj, &nb)) return W[nb];
-    return mirror_axis(W[at(g, i, j)], di != 0 ? 0 : 1);
+    int kind = neighbour_kind(g, i, j, di, dj, &nb);
+    if (kind == SIDE_FLUID) return W[nb];
+    return reflect(W[at(g, i, j)], di != 0 ? 0 : 1, kind);
 }
 
 /* Limited gradients of rho, u, v from a five-point stencil (Sec. 2.3.1, R1). */
@@ -295,6 +413,32 @@ static void new_pressure_gradient(prim w, const double gx[3], const double gy[3]
           + rho0 * grav_y;
 }
 
+/* Pressure gradient of an entity with the stencil (xm, xp, ym, yp) around c, by the method the
+ * problem asks for (Sec. 2.3.2, R14); grav is the gravity at the entity (reversed in wall
+ * ghosts). */
+static void pressure_gradient(const geom *g, prim c, prim xm, prim xp, prim ym, prim yp,
+                              const double gx[3], const double gy[3], double d_ru, double d_rv,
+                              double rho0, double grav_x, double grav_y, double *px, double *py)
+{
+    const orc_problem *pb = g->pb;
+    double dx = g->dx, dy = g->dy;
+    if (pb->pgrad == ORC_PGRAD_LIMITER) {
+        *px = orc_limiter((xp.p - c.p) / dx, (c.p - xm.p) / dx, pb->pk);
+        *py = orc_limiter((yp.p - c.p) / dy, (c.p - ym.p) / dy, pb->pk);
+    } else if (pb->pgrad == ORC_PGRAD_SPLIT) {
+        /* one-sided dynamic gradients minus the hydrostatic ones (rho_{i-1} + rho_i) g/2 and
+           (rho_i + rho_{i+1}) g/2 give the kinematic gradients; limit them, add rho_i g */
+        double kxr = (xp.p - c.p) / dx - 0.5 * (c.r + xp.r) * grav_x;
+        double kxl = (c.p - xm.p) / dx - 0.5 * (xm.r + c.r) * grav_x;
+        double kyr = (yp.p - c.p) / dy - 0.5 * (c.r + yp.r) * grav_y;
+        double kyl = (c.p - ym.p) / dy - 0.5 * (ym.r + c.r) * grav_y;
+        *px = c.r * grav_x + orc_limiter(kxr, kxl, pb->pk);
+        *py = c.r * grav_y + orc_limiter(kyr, kyl, pb->pk);
+    } else {
+        new_pressure_gradient(c, gx, gy, d_ru, d_rv, rho0, grav_x, grav_y, px, py);
+    }
+}
+
 /* Per-cell stage-0 data of one pseudo-iteration (R6). */
 typedef struct {
     double *D;    /* [3][n] real-time term I_C dQ/dt for rho, rho u, rho v */
@@ -303,19 +447,20 @@ typedef struct {
     double B0;    /* leading BDF coefficient (Table 1), for alpha_PI */
 } frozen;
 
-/* The ghost across the face of fluid cell (i,j) in direction (di,dj) (R8, R9). */
+/* The ghost across the face of fluid cell (i,j) in direction (di,dj) (R8, R9, R13). */
 static void ghost_entity(const geom *g, const prim *W, const frozen *fz, int i, int j, int di,
                          int dj, entity *e)
 {
-    size_t a = at(g, i, j);
+    size_t a = at(g, i, j), nb;
     int axis = (di != 0) ? 0 : 1;
+    int kind = neighbour_kind(g, i, j, di, dj, &nb);
     prim wa = W[a];
-    prim c = mirror_axis(wa, axis);
-    prim far = mirror_axis(seen(g, W, i, j, -di, -dj), axis); /* outer neighbour mirrors a - d */
+    prim c = reflect(wa, axis, kind);
+    prim far = reflect(seen(g, W, i, j, -di, -dj), axis, kind); /* outer neighbour: image of a - d */
     prim xm, xp, ym, yp;
     if (di != 0) {
-        ym = mirror_axis(seen(g, W, i, j, 0, -1), axis);
-        yp = mirror_axis(seen(g, W, i, j, 0, +1), axis);
+        ym = reflect(seen(g, W, i, j, 0, -1), axis, kind);
+        yp = reflect(seen(g, W, i, j, 0, +1), axis, kind);
         if (di > 0) {
             xm = wa;
             xp = far;
@@ -324,8 +469,8 @@ static void ghost_entity(const geom *g, const prim *W, const frozen *fz, int i, 
             xp = wa;
         }
     } else {
-        xm = mirror_axis(seen(g, W, i, j, -1, 0), axis);
-        xp = mirror_axis(seen(g, W, i, j, +1, 0), axis);
+        xm = reflect(seen(g, W, i, j, -1, 0), axis, kind);
+        xp = reflect(seen(g, W, i, j, +1, 0), axis, kind);
         if (dj > 0) {
             ym = wa;
             yp = far;
@@ -336,12 +481,17 @@ static void ghost_entity(const geom *g, const prim *W, const frozen *fz, int i, 
     }
     e->w = c;
     stencil_gradient(g, c, xm, xp, ym, yp, e->gx, e->gy);
-    /* the ghost's sources are mirrored like its state; gravity is reversed in the ghost */
+    /* a wall ghost's sources are mirrored like its state and gravity is reversed in it; a
+       zero-gradient ghost keeps both */
     double d_ru = fz->D[1 * g->n + a], d_rv = fz->D[2 * g->n + a];
-    if (!g_slip || axis == 0) d_ru = -d_ru;
-    if (!g_slip || axis == 1) d_rv = -d_rv;
-    new_pressure_gradient(c, e->gx, e->gy, d_ru, d_rv, fz->rho0[a], -g->pb->gx, -g->pb->gy,
-                          &e->px, &e->py);
+    double sg = 1.0;
+    if (kind == SIDE_WALL) {
+        if (!g_slip || axis == 0) d_ru = -d_ru;
+        if (!g_slip || axis == 1) d_rv = -d_rv;
+        sg = -1.0;
+    }
+    pressure_gradient(g, c, xm, xp, ym, yp, e->gx, e->gy, d_ru, d_rv, fz->rho0[a],
+                      sg * g->pb->gx, sg * g->pb->gy, &e->px, &e->py);
 }
 
 /* Reconstructed conserved state of entity e at its face in direction (di,dj): W + grad.(x_f-x_e)
@@ -386,24 +536,41 @@ static int valid_problem(const orc_problem *pb)
     if (!(pb->lx > 0.0) || !(pb->ly > 0.0) || !(pb->beta > 0.0)) return 0;
     if (pb->stages < 1 || pb->stages > 8) return 0;
     if (!(pb->cfl > 0.0) || !(pb->k >= 1.0 && pb->k <= 2.0)) return 0;
-    if (pb->bdf != 1 && pb->bdf != 2) return 0;
+    if (pb->bdf < 1 || pb->bdf > 3) return 0;
     if (pb->wall_slip != 0 && pb->wall_slip != 1) return 0;
+    if (pb->flux < ORC_FLUX_OSHER || pb->flux > ORC_FLUX_BASSI) return 0;
+    if (pb->pgrad < ORC_PGRAD_NEW || pb->pgrad > ORC_PGRAD_SPLIT) return 0;
+    if (pb->pgrad != ORC_PGRAD_NEW && !(pb->pk >= 1.0 && pb->pk <= 2.0)) return 0;
     for (int s = 0; s < 4; ++s)
-        if (pb->bc[s] != ORC_BC_WALL && pb->bc[s] != ORC_BC_PERIODIC) return 0;
+        if (pb->bc[s] != ORC_BC_WALL && pb->bc[s] != ORC_BC_PERIODIC &&
+            pb->bc[s] != ORC_BC_TRANSMISSIVE)
+            return 0;
     if ((pb->bc[0] == ORC_BC_PERIODIC) != (pb->bc[1] == ORC_BC_PERIODIC)) return 0;
     if ((pb->bc[2] == ORC_BC_PERIODIC) != (pb->bc[3] == ORC_BC_PERIODIC)) return 0;
     return 1;
 }
 
 /* Stage-0 data (Algorithm 1 before the Runge-Kutta loop): real-time term
- * (B0 Q^0 + B1 Q^n + B2 Q^{n-1})/dt on the I_C = 1 components (Table 1), rho^0 for the body force,
- * and the pseudo-time step.  Q arrays are internal-form [4][n]. */
+ * (B0 Q^0 + B1 Q^n + B2 Q^{n-1} + B3 Q^{n-2})/dt on the I_C = 1 components (Table 1, R16),
+ * rho^0 for the body force, and the pseudo-time step.  Q arrays are internal-form [4][n]. */
 static void freeze_sources(const geom *g, const double *Q0, const double *Qn, const double *Qnm1,
-                           double dt, frozen *fz)
+                           const double *Qnm2, double dt, frozen *fz)
 {
     size_t n = g->n;
-    int bdf2 = (g->pb->bdf == 2 && Qnm1 != NULL);
-    double B0 = bdf2 ? 1.5 : 1.0, B1 = bdf2 ? -2.0 : -1.0, B2 = bdf2 ? 0.5 : 0.0;
+    int order = 1;
+    if (g->pb->bdf >= 2 && Qnm1 != NULL) order = 2;
+    if (g->pb->bdf >= 3 && Qnm1 != NULL && Qnm2 != NULL) order = 3;
+    double B[4] = {1.0, -1.0, 0.0, 0.0};
+    if (order == 2) {
+        B[0] = 1.5;
+        B[1] = -2.0;
+        B[2] = 0.5;
+    } else if (order == 3) {
+        B[0] = 11.0 / 6.0;
+        B[1] = -3.0;
+        B[2] = 1.5;
+        B[3] = -1.0 / 3.0;
+    }
     double dmin = INFINITY;
     for (int j = 0; j < g->ny; ++j)
         for (int i = 0; i < g->nx; ++i) {
@@ -412,8 +579,9 @@ static void freeze_sources(const geom *g, const double *Q0, const double *Qn, co
             for (int k = 0; k < 3; ++k) {
                 double d = 0.0;
                 if (dt > 0.0) {
-                    double num = B0 * Q0[k * n + c] + B1 * Qn[k * n + c];
-                    if (bdf2) num += B2 * Qnm1[k * n + c];
+                    double num = B[0] * Q0[k * n + c] + B[1] * Qn[k * n + c];
+                    if (order >= 2) num += B[2] * Qnm1[k * n + c];
+                    if (order >= 3) num += B[3] * Qnm2[k * n + c];
                     d = num / dt;
                 }
                 fz->D[k * n + c] = d;
@@ -424,7 +592,7 @@ static void freeze_sources(const geom *g, const double *Q0, const double *Qn, co
         }
     if (!g->pb->local_dtau)
         for (size_t c = 0; c < n; ++c) fz->dtau[c] = dmin;
-    fz->B0 = B0;
+    fz->B0 = B[0];
 }
 
 /* Entity of fluid cell (i,j) and of its neighbours, for the face in direction (di,dj). */
@@ -470,11 +638,12 @@ static void stage_internal(const geom *g, const double *Qprev, const double *Q0,
         for (int i = 0; i < nx; ++i) {
             size_t c = at(g, i, j);
             if (is_solid(g, i, j)) continue;
+            prim xm = seen(g, W, i, j, -1, 0), xp = seen(g, W, i, j, +1, 0);
+            prim ym = seen(g, W, i, j, 0, -1), yp = seen(g, W, i, j, 0, +1);
             E[c].w = W[c];
-            stencil_gradient(g, W[c], seen(g, W, i, j, -1, 0), seen(g, W, i, j, +1, 0),
-                             seen(g, W, i, j, 0, -1), seen(g, W, i, j, 0, +1), E[c].gx, E[c].gy);
-            new_pressure_gradient(W[c], E[c].gx, E[c].gy, fz->D[n + c], fz->D[2 * n + c],
-                                  fz->rho0[c], pb->gx, pb->gy, &E[c].px, &E[c].py);
+            stencil_gradient(g, W[c], xm, xp, ym, yp, E[c].gx, E[c].gy);
+            pressure_gradient(g, W[c], xm, xp, ym, yp, E[c].gx, E[c].gy, fz->D[n + c],
+                              fz->D[2 * n + c], fz->rho0[c], pb->gx, pb->gy, &E[c].px, &E[c].py);
         }
 
     /* x-faces: face i is the left face of cell i, between cells i-1 and i */
@@ -499,7 +668,7 @@ static void stage_internal(const geom *g, const double *Qprev, const double *Q0,
             if (lf || rf) {
                 face_state(g, ea, +1, 0, qa);
                 face_state(g, eb, -1, 0, qb);
-                orc_face_flux(qa, qb, 1.0, 0.0, pb->beta, flux);
+                orc_face_flux_kind(qa, qb, 1.0, 0.0, pb->beta, pb->flux, flux);
             }
             for (int k = 0; k < 4; ++k) {
                 Fx[k * nfx + (size_t)j * (nx + 1) + f] = flux[k];
@@ -529,7 +698,7 @@ static void stage_internal(const geom *g, const double *Qprev, const double *Q0,
             if (lf || rf) {
                 face_state(g, ea, 0, +1, qa);
                 face_state(g, eb, 0, -1, qb);
-                orc_face_flux(qa, qb, 0.0, 1.0, pb->beta, flux);
+                orc_face_flux_kind(qa, qb, 0.0, 1.0, pb->beta, pb->flux, flux);
             }
             for (int k = 0; k < 4; ++k) {
                 Fy[k * nfy + (size_t)f * nx + i] = flux[k];
@@ -623,7 +792,8 @@ static void make_geom(const orc_problem *pb, geom *g)
 }
 
 int orc_stage(const orc_problem *pb, const double *qprev, const double *q0, const double *qn,
-              const double *qnm1, double dt, int stage, double *qout, orc_detail *detail)
+              const double *qnm1, const double *qnm2, double dt, int stage, double *qout,
+              orc_detail *detail)
 {
     if (!valid_problem(pb) || stage < 1 || stage > pb->stages) return -1;
     if (!qprev || !q0 || !qn || !qout) return -1;
@@ -634,6 +804,7 @@ int orc_stage(const orc_problem *pb, const double *qprev, const double *q0, cons
     double *Q0 = (double *)malloc(4 * n * sizeof(double));
     double *Qn = (double *)malloc(4 * n * sizeof(double));
     double *Qm = qnm1 ? (double *)malloc(4 * n * sizeof(double)) : NULL;
+    double *Qm2 = qnm2 ? (double *)malloc(4 * n * sizeof(double)) : NULL;
     double *Qo = (double *)malloc(4 * n * sizeof(double));
     double *R = (double *)calloc(4 * n, sizeof(double));
     frozen fz;
@@ -644,7 +815,8 @@ int orc_stage(const orc_problem *pb, const double *qprev, const double *q0, cons
     to_internal(&g, q0, Q0);
     to_internal(&g, qn, Qn);
     if (Qm) to_internal(&g, qnm1, Qm);
-    freeze_sources(&g, Q0, Qn, Qm, dt, &fz);
+    if (Qm2) to_internal(&g, qnm2, Qm2);
+    freeze_sources(&g, Q0, Qn, Qm, Qm2, dt, &fz);
     stage_internal(&g, Qp, Q0, &fz, dt, stage, Qo, R, detail);
     to_external(&g, Qo, qout);
     if (detail && detail->resid) memcpy(detail->resid, R, 4 * n * sizeof(double));
@@ -652,6 +824,7 @@ int orc_stage(const orc_problem *pb, const double *qprev, const double *q0, cons
     free(Q0);
     free(Qn);
     free(Qm);
+    free(Qm2);
     free(Qo);
     free(R);
     free(fz.D);
@@ -684,8 +857,8 @@ static void residual_norms(const geom *g, const double *R, int norm_kind, double
         res[k] = (norm_kind == 1) ? acc[k] : sqrt(acc[k] / (double)(count ? count : 1));
 }
 
-int orc_step(const orc_problem *pb, double *q, const double *qnm1, double dt, int max_pseudo,
-             double tol, int norm_kind, int *iters, double res[4])
+int orc_step(const orc_problem *pb, double *q, const double *qnm1, const double *qnm2, double dt,
+             int max_pseudo, double tol, int norm_kind, int *iters, double res[4])
 {
     if (!valid_problem(pb) || q == NULL || max_pseudo < 0 || (norm_kind != 0 && norm_kind != 1))
         return -1;
@@ -696,6 +869,7 @@ int orc_step(const orc_problem *pb, double *q, const double *qnm1, double dt, in
     double *Q = (double *)malloc(4 * n * sizeof(double));
     double *Qn = (double *)malloc(4 * n * sizeof(double));
     double *Qm = qnm1 ? (double *)malloc(4 * n * sizeof(double)) : NULL;
+    double *Qm2 = qnm2 ? (double *)malloc(4 * n * sizeof(double)) : NULL;
     double *Q0 = (double *)malloc(4 * n * sizeof(double));
     double *Qa = (double *)malloc(4 * n * sizeof(double));
     double *Qb = (double *)malloc(4 * n * sizeof(double));
@@ -709,11 +883,12 @@ int orc_step(const orc_problem *pb, double *q, const double *qnm1, double dt, in
 
     to_internal(&g, q, Q);
     if (Qm) to_internal(&g, qnm1, Qm);
+    if (Qm2) to_internal(&g, qnm2, Qm2);
     memcpy(Qn, Q, 4 * n * sizeof(double)); /* Algorithm 1: Q^n <- Q */
 
     for (m = 0; m < max_pseudo;) {
         memcpy(Q0, Q, 4 * n * sizeof(double)); /* Q^m <- Q (eq. RK1) */
-        freeze_sources(&g, Q0, Qn, Qm, dt, &fz);
+        freeze_sources(&g, Q0, Qn, Qm, Qm2, dt, &fz);
         const double *prev = Q0;
         for (int s = 1; s <= pb->stages; ++s) {
             double *out = (s % 2) ? Qa : Qb;
@@ -743,6 +918,7 @@ int orc_step(const orc_problem *pb, double *q, const double *qnm1, double dt, in
     free(Q);
     free(Qn);
     free(Qm);
+    free(Qm2);
     free(Q0);
     free(Qa);
     free(Qb);
@@ -751,4 +927,25 @@ int orc_step(const orc_problem *pb, double *q, const double *qnm1, double dt, in
     free(fz.rho0);
     free(fz.dtau);
     return status;
+}
+
+/* Sec. 2.2.4: dt = min over fluid cells of CFL_t |Omega| / (|u| dS_x + |v| dS_y), dS_x = dy and
+ * dS_y = dx in 2D. */
+double orc_realtime_dt(const orc_problem *pb, const double *q, double cfl_t)
+{
+    if (!valid_problem(pb) || q == NULL) return NAN;
+    geom g;
+    make_geom(pb, &g);
+    size_t n = g.n;
+    double dt = INFINITY;
+    for (int j = 0; j < g.ny; ++j)
+        for (int i = 0; i < g.nx; ++i) {
+            size_t c = at(&g, i, j);
+            if (is_solid(&g, i, j)) continue;
+            double u = q[n + c] / q[c], v = q[2 * n + c] / q[c];
+            double lam = fabs(u) * g.dy + fabs(v) * g.dx;
+            double d = cfl_t * (g.dx * g.dy) / lam; /* +infinity at rest */
+            if (d < dt) dt = d;
+        }
+    return dt;
 }

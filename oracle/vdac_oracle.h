@@ -21,23 +21,30 @@
 extern "C" {
 #endif
 
-enum { ORC_BC_WALL = 0, ORC_BC_PERIODIC = 1 };
+enum { ORC_BC_WALL = 0, ORC_BC_PERIODIC = 1, ORC_BC_TRANSMISSIVE = 2 };
+enum { ORC_FLUX_OSHER = 0, ORC_FLUX_ROE = 1, ORC_FLUX_BASSI = 2 };
+enum { ORC_PGRAD_NEW = 0, ORC_PGRAD_LIMITER = 1, ORC_PGRAD_SPLIT = 2 };
 
 typedef struct {
     int nx, ny;                 /* cells in x and y */
     double lx, ly;              /* domain extent; dx = lx/nx, dy = ly/ny */
     double gx, gy;              /* gravity */
     double beta;                /* artificial compressibility coefficient */
-    int bc[4];                  /* sides x-, x+, y-, y+ : ORC_BC_WALL or ORC_BC_PERIODIC */
+    int bc[4];                  /* sides x-, x+, y-, y+ : ORC_BC_WALL, ORC_BC_PERIODIC or
+                                   ORC_BC_TRANSMISSIVE (zero gradient of every variable) */
     const unsigned char *solid; /* nullable, [ny][nx]; nonzero = solid (obstacle) cell */
     int stages;                 /* Runge-Kutta stages s_max, 1..8 */
     double alpha[8];            /* RK coefficients alpha_1..alpha_smax */
     double cfl;                 /* pseudo-time Courant number CFL_tau */
     double k;                   /* k-limiter parameter: 1 minmod, 2 superbee */
     int local_dtau;             /* 1: local pseudo-time step per cell; 0: global minimum */
-    int bdf;                    /* real-time derivative: 1 backward Euler, 2 BDF2 */
+    int bdf;                    /* real-time derivative: 1 backward Euler, 2 BDF2, 3 BDF3 */
     int wall_slip;              /* 0: no-slip wall ghosts (both velocity components negated, as
                                    the paper states); 1: free-slip (normal component only) */
+    int flux;                   /* ORC_FLUX_OSHER, ORC_FLUX_ROE or ORC_FLUX_BASSI (Sec. 2.4) */
+    int pgrad;                  /* ORC_PGRAD_NEW (Sec. 2.3.2), ORC_PGRAD_LIMITER (the k-limiter
+                                   applied to p) or ORC_PGRAD_SPLIT (hydrostatic/kinematic split) */
+    double pk;                  /* k of the limiter on p for ORC_PGRAD_LIMITER and _SPLIT */
 } orc_problem;
 
 /* k-limiter G(a, b) of Sec. 2.3.1. */
@@ -57,11 +64,35 @@ void orc_abs_jacobian(const double q[4], double beta, double absA[16]);
  * path in conserved variables. */
 void orc_osher_x(const double ql[4], const double qr[4], double beta, double f[4]);
 
+/* Roe flux (Sec. 2.4.2): F = (F(Q_L) + F(Q_R) - |A(Q~)| (Q_R - Q_L))/2 at the Roe average Q~ of
+ * rho, u, v. */
+void orc_roe_x(const double ql[4], const double qr[4], double beta, double f[4]);
+
+/* Exact Riemann solution of the x-split pseudo-time system (Sec. 2.4.1): star[6] receives the
+ * acoustic wave speeds S_L, S_R, the star velocity and pressure u*, p* and the star densities
+ * rho*L, rho*R. */
+void orc_bassi_star(const double ql[4], const double qr[4], double beta, double star[6]);
+
+/* The exact solution sampled at xi = x/tau: Q_L left of S_L, the left star state up to u*, the
+ * right star state up to S_R, Q_R beyond. */
+void orc_exact_sample(const double ql[4], const double qr[4], double beta, double xi, double q[4]);
+
+/* Bassi flux: the physical flux of the exact solution at xi = 0. */
+void orc_bassi_x(const double ql[4], const double qr[4], double beta, double f[4]);
+
 /* Flux through a face with unit normal (nx, ny) pointing from cell a into cell b: the states
  * are rotated with R(n) built by Algorithm 2, the x-split flux is taken, and R^T rotates back
  * (Sec. 2.4). */
 void orc_face_flux(const double qa[4], const double qb[4], double nx, double ny, double beta,
                    double f[4]);
+
+/* The same with the x-split solver chosen by kind (ORC_FLUX_*). */
+void orc_face_flux_kind(const double qa[4], const double qb[4], double nx, double ny, double beta,
+                        int kind, double f[4]);
+
+/* Global real-time step (Sec. 2.2.4): min over fluid cells of CFL_t |Omega| / (|u| dy + |v| dx)
+ * for the state q [4][ny][nx] (rho, rho*u, rho*v, p); +infinity if the fluid is at rest. */
+double orc_realtime_dt(const orc_problem *pb, const double *q, double cfl_t);
 
 /* Intermediate results of one Runge-Kutta stage, for tests on tiny grids.  Every pointer is
  * nullable; sizes are given per member.  Fluid cells only; the rest are left untouched. */
@@ -75,21 +106,24 @@ typedef struct {
 } orc_detail;
 
 /* One Runge-Kutta stage s (1-based) of one pseudo-iteration.
- * qprev = Q^{s-1}, q0 = Q^0, qn = level n, qnm1 = level n-1 (BDF2 only, else nullable); all
- * [4][ny][nx] in the (rho, rho*u, rho*v, p) form.  qout receives Q^s in the same form.
+ * qprev = Q^{s-1}, q0 = Q^0, qn = level n, qnm1 = level n-1 and qnm2 = level n-2 (nullable; the
+ * BDF order used is the smallest of pb->bdf and the levels given); all [4][ny][nx] in the
+ * (rho, rho*u, rho*v, p) form.  qout receives Q^s in the same form.
  * dt <= 0 switches the real-time term off (pseudo-time only, alpha_PI = 1).
  * Returns 0, or -1 on invalid arguments. */
 int orc_stage(const orc_problem *pb, const double *qprev, const double *q0, const double *qn,
-              const double *qnm1, double dt, int stage, double *qout, orc_detail *detail);
+              const double *qnm1, const double *qnm2, double dt, int stage, double *qout,
+              orc_detail *detail);
 
 /* One real-time step (Algorithm 1): level n <- q, then pseudo-iterations until every
  * residual norm is below tol (tol <= 0: exactly max_pseudo iterations).
- * q [4][ny][nx] is updated in place.  qnm1 is level n-1 for BDF2 (nullable: backward Euler).
+ * q [4][ny][nx] is updated in place.  qnm1, qnm2 are levels n-1, n-2 (nullable; BDF order as in
+ * orc_stage).  dt <= 0: pseudo-time only.
  * norm_kind 0: RMS over fluid cells, 1: max norm.  iters and res (rho, rho*u, rho*v, p) are
  * nullable outputs.  Returns 0, -1 on invalid arguments, -2 if the iteration diverged
  * (non-finite residual or rho <= 0; q then holds the state after the failing iteration). */
-int orc_step(const orc_problem *pb, double *q, const double *qnm1, double dt, int max_pseudo,
-             double tol, int norm_kind, int *iters, double res[4]);
+int orc_step(const orc_problem *pb, double *q, const double *qnm1, const double *qnm2, double dt,
+             int max_pseudo, double tol, int norm_kind, int *iters, double res[4]);
 
 #ifdef __cplusplus
 }

@@ -8,14 +8,18 @@ Used only to pin the oracle.  It is built differently from the oracle on purpose
   * |A| comes from mpmath's eigendecomposition of the Jacobian printed in Sec. 2.1.3, not from
     the printed eigenvector matrices;
   * y-faces are handled by exchanging u and v (the rotation of Algorithm 2 for n = (0, 1));
+  * the exact (Bassi) flux solves the two p/beta jump conditions across the acoustic waves for
+    u* and p* and the mass conditions for the star densities, instead of using the printed
+    closed form;
   * arithmetic is mpmath at 40 significant digits.
-Only plain boxes (no solid cells) are supported.
+Zero-gradient sides fill their ghosts like walls but without negating velocities or reversing
+gravity.  Only plain boxes (no solid cells) are supported.
 """
 import mpmath as mp
 import numpy as np
 
 mp.mp.dps = 40
-WALL, PERIODIC = 0, 1
+WALL, PERIODIC, OPEN = 0, 1, 2
 
 
 def G(a, b, k):
@@ -47,6 +51,43 @@ def phys(q, beta):
     return [q[1], q[1] * u + beta * q[3], q[2] * u, u]
 
 
+def roe(ql, qr, beta):
+    rl, rr = ql[0], qr[0]
+    sl, sr = mp.sqrt(rl), mp.sqrt(rr)
+    ut = (sl * ql[1] / rl + sr * qr[1] / rr) / (sl + sr)
+    vt = (sl * ql[2] / rl + sr * qr[2] / rr) / (sl + sr)
+    rt = mp.sqrt(rl * rr)
+    dq = mp.matrix([qr[i] - ql[i] for i in range(4)])
+    d = absA([rt, rt * ut, rt * vt, 0], beta) * dq
+    fl, fr = phys(ql, beta), phys(qr, beta)
+    return [(fl[i] + fr[i] - d[i]) / 2 for i in range(4)]
+
+
+def exact_state(ql, qr, beta, xi=0):
+    rl, rr = ql[0], qr[0]
+    ul, ur = ql[1] / rl, qr[1] / rr
+    pl, pr = beta * ql[3], beta * qr[3]
+    sl = (ul - mp.sqrt(ul * ul + 4 * beta / rl)) / 2
+    sr = (ur + mp.sqrt(ur * ur + 4 * beta / rr)) / 2
+    # u* - u_L = S_L (p* - p_L)/beta and u_R - u* = S_R (p_R - p*)/beta
+    M = mp.matrix([[1, -sl / beta], [1, -sr / beta]])
+    rhs = mp.matrix([ul - sl * pl / beta, ur - sr * pr / beta])
+    us, ps = mp.lu_solve(M, rhs)
+    if xi < sl:
+        return list(ql)
+    if xi < us:
+        rs = rl * (ul - sl) / (us - sl)
+        return [rs, rs * us, rs * ql[2] / rl, ps / beta]
+    if xi < sr:
+        rs = rr * (ur - sr) / (us - sr)
+        return [rs, rs * us, rs * qr[2] / rr, ps / beta]
+    return list(qr)
+
+
+def bassi(ql, qr, beta):
+    return phys(exact_state(ql, qr, beta), beta)
+
+
 def osher(ql, qr, beta):
     xs = [-mp.sqrt(mp.mpf(3) / 5), mp.mpf(0), mp.sqrt(mp.mpf(3) / 5)]
     ws = [mp.mpf(5) / 9, mp.mpf(8) / 9, mp.mpf(5) / 9]
@@ -60,12 +101,22 @@ def osher(ql, qr, beta):
     return [(fl[i] + fr[i] - integ[i]) / 2 for i in range(4)]
 
 
-def stage(nx, ny, lx, ly, gx, gy, beta, bc, qprev, q0, qn, dt, alpha, cfl, k, slip=False):
-    """qprev, q0, qn: float64 [4, ny, nx] with the pressure itself.  Backward Euler, local dtau.
-    Returns a dict with prim, grad (8 planes), fx, fy, resid and qout as float64 arrays."""
+def stage(nx, ny, lx, ly, gx, gy, beta, bc, qprev, q0, qn, dt, alpha, cfl, k, slip=False,
+          flux="osher", pgrad=0, pk=1, qnm1=None, qnm2=None, local=True):
+    """qprev, q0, qn (qnm1, qnm2): float64 [4, ny, nx] with the pressure itself.  BDF order from
+    the levels given; dt <= 0: no real-time term.  pgrad 0 new method, 1 k-limiter on p, 2 split
+    limiter.  Returns a dict with prim, grad (8 planes), fx, fy, resid and qout as float64."""
     mpf = mp.mpf
     dx, dy = mpf(lx) / nx, mpf(ly) / ny
-    beta, gx, gy, dt, alpha, cfl, k = map(mpf, (beta, gx, gy, dt, alpha, cfl, k))
+    pseudo_only = dt <= 0
+    beta, gx, gy, dt, alpha, cfl, k, pk = map(mpf, (beta, gx, gy, dt, alpha, cfl, k, pk))
+    B = [mpf(1), mpf(-1)]
+    if qnm1 is not None and qnm2 is not None:
+        B = [mpf(11) / 6, mpf(-3), mpf(3) / 2, mpf(-1) / 3]
+    elif qnm1 is not None:
+        B = [mpf(3) / 2, mpf(-2), mpf(1) / 2]
+    levels = [q0, qn, qnm1, qnm2][:len(B)]
+    riemann = {"osher": osher, "roe": roe, "bassi": bassi}[flux]
     P = 2
     NX, NY = nx + 2 * P, ny + 2 * P
 
@@ -79,7 +130,9 @@ def stage(nx, ny, lx, ly, gx, gy, beta, bc, qprev, q0, qn, dt, alpha, cfl, k, sl
             r = mpf(qprev[0, j, i])
             W[j + P][i + P] = [r, mpf(qprev[1, j, i]) / r, mpf(qprev[2, j, i]) / r,
                                beta * (mpf(qprev[3, j, i]) / beta)]
-            D[j + P][i + P] = [(mpf(q0[c, j, i]) - mpf(qn[c, j, i])) / dt for c in range(3)]
+            D[j + P][i + P] = [0 if pseudo_only else
+                               sum(b * mpf(lv[c, j, i]) for b, lv in zip(B, levels)) / dt
+                               for c in range(3)]
             R0[j + P][i + P] = mpf(q0[0, j, i])
 
     def mir_x(w):
@@ -89,27 +142,30 @@ def stage(nx, ny, lx, ly, gx, gy, beta, bc, qprev, q0, qn, dt, alpha, cfl, k, sl
         return [w[0], w[1] if slip else -w[1], -w[2]] + list(w[3:])
 
     def fill(arr, mx, my):
-        # x sides first (rows of the interior), then y sides over the full padded width
+        # x sides first (rows of the interior), then y sides over the full padded width; a
+        # zero-gradient side copies the mirror position unchanged
+        def img(side, w, m):
+            return list(w) if bc[side] == OPEN else m(w)
         for j in range(P, P + ny):
             for d in (1, 2):
                 if bc[0] == PERIODIC:
                     arr[j][P - d] = list(arr[j][P + nx - d])
                 else:
-                    arr[j][P - d] = mx(arr[j][P + d - 1])
+                    arr[j][P - d] = img(0, arr[j][P + d - 1], mx)
                 if bc[1] == PERIODIC:
                     arr[j][P + nx - 1 + d] = list(arr[j][P + d - 1])
                 else:
-                    arr[j][P + nx - 1 + d] = mx(arr[j][P + nx - d])
+                    arr[j][P + nx - 1 + d] = img(1, arr[j][P + nx - d], mx)
         for i in range(NX):
             for d in (1, 2):
                 if bc[2] == PERIODIC:
                     arr[P - d][i] = list(arr[P + ny - d][i])
                 else:
-                    arr[P - d][i] = my(arr[P + d - 1][i])
+                    arr[P - d][i] = img(2, arr[P + d - 1][i], my)
                 if bc[3] == PERIODIC:
                     arr[P + ny - 1 + d][i] = list(arr[P + d - 1][i])
                 else:
-                    arr[P + ny - 1 + d][i] = my(arr[P + ny - d][i])
+                    arr[P + ny - 1 + d][i] = img(3, arr[P + ny - d][i], my)
 
     fill(W, mir_x, mir_y)
     fill(D, mir_x, mir_y)     # D = (D_rho, D_rho u, D_rho v) mirrors like (rho, u, v)
@@ -118,12 +174,10 @@ def stage(nx, ny, lx, ly, gx, gy, beta, bc, qprev, q0, qn, dt, alpha, cfl, k, sl
     # gravity sign: reversed in wall ghosts (non-corner ring cells are what matter)
     for j in range(NY):
         for i in range(NX):
-            inside_x = P <= i < P + nx
-            inside_y = P <= j < P + ny
             rev = False
-            if not inside_x and bc[0] != PERIODIC:
+            if i < P and bc[0] == WALL or i >= P + nx and bc[1] == WALL:
                 rev = not rev
-            if not inside_y and bc[2] != PERIODIC:
+            if j < P and bc[2] == WALL or j >= P + ny and bc[3] == WALL:
                 rev = not rev
             GS[j][i] = -1 if rev else 1
 
@@ -142,8 +196,20 @@ def stage(nx, ny, lx, ly, gx, gy, beta, bc, qprev, q0, qn, dt, alpha, cfl, k, sl
             rx, ux, vx = gxv
             ry, uy, vy = gyv
             Dc, rho0, sg = D[j][i], R0w[j][i][0], GS[j][i]
-            px = -Dc[1] - (u * u * rx + 2 * r * u * ux) - (u * v * ry + r * u * vy + r * v * uy) + rho0 * gx * sg
-            py = -Dc[2] - (u * v * rx + r * u * vx + r * v * ux) - (v * v * ry + 2 * r * v * vy) + rho0 * gy * sg
+            if pgrad == 1:
+                px = G((W[j][i + 1][3] - c[3]) / dx, (c[3] - W[j][i - 1][3]) / dx, pk)
+                py = G((W[j + 1][i][3] - c[3]) / dy, (c[3] - W[j - 1][i][3]) / dy, pk)
+            elif pgrad == 2:
+                gxs, gys = gx * sg, gy * sg
+                kxr = (W[j][i + 1][3] - c[3]) / dx - (c[0] + W[j][i + 1][0]) * gxs / 2
+                kxl = (c[3] - W[j][i - 1][3]) / dx - (W[j][i - 1][0] + c[0]) * gxs / 2
+                kyr = (W[j + 1][i][3] - c[3]) / dy - (c[0] + W[j + 1][i][0]) * gys / 2
+                kyl = (c[3] - W[j - 1][i][3]) / dy - (W[j - 1][i][0] + c[0]) * gys / 2
+                px = c[0] * gxs + G(kxr, kxl, pk)
+                py = c[0] * gys + G(kyr, kyl, pk)
+            else:
+                px = -Dc[1] - (u * u * rx + 2 * r * u * ux) - (u * v * ry + r * u * vy + r * v * uy) + rho0 * gx * sg
+                py = -Dc[2] - (u * v * rx + r * u * vx + r * v * ux) - (v * v * ry + 2 * r * v * vy) + rho0 * gy * sg
             gp[(j, i)] = (px, py)
 
     def state(j, i, di, dj):
@@ -164,7 +230,7 @@ def stage(nx, ny, lx, ly, gx, gy, beta, bc, qprev, q0, qn, dt, alpha, cfl, k, sl
     for j in range(ny):
         for f in range(nx + 1):
             jj, il, ir = j + P, f + P - 1, f + P
-            F = osher(state(jj, il, +1, 0), state(jj, ir, -1, 0), beta)
+            F = riemann(state(jj, il, +1, 0), state(jj, ir, -1, 0), beta)
             FX[(j, f)] = F
             fx[:, j, f] = [float(x) for x in F]
     sw = [0, 2, 1, 3]
@@ -172,7 +238,7 @@ def stage(nx, ny, lx, ly, gx, gy, beta, bc, qprev, q0, qn, dt, alpha, cfl, k, sl
         for i in range(nx):
             ii, jl, jr = i + P, f + P - 1, f + P
             a, b = state(jl, ii, 0, +1), state(jr, ii, 0, -1)
-            F = osher([a[m] for m in sw], [b[m] for m in sw], beta)
+            F = riemann([a[m] for m in sw], [b[m] for m in sw], beta)
             F = [F[m] for m in sw]
             FY[(f, i)] = F
             fy[:, f, i] = [float(x) for x in F]
@@ -182,6 +248,17 @@ def stage(nx, ny, lx, ly, gx, gy, beta, bc, qprev, q0, qn, dt, alpha, cfl, k, sl
     resid = np.zeros((4, ny, nx))
     qout = np.zeros((4, ny, nx))
     dtau = np.zeros((ny, nx))
+    dtau_mp = {}
+    for j in range(ny):
+        for i in range(nx):
+            r0 = mpf(q0[0, j, i])
+            u0, v0 = mpf(q0[1, j, i]) / r0, mpf(q0[2, j, i]) / r0
+            cx = mp.sqrt(u0 * u0 + 4 * beta / r0)
+            cy = mp.sqrt(v0 * v0 + 4 * beta / r0)
+            dtau_mp[(j, i)] = cfl * dx * dy / ((abs(u0) + cx) / 2 * dy + (abs(v0) + cy) / 2 * dx)
+    if not local:
+        m = min(dtau_mp.values())
+        dtau_mp = {key: m for key in dtau_mp}
     for j in range(ny):
         for i in range(nx):
             jj, ii = j + P, i + P
@@ -190,10 +267,7 @@ def stage(nx, ny, lx, ly, gx, gy, beta, bc, qprev, q0, qn, dt, alpha, cfl, k, sl
             gout[:, j, i] = [float(x) for x in gxv] + [float(gp[(jj, ii)][0])] + \
                 [float(x) for x in gyv] + [float(gp[(jj, ii)][1])]
             r0 = mpf(q0[0, j, i])
-            u0, v0 = mpf(q0[1, j, i]) / r0, mpf(q0[2, j, i]) / r0
-            cx = mp.sqrt(u0 * u0 + 4 * beta / r0)
-            cy = mp.sqrt(v0 * v0 + 4 * beta / r0)
-            dtau_c = cfl * dx * dy / ((abs(u0) + cx) / 2 * dy + (abs(v0) + cy) / 2 * dx)
+            dtau_c = dtau_mp[(j, i)]
             dtau[j, i] = float(dtau_c)
             body = [0, r0 * gx, r0 * gy, 0]
             Dk = list(D[jj][ii]) + [0]
@@ -201,7 +275,7 @@ def stage(nx, ny, lx, ly, gx, gy, beta, bc, qprev, q0, qn, dt, alpha, cfl, k, sl
             for c in range(4):
                 br = -((FX[(j, i + 1)][c] - FX[(j, i)][c]) / dx + (FY[(j + 1, i)][c] - FY[(j, i)][c]) / dy) \
                     - Dk[c] + body[c]
-                api = 1 + alpha * dtau_c / dt if c < 3 else 1
+                api = 1 + B[0] * alpha * dtau_c / dt if c < 3 and not pseudo_only else 1
                 qn_c = q0v[c] + alpha * dtau_c / api * br
                 resid[c, j, i] = float(br * beta if c == 3 else br)
                 qout[c, j, i] = float(qn_c * beta if c == 3 else qn_c)
