@@ -43,8 +43,19 @@ enum {
     VDAC_E_DIVERGED = 4  /* non-finite residual or rho <= 0 during stepping */
 };
 
-/* Boundary kind per side, in the order x-, x+, y-, y+ (periodic sides must come in pairs). */
-enum { VDAC_BC_WALL = 0, VDAC_BC_PERIODIC = 1 };
+/* Boundary kind per side, in the order x-, x+, y-, y+ (periodic sides must come in pairs):
+ * walls (Sec. 2.5), periodic, or zero gradient of every variable (transmissive; its ghosts
+ * reflect the interior without changing any sign and keep gravity). */
+enum { VDAC_BC_WALL = 0, VDAC_BC_PERIODIC = 1, VDAC_BC_TRANSMISSIVE = 2 };
+
+/* x-split Riemann solver (Sec. 2.4): Osher-Dumbser-Toro (2.4.3), Roe at the Roe average
+ * (2.4.2), or the exact solver of Sec. 2.4.1 (Bassi et al.). */
+enum { VDAC_FLUX_OSHER = 0, VDAC_FLUX_ROE = 1, VDAC_FLUX_BASSI = 2 };
+
+/* Pressure gradient of the reconstruction (Sec. 2.3.2): the new method (rearranged momentum
+ * equation), the k-limiter applied to p, or the split limiter (hydrostatic part removed before
+ * limiting, restored after). */
+enum { VDAC_PGRAD_NEW = 0, VDAC_PGRAD_LIMITER = 1, VDAC_PGRAD_SPLIT = 2 };
 
 enum { VDAC_FP64 = 0, VDAC_FP32_MIXED = 1 };
 enum { VDAC_NORM_RMS = 0, VDAC_NORM_MAX = 1 };
@@ -67,8 +78,10 @@ typedef struct {
     double rk_alpha[8];  /* alpha_1..alpha_smax; alpha_smax must be 1 (Sec. 2.2.2) */
     double cfl_tau;      /* pseudo-time Courant number (Sec. 2.2.3), > 0 */
     double limiter_k;    /* k-limiter: 1 minmod, 2 superbee, in [1, 2] (Sec. 2.3.1) */
-    int32_t local_dtau;  /* must be 1: local pseudo-time steps (Sec. 2.2.3) */
-    int32_t bdf_order;   /* 1 backward Euler, 2 BDF2 (Table 1) */
+    int32_t local_dtau;  /* 1: local pseudo-time steps (Sec. 2.2.3); 0: one global step per
+                            tank and pseudo-iteration, the minimum local step */
+    int32_t bdf_order;   /* 1 backward Euler, 2 BDF2, 3 BDF3 (Table 1); the first step after
+                            set_state is backward Euler, the second at most BDF2 */
     int32_t norm;        /* VDAC_NORM_RMS or VDAC_NORM_MAX over fluid cells */
     int32_t wall_slip;   /* 0: no-slip wall ghosts as in Sec. 2.5; 1: free-slip ghosts */
     int32_t tile_x, tile_y; /* stage-kernel shape: 0 x 0 automatic; 1 x 1 one thread per cell;
@@ -77,10 +90,17 @@ typedef struct {
                                32 x 8, 16 x 16 or 64 x 4 two-dimensional LDS tiles */
     int32_t graph_iters; /* pseudo-iterations captured per HIP graph and replayed on the stream:
                             0 automatic, K > 0 exactly K, -1 launch kernels one by one */
+    int32_t flux;        /* VDAC_FLUX_* */
+    int32_t pgrad;       /* VDAC_PGRAD_* */
+    double p_limiter_k;  /* k of the limiter on p for VDAC_PGRAD_LIMITER / _SPLIT, in [1, 2] */
 } vdac_options;
+/* Options other than the defaults of flux, pgrad and local_dtau, BDF3 and zero-gradient sides
+ * run on the row-marching stage kernel only (tile 0 x 0 or -W x L); the split limiter is not
+ * available with zero-gradient sides. */
 
 /* Fills o with the defaults: FP64, 3 stages alpha = (1/3, 1/2, 1), CFL_tau 0.48, minmod,
- * local dtau, backward Euler, RMS norm, no-slip walls, automatic tiles, automatic graphs. */
+ * local dtau, backward Euler, RMS norm, no-slip walls, automatic tiles, automatic graphs, Osher
+ * flux, new pressure gradient. */
 void vdac_default_options(vdac_options *o);
 
 /* Device bytes create_grid needs for these tanks and options (0 on invalid arguments). */
@@ -99,8 +119,10 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
  * (Sec. 2.2.2).  rho must be finite and > 0 in every fluid cell, else VDAC_E_INVALID. */
 int set_state(vdac_grid *g, int32_t tank, const double *q);
 
-/* One real-time step of size dt > 0 for every tank (Algorithm 1).  Pseudo-iterations stop per
- * tank once every residual norm is below tol; tol <= 0 runs exactly max_pseudo iterations.
+/* One real-time step of size dt > 0 for every tank (Algorithm 1); dt = +infinity switches the
+ * real-time term off (pseudo-time only, as in the Riemann problems of Sec. 3.1).
+ * Pseudo-iterations stop per tank once every residual norm is below tol; tol <= 0 runs exactly
+ * max_pseudo iterations.
  * pseudo_done (nullable, [n_tanks]) receives the iterations each tank ran.  Returns
  * VDAC_E_DIVERGED if any tank produced a non-finite residual or rho <= 0 (that tank stops; its
  * state is the one after the failing iteration). */
@@ -113,6 +135,10 @@ int residual_norm(const vdac_grid *g, int32_t tank, double out[4]);
 
 /* Copies one tank's state to the host array q [4][ny][nx] (rho, rho*u, rho*v, p). */
 int get_state(const vdac_grid *g, int32_t tank, double *q);
+
+/* Global real-time step of one tank from its current state (Sec. 2.2.4):
+ * *dt = min over fluid cells of cfl_t dx dy / (|u| dy + |v| dx), +infinity at rest. */
+int realtime_dt(const vdac_grid *g, int32_t tank, double cfl_t, double *dt);
 
 /* Measurement: while enabled, step_dual_time launches kernels one by one (no graphs) and
  * brackets the s_max back-to-back Runge-Kutta stage launches of every pseudo-iteration with a

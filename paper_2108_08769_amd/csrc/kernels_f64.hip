@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
 
     const int i = blockIdx.x * kDirectTX + threadIdx.x;
     const int j = blockIdx.y * kDirectTY + threadIdx.y;
-    double part[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double part[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
 
     if (i < t.nx && j < t.ny) {
         const size_t c = (size_t)j * t.nx + i;
@@ -169,11 +169,12 @@ __global__ void __launch_bounds__(256) finalize_kernel(const TankDev *__restrict
     Status *st = t.status;
     if (st->done) return;
     const int n_blocks = t.n_partials;
-    double acc[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
     for (int b = threadIdx.x; b < n_blocks; b += 256)
         for (int k = 0; k < kPartialWidth; ++k) {
             const double x = t.partials[(size_t)b * kPartialWidth + k];
-            acc[k] = (NORM_MAX && k < 4) ? combine<true>(acc[k], x) : acc[k] + x;
+            acc[k] = (k == 5) ? fmin(acc[k], x)
+                              : ((NORM_MAX && k < 4) ? combine<true>(acc[k], x) : acc[k] + x);
         }
     __shared__ double red[256][kPartialWidth];
     for (int k = 0; k < kPartialWidth; ++k) red[threadIdx.x][k] = acc[k];
@@ -182,8 +183,9 @@ __global__ void __launch_bounds__(256) finalize_kernel(const TankDev *__restrict
         if ((int)threadIdx.x < s)
             for (int k = 0; k < kPartialWidth; ++k) {
                 const double y = red[threadIdx.x + s][k];
-                red[threadIdx.x][k] = (NORM_MAX && k < 4) ? combine<true>(red[threadIdx.x][k], y)
-                                                          : red[threadIdx.x][k] + y;
+                const double x = red[threadIdx.x][k];
+                red[threadIdx.x][k] = (k == 5) ? fmin(x, y)
+                                               : ((NORM_MAX && k < 4) ? combine<true>(x, y) : x + y);
             }
         __syncthreads();
     }
@@ -203,13 +205,15 @@ __global__ void __launch_bounds__(256) finalize_kernel(const TankDev *__restrict
         if (bad) st->diverged = 1;
         const bool converged = st->tol > 0.0 && below;
         st->done = (bad || converged || iters >= st->max_pseudo) ? 1 : 0;
+        if (red[0][5] < INFINITY) st->dtau_global = red[0][5];  // reduced only when global
     }
 }
 
-// Start of a real-time step (Algorithm 1) for tank blockIdx.y: level n-1 <- level n (BDF2 with
-// history) or <- the new level n (BDF2 without), level n <- current state, and a fresh
-// pseudo-loop status; workgroup (0, 0) also stores the step's BDF coefficients.  In the mixed
-// form the new level n is level n plus the current deviation, which then becomes zero.
+// Start of a real-time step (Algorithm 1) for tank blockIdx.y: with history the real-time levels
+// shift (n-2 <- n-1 <- n), else the kept earlier levels are set to the new level n; then level
+// n <- current state and a fresh pseudo-loop status; workgroup (0, 0) also stores the step's BDF
+// coefficients.  In the mixed form the new level n is level n plus the current deviation, which
+// then becomes zero.
 __global__ void __launch_bounds__(256)
     begin_step_kernel(const TankDev *__restrict__ tanks, StepParams sp, int max_pseudo, double tol,
                       int use_history, int mixed)
@@ -220,24 +224,20 @@ __global__ void __launch_bounds__(256)
     const size_t plane = t.plane;
     for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < plane;
          c += (size_t)gridDim.x * 256) {
-        if (mixed) {
-            float *d = (float *)t.state[cur];
+        float *d = (float *)t.state[cur];
+        const double *q = (const double *)t.state[cur];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const double old = t.level_n[k * plane + c];
-                const double nw = old + (double)d[k * plane + c];
-                if (k < 3 && t.level_nm1) t.level_nm1[k * plane + c] = use_history ? old : nw;
-                t.level_n[k * plane + c] = nw;
-                d[k * plane + c] = 0.0f;
+        for (int k = 0; k < 4; ++k) {
+            if (k == 3 && !mixed) break;  // the FP64 form keeps no level-n pressure
+            const size_t e = k * plane + c;
+            const double old = t.level_n[e];
+            const double nw = mixed ? old + (double)d[e] : q[e];
+            if (k < 3) {
+                if (t.level_nm2) t.level_nm2[e] = use_history ? t.level_nm1[e] : nw;
+                if (t.level_nm1) t.level_nm1[e] = use_history ? old : nw;
             }
-        } else {
-            const double *q = (const double *)t.state[cur];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const double nw = q[k * plane + c];
-                if (t.level_nm1) t.level_nm1[k * plane + c] = use_history ? t.level_n[k * plane + c] : nw;
-                t.level_n[k * plane + c] = nw;
-            }
+            t.level_n[e] = nw;
+            if (mixed) d[e] = 0.0f;
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(256)
 }
 
 // Mixed form: the caller's FP64 state q [4][plane] (rho, rho u, rho v, p) becomes level n (and
-// n-1 for the first three fields) and zero deviations in all three state buffers.
+// n-1, n-2 for the first three fields) and zero deviations in all three state buffers.
 __global__ void __launch_bounds__(256) import_mixed_kernel(TankDev t, const double *__restrict__ q)
 {
     const size_t plane = t.plane;
@@ -262,6 +262,7 @@ __global__ void __launch_bounds__(256) import_mixed_kernel(TankDev t, const doub
             const double v = q[k * plane + c];
             t.level_n[k * plane + c] = v;
             if (k < 3 && t.level_nm1) t.level_nm1[k * plane + c] = v;
+            if (k < 3 && t.level_nm2) t.level_nm2[k * plane + c] = v;
         }
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
@@ -283,6 +284,40 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int k = 0; k < 4; ++k) q[k * plane + c] = t.level_n[k * plane + c] + (double)d[k * plane + c];
     }
+}
+
+// Global real-time step (Sec. 2.2.4): per-workgroup minima over fluid cells of
+// CFL_t dx dy / (|u| dy + |v| dx) of the current state (infinity at rest).
+__global__ void __launch_bounds__(256)
+    realtime_dt_kernel(TankDev t, int mixed, double cfl_t, double *__restrict__ out)
+{
+    const Status *st = t.status;
+    const int cur = st->cur;
+    const size_t plane = t.plane;
+    double m = INFINITY;
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < plane;
+         c += (size_t)gridDim.x * 256) {
+        if (t.flags[c] & FLAG_SOLID) continue;
+        double r, mu, mv;
+        if (mixed) {
+            const float *d = (const float *)t.state[cur];
+            r = t.level_n[c] + (double)d[c];
+            mu = t.level_n[plane + c] + (double)d[plane + c];
+            mv = t.level_n[2 * plane + c] + (double)d[2 * plane + c];
+        } else {
+            const double *q = (const double *)t.state[cur];
+            r = q[c];
+            mu = q[plane + c];
+            mv = q[2 * plane + c];
+        }
+        const double lam = (fabs(mu) * t.dy + fabs(mv) * t.dx) / r;
+        m = fmin(m, cfl_t * (t.dx * t.dy) / lam);
+    }
+    for (int off = 32; off >= 1; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
 unsigned cell_blocks(size_t plane)
@@ -307,6 +342,14 @@ int launch_begin_step_all(const TankDev *tanks_dev, int n_tanks, size_t max_plan
     const dim3 grid(cell_blocks(max_plane), (unsigned)n_tanks);
     hipLaunchKernelGGL(begin_step_kernel, grid, dim3(256), 0, (hipStream_t)stream, tanks_dev, sp,
                        max_pseudo, tol, use_history, sc.mixed);
+    return (int)hipGetLastError();
+}
+
+int launch_realtime_dt(const TankDev &t, int mixed, double cfl_t, double *out, int n_blocks,
+                       void *stream)
+{
+    hipLaunchKernelGGL(realtime_dt_kernel, dim3((unsigned)n_blocks), dim3(256), 0,
+                       (hipStream_t)stream, t, mixed, cfl_t, out);
     return (int)hipGetLastError();
 }
 

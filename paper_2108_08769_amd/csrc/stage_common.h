@@ -48,6 +48,7 @@ __device__ __forceinline__ TankDev load_tank(const TankDev *__restrict__ p)
     t.state[0] = t.state[1] = t.state[2] = nullptr;  // see state_buf
     t.level_n = uni(p->level_n);
     t.level_nm1 = uni(p->level_nm1);
+    t.level_nm2 = uni(p->level_nm2);
     t.flags = uni(p->flags);
     t.partials = uni(p->partials);
     t.status = uni(p->status);
@@ -56,6 +57,7 @@ __device__ __forceinline__ TankDev load_tank(const TankDev *__restrict__ p)
     t.n_partials = uni(p->n_partials);
     t.n_strips = uni(p->n_strips);
     t.chunk = uni(p->chunk);
+    t.open = uni(p->open);
     return t;
 }
 
@@ -100,7 +102,8 @@ __device__ __forceinline__ double combine(double a, double b)
     return NORM_MAX ? (a > b || a != a ? a : b) : a + b;
 }
 
-// Workgroup reduction of the residual partials (fixed order: deterministic).
+// Workgroup reduction of the residual partials (fixed order: deterministic): sums or maxima of the
+// four fields, the sum of bad cells, the minimum pseudo-time step.
 template <bool NORM_MAX, int NT>
 __device__ __forceinline__ void block_reduce_store(double v[kPartialWidth], double *out)
 {
@@ -111,7 +114,7 @@ __device__ __forceinline__ void block_reduce_store(double v[kPartialWidth], doub
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             const double y = __shfl_xor(x, off, 64);
-            x = mx ? combine<true>(x, y) : x + y;
+            x = (k == 5) ? fmin(x, y) : (mx ? combine<true>(x, y) : x + y);
         }
         v[k] = x;
     }
@@ -125,7 +128,8 @@ __device__ __forceinline__ void block_reduce_store(double v[kPartialWidth], doub
         for (int k = 0; k < kPartialWidth; ++k) {
             double x = red[0][k];
             for (int w = 1; w < NT / 64; ++w)
-                x = (NORM_MAX && k < 4) ? combine<true>(x, red[w][k]) : x + red[w][k];
+                x = (k == 5) ? fmin(x, red[w][k])
+                             : ((NORM_MAX && k < 4) ? combine<true>(x, red[w][k]) : x + red[w][k]);
             out[k] = x;
         }
     }
@@ -198,60 +202,6 @@ __device__ __forceinline__ void store_state(const TankDev &t, void *buf, size_t 
         q[2 * plane + c] = n;
     }
     q[3 * plane + c] = (typename P::Store)p;
-}
-
-// Stage-0 data of one cell: Q^0 (rho, rho u, rho v, p), level n, and the real-time term
-// (B0 Q^0 + B1 Q^n + B2 Q^{n-1})/dt of eq. bdf on rho, rho u, rho v.  The mixed form keeps the
-// stored deviations d = Q^0 - Q^n and, since B0 + B1 + B2 = 0, forms the term as
-// (B0 d + B2 (Q^{n-1} - Q^n))/dt without cancellation.
-struct Stage0 {
-    double z0, z1, z2, z3;  // Q^0
-    double n0, n1, n2;      // level n
-    double d0, d1, d2;      // real-time term
-};
-
-template <class P, bool BDF2>
-__device__ __forceinline__ Stage0 load_stage0(const TankDev &t, const void *q0buf, size_t c,
-                                              const StepParams &sp)
-{
-    const size_t plane = t.plane;
-    const typename P::Store *q = (const typename P::Store *)q0buf;
-    Stage0 s;
-    s.n0 = t.level_n[c];
-    s.n1 = t.level_n[plane + c];
-    s.n2 = t.level_n[2 * plane + c];
-    s.z3 = (double)q[3 * plane + c];
-    if (P::kMixed) {
-        const double e0 = q[c], e1 = q[plane + c], e2 = q[2 * plane + c];
-        s.z0 = s.n0 + e0;
-        s.z1 = s.n1 + e1;
-        s.z2 = s.n2 + e2;
-        double a0 = sp.b0 * e0, a1 = sp.b0 * e1, a2 = sp.b0 * e2;
-        if (BDF2) {
-            a0 = fma(sp.b2, t.level_nm1[c] - s.n0, a0);
-            a1 = fma(sp.b2, t.level_nm1[plane + c] - s.n1, a1);
-            a2 = fma(sp.b2, t.level_nm1[2 * plane + c] - s.n2, a2);
-        }
-        s.d0 = a0 * sp.inv_dt;
-        s.d1 = a1 * sp.inv_dt;
-        s.d2 = a2 * sp.inv_dt;
-    } else {
-        s.z0 = q[c];
-        s.z1 = q[plane + c];
-        s.z2 = q[2 * plane + c];
-        double a0 = fma(sp.b0, s.z0, sp.b1 * s.n0);
-        double a1 = fma(sp.b0, s.z1, sp.b1 * s.n1);
-        double a2 = fma(sp.b0, s.z2, sp.b1 * s.n2);
-        if (BDF2) {
-            a0 = fma(sp.b2, t.level_nm1[c], a0);
-            a1 = fma(sp.b2, t.level_nm1[plane + c], a1);
-            a2 = fma(sp.b2, t.level_nm1[2 * plane + c], a2);
-        }
-        s.d0 = a0 * sp.inv_dt;
-        s.d1 = a1 * sp.inv_dt;
-        s.d2 = a2 * sp.inv_dt;
-    }
-    return s;
 }
 
 // A fluid cell as the reconstruction sees it: W, limited slopes along x and y, and the stage-0

@@ -1,0 +1,660 @@
+// stage_march.h -- the Runge-Kutta stage kernel for gfx950 in its row-marching form, for the
+// FP64 and the mixed-precision storage, over any number of tanks in one launch.  Instantiated
+// by stage_march.hip (the default scheme: Osher-Dumbser-Toro flux, new pressure gradient, walls
+// and periodic sides, local pseudo-time steps) and stage_march_gen.hip (GEN: the Roe or exact
+// flux, the k-limiter or the split limiter on p, zero-gradient sides and the global
+// pseudo-time step chosen at run time).
+//
+// Work comes from a unit table: entry e of the table is the work of wave e % W of workgroup
+// e / W (W waves per workgroup), one chunk of rows of one 64-column strip of one tank.  The host
+// orders the table so that workgroup b, which the dispatcher places on XCD b % 8, gets a unit
+// next to the other units of that XCD (one L2 per XCD).
+//
+// Each 64-lane wave owns a strip of 64 consecutive columns (lanes 2..61 produce output, lanes
+// 0-1 and 62-63 are the halo the reconstruction and the x-faces need) and sweeps its chunk of
+// rows upward.  The three rows the limited slopes need stay in registers, x-neighbours come from
+// cross-lane DPP moves, and the loads of the next row are issued a full row ahead of their use.
+// No LDS, no workgroup barrier.  Per row r the wave
+//   1. reconstructs row r once per lane: limited slopes (Sec. 2.3.1), the stage-0 sources from
+//      Q^0 and level n, the new pressure gradient (Sec. 2.3.2), and the states at the four faces;
+//   2. evaluates the x-faces of row r with the Osher-Dumbser-Toro flux (Sec. 2.4.3): lane x takes
+//      the face on its right, its right neighbour receives the result for its left face; a lane
+//      whose left face is a wall evaluates that face itself from its own ghost (Sec. 2.5);
+//   3. evaluates the y-face between rows r-1 and r (rotated, Sec. 2.4); a face with a wall above
+//      row r is evaluated with row r's ghost and carried to the next row;
+//   4. completes row r-1: flux divergence, frozen sources, point-implicit update (eq. RK2), and
+//      on the last stage the residual partial.
+// Each face is evaluated once.  Periodic sides wrap indices; cells outside a non-periodic side
+// read as non-fluid.
+//
+// Mixed form: all four fields are stored as FP32 deviations from the FP64 level n, so the
+// absolute state is known to FP64 accuracy up to the FP32 rounding of the (small) deviations.
+// The reconstruction and the fluxes run in FP32 on pressures measured from the pressure of the
+// face's lower-index cell (the ghost's, equal to the cell's own, on a wall).  The Osher flux
+// depends on p only through the p term of the normal momentum flux and through p differences, so
+// the shift is exact: the divergence adds back p_i - p_ref of the lower face in FP64.  This keeps
+// the hydrostatic pressure differences, which are small against p itself, to FP32 precision of
+// the differences.  Sources, divergence, update and norm run in FP64; the update is formed on
+// the deviation from level n, then rounded to FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "stage_common.h"
+
+namespace vdac {
+
+namespace march {
+
+constexpr int kLanes = 64;
+constexpr int kOut = 60;            // output columns per strip (lanes 2..61)
+constexpr int kMaxWavesPerBlock = 4;
+
+__device__ __forceinline__ bool locate_axis(int g, int n, int periodic, int &out)
+{
+    if (g < 0 || g >= n) {
+        if (!periodic) return false;
+        while (g < 0) g += n;
+        while (g >= n) g -= n;
+    }
+    out = g;
+    return true;
+}
+
+// Neighbour exchange across the wave with DPP moves (wave_shr:1 / wave_shl:1 shift a value one
+// lane up / down the whole 64-lane wave in one VALU instruction); the lane without a source
+// (lane 0, resp. 63, a halo lane) reads zero.
+constexpr int kDppWaveShr1 = 0x138, kDppWaveShl1 = 0x130;
+
+__device__ __forceinline__ float from_left(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kDppWaveShr1, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_right(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kDppWaveShl1, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double from_left(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, kDppWaveShr1, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), kDppWaveShr1, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double from_right(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, kDppWaveShl1, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), kDppWaveShl1, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <typename T>
+__device__ __forceinline__ Prim<T> prim_from_left(const Prim<T> &w)
+{
+    return {from_left(w.r), from_left(w.u), from_left(w.v), from_left(w.p)};
+}
+template <typename T>
+__device__ __forceinline__ Prim<T> prim_from_right(const Prim<T> &w)
+{
+    return {from_right(w.r), from_right(w.u), from_right(w.v), from_right(w.p)};
+}
+
+template <typename T, typename U>
+__device__ __forceinline__ Vec4<T> cast4(const Vec4<U> &a)
+{
+    return {(T)a.a, (T)a.b, (T)a.c, (T)a.d};
+}
+
+// Loads of one row, issued one step ahead of their use: the stage input is fetched two rows
+// ahead (it is the upper neighbour of the next row), the stage-0 state, level n (and level
+// n-1) and the flags one row ahead.
+template <class P>
+struct InputLoad {
+    typename P::Store r, m, n, p;  // stage input Q^{s-1} (mixed: deviations from level n)
+    double lr, lm, ln, lp;         // level n of rho, rho u, rho v, p (mixed form only)
+};
+template <class P>
+struct SourceLoad {
+    typename P::Store z0, z1, z2, z3;  // stage-0 state Q^0 (mixed: deviations from level n)
+    double n0, n1, n2;                 // level n (FP64 form only)
+    double m0, m1, m2;                 // level n-1 (BDF2, BDF3)
+    double k0, k1, k2;                 // level n-2 (BDF3)
+    uint8_t f;                         // cell flags (FLAG_SOLID if outside the tank)
+};
+
+template <class P>
+__device__ __forceinline__ InputLoad<P> load_input(const TankDev &t,
+                                                   const typename P::Store *__restrict__ qprev,
+                                                   bool have_col, int gi, int r)
+{
+    using S = typename P::Store;
+    int gj;
+    InputLoad<P> L;
+    L.r = P::kMixed ? S(0) : S(1);
+    L.m = L.n = L.p = S(0);
+    L.lr = 1.0;
+    L.lm = L.ln = L.lp = 0.0;
+    if (have_col && locate_axis(r, t.ny, t.per_y, gj)) {
+        const size_t plane = t.plane;
+        const size_t c = (size_t)gj * t.nx + gi;
+        L.r = qprev[c];
+        L.m = qprev[plane + c];
+        L.n = qprev[2 * plane + c];
+        L.p = qprev[3 * plane + c];
+        if (P::kMixed) {
+            L.lr = t.level_n[c];
+            L.lm = t.level_n[plane + c];
+            L.ln = t.level_n[2 * plane + c];
+            L.lp = t.level_n[3 * plane + c];
+        }
+    }
+    return L;
+}
+
+template <class P, int BDF>
+__device__ __forceinline__ SourceLoad<P> load_sources(const TankDev &t,
+                                                      const typename P::Store *__restrict__ q0,
+                                                      bool have_col, int gi, int r)
+{
+    using S = typename P::Store;
+    int gj;
+    SourceLoad<P> L;
+    L.z0 = P::kMixed ? S(0) : S(1);
+    L.z1 = L.z2 = L.z3 = S(0);
+    L.n0 = L.m0 = L.k0 = 1.0;
+    L.n1 = L.n2 = L.m1 = L.m2 = L.k1 = L.k2 = 0.0;
+    L.f = FLAG_SOLID;
+    if (have_col && locate_axis(r, t.ny, t.per_y, gj)) {
+        const size_t plane = t.plane;
+        const size_t c = (size_t)gj * t.nx + gi;
+        L.f = t.flags[c];
+        L.z0 = q0[c];
+        L.z1 = q0[plane + c];
+        L.z2 = q0[2 * plane + c];
+        L.z3 = q0[3 * plane + c];
+        if (!P::kMixed) {  // the mixed form takes level n from the input row (it carries it)
+            L.n0 = t.level_n[c];
+            L.n1 = t.level_n[plane + c];
+            L.n2 = t.level_n[2 * plane + c];
+        }
+        if (BDF >= 2) {
+            L.m0 = t.level_nm1[c];
+            L.m1 = t.level_nm1[plane + c];
+            L.m2 = t.level_nm1[2 * plane + c];
+        }
+        if (BDF >= 3) {
+            L.k0 = t.level_nm2[c];
+            L.k1 = t.level_nm2[plane + c];
+            L.k2 = t.level_nm2[2 * plane + c];
+        }
+    }
+    return L;
+}
+
+// Primitives of a loaded cell in the reconstruction precision.  In the mixed form p is left at
+// zero: the face pressures come from the FP64 pressure (abs_p) through differences.
+template <class P>
+__device__ __forceinline__ Prim<typename P::Real> to_prim(const InputLoad<P> &L)
+{
+    if constexpr (P::kMixed) {
+        const float r = (float)(L.lr + (double)L.r);
+        const float m = (float)(L.lm + (double)L.m);
+        const float n = (float)(L.ln + (double)L.n);
+        const float ir = rcp_pos(r);
+        return {r, m * ir, n * ir, 0.0f};
+    } else {
+        const double ir = rcp_pos(L.r);
+        return {L.r, L.m * ir, L.n * ir, L.p};
+    }
+}
+
+// Absolute pressure of a loaded cell in FP64.
+template <class P>
+__device__ __forceinline__ double abs_p(const InputLoad<P> &L)
+{
+    return P::kMixed ? L.lp + (double)L.p : (double)L.p;
+}
+
+// Pressure gradient along one axis by the k-limiter on p (pgrad 1) or the split limiter
+// (pgrad 2, Sec. 2.3.2): from the pressure differences dpr = p_{i+1} - p_i, dpl = p_i - p_{i-1}
+// (FP64), the densities of the stencil and the gravity component g along the axis.
+__device__ __forceinline__ double pgrad_limited(int pgrad, double pk, double dpr, double dpl,
+                                               double inv_h, double rl, double rc, double rr,
+                                               double g)
+{
+    if (pgrad == 1) return limiter(dpr * inv_h, dpl * inv_h, pk);
+    const double kr = fma(dpr, inv_h, -0.5 * (rc + rr) * g);
+    const double kl = fma(dpl, inv_h, -0.5 * (rl + rc) * g);
+    return fma(rc, g, limiter(kr, kl, pk));
+}
+
+// Ghost of a reconstructed cell for the general kernel: across a wall (open = false) or a
+// zero-gradient side (open = true: no velocity sign change, gravity kept, sources kept).  Its
+// normal p-slope: the new method evaluates the rearranged momentum equation in the ghost; the
+// k-limiter on p gives zero at such a face on both sides; the split limiter gives minus the
+// cell's (the wall ghost's stencil is the cell's reflected, with gravity reversed).
+template <typename R>
+__device__ __forceinline__ Prim<R> ghost_state_gen(const TankDev &t, const Scheme &sc,
+                                                   const CellRecT<R> &c, int axis, int sd,
+                                                   bool open, R p_own_slope, R pbase)
+{
+    const bool slip = sc.slip != 0;
+    const R su = (open || (slip && axis == 1)) ? R(1) : R(-1);
+    const R sv = (open || (slip && axis == 0)) ? R(1) : R(-1);
+    const R gs = open ? R(1) : R(-1);
+    const Prim<R> w = {c.w.r, su * c.w.u, sv * c.w.v, c.w.p};
+    if (axis == 0) {
+        const Slope<R> gx = c.gx;
+        const Slope<R> gy = {c.gy.r, su * c.gy.u, sv * c.gy.v};
+        const R px = sc.pgrad == 0 ? gradp_x(w, gx, gy, su * c.d_ru, gs * (c.rho0 * (R)t.gx))
+                                   : (sc.pgrad == 1 ? p_own_slope : -p_own_slope);
+        const R h = sd > 0 ? -(R)t.half_dx : (R)t.half_dx;
+        return state_at(w, gx, px, h, pbase);
+    }
+    const Slope<R> gy = c.gy;
+    const Slope<R> gx = {c.gx.r, su * c.gx.u, sv * c.gx.v};
+    const R py = sc.pgrad == 0 ? gradp_y(w, gx, gy, sv * c.d_rv, gs * (c.rho0 * (R)t.gy))
+                               : (sc.pgrad == 1 ? p_own_slope : -p_own_slope);
+    const R h = sd > 0 ? -(R)t.half_dy : (R)t.half_dy;
+    return state_at(w, gy, py, h, pbase);
+}
+
+// WAVES: the register budget as waves per SIMD (2: up to 256 VGPRs per lane, 3: up to 168).
+// BDF: the highest real-time order of the grid (levels n-1, n-2 read); GEN: general options.
+template <class P, bool NORM_MAX, int BDF, bool LAST, int WAVES, bool GEN>
+__global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
+    stage_march(const TankDev *__restrict__ tanks, const MarchUnit *__restrict__ units, Scheme sc,
+                int stage)
+{
+    using R = typename P::Real;
+    using S = typename P::Store;
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    const int lane = threadIdx.x % kLanes;
+    const MarchUnit un = units[blockIdx.x * (blockDim.x / kLanes) + wave];
+    if (un.tank < 0) return;  // padding (uniform per wave)
+    const TankDev t = load_tank(tanks + un.tank);
+    const Status *st = t.status;
+    if (st->done) return;
+
+    const int strip = un.local % t.n_strips, ch = un.local / t.n_strips;
+    const int col = strip * kOut - 2 + lane;  // this lane's column (may lie outside the tank)
+    int gi = 0;
+    const bool have_col = locate_axis(col, t.nx, t.per_x, gi);
+    const bool out_lane = lane >= 2 && lane < 2 + kOut && col >= 0 && col < t.nx;
+    const int j0 = ch * t.chunk;
+    const int j1 = min(j0 + t.chunk, t.ny);
+
+    const int cur = st->cur;
+    const StageBuffers bufs = stage_buffers(cur, stage);
+    const S *__restrict__ qprev = (const S *)state_buf(tanks + un.tank, bufs.in);
+    const S *__restrict__ q0 = (const S *)state_buf(tanks + un.tank, cur);
+    S *__restrict__ qout = (S *)state_buf(tanks + un.tank, bufs.out);
+    const StepParams sp = *t.step;
+    const bool slip = sc.slip != 0;
+    const R kl = (R)sc.k;
+    const double alpha = sc.alpha[stage - 1];
+    const size_t plane = t.plane;
+    const R hx = (R)t.half_dx, hy = (R)t.half_dy;
+    const R beta = (R)t.beta, inv_beta = (R)t.inv_beta;
+    // general options: zero-gradient faces of this lane's column, global pseudo-time step
+    const bool open_xm = GEN && col == 0 && (t.open & 1);
+    const bool open_xp = GEN && col == t.nx - 1 && (t.open & 2);
+    const double dtau_glob = GEN ? st->dtau_global : 0.0;
+    const bool use_glob = GEN && sc.global_dtau != 0;
+
+    // window of primitives: rows r-1 (lo), r (mid), r+1 (hi); loads for later rows in flight
+    // (plo, pmid, phi: their absolute pressures in FP64)
+    // (mixed form: lvl_mid, lvl_hi carry level n of rho, rho u, rho v of rows r and r+1, which
+    // the input loads fetched, so that the sources need not fetch it again)
+    Prim<R> lo, mid, hi;
+    double plo, pmid, phi;
+    Vec4<double> lvl_mid = zero4<double>(), lvl_hi = zero4<double>();
+    {
+        const InputLoad<P> a = load_input<P>(t, qprev, have_col, gi, j0 - 2);
+        const InputLoad<P> b = load_input<P>(t, qprev, have_col, gi, j0 - 1);
+        const InputLoad<P> c = load_input<P>(t, qprev, have_col, gi, j0);
+        lo = to_prim(a);
+        mid = to_prim(b);
+        hi = to_prim(c);
+        plo = abs_p(a);
+        pmid = abs_p(b);
+        phi = abs_p(c);
+        if constexpr (P::kMixed) {
+            lvl_mid = {b.lr, b.lm, b.ln, 0.0};
+            lvl_hi = {c.lr, c.lm, c.ln, 0.0};
+        }
+    }
+    InputLoad<P> in_ld = load_input<P>(t, qprev, have_col, gi, j0 + 1);             // row r+2
+    SourceLoad<P> src_ld = load_sources<P, BDF>(t, q0, have_col, gi, j0 - 1);       // row r
+
+    // carries from row r-1:
+    //  below      its state at its upper face, or, if that face is a wall, the face's flux
+    //  pre        its update without the flux above it: non-final stages carry
+    //             pre = Q^0 + fac R_partial; the final stage keeps Q^0 and R_partial apart for
+    //             the residual norm (mixed form: deviations from level n in place of Q)
+    //  lvl        final stage, mixed form: its level-n density (for the positivity check); the
+    //             general kernel also keeps rho u, rho v of level n (lvl_m, lvl_n) for the
+    //             pseudo-time step of the updated state
+    Vec4<R> below = {R(1), R(0), R(0), R(0)};
+    Vec4<double> pre = zero4<double>();
+    Vec4<double> rpart = zero4<double>();
+    double fac = 0.0, adt = 0.0, lvl = 0.0, lvl_m = 0.0, lvl_n = 0.0;
+    bool fluid_lo = false;
+    double part0 = 0.0, part1 = 0.0, part2 = 0.0, part3 = 0.0, part4 = 0.0, part5 = INFINITY;
+
+    for (int r = j0 - 1; r <= j1; ++r) {
+        // sources of row r (loaded one step ahead), then the next loads
+        const uint8_t f = src_ld.f;
+        const bool fluid = !(f & FLAG_SOLID);
+        // z: the base of the update (Q^0, or its deviation and p^0); a0..a2: absolute Q^0
+        const Vec4<double> z = {(double)src_ld.z0, (double)src_ld.z1, (double)src_ld.z2,
+                                (double)src_ld.z3};
+        double a0, a1, a2, num0, num1, num2;
+        double lvl_r;  // level-n density of row r
+        if constexpr (P::kMixed) {
+            // (B0 Q^0 + B1 Q^n + B2 Q^{n-1}) = B0 (Q^0 - Q^n) + B2 (Q^{n-1} - Q^n): B0+B1+B2 = 0
+            a0 = lvl_mid.a + z.a;
+            a1 = lvl_mid.b + z.b;
+            a2 = lvl_mid.c + z.c;
+            num0 = sp.b0 * z.a;
+            num1 = sp.b0 * z.b;
+            num2 = sp.b0 * z.c;
+            if (BDF >= 2) {
+                num0 = fma(sp.b2, src_ld.m0 - lvl_mid.a, num0);
+                num1 = fma(sp.b2, src_ld.m1 - lvl_mid.b, num1);
+                num2 = fma(sp.b2, src_ld.m2 - lvl_mid.c, num2);
+            }
+            if (BDF >= 3) {
+                num0 = fma(sp.b3, src_ld.k0 - lvl_mid.a, num0);
+                num1 = fma(sp.b3, src_ld.k1 - lvl_mid.b, num1);
+                num2 = fma(sp.b3, src_ld.k2 - lvl_mid.c, num2);
+            }
+            lvl_r = lvl_mid.a;
+        } else {
+            a0 = z.a;
+            a1 = z.b;
+            a2 = z.c;
+            num0 = fma(sp.b0, z.a, sp.b1 * src_ld.n0);
+            num1 = fma(sp.b0, z.b, sp.b1 * src_ld.n1);
+            num2 = fma(sp.b0, z.c, sp.b1 * src_ld.n2);
+            if (BDF >= 2) {
+                num0 = fma(sp.b2, src_ld.m0, num0);
+                num1 = fma(sp.b2, src_ld.m1, num1);
+                num2 = fma(sp.b2, src_ld.m2, num2);
+            }
+            if (BDF >= 3) {
+                num0 = fma(sp.b3, src_ld.k0, num0);
+                num1 = fma(sp.b3, src_ld.k1, num1);
+                num2 = fma(sp.b3, src_ld.k2, num2);
+            }
+            lvl_r = src_ld.n0;
+        }
+        const double d_r = num0 * sp.inv_dt, d_ru = num1 * sp.inv_dt, d_rv = num2 * sp.inv_dt;
+        const Prim<R> next_hi = to_prim(in_ld);
+        const double next_phi = abs_p(in_ld);
+        const Vec4<double> next_lvl = {in_ld.lr, in_ld.lm, in_ld.ln, 0.0};
+        in_ld = load_input<P>(t, qprev, have_col, gi, r + 3);
+        src_ld = load_sources<P, BDF>(t, q0, have_col, gi, r + 1);
+
+        // ---- reconstruction of row r ------------------------------------------------------
+        const Prim<R> wl = prim_from_left(mid);
+        const Prim<R> wr = prim_from_right(mid);
+        CellRecT<R> rec;
+        rec.w = mid;
+        rec.d_r = (R)d_r;
+        rec.d_ru = (R)d_ru;
+        rec.d_rv = (R)d_rv;
+        rec.rho0 = (R)a0;
+        // zero-gradient faces of row r (general kernel)
+        const bool open_ym = GEN && r == 0 && (t.open & 4);
+        const bool open_yp = GEN && r == t.ny - 1 && (t.open & 8);
+        const double pright = GEN ? from_right(pmid) : 0.0;  // shuffles: every lane takes part
+        const double pleft_g = GEN ? from_left(pmid) : 0.0;
+        R px = R(0), py = R(0);
+        if (fluid) {
+            const Prim<R> xm = (f & FLAG_WALL_XM) ? (open_xm ? mid : mirror(mid, 0, slip)) : wl;
+            const Prim<R> xp = (f & FLAG_WALL_XP) ? (open_xp ? mid : mirror(mid, 0, slip)) : wr;
+            const Prim<R> ym = (f & FLAG_WALL_YM) ? (open_ym ? mid : mirror(mid, 1, slip)) : lo;
+            const Prim<R> yp = (f & FLAG_WALL_YP) ? (open_yp ? mid : mirror(mid, 1, slip)) : hi;
+            rec.gx = slopes(xm, mid, xp, (R)t.inv_dx, kl);
+            rec.gy = slopes(ym, mid, yp, (R)t.inv_dy, kl);
+            if (GEN && sc.pgrad != 0) {
+                // across a wall or zero-gradient face the stencil sees the cell's own p and rho
+                const double dpr_x = (f & FLAG_WALL_XP) ? 0.0 : pright - pmid;
+                const double dpl_x = (f & FLAG_WALL_XM) ? 0.0 : pmid - pleft_g;
+                const double dpr_y = (f & FLAG_WALL_YP) ? 0.0 : phi - pmid;
+                const double dpl_y = (f & FLAG_WALL_YM) ? 0.0 : pmid - plo;
+                px = (R)pgrad_limited(sc.pgrad, sc.pk, dpr_x, dpl_x, t.inv_dx, (double)xm.r,
+                                      (double)mid.r, (double)xp.r, t.gx);
+                py = (R)pgrad_limited(sc.pgrad, sc.pk, dpr_y, dpl_y, t.inv_dy, (double)ym.r,
+                                      (double)mid.r, (double)yp.r, t.gy);
+            } else {
+                px = cell_gradp_x(t, rec);
+                py = cell_gradp_y(t, rec);
+            }
+        } else {
+            rec.gx = {R(0), R(0), R(0)};
+            rec.gy = {R(0), R(0), R(0)};
+        }
+        // pressure each face state is expressed from: the absolute p (FP64 form), or p minus
+        // the pressure of the face's lower-index cell (mixed form); sx, sy add that reference
+        // back at the lower faces in FP64
+        R pb_own = mid.p, pb_xl = mid.p, pb_yb = mid.p;
+        double sx = 0.0, sy = 0.0;
+        if constexpr (P::kMixed) {
+            const double pleft = from_left(pmid);  // a shuffle: every lane takes part
+            sx = (f & FLAG_WALL_XM) ? 0.0 : pmid - pleft;
+            sy = (f & FLAG_WALL_YM) ? 0.0 : pmid - plo;
+            pb_own = R(0);
+            pb_xl = (R)sx;
+            pb_yb = (R)sy;
+        }
+
+        // ---- y-face between rows r-1 and r ------------------------------------------------
+        Vec4<R> gb = zero4<R>();
+        if (r >= j0) {
+            if (fluid) {
+                Prim<R> L;
+                if (fluid_lo)
+                    L = Prim<R>{below.a, below.b, below.c, below.d};
+                else if (GEN)
+                    L = ghost_state_gen(t, sc, rec, 1, -1, open_ym, py, pb_own);
+                else
+                    L = ghost_state(t, rec, 1, -1, slip, pb_own);
+                const Prim<R> Rs = state_at(mid, rec.gy, py, -hy, pb_yb);
+                gb = GEN ? flux_y(sc.flux, L, Rs, beta, inv_beta) : osher_y(L, Rs, beta, inv_beta);
+            } else if (fluid_lo) {
+                gb = below;  // evaluated with row r-1's ghost
+            }
+        }
+        const Vec4<double> gbd = cast4<double>(gb);
+
+        // ---- update of row r-1 ------------------------------------------------------------
+        if (r - 1 >= j0 && out_lane && fluid_lo) {
+            int gj;
+            locate_axis(r - 1, t.ny, t.per_y, gj);
+            const size_t c = (size_t)gj * t.nx + gi;
+            if (LAST) {
+                const double R0 = fma(-gbd.a, t.inv_dy, rpart.a);
+                const double R1 = fma(-gbd.b, t.inv_dy, rpart.b);
+                const double R2 = fma(-gbd.c, t.inv_dy, rpart.c);
+                const double R3 = fma(-gbd.d, t.inv_dy, rpart.d);
+                const double rn = fma(fac, R0, pre.a);
+                qout[c] = (S)rn;
+                qout[plane + c] = (S)fma(fac, R1, pre.b);
+                qout[2 * plane + c] = (S)fma(fac, R2, pre.c);
+                qout[3 * plane + c] = (S)fma(t.beta, adt * R3, pre.d);
+                const double rp = t.beta * R3;
+                if (NORM_MAX) {
+                    part0 = combine<true>(part0, fabs(R0));
+                    part1 = combine<true>(part1, fabs(R1));
+                    part2 = combine<true>(part2, fabs(R2));
+                    part3 = combine<true>(part3, fabs(rp));
+                } else {
+                    part0 = fma(R0, R0, part0);
+                    part1 = fma(R1, R1, part1);
+                    part2 = fma(R2, R2, part2);
+                    part3 = fma(rp, rp, part3);
+                }
+                const double rho_new = P::kMixed ? lvl + rn : rn;
+                part4 += (rho_new > 0.0 && rho_new < INFINITY) ? 0.0 : 1.0;
+                if (GEN && sc.global_dtau) {
+                    // pseudo-time step of the updated state: the next iteration's stage 0
+                    const double m_new = fma(fac, R1, pre.b) + (P::kMixed ? lvl_m : 0.0);
+                    const double n_new = fma(fac, R2, pre.c) + (P::kMixed ? lvl_n : 0.0);
+                    if (rho_new > 0.0) part5 = fmin(part5, local_dtau(t, t.cfl, rho_new, m_new, n_new));
+                }
+            } else {
+                // fac and adt already carry 1/dy here
+                qout[c] = (S)fma(-fac, gbd.a, pre.a);
+                qout[plane + c] = (S)fma(-fac, gbd.b, pre.b);
+                qout[2 * plane + c] = (S)fma(-fac, gbd.c, pre.c);
+                qout[3 * plane + c] = (S)fma(-adt, gbd.d, pre.d);
+            }
+        }
+
+        // ---- x-faces of row r and its residual without the upper y-face ------------------
+        Vec4<double> rp4 = zero4<double>();
+        if (r >= j0 && r < j1) {
+            const Prim<R> sxl = state_at(mid, rec.gx, px, -hx, pb_xl);
+            const Prim<R> partner = prim_from_right(sxl);  // right neighbour's left state
+            Vec4<R> fr = zero4<R>();
+            if (fluid) {
+                Prim<R> Rs = partner;
+                if (f & FLAG_WALL_XP)
+                    Rs = GEN ? ghost_state_gen(t, sc, rec, 0, +1, open_xp, px, pb_own)
+                             : ghost_state(t, rec, 0, +1, slip, pb_own);
+                const Prim<R> Ls = state_at(mid, rec.gx, px, hx, pb_own);
+                fr = GEN ? flux_x(sc.flux, Ls, Rs, beta, inv_beta) : osher_x(Ls, Rs, beta, inv_beta);
+            }
+            Vec4<R> fl = {from_left(fr.a), from_left(fr.b), from_left(fr.c), from_left(fr.d)};
+            if (fluid && (f & FLAG_WALL_XM)) {
+                const Prim<R> Lg = GEN ? ghost_state_gen(t, sc, rec, 0, -1, open_xm, px, pb_own)
+                                       : ghost_state(t, rec, 0, -1, slip, pb_own);
+                fl = GEN ? flux_x(sc.flux, Lg, sxl, beta, inv_beta) : osher_x(Lg, sxl, beta, inv_beta);
+            }
+            const Vec4<double> frd = cast4<double>(fr), fld = cast4<double>(fl);
+            // -(x-divergence) + lower flux / dy - real-time term + body force
+            rp4.a = fma(gbd.a, t.inv_dy, -((frd.a - fld.a) * t.inv_dx)) - d_r;
+            rp4.b = fma(gbd.b, t.inv_dy, -((frd.b - fld.b) * t.inv_dx)) + fma(a0, t.gx, -d_ru);
+            rp4.c = fma(gbd.c, t.inv_dy, -((frd.c - fld.c) * t.inv_dx)) + fma(a0, t.gy, -d_rv);
+            rp4.d = fma(gbd.d, t.inv_dy, -((frd.d - fld.d) * t.inv_dx));
+            if constexpr (P::kMixed) {
+                rp4.b = fma(-sx, t.inv_dx, rp4.b);
+                rp4.c = fma(-sy, t.inv_dy, rp4.c);
+            }
+        }
+
+        // ---- carries of row r -------------------------------------------------------------
+        const Prim<R> syt = state_at(mid, rec.gy, py, hy, pb_own);
+        if (fluid && (f & FLAG_WALL_YP) && r < j1) {  // a wall above row r: that face's flux now
+            if (GEN)
+                below = flux_y(sc.flux, syt, ghost_state_gen(t, sc, rec, 1, +1, open_yp, py, pb_own),
+                               beta, inv_beta);
+            else
+                below = osher_y(syt, ghost_state(t, rec, 1, +1, slip, pb_own), beta, inv_beta);
+        } else {
+            below = {syt.r, syt.u, syt.v, syt.p};
+        }
+        if (fluid && r >= j0 && r < j1) {
+            const double dtau = use_glob ? dtau_glob : local_dtau(t, t.cfl, a0, a1, a2);
+            const double ad = alpha * dtau;
+            const double fc = ad * rcp_pos(fma(sp.b0 * ad, sp.inv_dt, 1.0));
+            if (LAST) {
+                pre = z;
+                rpart = rp4;
+                fac = fc;
+                adt = ad;
+                lvl = lvl_r;
+                if (GEN && P::kMixed) {
+                    lvl_m = lvl_mid.b;
+                    lvl_n = lvl_mid.c;
+                }
+            } else {
+                pre = {fma(fc, rp4.a, z.a), fma(fc, rp4.b, z.b), fma(fc, rp4.c, z.c),
+                       fma(t.beta * ad, rp4.d, z.d)};
+                fac = fc * t.inv_dy;
+                adt = t.beta * ad * t.inv_dy;
+            }
+        }
+        fluid_lo = fluid;
+        lo = mid;
+        mid = hi;
+        hi = next_hi;
+        plo = pmid;
+        pmid = phi;
+        phi = next_phi;
+        if constexpr (P::kMixed) {
+            lvl_mid = lvl_hi;
+            lvl_hi = next_lvl;
+        }
+    }
+
+    if (LAST) {
+        // wave reduction (fixed order) and one partial per unit
+        const double part[kPartialWidth] = {part0, part1, part2, part3, part4, part5};
+#pragma unroll
+        for (int k = 0; k < kPartialWidth; ++k) {
+            double x = part[k];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double y = __shfl_xor(x, off, kLanes);
+                x = (k == 5) ? fmin(x, y) : ((NORM_MAX && k < 4) ? combine<true>(x, y) : x + y);
+            }
+            if (lane == 0) t.partials[(size_t)un.local * kPartialWidth + k] = x;
+        }
+    }
+}
+
+template <class P, bool NM, int BDF, bool LS, bool GEN>
+void launch_t(const TankDev *tanks, const MarchUnit *units, dim3 g, dim3 b, int waves_simd,
+              const Scheme &sc, int stage, hipStream_t s)
+{
+    if constexpr (!GEN) {
+        if (waves_simd == 3) {
+            hipLaunchKernelGGL((stage_march<P, NM, BDF, LS, 3, GEN>), g, b, 0, s, tanks, units, sc,
+                               stage);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((stage_march<P, NM, BDF, LS, 2, GEN>), g, b, 0, s, tanks, units, sc, stage);
+}
+
+template <class P, int BDF, bool GEN>
+void launch_b(const TankDev *tanks, const MarchUnit *units, dim3 g, dim3 b, int waves_simd,
+              const Scheme &sc, int stage, hipStream_t s)
+{
+    if (stage == sc.smax) {
+        if (sc.norm_max) launch_t<P, true, BDF, true, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+        else launch_t<P, false, BDF, true, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+    } else {
+        launch_t<P, false, BDF, false, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+    }
+}
+
+// One stage over the unit table, for the scheme's precision and BDF order.
+template <bool GEN>
+int launch(const TankDev *tanks, const MarchUnit *units, int n_entries, int waves_per_block,
+           const Scheme &sc, int stage, int waves_simd, void *stream)
+{
+    if (waves_per_block < 1 || waves_per_block > kMaxWavesPerBlock || n_entries % waves_per_block)
+        return (int)hipErrorInvalidValue;
+    const dim3 g(n_entries / waves_per_block), b(kLanes * waves_per_block);
+    hipStream_t s = (hipStream_t)stream;
+    if (sc.mixed) {
+        if (sc.bdf >= 3) launch_b<PrecMixed, 3, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+        else if (sc.bdf == 2) launch_b<PrecMixed, 2, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+        else launch_b<PrecMixed, 1, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+    } else {
+        if (sc.bdf >= 3) launch_b<PrecF64, 3, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+        else if (sc.bdf == 2) launch_b<PrecF64, 2, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+        else launch_b<PrecF64, 1, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+    }
+    return (int)hipGetLastError();
+}
+
+}  // namespace march
+
+}  // namespace vdac

@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     // ---- phase 4: divergence, sources and the point-implicit update ------------------------
     const double alpha = sc.alpha[stage - 1];
     const bool last = (stage == sc.smax);
-    double part[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double part[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
     if (tid < NC) {
         const int i = tid % TX, j = tid / TX;
         const int gi = x0 + i, gj = y0 + j;

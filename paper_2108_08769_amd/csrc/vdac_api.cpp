@@ -41,7 +41,7 @@ int hip_fail(hipError_t e, const char *what)
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct TankLayout {
-    size_t state[3], level_n, level_nm1, flags, partials, end;
+    size_t state[3], level_n, level_nm1, level_nm2, flags, partials, end;
 };
 
 enum Kind { KIND_DIRECT, KIND_TILE, KIND_MARCH };
@@ -81,7 +81,8 @@ struct vdac_grid {
     MarchUnit *units_dev;               // [plan.n_entries] (row marching only)
     double *staging;                    // [4][max_plane] (mixed form only)
     std::vector<Status> status_host;
-    int hist_ok;                        // every tank's level n-1 holds a real-time level
+    int hist;                           // completed real steps since set_state (capped at 2):
+                                        // how many earlier real-time levels are valid
     // captured pseudo-iterations, keyed by the number of iterations per graph
     hipStream_t cap_stream;
     std::vector<std::pair<int, hipGraphExec_t>> graphs;
@@ -115,10 +116,16 @@ int check_options(const vdac_options *o)
         return fail(VDAC_E_INVALID, "cfl_tau must be finite and > 0");
     if (!(o->limiter_k >= 1.0 && o->limiter_k <= 2.0))
         return fail(VDAC_E_INVALID, "limiter_k must lie in [1, 2]");
-    if (o->local_dtau != 1)
-        return fail(VDAC_E_INVALID, "only local pseudo-time steps are available (local_dtau = 1)");
-    if (o->bdf_order != 1 && o->bdf_order != 2)
-        return fail(VDAC_E_INVALID, "bdf_order must be 1 or 2");
+    if (o->local_dtau != 0 && o->local_dtau != 1)
+        return fail(VDAC_E_INVALID, "local_dtau must be 1 (local steps) or 0 (one global step)");
+    if (o->bdf_order < 1 || o->bdf_order > 3)
+        return fail(VDAC_E_INVALID, "bdf_order must be 1, 2 or 3");
+    if (o->flux < VDAC_FLUX_OSHER || o->flux > VDAC_FLUX_BASSI)
+        return fail(VDAC_E_INVALID, "flux must be VDAC_FLUX_OSHER, VDAC_FLUX_ROE or VDAC_FLUX_BASSI");
+    if (o->pgrad < VDAC_PGRAD_NEW || o->pgrad > VDAC_PGRAD_SPLIT)
+        return fail(VDAC_E_INVALID, "pgrad must be VDAC_PGRAD_NEW, VDAC_PGRAD_LIMITER or VDAC_PGRAD_SPLIT");
+    if (o->pgrad != VDAC_PGRAD_NEW && !(o->p_limiter_k >= 1.0 && o->p_limiter_k <= 2.0))
+        return fail(VDAC_E_INVALID, "p_limiter_k must lie in [1, 2]");
     if (o->norm != VDAC_NORM_RMS && o->norm != VDAC_NORM_MAX)
         return fail(VDAC_E_INVALID, "norm must be VDAC_NORM_RMS or VDAC_NORM_MAX");
     if (o->wall_slip != 0 && o->wall_slip != 1)
@@ -135,6 +142,11 @@ int check_options(const vdac_options *o)
     if (o->precision == VDAC_FP32_MIXED && !auto_tile && !march)
         return fail(VDAC_E_INVALID, "the mixed precision form runs the row-marching kernel only "
                     "(tile 0 x 0 or -W x L)");
+    const bool general = o->flux != VDAC_FLUX_OSHER || o->pgrad != VDAC_PGRAD_NEW || o->local_dtau == 0;
+    if ((general || o->bdf_order == 3) && !auto_tile && !march)
+        return fail(VDAC_E_INVALID, "the Roe and exact fluxes, the limited pressure gradients, the "
+                    "global pseudo-time step and BDF3 run on the row-marching kernel only (tile 0 x 0 "
+                    "or -W x L)");
     return VDAC_OK;
 }
 
@@ -151,8 +163,9 @@ int check_tank(const vdac_tank *t, int idx)
     if (!std::isfinite(t->gx) || !std::isfinite(t->gy))
         return fail(VDAC_E_INVALID, "tank %d: gravity must be finite", idx);
     for (int s = 0; s < 4; ++s)
-        if (t->bc[s] != VDAC_BC_WALL && t->bc[s] != VDAC_BC_PERIODIC)
-            return fail(VDAC_E_INVALID, "tank %d: bc[%d] must be VDAC_BC_WALL or VDAC_BC_PERIODIC", idx, s);
+        if (t->bc[s] != VDAC_BC_WALL && t->bc[s] != VDAC_BC_PERIODIC && t->bc[s] != VDAC_BC_TRANSMISSIVE)
+            return fail(VDAC_E_INVALID, "tank %d: bc[%d] must be VDAC_BC_WALL, VDAC_BC_PERIODIC or "
+                        "VDAC_BC_TRANSMISSIVE", idx, s);
     if ((t->bc[0] == VDAC_BC_PERIODIC) != (t->bc[1] == VDAC_BC_PERIODIC) ||
         (t->bc[2] == VDAC_BC_PERIODIC) != (t->bc[3] == VDAC_BC_PERIODIC))
         return fail(VDAC_E_INVALID, "tank %d: periodic sides must come in pairs", idx);
@@ -246,6 +259,28 @@ std::vector<MarchUnit> unit_table(const Plan &p, const vdac_tank *tanks, int n_t
 
 size_t elem_bytes(const vdac_options *o) { return o->precision == VDAC_FP32_MIXED ? 4 : 8; }
 
+bool has_open_side(const vdac_tank *t)
+{
+    for (int s = 0; s < 4; ++s)
+        if (t->bc[s] == VDAC_BC_TRANSMISSIVE) return true;
+    return false;
+}
+
+// Options a tank's sides restrict: zero-gradient sides run on the row-marching kernel, not with
+// the split limiter (whose zero-gradient ghost is not derived here).
+int check_tank_options(const vdac_tank *t, int idx, const vdac_options *o)
+{
+    if (!has_open_side(t)) return VDAC_OK;
+    const bool auto_tile = o->tile_x == 0 && o->tile_y == 0;
+    if (!auto_tile && o->tile_x > -1)
+        return fail(VDAC_E_INVALID, "tank %d: zero-gradient sides run on the row-marching kernel "
+                    "only (tile 0 x 0 or -W x L)", idx);
+    if (o->pgrad == VDAC_PGRAD_SPLIT)
+        return fail(VDAC_E_INVALID, "tank %d: the split pressure limiter is not available with "
+                    "zero-gradient sides", idx);
+    return VDAC_OK;
+}
+
 TankLayout layout_of(const vdac_tank *t, const vdac_options *o, int n_partials)
 {
     const size_t plane = (size_t)t->nx * (size_t)t->ny;
@@ -258,7 +293,9 @@ TankLayout layout_of(const vdac_tank *t, const vdac_options *o, int n_partials)
     L.level_n = off;
     off += align256((o->precision == VDAC_FP32_MIXED ? 4 : 3) * plane * sizeof(double));
     L.level_nm1 = off;
-    if (o->bdf_order == 2) off += align256(3 * plane * sizeof(double));
+    if (o->bdf_order >= 2) off += align256(3 * plane * sizeof(double));
+    L.level_nm2 = off;
+    if (o->bdf_order >= 3) off += align256(3 * plane * sizeof(double));
     L.flags = off;
     off += align256(plane);
     L.partials = off;
@@ -395,6 +432,23 @@ int collect_timing(vdac_grid *g, const std::vector<int> &iters_before, const std
     return VDAC_OK;
 }
 
+// The smallest local pseudo-time step (Sec. 2.2.3) of a host state over the tank's fluid cells:
+// the global step of the first pseudo-iteration after set_state (later ones come from the
+// final stage of the previous iteration).
+double min_local_dtau(const TankHost &th, const double *q)
+{
+    const TankDev &d = th.dev;
+    double m = INFINITY;
+    for (size_t c = 0; c < d.plane; ++c) {
+        if (th.flags[c] & FLAG_SOLID) continue;
+        const double r = q[c], u = q[d.plane + c] / r, v = q[2 * d.plane + c] / r;
+        const double cx = std::sqrt(u * u + 4.0 * d.beta / r), cy = std::sqrt(v * v + 4.0 * d.beta / r);
+        const double dt = d.cfl * (d.dx * d.dy) / (0.5 * (std::fabs(u) + cx) * d.dy + 0.5 * (std::fabs(v) + cy) * d.dx);
+        m = std::min(m, dt);
+    }
+    return m;
+}
+
 // Uploads an FP64 state [4][plane] into tank t: plain copies into the three state buffers and
 // level n (FP64 form), or through the staging buffer and the import kernel (mixed form).
 int upload_state(vdac_grid *g, int t, const double *q)
@@ -411,10 +465,13 @@ int upload_state(vdac_grid *g, int t, const double *q)
             e = hipMemcpyAsync(d.level_n, q, 3 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
         if (e == hipSuccess && d.level_nm1)
             e = hipMemcpyAsync(d.level_nm1, q, 3 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
+        if (e == hipSuccess && d.level_nm2)
+            e = hipMemcpyAsync(d.level_nm2, q, 3 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
     }
     Status st;
     std::memset(&st, 0, sizeof st);
     st.done = 1;  // cur = 0
+    st.dtau_global = min_local_dtau(g->tanks[t], q);
     if (e == hipSuccess) e = hipMemcpyAsync(d.status, &st, sizeof st, hipMemcpyHostToDevice, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "uploading the state");
@@ -441,6 +498,9 @@ void vdac_default_options(vdac_options *o)
     o->norm = VDAC_NORM_RMS;
     o->wall_slip = 0;
     o->graph_iters = 0;
+    o->flux = VDAC_FLUX_OSHER;
+    o->pgrad = VDAC_PGRAD_NEW;
+    o->p_limiter_k = 1.0;
 }
 
 size_t workspace_bytes(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o)
@@ -473,8 +533,10 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
     }
     int rc = check_options(o);
     if (rc != VDAC_OK) return rc;
-    for (int t = 0; t < n_tanks; ++t)
+    for (int t = 0; t < n_tanks; ++t) {
         if ((rc = check_tank(&tanks[t], t)) != VDAC_OK) return rc;
+        if ((rc = check_tank_options(&tanks[t], t, o)) != VDAC_OK) return rc;
+    }
     const size_t need = workspace_bytes(tanks, n_tanks, o);
 
     vdac_grid *g = new (std::nothrow) vdac_grid();
@@ -513,13 +575,20 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
     sc.k = o->limiter_k;
     sc.slip = o->wall_slip;
     sc.norm_max = (o->norm == VDAC_NORM_MAX);
-    sc.bdf2 = (o->bdf_order == 2);
+    sc.bdf = o->bdf_order;
     sc.mixed = (o->precision == VDAC_FP32_MIXED);
+    sc.flux = o->flux;
+    sc.pgrad = o->pgrad;
+    sc.pk = o->p_limiter_k;
+    sc.global_dtau = o->local_dtau == 0;
+    sc.general = sc.flux != VDAC_FLUX_OSHER || sc.pgrad != VDAC_PGRAD_NEW || sc.global_dtau;
+    for (int t = 0; t < n_tanks; ++t)
+        if (has_open_side(&tanks[t])) sc.general = 1;
 
     const Plan &pl = g->plan;
     g->tanks.resize(n_tanks);
     g->status_host.assign(n_tanks, Status());
-    g->hist_ok = 0;
+    g->hist = 0;
     g->timing = false;
     g->t_ms = 0.0;
     g->t_launches = 0;
@@ -561,7 +630,8 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         d.plane = (size_t)d.nx * d.ny;
         for (int b = 0; b < 3; ++b) d.state[b] = (void *)(g->ws + base + L.state[b]);
         d.level_n = (double *)(g->ws + base + L.level_n);
-        d.level_nm1 = sc.bdf2 ? (double *)(g->ws + base + L.level_nm1) : nullptr;
+        d.level_nm1 = sc.bdf >= 2 ? (double *)(g->ws + base + L.level_nm1) : nullptr;
+        d.level_nm2 = sc.bdf >= 3 ? (double *)(g->ws + base + L.level_nm2) : nullptr;
         d.flags = (const uint8_t *)(g->ws + base + L.flags);
         d.partials = (double *)(g->ws + base + L.partials);
         d.status = g->status_dev + t;
@@ -570,6 +640,9 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         d.n_partials = pl.n_partials[t];
         d.n_strips = march_strips(d.nx);
         d.chunk = pl.chunk[t] > 0 ? pl.chunk[t] : 1;
+        d.open = 0;
+        for (int side = 0; side < 4; ++side)
+            if (tanks[t].bc[side] == VDAC_BC_TRANSMISSIVE) d.open |= 1 << side;
         devs[t] = d;
         base += L.end;
     }
@@ -629,7 +702,7 @@ int set_state(vdac_grid *g, int32_t tank, const double *q)
     }
     const int rc = upload_state(g, tank, q);
     if (rc != VDAC_OK) return rc;
-    g->hist_ok = 0;
+    g->hist = 0;
     return VDAC_OK;
 }
 
@@ -707,18 +780,22 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
 {
     g_error.clear();
     if (!g) return fail(VDAC_E_INVALID, "grid is NULL");
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(VDAC_E_INVALID, "dt must be finite and > 0");
+    if (!(dt > 0.0)) return fail(VDAC_E_INVALID, "dt must be > 0 (+infinity: pseudo-time only)");
     if (max_pseudo < 0) return fail(VDAC_E_INVALID, "max_pseudo must be >= 0");
     if (std::isnan(tol)) return fail(VDAC_E_INVALID, "tol is NaN");
     const int nt = (int)g->tanks.size();
     int rc;
-    // Table 1: backward Euler, or BDF2 once level n-1 holds a real-time level
-    const int use_history = g->sc.bdf2 && g->hist_ok;
+    // Table 1: the order is the grid's, limited by the earlier real-time levels available (the
+    // first step after set_state is backward Euler, the second at most BDF2); dt = +infinity
+    // switches the real-time term off (1/dt = 0: no source, alpha_PI = 1)
+    const int order = std::min(g->sc.bdf, 1 + g->hist);
     StepParams sp;
-    sp.inv_dt = 1.0 / dt;
-    sp.b0 = use_history ? 1.5 : 1.0;
-    sp.b1 = use_history ? -2.0 : -1.0;
-    sp.b2 = use_history ? 0.5 : 0.0;
+    sp.inv_dt = std::isfinite(dt) ? 1.0 / dt : 0.0;
+    sp.b0 = order == 3 ? 11.0 / 6.0 : (order == 2 ? 1.5 : 1.0);
+    sp.b1 = order == 3 ? -3.0 : (order == 2 ? -2.0 : -1.0);
+    sp.b2 = order == 3 ? 1.5 : (order == 2 ? 0.5 : 0.0);
+    sp.b3 = order == 3 ? -1.0 / 3.0 : 0.0;
+    const int use_history = g->hist > 0;
     rc = launch_begin_step_all(g->tanks_dev, nt, g->plan.max_plane, g->sc, sp, max_pseudo, tol,
                                use_history, g->stream);
     if (rc != 0) return hip_fail((hipError_t)rc, "begin_step launch");
@@ -764,9 +841,30 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
         if (st.diverged && status == VDAC_OK)
             status = fail(VDAC_E_DIVERGED, "tank %d diverged at pseudo-iteration %d", t, st.iters);
     }
-    g->hist_ok = 1;
+    g->hist = std::min(g->hist + 1, 2);
     if (g->timing && (rc = collect_timing(g, before, after)) != VDAC_OK) return rc;
     return status;
+}
+
+int realtime_dt(const vdac_grid *g, int32_t tank, double cfl_t, double *dt)
+{
+    g_error.clear();
+    if (!g || !dt) return fail(VDAC_E_INVALID, "grid or dt is NULL");
+    if (tank < 0 || tank >= (int)g->tanks.size()) return fail(VDAC_E_INVALID, "no tank %d", tank);
+    if (!(cfl_t > 0.0) || !std::isfinite(cfl_t)) return fail(VDAC_E_INVALID, "cfl_t must be finite and > 0");
+    const TankDev &d = g->tanks[tank].dev;
+    // the tank's residual partials serve as the per-workgroup minima (no stage is running)
+    const int n_blocks = std::max(1, std::min(d.n_partials * kPartialWidth, 1024));
+    hipError_t e = (hipError_t)launch_realtime_dt(d, g->sc.mixed, cfl_t, d.partials, n_blocks, g->stream);
+    std::vector<double> mins(n_blocks);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(mins.data(), d.partials, n_blocks * sizeof(double), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "realtime_dt");
+    double m = INFINITY;
+    for (double x : mins) m = std::min(m, x);
+    *dt = m;
+    return VDAC_OK;
 }
 
 int stage_timing(vdac_grid *g, int32_t enable)
@@ -835,10 +933,12 @@ std::string tune_key(const vdac_tank *tanks, int n_tanks, const vdac_options *o)
 {
     std::string k = std::to_string(o->precision) + "/" + std::to_string(o->rk_stages) + "/" +
                     std::to_string(o->bdf_order) + "/" + std::to_string(o->norm) + "/" +
-                    std::to_string((int)o->limiter_k);
+                    std::to_string((int)o->limiter_k) + "/" + std::to_string(o->flux) + "/" +
+                    std::to_string(o->pgrad) + "/" + std::to_string(o->local_dtau);
     for (int t = 0; t < n_tanks; ++t)
-        k += ":" + std::to_string(tanks[t].nx) + "x" + std::to_string(tanks[t].ny) +
-             (tanks[t].bc[0] == VDAC_BC_PERIODIC ? "p" : "w") + (tanks[t].bc[2] == VDAC_BC_PERIODIC ? "p" : "w");
+        k += ":" + std::to_string(tanks[t].nx) + "x" + std::to_string(tanks[t].ny) + "/" +
+             std::to_string(tanks[t].bc[0]) + std::to_string(tanks[t].bc[1]) +
+             std::to_string(tanks[t].bc[2]) + std::to_string(tanks[t].bc[3]);
     return k;
 }
 
@@ -873,7 +973,9 @@ int autotune_tile(const vdac_tank *tanks, int32_t n_tanks, vdac_options *o, void
     for (int w : {2, 3})
         for (int c : chunks)
             if (c == 1 || c / 2 < max_ny) cand.push_back({-w, c});
-    if (base.precision == VDAC_FP64 && n_tanks == 1)
+    const bool march_only = base.flux != VDAC_FLUX_OSHER || base.pgrad != VDAC_PGRAD_NEW ||
+                            base.local_dtau == 0 || base.bdf_order == 3 || has_open_side(&tanks[0]);
+    if (base.precision == VDAC_FP64 && n_tanks == 1 && !march_only)
         for (auto tl : {std::pair<int, int>{3208, 2}, {1616, 2}, {32, 8}, {16, 16}}) cand.push_back(tl);
 
     double best_ms = 0.0;

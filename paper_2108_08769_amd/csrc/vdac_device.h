@@ -145,6 +145,59 @@ __device__ __forceinline__ T gradp_y(const Prim<T> &w, const Slope<T> &gx, const
 //   l_4 . dQ =  (rho/c)(lambda_4 a + dq),   l_5 . dQ = -(rho/c)(lambda_5 a + dq),
 //   r_4 = (lambda_4, u lambda_4 + beta/rho, v lambda_4, -lambda_5/rho),
 //   r_5 = (lambda_5, u lambda_5 + beta/rho, v lambda_5, -lambda_4/rho).
+// Accumulator of sum_j w_j |A(Q_j)| dQ / 2 in the closed form below, one point at a time.
+template <typename T>
+struct AbsAAcc {
+    T sau, a0, a1u, a1b, a2, a3;
+};
+
+// Adds the point (rho, u, v), 1/rho = ir, with half weight wj (and wjb = wj / beta) to acc, for
+// the jump (dr, dm, dn, dp) in (rho, rho u, rho v, p):
+//   |A| dQ = |u| dQ + (lambda_4 - |u|)(l_4 . dQ) r_4 + (-lambda_5 - |u|)(l_5 . dQ) r_5,
+// where, with a = (d(rho u) - u d(rho))/beta and dq = d(p/beta),
+//   l_4 . dQ =  (rho/c)(lambda_4 a + dq),   l_5 . dQ = -(rho/c)(lambda_5 a + dq),
+//   r_4 = (lambda_4, u lambda_4 + beta/rho, v lambda_4, -lambda_5/rho),
+//   r_5 = (lambda_5, u lambda_5 + beta/rho, v lambda_5, -lambda_4/rho).
+// The weight is folded into k4 and k5; with a' = beta a and dp = beta dq,
+//   k4 = (lambda_4 - |u|)(w/(2 beta))(rho/c)(lambda_4 a' + dp), k5 alike; component 1 is kept
+// as sum u s + beta sum (k4 + k5)/rho.
+template <typename T>
+__device__ __forceinline__ void absA_point(AbsAAcc<T> &acc, T rho, T ir, T u, T v, T wj, T wjb,
+                                           T four_beta, T dr, T dm, T dp)
+{
+    const T c2 = fma(u, u, four_beta * ir);
+    const T y = rsqrt_pos(c2);          // 1/c
+    const T hc = T(0.5) * (c2 * y);     // c/2
+    const T rcw = wjb * rho * y;        // (w/2) rho / (beta c)
+    const T l4 = fma(T(0.5), u, hc), l5 = fma(T(0.5), u, -hc);
+    const T au = fabs(u);
+    acc.sau = fma(wj, au, acc.sau);
+    const T a = fma(-u, dr, dm);
+    const T k4 = (l4 - au) * rcw * fma(l4, a, dp);
+    const T k5 = (l5 + au) * rcw * fma(l5, a, dp);
+    const T s = fma(k4, l4, k5 * l5);
+    acc.a0 += s;
+    acc.a1u = fma(u, s, acc.a1u);
+    acc.a1b = fma(ir, k4 + k5, acc.a1b);
+    acc.a2 = fma(v, s, acc.a2);
+    acc.a3 = fma(-ir, fma(k4, l5, k5 * l4), acc.a3);
+}
+
+// F = (F(Q_L) + F(Q_R) - acc)/2 with acc = sum_j (w_j/2) |A_j| dQ.
+template <typename T>
+__device__ __forceinline__ Vec4<T> upwind_flux(const Prim<T> &L, const Prim<T> &R, T mL, T mR,
+                                               T dr, T dm, T dn, T dp, T beta, T inv_beta,
+                                               const AbsAAcc<T> &acc)
+{
+    const T a1 = fma(beta, acc.a1b, acc.a1u);
+    Vec4<T> F;
+    F.a = T(0.5) * (mL + mR - fma(acc.sau, dr, acc.a0));
+    F.b = T(0.5) * (fma(mL, L.u, L.p) + fma(mR, R.u, R.p) - fma(acc.sau, dm, a1));
+    F.c = T(0.5) * (mL * L.v + mR * R.v - fma(acc.sau, dn, acc.a2));
+    F.d = T(0.5) * (L.u + R.u - fma(acc.sau, dp * inv_beta, acc.a3));
+    return F;
+}
+
 template <typename T>
 __device__ __forceinline__ Vec4<T> osher_x(const Prim<T> &L, const Prim<T> &R, T beta, T inv_beta)
 {
@@ -160,11 +213,7 @@ __device__ __forceinline__ Vec4<T> osher_x(const Prim<T> &L, const Prim<T> &R, T
     const T w0 = T(5.0) / T(18.0), w1 = T(8.0) / T(18.0);
     const T w0b = w0 * inv_beta, w1b = w1 * inv_beta;
 
-    // sum_j (w_j/2) |A_j| dQ = (sum_j (w_j/2)|u_j|) dQ + sum_j [k4 r4 + k5 r5]_j with the weight
-    // folded into k4 and k5.  With a' = d(rho u) - u d(rho) = beta a and dp = beta dq,
-    //   k4 = (lambda_4 - |u|)(w/2)(rho/c)(lambda_4 a + dq) = (lambda_4 - |u|)(w/(2 beta))(rho/c)(lambda_4 a' + dp)
-    // and alike for k5; component 1 is accumulated as sum u s + beta sum (k4 + k5)/rho.
-    T sau = T(0), a0 = T(0), a1u = T(0), a1b = T(0), a2 = T(0), a3 = T(0);
+    AbsAAcc<T> acc = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const T t = (j == 0) ? t0 : ((j == 1) ? T(0.5) : t2);
@@ -174,31 +223,55 @@ __device__ __forceinline__ Vec4<T> osher_x(const Prim<T> &L, const Prim<T> &R, T
         const T m = fma(dm, t, mL);
         const T n = fma(dn, t, nL);
         const T ir = rcp_pos(rho);
-        const T u = m * ir, v = n * ir;
-        const T c2 = fma(u, u, four_beta * ir);
-        const T y = rsqrt_pos(c2);          // 1/c
-        const T hc = T(0.5) * (c2 * y);     // c/2
-        const T rcw = wjb * rho * y;        // (w_j/2) rho / (beta c)
-        const T l4 = fma(T(0.5), u, hc), l5 = fma(T(0.5), u, -hc);
-        const T au = fabs(u);
-        sau = fma(wj, au, sau);
-        const T a = fma(-u, dr, dm);
-        const T k4 = (l4 - au) * rcw * fma(l4, a, dp);
-        const T k5 = (l5 + au) * rcw * fma(l5, a, dp);
-        const T s = fma(k4, l4, k5 * l5);
-        a0 += s;
-        a1u = fma(u, s, a1u);
-        a1b = fma(ir, k4 + k5, a1b);
-        a2 = fma(v, s, a2);
-        a3 = fma(-ir, fma(k4, l5, k5 * l4), a3);
+        absA_point(acc, rho, ir, m * ir, n * ir, wj, wjb, four_beta, dr, dm, dp);
     }
-    const T a1 = fma(beta, a1b, a1u);
-    Vec4<T> F;
-    F.a = T(0.5) * (mL + mR - fma(sau, dr, a0));
-    F.b = T(0.5) * (fma(mL, L.u, L.p) + fma(mR, R.u, R.p) - fma(sau, dm, a1));
-    F.c = T(0.5) * (mL * L.v + mR * R.v - fma(sau, dn, a2));
-    F.d = T(0.5) * (L.u + R.u - fma(sau, dp * inv_beta, a3));
-    return F;
+    return upwind_flux(L, R, mL, mR, dr, dm, dn, dp, beta, inv_beta, acc);
+}
+
+// Roe flux (Sec. 2.4.2): |A| at the Roe average rho~ = sqrt(rho_L rho_R),
+// u~ = (sqrt(rho_L) u_L + sqrt(rho_R) u_R)/(sqrt(rho_L) + sqrt(rho_R)), v~ alike, applied to the
+// jump with weight 1 (p does not enter the eigenstructure).
+template <typename T>
+__device__ __forceinline__ Vec4<T> roe_x(const Prim<T> &L, const Prim<T> &R, T beta, T inv_beta)
+{
+    const T mL = L.r * L.u, nL = L.r * L.v;
+    const T mR = R.r * R.u, nR = R.r * R.v;
+    const T dr = R.r - L.r, dm = mR - mL, dn = nR - nL;
+    const T dp = R.p - L.p;
+    const T sl = L.r * rsqrt_pos(L.r), sr = R.r * rsqrt_pos(R.r);  // square roots
+    const T iw = rcp_pos(sl + sr);
+    const T rho = sl * sr;
+    const T ut = fma(sl, L.u, sr * R.u) * iw;
+    const T vt = fma(sl, L.v, sr * R.v) * iw;
+    AbsAAcc<T> acc = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    absA_point(acc, rho, rcp_pos(rho), ut, vt, T(1), inv_beta, T(4) * beta, dr, dm, dp);
+    return upwind_flux(L, R, mL, mR, dr, dm, dn, dp, beta, inv_beta, acc);
+}
+
+// Exact (Bassi) flux (Sec. 2.4.1): acoustic speeds S_L = lambda_5,L < 0 < S_R = lambda_4,R, so
+// x/tau = 0 lies in the star region, on the contact's left if u* > 0:
+//   u* = (p_R - p_L + rho_R u_R lambda_5,R - rho_L u_L lambda_4,L)/(rho_R lambda_5,R - rho_L lambda_4,L),
+//   p* = p_R + rho_R lambda_5,R (u_R - u*),
+//   rho*_L = rho_L lambda_4,L/(u* - lambda_5,L),  rho*_R = rho_R lambda_5,R/(u* - lambda_4,R),
+// and the tangential velocity of the side; the flux is the physical flux of that state.
+template <typename T>
+__device__ __forceinline__ Vec4<T> bassi_x(const Prim<T> &L, const Prim<T> &R, T beta, T inv_beta)
+{
+    const T four_beta = T(4) * beta;
+    const T cl2 = fma(L.u, L.u, four_beta * rcp_pos(L.r));
+    const T cr2 = fma(R.u, R.u, four_beta * rcp_pos(R.r));
+    const T hcl = T(0.5) * (cl2 * rsqrt_pos(cl2)), hcr = T(0.5) * (cr2 * rsqrt_pos(cr2));
+    const T l4l = fma(T(0.5), L.u, hcl), l5l = fma(T(0.5), L.u, -hcl);
+    const T l4r = fma(T(0.5), R.u, hcr), l5r = fma(T(0.5), R.u, -hcr);
+    const T rl4 = L.r * l4l, rr5 = R.r * l5r;
+    const T us = (R.p - L.p + fma(rr5, R.u, -(rl4 * L.u))) / (rr5 - rl4);
+    const T ps = fma(rr5, R.u - us, R.p);
+    const bool left = us > T(0);
+    const T rs = left ? rl4 / (us - l5l) : rr5 / (us - l4r);
+    const T vs = left ? L.v : R.v;
+    const T ms = rs * us;
+    (void)inv_beta;
+    return {ms, fma(ms, us, ps), ms * vs, us};
 }
 
 // Face flux with normal +y: Algorithm 2 gives t1 = (1, 0, 0) for n = (0, 1, 0), so the rotated
@@ -210,6 +283,27 @@ __device__ __forceinline__ Vec4<T> osher_y(const Prim<T> &L, const Prim<T> &R, T
     const Prim<T> Ls = {L.r, L.v, L.u, L.p};
     const Prim<T> Rs = {R.r, R.v, R.u, R.p};
     const Vec4<T> G = osher_x(Ls, Rs, beta, inv_beta);
+    return {G.a, G.c, G.b, G.d};
+}
+
+// x-split flux chosen at run time: 0 Osher-Dumbser-Toro, 1 Roe, 2 exact (Bassi); the y-face form
+// exchanges u and v as above.
+template <typename T>
+__device__ __forceinline__ Vec4<T> flux_x(int kind, const Prim<T> &L, const Prim<T> &R, T beta,
+                                          T inv_beta)
+{
+    if (kind == 1) return roe_x(L, R, beta, inv_beta);
+    if (kind == 2) return bassi_x(L, R, beta, inv_beta);
+    return osher_x(L, R, beta, inv_beta);
+}
+
+template <typename T>
+__device__ __forceinline__ Vec4<T> flux_y(int kind, const Prim<T> &L, const Prim<T> &R, T beta,
+                                          T inv_beta)
+{
+    const Prim<T> Ls = {L.r, L.v, L.u, L.p};
+    const Prim<T> Rs = {R.r, R.v, R.u, R.p};
+    const Vec4<T> G = flux_x(kind, Ls, Rs, beta, inv_beta);
     return {G.a, G.c, G.b, G.d};
 }
 

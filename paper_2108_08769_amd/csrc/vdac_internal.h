@@ -37,18 +37,20 @@ struct Status {
     int32_t pad;
     double tol;          // <= 0: run exactly max_pseudo iterations
     double norms[4];     // residual norms of the last iteration (rho, rho u, rho v, p)
+    double dtau_global;  // global pseudo-time step: the minimum local step of the current state
 };
 
 // Real-time coefficients of the current real step (Table 1), in device memory so that a captured
 // pseudo-iteration graph stays valid from one step to the next.
 struct StepParams {
-    double inv_dt;          // 1/dt
-    double b0, b1, b2;      // BDF coefficients: dQ/dt = (b0 Q^0 + b1 Q^n + b2 Q^{n-1}) / dt
+    double inv_dt;          // 1/dt (0: pseudo-time only)
+    double b0, b1, b2, b3;  // BDF coefficients: dQ/dt = (b0 Q^0 + b1 Q^n + b2 Q^{n-1} + b3 Q^{n-2})/dt
 };
 
-// Number of doubles per workgroup in the residual partials: four field sums (or maxima) and the
-// count of cells whose updated density is not finite and positive.
-constexpr int kPartialWidth = 5;
+// Number of doubles per work unit in the residual partials: four field sums (or maxima), the
+// count of cells whose updated density is not finite and positive, and the minimum local
+// pseudo-time step of the updated state (infinity where not computed).
+constexpr int kPartialWidth = 6;
 
 // Buffer rotation: stage s of a pseudo-iteration whose stage-0 state is in buffer `cur` reads
 // Q^{s-1} from `in` and writes Q^s to `out`; neither is `cur` for s >= 2, and no stage writes the
@@ -78,7 +80,8 @@ struct TankDev {
     size_t plane;             // nx*ny
     void *state[3];           // 4 planes each (double, or float in the mixed form)
     double *level_n;          // 3 planes (4 in the mixed form)
-    double *level_nm1;        // 3 planes (BDF2) or nullptr
+    double *level_nm1;        // 3 planes (BDF2, BDF3) or nullptr
+    double *level_nm2;        // 3 planes (BDF3) or nullptr
     const uint8_t *flags;
     double *partials;         // [n_partials][kPartialWidth]
     Status *status;
@@ -87,6 +90,7 @@ struct TankDev {
     int32_t n_partials;       // residual partials one stage launch writes for this tank
     int32_t n_strips;         // row-marching kernel: 64-column strips across the tank
     int32_t chunk;            // row-marching kernel: rows per work unit
+    int32_t open;             // zero-gradient sides: bit 0 x-, 1 x+, 2 y-, 3 y+
 };
 
 // One wave's work in the row-marching kernel: rows [chunk*c, chunk*(c+1)) of strip s of a tank,
@@ -103,8 +107,13 @@ struct Scheme {
     double k;        // limiter parameter
     int32_t slip;    // free-slip wall ghosts
     int32_t norm_max;
-    int32_t bdf2;    // the grid keeps a level n-1 history
+    int32_t bdf;     // highest BDF order of the grid (1..3): levels n-1 (, n-2) are kept
     int32_t mixed;   // FP32 deviation storage and FP32 reconstruction / flux
+    int32_t general; // a non-default option below is set: the general stage kernel runs
+    int32_t flux;    // 0 Osher-Dumbser-Toro, 1 Roe, 2 exact (Bassi)
+    int32_t pgrad;   // 0 new method, 1 k-limiter on p, 2 split limiter
+    double pk;       // k of the limiter on p
+    int32_t global_dtau;  // one pseudo-time step for the whole tank (the minimum local step)
 };
 
 // Launch wrappers.  All return hipError_t cast to int.
@@ -126,6 +135,12 @@ int launch_stage_tile_f64(const TankDev &t, const Scheme &sc, int stage, int til
                           void *stream);
 int launch_stage_march(const TankDev *tanks_dev, const MarchUnit *units, int n_entries,
                        int waves_per_block, const Scheme &sc, int stage, int waves_simd,
+                       void *stream);
+int launch_stage_march_general(const TankDev *tanks_dev, const MarchUnit *units, int n_entries,
+                               int waves_per_block, const Scheme &sc, int stage, void *stream);
+// Global real-time step of one tank (Sec. 2.2.4): per-workgroup minima of
+// CFL_t dx dy / (|u| dy + |v| dx) over the fluid cells of the current state into out[n_blocks].
+int launch_realtime_dt(const TankDev &t, int mixed, double cfl_t, double *out, int n_blocks,
                        void *stream);
 // Conversions between the caller's FP64 conserved state [4][ny][nx] (rho, rho u, rho v, p) in
 // device memory and the mixed form's storage (cur = 0 after import).

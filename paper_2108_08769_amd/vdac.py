@@ -15,13 +15,15 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libvdac.so")
 
 VDAC_OK, VDAC_E_INVALID, VDAC_E_NOMEM, VDAC_E_DEVICE, VDAC_E_DIVERGED = range(5)
-BC_WALL, BC_PERIODIC = 0, 1
+BC_WALL, BC_PERIODIC, BC_TRANSMISSIVE = 0, 1, 2
+FLUX_OSHER, FLUX_ROE, FLUX_BASSI = 0, 1, 2
+PGRAD_NEW, PGRAD_LIMITER, PGRAD_SPLIT = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 NORM_RMS, NORM_MAX = 0, 1
 
 EXPORTS = ("vdac_default_options", "workspace_bytes", "create_grid", "set_state",
            "step_dual_time", "residual_norm", "get_state", "stage_timing", "stage_timing_read",
-           "autotune_tile", "destroy_grid", "last_error")
+           "autotune_tile", "realtime_dt", "destroy_grid", "last_error")
 
 
 class VdacError(RuntimeError):
@@ -55,6 +57,9 @@ class Options(ctypes.Structure):
         ("tile_x", ctypes.c_int32),
         ("tile_y", ctypes.c_int32),
         ("graph_iters", ctypes.c_int32),
+        ("flux", ctypes.c_int32),
+        ("pgrad", ctypes.c_int32),
+        ("p_limiter_k", ctypes.c_double),
     ]
 
 
@@ -99,6 +104,8 @@ def lib():
         L.autotune_tile.argtypes = [ctypes.POINTER(Tank), ctypes.c_int32, ctypes.POINTER(Options),
                                     vp, ctypes.c_int32]
         L.autotune_tile.restype = ctypes.c_int
+        L.realtime_dt.argtypes = [vp, ctypes.c_int32, ctypes.c_double, dp]
+        L.realtime_dt.restype = ctypes.c_int
         L.destroy_grid.argtypes = [vp]
         L.destroy_grid.restype = None
         L.last_error.argtypes = []
@@ -119,7 +126,8 @@ def default_options() -> Options:
 
 
 def make_options(precision="f64", stages=3, alpha=(1.0 / 3.0, 0.5, 1.0), cfl=0.48, k=1.0,
-                 bdf=1, norm=NORM_RMS, wall_slip=False, tile=(0, 0), graph_iters=0) -> Options:
+                 bdf=1, norm=NORM_RMS, wall_slip=False, tile=(0, 0), graph_iters=0, flux=0,
+                 pgrad=0, pk=1.0, local_dtau=True) -> Options:
     o = default_options()
     o.precision = {"f64": FP64, "mixed": FP32_MIXED}[precision] if isinstance(precision, str) \
         else int(precision)
@@ -133,6 +141,8 @@ def make_options(precision="f64", stages=3, alpha=(1.0 / 3.0, 0.5, 1.0), cfl=0.4
     o.wall_slip = int(bool(wall_slip))
     o.tile_x, o.tile_y = int(tile[0]), int(tile[1])
     o.graph_iters = int(graph_iters)
+    o.flux, o.pgrad, o.p_limiter_k = int(flux), int(pgrad), float(pk)
+    o.local_dtau = int(bool(local_dtau))
     return o
 
 
@@ -254,6 +264,12 @@ class Grid:
         ms, n, cs = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         _check(self._lib.stage_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(cs)))
         return ms.value, n.value, cs.value
+
+    def realtime_dt(self, tank: int = 0, cfl_t: float = 0.45) -> float:
+        """Global real-time step of one tank from its current state (Sec. 2.2.4)."""
+        dt = ctypes.c_double()
+        _check(self._lib.realtime_dt(self._h, tank, float(cfl_t), ctypes.byref(dt)))
+        return dt.value
 
     def get_state(self, tank: int = 0) -> np.ndarray:
         ny, nx = self._shapes[tank]

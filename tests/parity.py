@@ -10,24 +10,27 @@ from paper_2108_08769_amd import workloads as wl
 
 
 def gpu_options(wk: wl.Workload, precision=None, norm=0, wall_slip=False, tile=(0, 0),
-                graph_iters=0):
+                graph_iters=0, flux=0, pgrad=0, pk=1.0):
     return vdac.make_options(precision=precision or wk.precision, stages=wk.stages,
                              alpha=wk.alpha, cfl=wk.cfl, k=wk.k, bdf=wk.bdf, norm=norm,
-                             wall_slip=wall_slip, tile=tile, graph_iters=graph_iters)
+                             wall_slip=wall_slip, tile=tile, graph_iters=graph_iters, flux=flux,
+                             pgrad=pgrad, pk=pk, local_dtau=wk.local_dtau)
 
 
-def oracle_problem(t: wl.Tank, wk: wl.Workload, wall_slip=False):
+def oracle_problem(t: wl.Tank, wk: wl.Workload, wall_slip=False, flux=0, pgrad=0, pk=1.0):
     return oracle.Problem(t.nx, t.ny, t.lx, t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
                           solid=t.solid, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl, k=wk.k,
-                          local_dtau=wk.local_dtau, bdf=wk.bdf, wall_slip=wall_slip)
+                          local_dtau=wk.local_dtau, bdf=wk.bdf, wall_slip=wall_slip, flux=flux,
+                          pgrad=pgrad, pk=pk)
 
 
 def run_gpu(wk: wl.Workload, steps: int, max_pseudo: int, tol: float = 0.0, norm=0,
-            wall_slip=False, precision=None, tile=(0, 0), graph_iters=0):
+            wall_slip=False, precision=None, tile=(0, 0), graph_iters=0, flux=0, pgrad=0, pk=1.0):
     """Returns (states per tank, iterations [steps, tanks], norms [tanks, 4], status codes)."""
     tanks = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
                   solid=t.solid) for t in wk.tanks]
-    grid = vdac.Grid(tanks, gpu_options(wk, precision, norm, wall_slip, tile, graph_iters))
+    grid = vdac.Grid(tanks, gpu_options(wk, precision, norm, wall_slip, tile, graph_iters, flux,
+                                        pgrad, pk))
     try:
         for i, t in enumerate(wk.tanks):
             grid.set_state(i, t.q)
@@ -44,16 +47,19 @@ def run_gpu(wk: wl.Workload, steps: int, max_pseudo: int, tol: float = 0.0, norm
 
 
 def run_oracle(wk: wl.Workload, steps: int, max_pseudo: int, tol: float = 0.0, norm=0,
-               wall_slip=False, **_ignored):
+               wall_slip=False, flux=0, pgrad=0, pk=1.0, **_ignored):
+    """The oracle on the same workload; dt = +infinity (pseudo-time only) is dt = 0 there."""
     states, iters, norms, codes = [], [], [], []
     per_tank_iters = [[] for _ in wk.tanks]
+    dt = 0.0 if np.isinf(wk.dt) else wk.dt
     for ti, t in enumerate(wk.tanks):
-        pb = oracle_problem(t, wk, wall_slip)
-        q, prev = t.q.copy(), None
+        pb = oracle_problem(t, wk, wall_slip, flux, pgrad, pk)
+        q, prev, prev2 = t.q.copy(), None, None
         for _ in range(steps):
-            qnew, it, res, rc = oracle.step(pb, q, wk.dt, max_pseudo, tol, norm,
-                                            qnm1=prev if wk.bdf == 2 else None)
-            prev, q = q, qnew
+            qnew, it, res, rc = oracle.step(pb, q, dt, max_pseudo, tol, norm,
+                                            qnm1=prev if wk.bdf >= 2 else None,
+                                            qnm2=prev2 if wk.bdf >= 3 else None)
+            prev2, prev, q = prev, q, qnew
             per_tank_iters[ti].append(it)
             codes.append(rc)
         states.append(q)

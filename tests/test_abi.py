@@ -72,9 +72,17 @@ def _create(tanks, opt):
     (lambda t, o: o.rk_alpha.__setitem__(2, 0.9), "last Runge-Kutta"),
     (lambda t, o: setattr(o, "cfl_tau", 0.0), "cfl_tau"),
     (lambda t, o: setattr(o, "limiter_k", 3.0), "limiter_k"),
-    (lambda t, o: setattr(o, "bdf_order", 3), "bdf_order"),
+    (lambda t, o: setattr(o, "bdf_order", 4), "bdf_order"),
     (lambda t, o: setattr(o, "norm", 5), "norm"),
-    (lambda t, o: setattr(o, "local_dtau", 0), "local"),
+    (lambda t, o: setattr(o, "local_dtau", 2), "local"),
+    (lambda t, o: setattr(o, "flux", 3), "flux"),
+    (lambda t, o: setattr(o, "pgrad", 3), "pgrad"),
+    (lambda t, o: (setattr(o, "pgrad", 1), setattr(o, "p_limiter_k", 3.0)), "p_limiter_k"),
+    (lambda t, o: (setattr(o, "flux", 1), setattr(o, "tile_x", 32), setattr(o, "tile_y", 8)),
+     "row-marching"),
+    (lambda t, o: (setattr(o, "bdf_order", 3), setattr(o, "tile_x", 1), setattr(o, "tile_y", 1)),
+     "row-marching"),
+    (lambda t, o: (t.bc.__setitem__(0, 2), setattr(o, "pgrad", 2)), "split"),
 ])
 def test_create_grid_rejects_bad_arguments(change, needle):
     t, _ = vdac.make_tank(8, 8, 1.0, 1.0)

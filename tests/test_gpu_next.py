@@ -1,0 +1,236 @@
+"""GPU path of the further options against the oracle, through the C ABI: the Roe and exact
+(Bassi) fluxes, the k-limiter and split limiter on p, zero-gradient sides with the
+pseudo-time-only mode and global pseudo-time steps (the Riemann problems of Table 2), BDF3, and
+the global real-time step; the mixed form of each against FP64.
+
+Bars as in the other parity files: FP64 per field max |gpu - oracle| / max(max |oracle|,
+physical scale) <= 1e-12 with equal iteration counts; mixed against FP64 normwise <= 1e-6 (rho),
+1e-5 (rho u; rho v against its physical scale), 1e-4 (p).
+"""
+import csv
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2108_08769_amd import vdac
+from paper_2108_08769_amd import workloads as wl
+from parity import run_gpu, run_oracle, field_errors, field_scales
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+W, P, O = 0, 1, 2
+OSHER, ROE, BASSI = 0, 1, 2
+NEW, LIMITER, SPLIT = 0, 1, 2
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def check(wk, steps, pseudo, bar=TOL, scales=None, **kw):
+    print(f"[next] {wk.name} steps={steps} pseudo={pseudo} {kw}", flush=True)
+    g = run_gpu(wk, steps, pseudo, **kw)
+    o = run_oracle(wk, steps, pseudo, **kw)
+    assert all(c == 0 for c in g[3]) and all(c == 0 for c in o[3]), (g[3], o[3])
+    np.testing.assert_array_equal(g[1], o[1])
+    worst = 0.0
+    for t, a, b in zip(wk.tanks, g[0], o[0]):
+        err = field_errors(a, b, t.solid, field_scales(t) if scales is None else scales)
+        worst = max(worst, err.max())
+        assert np.all(err <= bar), (t.nx, t.ny, err)
+    for a, b in zip(g[2], o[2]):
+        # norms agree to rtol 1e-7 above the rounding floor of the flux divergence: the kernel
+        # sums face fluxes scaled by 1/h, so a field whose fluxes cancel (v = 0 in a 1D problem)
+        # keeps the rounding error of p/h, about 1e-16 of the largest residual
+        np.testing.assert_allclose(a, b, rtol=1e-7, atol=max(1e-12, 1e-14 * np.abs(b).max()))
+    print(f"[next]   worst field error {worst:.3e}", flush=True)
+
+
+def check_mixed(wk, steps, pseudo, **kw):
+    print(f"[next-mixed] {wk.name} steps={steps} pseudo={pseudo} {kw}", flush=True)
+    m = run_gpu(wk, steps, pseudo, precision="mixed", **kw)
+    d = run_gpu(wk, steps, pseudo, precision="f64", **kw)
+    assert all(c == 0 for c in m[3]) and all(c == 0 for c in d[3])
+    np.testing.assert_array_equal(m[1], d[1])
+    for t, a, b in zip(wk.tanks, m[0], d[0]):
+        mask = np.ones(a.shape[1:], bool) if t.solid is None else t.solid == 0
+        nw = [np.abs(a[k][mask] - b[k][mask]).max() / max(np.abs(b[k][mask]).max(), 1e-300)
+              for k in range(4)]
+        sc = field_errors(a, b, t.solid, field_scales(t))
+        print(f"[next-mixed]   normwise rho {nw[0]:.2e} rho_u {nw[1]:.2e} rho_v(scaled) "
+              f"{sc[2]:.2e} p {nw[3]:.2e}", flush=True)
+        assert nw[0] <= 1e-6 and nw[1] <= 1e-5 and sc[2] <= 1e-5 and nw[3] <= 1e-4, (nw, sc)
+
+
+def dam(nx, ny, bc=(W, W, W, W), dt=1e-3, lx=4.0, ly=2.0, **wkargs):
+    xc = (np.arange(nx) + 0.5) * lx / nx
+    yc = (np.arange(ny) + 0.5) * ly / ny
+    rho = np.where((xc[None, :] < 1.0) & (yc[:, None] < 1.0), 1000.0, 1.0)
+    q = np.zeros((4, ny, nx))
+    q[0] = rho
+    return wl.Workload(f"dam_{nx}x{ny}", [wl.Tank(nx, ny, lx, ly, q, gy=-9.81, beta=1100.0, bc=bc)],
+                       dt=dt, steps=1, max_pseudo=1, **wkargs)
+
+
+def obstacle(n=48):
+    wk = wl.obstacle_dam_break(n=n)
+    wk.dt = 1e-3
+    return wk
+
+
+# ---- fluxes and pressure gradients ------------------------------------------------------------
+
+@pytest.mark.parametrize("flux", [ROE, BASSI])
+def test_riemann_solvers(flux):
+    check(dam(37, 23), steps=3, pseudo=20, flux=flux)
+    check(wl.rayleigh_taylor(nx=32, ny=72, precision="f64"), steps=2, pseudo=10, flux=flux)
+
+
+@pytest.mark.parametrize("pgrad,pk", [(LIMITER, 1.0), (LIMITER, 2.0), (SPLIT, 1.0), (SPLIT, 2.0)])
+def test_pressure_gradient_variants(pgrad, pk):
+    check(dam(37, 23), steps=3, pseudo=20, pgrad=pgrad, pk=pk)
+    check(obstacle(), steps=2, pseudo=10, pgrad=pgrad, pk=pk)
+
+
+def test_split_limiter_is_well_balanced_on_gpu():
+    """The exact discrete hydrostatic state is a steady state of the split limiter."""
+    ny, nx = 40, 8
+    dy = 1.0 / ny
+    yc = (np.arange(ny) + 0.5) * dy
+    rho = np.where(yc < 0.5, 1000.0, 1.0)
+    p = np.zeros(ny)
+    for j in range(ny - 1):
+        p[j + 1] = p[j] - 9.81 * dy * (rho[j] + rho[j + 1]) / 2
+    q = np.zeros((4, ny, nx))
+    q[0], q[3] = rho[:, None], (p + 50.0)[:, None]
+    wk = wl.Workload("hydro_split", [wl.Tank(nx, ny, 0.2, 1.0, q, gy=-9.81, beta=1000.0)], dt=1e-3,
+                     steps=1, max_pseudo=1)
+    states, _, norms, codes = run_gpu(wk, 2, 30, pgrad=SPLIT, pk=2.0)
+    assert codes == [0, 0]
+    assert np.abs(states[0][1:3]).max() <= 1e-9 and norms[0].max() <= 1e-8
+
+
+# ---- zero-gradient sides, global pseudo-time steps, pseudo-time only --------------------------
+
+def table2():
+    with open(os.path.join(GOLDEN, "riemann_problems_table2.csv")) as f:
+        rows = [r for r in csv.reader(line for line in f if not line.startswith("#"))]
+    return [dict(zip(rows[0], map(float, r))) for r in rows[1:]]
+
+
+def rp_workload(rp, nx):
+    """Sec. 3.1 setup: nx x 1 square cells on [0, 1], jump at x = 1/2, zero-gradient sides, no
+    gravity, global pseudo-time steps at CFL 0.98, no real-time term (dt = +infinity)."""
+    dx = 1.0 / nx
+    x = (np.arange(nx) + 0.5) * dx
+    left = x < 0.5
+    q = np.zeros((4, 1, nx))
+    q[0, 0] = np.where(left, rp["rho_L"], rp["rho_R"])
+    q[1, 0] = q[0, 0] * np.where(left, rp["u_L"], rp["u_R"])
+    q[3, 0] = np.where(left, rp["p_L"], rp["p_R"])
+    t = wl.Tank(nx, 1, 1.0, dx, q, gx=0.0, gy=0.0, beta=rp["beta"], bc=(O, O, O, O))
+    return wl.Workload(f"rp_{int(rp['rp'])}_{nx}", [t], dt=math.inf, steps=1, max_pseudo=1,
+                       cfl=0.98, local_dtau=False)
+
+
+@pytest.mark.parametrize("flux", [OSHER, ROE, BASSI])
+@pytest.mark.parametrize("rp_index", [0, 1, 4])
+def test_riemann_problems_of_table2(rp_index, flux):
+    rp = table2()[rp_index]
+    wk = rp_workload(rp, 100)
+    t = wk.tanks[0]
+    scales = np.array([np.abs(t.q[0]).max(), np.abs(t.q[0]).max() * 10.0,
+                       np.abs(t.q[0]).max() * 10.0, np.abs(t.q[3]).max()])
+    check(wk, steps=1, pseudo=25, scales=scales, flux=flux, pgrad=LIMITER, pk=1.0)
+
+
+def test_zero_gradient_sides_on_a_dam_break():
+    check(dam(37, 23, bc=(O, O, W, W)), steps=3, pseudo=20)
+    check(dam(41, 19, bc=(W, O, W, O)), steps=2, pseudo=15, pgrad=LIMITER, pk=2.0, flux=ROE)
+
+
+def test_global_pseudo_time_step():
+    wk = dam(37, 23, local_dtau=False)
+    check(wk, steps=3, pseudo=20)
+
+
+def test_pseudo_time_only_with_walls():
+    """Pseudo-time only (dt = +infinity) on the two-layer tank relaxing from p = 0 (a dam break
+    without the real-time term diverges, on the GPU and in the oracle alike)."""
+    wk = wl.hydrostatic(16, 16)
+    wk.dt = math.inf
+    check(wk, steps=2, pseudo=20)
+
+
+# ---- BDF3 and the real-time step ---------------------------------------------------------------
+
+def test_bdf3():
+    """Five steps: backward Euler, BDF2, then BDF3 (Table 1), as in the oracle."""
+    wk = dam(37, 23, bdf=3)
+    check(wk, steps=5, pseudo=10)
+
+
+def test_realtime_dt_matches_oracle():
+    import oracle
+    from parity import oracle_problem
+    wk = dam(37, 23)
+    tanks = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc)
+             for t in wk.tanks]
+    for prec in ("f64", "mixed"):
+        grid = vdac.Grid(tanks, vdac.make_options(precision=prec))
+        try:
+            grid.set_state(0, wk.tanks[0].q)
+            assert grid.realtime_dt(0, 0.45) == math.inf       # at rest
+            for _ in range(3):
+                grid.step(wk.dt, 20)
+            q = grid.get_state(0)
+            got = grid.realtime_dt(0, 0.45)
+        finally:
+            grid.close()
+        ref = oracle.realtime_dt(oracle_problem(wk.tanks[0], wk), q, 0.45)
+        print(f"[next] realtime dt {prec}: {got:.6e} (oracle on the same state {ref:.6e})", flush=True)
+        assert got == pytest.approx(ref, rel=1e-14)
+
+
+# ---- the mixed form, graphs and batches of the general kernel ---------------------------------
+
+@pytest.mark.parametrize("case", ["roe", "bassi", "limiter", "split", "open", "global", "bdf3"])
+def test_mixed_general_options(case):
+    kw, wkargs, bc = {}, {}, (W, W, W, W)
+    if case == "roe":
+        kw["flux"] = ROE
+    elif case == "bassi":
+        kw["flux"] = BASSI
+    elif case == "limiter":
+        kw.update(pgrad=LIMITER, pk=1.0)
+    elif case == "split":
+        kw.update(pgrad=SPLIT, pk=2.0)
+    elif case == "open":
+        bc = (O, O, W, W)
+    elif case == "global":
+        wkargs["local_dtau"] = False
+    elif case == "bdf3":
+        wkargs["bdf"] = 3
+    check_mixed(dam(96, 48, bc=bc, **wkargs), steps=4, pseudo=20, **kw)
+
+
+def test_general_kernel_graph_replay_matches_eager():
+    wk = dam(70, 40, bc=(O, W, W, W), local_dtau=False)
+    a = run_gpu(wk, 3, 12, flux=BASSI, pgrad=LIMITER, graph_iters=0)
+    b = run_gpu(wk, 3, 12, flux=BASSI, pgrad=LIMITER, graph_iters=-1)
+    for x, y in zip(a[0], b[0]):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(a[2], b[2])
+
+
+def test_general_kernel_batch_equals_single_tanks():
+    """Tanks with different side kinds in one grid (one launch per stage) come out bit for bit
+    as in grids of their own."""
+    tanks = [dam(37, 23, bc=(O, O, W, W)).tanks[0], dam(45, 17).tanks[0],
+             dam(29, 31, bc=(W, O, O, W)).tanks[0]]
+    wk = wl.Workload("mixed_sides", tanks, dt=1e-3, steps=1, max_pseudo=1)
+    batch = run_gpu(wk, 2, 8, flux=ROE, pgrad=LIMITER, tile=(-2, 8))
+    for i, t in enumerate(tanks):
+        one = wl.Workload("one", [t], dt=1e-3, steps=1, max_pseudo=1)
+        single = run_gpu(one, 2, 8, flux=ROE, pgrad=LIMITER, tile=(-2, 8))
+        np.testing.assert_array_equal(batch[0][i], single[0][0], err_msg=f"tank {i}")
