@@ -131,6 +131,13 @@ def main():
     ap.add_argument("--unbatched", action="store_true",
                     help="one grid per tank, stepped one after the other (the baseline of the "
                          "batched form)")
+    ap.add_argument("--flux", default="osher", choices=["osher", "roe", "bassi"],
+                    help="Riemann solver (Sec. 2.4)")
+    ap.add_argument("--pgrad", default="new", choices=["new", "limiter", "split"],
+                    help="pressure gradient (Sec. 2.3.2)")
+    ap.add_argument("--pk", type=float, default=1.0, help="k of the limiter on p")
+    ap.add_argument("--global-dtau", action="store_true", help="one pseudo-time step per tank")
+    ap.add_argument("--bdf", type=int, default=0, help="BDF order (0: the workload's)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only copy this many MiB device to device 20 times and print the rate "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -163,13 +170,20 @@ def main():
     wk = build_workload(args.workload, args.precision)
     if args.max_pseudo > 0:
         wk.max_pseudo = args.max_pseudo
+    if args.bdf > 0:
+        wk.bdf = args.bdf
+    if args.global_dtau:
+        wk.local_dtau = False
+    flux = {"osher": vdac.FLUX_OSHER, "roe": vdac.FLUX_ROE, "bassi": vdac.FLUX_BASSI}[args.flux]
+    pgrad = {"new": vdac.PGRAD_NEW, "limiter": vdac.PGRAD_LIMITER, "split": vdac.PGRAD_SPLIT}[args.pgrad]
     tanks = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
                   solid=t.solid) for t in wk.tanks]
     torch.cuda.set_device(0)
     tune = args.tile == "autotune"
     tile = (0, 0) if tune else tuple(int(v) for v in args.tile.lower().split("x"))
     opts = vdac.make_options(precision=wk.precision, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl,
-                             k=wk.k, bdf=wk.bdf, tile=tile, graph_iters=args.graph_iters)
+                             k=wk.k, bdf=wk.bdf, tile=tile, graph_iters=args.graph_iters,
+                             flux=flux, pgrad=pgrad, pk=args.pk, local_dtau=wk.local_dtau)
     if tune and not args.unbatched:
         # untimed: the tuner times each candidate shape on scratch grids of the same tanks
         opts = vdac.autotune(tanks, opts, iters=5)
@@ -224,7 +238,7 @@ def main():
             kms, launches, kcs = kms + a, launches + b, kcs + c
             g.stage_timing(False)
         if launches > 0 and kms > 0:
-            bpc = BYTES_PER_CELL_STAGE[wk.precision]
+            bpc = BYTES_PER_CELL_STAGE[wk.precision] + 24.0 * (wk.bdf - 1)  # levels n-1, n-2
             avg_s = kms / 1e3 / launches
             bytes_per_launch = bpc * kcs / launches
             achieved = bytes_per_launch / avg_s / 1e9
@@ -257,7 +271,8 @@ def main():
                    "tanks": len(wk.tanks), "batched": not args.unbatched,
                    "graph_iters": args.graph_iters,
                    "dt": wk.dt, "max_pseudo": wk.max_pseudo, "tol": wk.tol,
-                   "rk_stages": wk.stages, "pseudo_iterations": iters},
+                   "rk_stages": wk.stages, "pseudo_iterations": iters, "flux": args.flux,
+                   "pgrad": args.pgrad, "local_dtau": bool(wk.local_dtau), "bdf": wk.bdf},
         "roofline": roofline,
     }
     if args.cpu_budget > 0:
