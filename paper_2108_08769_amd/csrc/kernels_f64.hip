@@ -1,6 +1,7 @@
 // kernels_f64.hip -- kernels of one real-time step on gfx950 other than the row-marching stage:
-// begin-of-step bookkeeping and the deterministic residual finalize (all tanks in one launch),
-// the conversions of the mixed-precision storage, and the plain FP64 stage kernel.
+// begin-of-step bookkeeping and the deterministic residual finalize (all tanks in one launch each),
+// the conversions of the mixed-precision storage, the real-time step bound, and the plain FP64
+// stage kernel.
 //
 // stage_direct_f64 is the plain form of a stage: one thread per cell, which reconstructs itself
 // and its four neighbours and evaluates all four of its faces.  Every face is therefore computed
@@ -70,6 +71,9 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
     const int i = blockIdx.x * kDirectTX + threadIdx.x;
     const int j = blockIdx.y * kDirectTY + threadIdx.y;
     double part[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
+    constexpr size_t kNoCell = ~(size_t)0;
+    size_t out_c = kNoCell;  // this thread's updated cell, if any, and its new state
+    double out[4] = {0.0, 0.0, 0.0, 0.0};
 
     if (i < t.nx && j < t.ny) {
         const size_t c = (size_t)j * t.nx + i;
@@ -132,10 +136,10 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
                 R4[k] = -div + (k < 3 ? src[k] : 0.0);
             }
             const double fac = ad * rcp_pos(api);
+            out_c = c;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) qout[k * plane + c] = base[k] + fac * R4[k];
-            const double pnew = p0 + t.beta * (ad * R4[3]);
-            qout[3 * plane + c] = pnew;
+            for (int k = 0; k < 3; ++k) out[k] = base[k] + fac * R4[k];
+            out[3] = p0 + t.beta * (ad * R4[3]);
             if (last) {
                 const double rp = t.beta * R4[3];
                 if (NORM_MAX) {
@@ -149,63 +153,84 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
                     part[2] = R4[2] * R4[2];
                     part[3] = rp * rp;
                 }
-                const double rn = qout[c];
-                part[4] = (rn > 0.0 && rn < INFINITY) ? 0.0 : 1.0;
+                part[4] = (out[0] > 0.0 && out[0] < INFINITY) ? 0.0 : 1.0;
             }
         }
     }
+    // the residual is reduced before the state is stored: the workgroup barrier of the reduction
+    // would otherwise wait for the stores to complete
     if (last) {
         const int blk = blockIdx.x + blockIdx.y * gridDim.x;
-        block_reduce_store<NORM_MAX, kDirectTX * kDirectTY>(part, t.partials + (size_t)blk * kPartialWidth);
+        block_reduce<NORM_MAX, kDirectTX * kDirectTY>(part);
+        if (threadIdx.x == 0 && threadIdx.y == 0)
+            for (int k = 0; k < kPartialWidth; ++k) t.partials[(size_t)blk * kPartialWidth + k] = part[k];
     }
+    if (out_c != kNoCell)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) qout[k * plane + out_c] = out[k];
 }
 
-// Deterministic second pass of the residual: sums (or maxima) over the partials of one tank
-// in a fixed order, then the pseudo-loop control of the tank.  Workgroup b serves tank b.
+// Deterministic second pass of the residual and the pseudo-loop control of one tank per
+// workgroup (Algorithm 1): one wave combines the tank's partials in a fixed order (lane-strided,
+// then the wave tree), then stores the norms, the stop flags, the buffer rotation and the global
+// pseudo-time step.  One wave and no barrier keep this short launch as short as it gets.
 template <bool NORM_MAX>
-__global__ void __launch_bounds__(256) finalize_kernel(const TankDev *__restrict__ tanks, Scheme sc)
+__global__ void __launch_bounds__(64) finalize_kernel(const TankDev *__restrict__ tanks, Scheme sc)
 {
-    const TankDev &t = tanks[blockIdx.x];
-    Status *st = t.status;
-    if (st->done) return;
-    const int n_blocks = t.n_partials;
+    const TankDev *p = tanks + blockIdx.x;
+    Status *st = uni(p->status);
+    const int n = uni(p->n_partials);
+    const double *partials = uni(p->partials);
+    const int lane = threadIdx.x;
+    // the partials are read before the stop flag is known (one memory round trip fewer); a
+    // stopped tank discards them
     double acc[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
-    for (int b = threadIdx.x; b < n_blocks; b += 256)
-        for (int k = 0; k < kPartialWidth; ++k) {
-            const double x = t.partials[(size_t)b * kPartialWidth + k];
-            acc[k] = (k == 5) ? fmin(acc[k], x)
-                              : ((NORM_MAX && k < 4) ? combine<true>(acc[k], x) : acc[k] + x);
+    constexpr int kBatch = 4;  // partials per lane whose loads are in flight together
+    for (int b0 = 0; b0 < n; b0 += kBatch * 64) {
+        double x[kBatch][kPartialWidth];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            const int b = min(b0 + q * 64 + lane, n - 1);
+#pragma unroll
+            for (int k = 0; k < kPartialWidth; ++k) x[q][k] = partials[(size_t)b * kPartialWidth + k];
         }
-    __shared__ double red[256][kPartialWidth];
-    for (int k = 0; k < kPartialWidth; ++k) red[threadIdx.x][k] = acc[k];
-    __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < kPartialWidth; ++k) {
-                const double y = red[threadIdx.x + s][k];
-                const double x = red[threadIdx.x][k];
-                red[threadIdx.x][k] = (k == 5) ? fmin(x, y)
-                                               : ((NORM_MAX && k < 4) ? combine<true>(x, y) : x + y);
-            }
-        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            if (b0 + q * 64 + lane >= n) continue;
+#pragma unroll
+            for (int k = 0; k < kPartialWidth; ++k)
+                acc[k] = (k == 5) ? fmin(acc[k], x[q][k])
+                                  : ((NORM_MAX && k < 4) ? combine<true>(acc[k], x[q][k]) : acc[k] + x[q][k]);
+        }
     }
-    if (threadIdx.x == 0) {
-        double norms[4];
+    auto sum = [](double a, double b) { return a + b; };
+    auto mx = [](double a, double b) { return combine<true>(a, b); };
+    auto mn = [](double a, double b) { return fmin(a, b); };
+#pragma unroll
+    for (int k = 0; k < kPartialWidth; ++k)
+        acc[k] = (k == 5) ? wave_reduce_to_lane63(acc[k], INFINITY, mn)
+                          : ((NORM_MAX && k < 4) ? wave_reduce_to_lane63(acc[k], 0.0, mx)
+                                                 : wave_reduce_to_lane63(acc[k], 0.0, sum));
+    if (st->done) return;
+    if (lane == 63) {
+        const int n_fluid = uni(p->n_fluid);
+        const double tol = st->tol;
         bool finite = true, below = true;
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
-            norms[k] = NORM_MAX ? red[0][k] : sqrt(red[0][k] / (double)(t.n_fluid > 0 ? t.n_fluid : 1));
-            if (!(norms[k] < INFINITY)) finite = false;  // NaN or Inf
-            if (!(norms[k] < st->tol)) below = false;
-            st->norms[k] = norms[k];
+            const double nk = NORM_MAX ? acc[k] : sqrt(acc[k] / (double)(n_fluid > 0 ? n_fluid : 1));
+            if (!(nk < INFINITY)) finite = false;  // NaN or Inf
+            if (!(nk < tol)) below = false;
+            st->norms[k] = nk;
         }
         const int iters = st->iters + 1;
-        const bool bad = !finite || red[0][4] > 0.0;
+        const bool bad = !finite || acc[4] > 0.0;
         st->iters = iters;
         st->cur = next_cur(st->cur, sc.smax);
         if (bad) st->diverged = 1;
-        const bool converged = st->tol > 0.0 && below;
+        const bool converged = tol > 0.0 && below;
         st->done = (bad || converged || iters >= st->max_pseudo) ? 1 : 0;
-        if (red[0][5] < INFINITY) st->dtau_global = red[0][5];  // reduced only when global
+        if (acc[5] < INFINITY) st->dtau_global = acc[5];  // reduced only when global
     }
 }
 
@@ -381,10 +406,10 @@ int launch_stage_direct_f64(const TankDev &t, const Scheme &sc, int stage, void 
 int launch_finalize_all(const TankDev *tanks_dev, int n_tanks, const Scheme &sc, void *stream)
 {
     if (sc.norm_max)
-        hipLaunchKernelGGL(finalize_kernel<true>, dim3((unsigned)n_tanks), dim3(256), 0,
+        hipLaunchKernelGGL(finalize_kernel<true>, dim3((unsigned)n_tanks), dim3(64), 0,
                            (hipStream_t)stream, tanks_dev, sc);
     else
-        hipLaunchKernelGGL(finalize_kernel<false>, dim3((unsigned)n_tanks), dim3(256), 0,
+        hipLaunchKernelGGL(finalize_kernel<false>, dim3((unsigned)n_tanks), dim3(64), 0,
                            (hipStream_t)stream, tanks_dev, sc);
     return (int)hipGetLastError();
 }

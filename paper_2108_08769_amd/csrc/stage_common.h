@@ -102,35 +102,69 @@ __device__ __forceinline__ double combine(double a, double b)
     return NORM_MAX ? (a > b || a != a ? a : b) : a + b;
 }
 
-// Workgroup reduction of the residual partials (fixed order: deterministic): sums or maxima of the
-// four fields, the sum of bad cells, the minimum pseudo-time step.
-template <bool NORM_MAX, int NT>
-__device__ __forceinline__ void block_reduce_store(double v[kPartialWidth], double *out)
+// DPP move of a double (gfx9 data-parallel primitives, in VALU: no LDS traffic).  Lanes whose
+// source lies outside the pattern, and rows outside ROW_MASK, keep `old`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double old, double x)
 {
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)b, CTRL,
+                                                              ROW_MASK, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(b >> 32),
+                                                              CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Row shift: lane i of each row of 16 lanes receives x from lane i - N of the same row.
+template <int N>
+__device__ __forceinline__ double dpp_row_shr(double old, double x)
+{
+    static_assert(N >= 1 && N <= 15, "row_shr takes 1..15");
+    return dpp_f64<0x110 | N, 0xf>(old, x);
+}
+
+// Fixed-order reduction over the 64 lanes of a wave with the associative op (identity id): a tree
+// within each row of 16 lanes, then the rows combined by broadcasts of lanes 15 and 31.  The
+// result is complete in lane 63 only.
+template <class Op>
+__device__ __forceinline__ double wave_reduce_to_lane63(double x, double id, Op op)
+{
+    x = op(x, dpp_row_shr<1>(id, x));
+    x = op(x, dpp_row_shr<2>(id, x));
+    x = op(x, dpp_row_shr<4>(id, x));
+    x = op(x, dpp_row_shr<8>(id, x));        // lane 15 of each row: the row
+    x = op(x, dpp_f64<0x142, 0xa>(id, x));   // row_bcast:15 -> lane 31: rows 0-1, lane 63: rows 2-3
+    x = op(x, dpp_f64<0x143, 0xc>(id, x));   // row_bcast:31 -> lane 63: all rows
+    return x;
+}
+
+// Workgroup reduction of the residual partials (fixed order: deterministic): sums or maxima of the
+// four fields, the sum of bad cells, the minimum pseudo-time step.  The totals end up in every lane
+// of wave 0 (each wave's tree in VALU, then the waves' results through LDS).
+template <bool NORM_MAX, int NT>
+__device__ __forceinline__ void block_reduce(double v[kPartialWidth])
+{
+    auto sum = [](double a, double b) { return a + b; };
+    auto mx = [](double a, double b) { return combine<true>(a, b); };
+    auto mn = [](double a, double b) { return fmin(a, b); };
 #pragma unroll
-    for (int k = 0; k < kPartialWidth; ++k) {
-        double x = v[k];
-        const bool mx = NORM_MAX && k < 4;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double y = __shfl_xor(x, off, 64);
-            x = (k == 5) ? fmin(x, y) : (mx ? combine<true>(x, y) : x + y);
-        }
-        v[k] = x;
-    }
+    for (int k = 0; k < kPartialWidth; ++k)
+        v[k] = (k == 5) ? wave_reduce_to_lane63(v[k], INFINITY, mn)
+                        : ((NORM_MAX && k < 4) ? wave_reduce_to_lane63(v[k], 0.0, mx)
+                                               : wave_reduce_to_lane63(v[k], 0.0, sum));
     __shared__ double red[NT / 64][kPartialWidth];
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int wave = tid >> 6, lane = tid & 63;
-    if (lane == 0)
+    if (lane == 63)
         for (int k = 0; k < kPartialWidth; ++k) red[wave][k] = v[k];
     __syncthreads();
-    if (tid == 0) {
+    if (wave == 0) {
         for (int k = 0; k < kPartialWidth; ++k) {
             double x = red[0][k];
             for (int w = 1; w < NT / 64; ++w)
                 x = (k == 5) ? fmin(x, red[w][k])
                              : ((NORM_MAX && k < 4) ? combine<true>(x, red[w][k]) : x + red[w][k]);
-            out[k] = x;
+            v[k] = x;
         }
     }
 }

@@ -593,17 +593,17 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     }
 
     if (LAST) {
-        // wave reduction (fixed order) and one partial per unit
+        // wave reduction (fixed order, in VALU) and one partial per unit
         const double part[kPartialWidth] = {part0, part1, part2, part3, part4, part5};
+        auto sum = [](double a, double b) { return a + b; };
+        auto mx = [](double a, double b) { return combine<true>(a, b); };
+        auto mn = [](double a, double b) { return fmin(a, b); };
 #pragma unroll
         for (int k = 0; k < kPartialWidth; ++k) {
-            double x = part[k];
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double y = __shfl_xor(x, off, kLanes);
-                x = (k == 5) ? fmin(x, y) : ((NORM_MAX && k < 4) ? combine<true>(x, y) : x + y);
-            }
-            if (lane == 0) t.partials[(size_t)un.local * kPartialWidth + k] = x;
+            const double x = (k == 5) ? wave_reduce_to_lane63(part[k], INFINITY, mn)
+                                      : ((NORM_MAX && k < 4) ? wave_reduce_to_lane63(part[k], 0.0, mx)
+                                                             : wave_reduce_to_lane63(part[k], 0.0, sum));
+            if (lane == kLanes - 1) t.partials[(size_t)un.local * kPartialWidth + k] = x;
         }
     }
 }

@@ -70,14 +70,10 @@ struct SourceData {
     double z0, z1, z2, n0, n1, n2, m0, m1, m2;
 };
 
-__device__ __forceinline__ SourceData load_source(const TankDev &t, const double *q0, size_t c,
-                                                  bool bdf2)
+// Level n (and n-1 with BDF2) of cell c; these do not depend on the pseudo-loop status.
+__device__ __forceinline__ void load_levels(const TankDev &t, size_t c, bool bdf2, SourceData &s)
 {
     const size_t plane = t.plane;
-    SourceData s;
-    s.z0 = q0[c];
-    s.z1 = q0[plane + c];
-    s.z2 = q0[2 * plane + c];
     s.n0 = t.level_n[c];
     s.n1 = t.level_n[plane + c];
     s.n2 = t.level_n[2 * plane + c];
@@ -88,7 +84,49 @@ __device__ __forceinline__ SourceData load_source(const TankDev &t, const double
     } else {
         s.m0 = s.m1 = s.m2 = 0.0;
     }
+}
+
+__device__ __forceinline__ SourceData load_source(const TankDev &t, const double *q0, size_t c,
+                                                  bool bdf2)
+{
+    const size_t plane = t.plane;
+    SourceData s;
+    s.z0 = q0[c];
+    s.z1 = q0[plane + c];
+    s.z2 = q0[2 * plane + c];
+    load_levels(t, c, bdf2, s);
     return s;
+}
+
+// Residual partial of one tile in a fixed order (deterministic): each tile cell's six values go
+// to LDS, then value k is combined by lanes 8k .. 8k+7 of wave 0, each over NC/8 cells, and a DPP
+// tree within those 8 lanes combines them; lane 8k+7 stores value k.  Only wave 0 works after the
+// barrier, and no lane exchange goes through LDS.
+template <bool NORM_MAX, int NC>
+__device__ __forceinline__ void tile_reduce_store(const double part[kPartialWidth], double *scratch,
+                                                  double *out)
+{
+    static_assert(NC % 8 == 0, "eight lanes per value");
+    const int tid = threadIdx.x;
+    if (tid < NC)
+#pragma unroll
+        for (int k = 0; k < kPartialWidth; ++k) scratch[k * NC + tid] = part[k];
+    __syncthreads();
+    if (tid < 8 * kPartialWidth) {
+        const int k = tid >> 3, l = tid & 7;
+        const bool mn = k == 5;               // minimum pseudo-time step
+        const bool mx = NORM_MAX && k < 4;    // maximum norm
+        const double id = mn ? INFINITY : 0.0;
+        auto op = [&](double a, double b) { return mn ? fmin(a, b) : (mx ? combine<true>(a, b) : a + b); };
+        double x = scratch[k * NC + l];
+#pragma unroll
+        for (int j = 1; j < NC / 8; ++j) x = op(x, scratch[k * NC + l + 8 * j]);
+        // row shifts stay within rows of 16 lanes; lane 8k+7 only ever combines lanes 8k .. 8k+7
+        x = op(x, dpp_row_shr<1>(id, x));
+        x = op(x, dpp_row_shr<2>(id, x));
+        x = op(x, dpp_row_shr<4>(id, x));
+        if (l == 7) out[k] = x;
+    }
 }
 
 // NT threads per tile: 256 (one per tile cell) or 512 (every phase finishes in at most two
@@ -101,6 +139,7 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     constexpr int SX = TX + 2, SY = TY + 2, NR1 = SX * SY;  // flags: tile + 1-cell ring
     constexpr int NC = TX * TY;
     static_assert(NC <= NT, "at most one tile cell per thread");
+    static_assert(kPartialWidth * NC <= 4 * NR2, "the residual reduction reuses the primitives' LDS");
     constexpr int NRING = 2 * (TX + TY);                    // ring positions without corners
     constexpr int NPOS = NC + NRING;
     constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
@@ -110,9 +149,6 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     __shared__ double sXL[4][NFX], sXR[4][NFX];  // x-face states (then fluxes in sXL)
     __shared__ double sYL[4][NFY], sYU[4][NFY];  // y-face states (then fluxes in sYL)
 
-    const Status *st = t.status;
-    if (st->done) return;
-
     // XCD-aware tile order: the hardware hands block b to XCD b % 8; each XCD gets a contiguous
     // run of tiles so that neighbouring tiles, which share halo cells, share an L2.
     const int per = (n_tiles + 7) >> 3;
@@ -121,19 +157,46 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     const int x0 = (tile % tiles_x) * TX;
     const int y0 = (tile / tiles_x) * TY;
     const int tid = threadIdx.x;
+    const size_t plane = t.plane;
+    const bool slip = sc.slip != 0;
+    const double k = sc.k;
 
+    // ---- phase 1: every global load of the stage is issued here --------------------------
+    // Loads that do not depend on the pseudo-loop status go first, so that their latency
+    // overlaps the status read: the cell flags and the real-time levels of this thread's first
+    // phase-2 cell.
+    constexpr int NFL = (NR1 + NT - 1) / NT;
+    uint8_t fl[NFL];
+#pragma unroll
+    for (int q = 0; q < NFL; ++q) {
+        const int r = tid + q * NT;
+        const int ri = r % SX, rj = r / SX;
+        int gi, gj;
+        fl[q] = FLAG_SOLID;  // outside a non-periodic side: not a fluid cell
+        if (r < NR1 && locate(x0 - 1 + ri, t.nx, t.per_x, gi) && locate(y0 - 1 + rj, t.ny, t.per_y, gj))
+            fl[q] = t.flags[(size_t)gj * t.nx + gi];
+    }
+    const StepParams sp = *t.step;
+    const bool bdf2 = sp.b2 != 0.0;
+    SourceData src0 = {1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+    size_t own_c = ~(size_t)0;  // this thread's first phase-2 cell, if inside the tank
+    if (tid < NPOS) {
+        int i, j, gi, gj;
+        ring_position<TX, TY>(tid, i, j);
+        if (locate(x0 + i, t.nx, t.per_x, gi) && locate(y0 + j, t.ny, t.per_y, gj)) {
+            own_c = (size_t)gj * t.nx + gi;
+            load_levels(t, own_c, bdf2, src0);
+        }
+    }
+
+    const Status *st = t.status;
+    if (st->done) return;
     const int cur = st->cur;
     const StageBuffers bufs = stage_buffers(cur, stage);
     const double *qprev = (const double *)t.state[bufs.in];
     const double *q0 = (const double *)t.state[cur];
     double *qout = (double *)t.state[bufs.out];
-    const StepParams sp = *t.step;
-    const size_t plane = t.plane;
-    const bool slip = sc.slip != 0;
-    const bool bdf2 = sp.b2 != 0.0;
-    const double k = sc.k;
 
-    // ---- phase 1: every global load of the stage is issued here --------------------------
     for (int r = tid; r < NR2; r += NT) {
         const int ri = r % RX, rj = r / RX;
         int gi, gj;
@@ -145,26 +208,17 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
         sW[2][r] = w.v;
         sW[3][r] = w.p;
     }
-    for (int r = tid; r < NR1; r += NT) {
-        const int ri = r % SX, rj = r / SX;
-        int gi, gj;
-        uint8_t f = FLAG_SOLID;  // outside a non-periodic side: not a fluid cell
-        if (locate(x0 - 1 + ri, t.nx, t.per_x, gi) && locate(y0 - 1 + rj, t.ny, t.per_y, gj))
-            f = t.flags[(size_t)gj * t.nx + gi];
-        sF[r] = f;
-    }
-    // stage-0 data of this thread's first phase-2 cell, and Q^0's pressure of its tile cell
-    SourceData src0 = {1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+    // Q^0 of this thread's first phase-2 cell (and its pressure for the tile cell's update)
     double own_p0 = 0.0;
-    if (tid < NPOS) {
-        int i, j, gi, gj;
-        ring_position<TX, TY>(tid, i, j);
-        if (locate(x0 + i, t.nx, t.per_x, gi) && locate(y0 + j, t.ny, t.per_y, gj)) {
-            const size_t c = (size_t)gj * t.nx + gi;
-            src0 = load_source(t, q0, c, bdf2);
-            if (tid < NC) own_p0 = q0[3 * plane + c];
-        }
+    if (own_c != ~(size_t)0) {
+        src0.z0 = q0[own_c];
+        src0.z1 = q0[plane + own_c];
+        src0.z2 = q0[2 * plane + own_c];
+        if (tid < NC) own_p0 = q0[3 * plane + own_c];
     }
+#pragma unroll
+    for (int q = 0; q < NFL; ++q)
+        if (tid + q * NT < NR1) sF[tid + q * NT] = fl[q];
     __syncthreads();
 
     // ---- phase 2: reconstruction of the tile and ring cells --------------------------------
@@ -292,6 +346,9 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     const double alpha = sc.alpha[stage - 1];
     const bool last = (stage == sc.smax);
     double part[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
+    constexpr size_t kNoCell = ~(size_t)0;
+    size_t out_c = kNoCell;  // this thread's updated cell, if any, and its new state
+    double out[4] = {0.0, 0.0, 0.0, 0.0};
     if (tid < NC) {
         const int i = tid % TX, j = tid / TX;
         const int gi = x0 + i, gj = y0 + j;
@@ -314,10 +371,11 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
             const double ad = alpha * dtau;
             const double api = 1.0 + sp.b0 * ad * sp.inv_dt;
             const double fac = ad * rcp_pos(api);
-            qout[c] = r0 + fac * R4[0];
-            qout[plane + c] = m0 + fac * R4[1];
-            qout[2 * plane + c] = n0 + fac * R4[2];
-            qout[3 * plane + c] = own_p0 + t.beta * (ad * R4[3]);
+            out_c = c;
+            out[0] = r0 + fac * R4[0];
+            out[1] = m0 + fac * R4[1];
+            out[2] = n0 + fac * R4[2];
+            out[3] = own_p0 + t.beta * (ad * R4[3]);
             if (last) {
                 const double rp = t.beta * R4[3];
                 if (NORM_MAX) {
@@ -331,12 +389,19 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
                     part[2] = R4[2] * R4[2];
                     part[3] = rp * rp;
                 }
-                const double rn = r0 + fac * R4[0];
-                part[4] = (rn > 0.0 && rn < INFINITY) ? 0.0 : 1.0;
+                part[4] = (out[0] > 0.0 && out[0] < INFINITY) ? 0.0 : 1.0;
             }
         }
     }
-    if (last) block_reduce_store<NORM_MAX, NT>(part, t.partials + (size_t)tile * kPartialWidth);
+    // the residual is reduced before the state is stored: the workgroup barrier of the reduction
+    // would otherwise wait for the stores to complete
+    if (last) tile_reduce_store<NORM_MAX, NC>(part, &sW[0][0], t.partials + (size_t)tile * kPartialWidth);
+    if (out_c != kNoCell) {
+        qout[out_c] = out[0];
+        qout[plane + out_c] = out[1];
+        qout[2 * plane + out_c] = out[2];
+        qout[3 * plane + out_c] = out[3];
+    }
 }
 
 template <int TX, int TY, int NT>
