@@ -53,11 +53,11 @@ constexpr int kDirectTX = 16, kDirectTY = 16;
 
 template <bool NORM_MAX>
 __global__ void __launch_bounds__(kDirectTX *kDirectTY)
-    stage_direct_f64(TankDev t, Scheme sc, int stage)
+    stage_direct_f64(TankDev t, Scheme sc, int stage, IterArgs ia)
 {
     const Status *st = t.status;
     if (st->done) return;
-    const int cur = st->cur;
+    const int cur = iter_cur(st->cur0, ia.cur_off);
     const StageBuffers b = stage_buffers(cur, stage);
     const double *qprev = (const double *)t.state[b.in];
     const double *q0 = (const double *)t.state[cur];
@@ -170,68 +170,10 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
         for (int k = 0; k < 4; ++k) qout[k * plane + out_c] = out[k];
 }
 
-// Deterministic second pass of the residual and the pseudo-loop control of one tank per
-// workgroup (Algorithm 1): one wave combines the tank's partials in a fixed order (lane-strided,
-// then the wave tree), then stores the norms, the stop flags, the buffer rotation and the global
-// pseudo-time step.  One wave and no barrier keep this short launch as short as it gets.
-template <bool NORM_MAX>
+// The finalize of every tank in its own launch (one wave per tank; see finalize_wave).
 __global__ void __launch_bounds__(64) finalize_kernel(const TankDev *__restrict__ tanks, Scheme sc)
 {
-    const TankDev *p = tanks + blockIdx.x;
-    Status *st = uni(p->status);
-    const int n = uni(p->n_partials);
-    const double *partials = uni(p->partials);
-    const int lane = threadIdx.x;
-    // the partials are read before the stop flag is known (one memory round trip fewer); a
-    // stopped tank discards them
-    double acc[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
-    constexpr int kBatch = 4;  // partials per lane whose loads are in flight together
-    for (int b0 = 0; b0 < n; b0 += kBatch * 64) {
-        double x[kBatch][kPartialWidth];
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-            const int b = min(b0 + q * 64 + lane, n - 1);
-#pragma unroll
-            for (int k = 0; k < kPartialWidth; ++k) x[q][k] = partials[(size_t)b * kPartialWidth + k];
-        }
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-            if (b0 + q * 64 + lane >= n) continue;
-#pragma unroll
-            for (int k = 0; k < kPartialWidth; ++k)
-                acc[k] = (k == 5) ? fmin(acc[k], x[q][k])
-                                  : ((NORM_MAX && k < 4) ? combine<true>(acc[k], x[q][k]) : acc[k] + x[q][k]);
-        }
-    }
-    auto sum = [](double a, double b) { return a + b; };
-    auto mx = [](double a, double b) { return combine<true>(a, b); };
-    auto mn = [](double a, double b) { return fmin(a, b); };
-#pragma unroll
-    for (int k = 0; k < kPartialWidth; ++k)
-        acc[k] = (k == 5) ? wave_reduce_to_lane63(acc[k], INFINITY, mn)
-                          : ((NORM_MAX && k < 4) ? wave_reduce_to_lane63(acc[k], 0.0, mx)
-                                                 : wave_reduce_to_lane63(acc[k], 0.0, sum));
-    if (st->done) return;
-    if (lane == 63) {
-        const int n_fluid = uni(p->n_fluid);
-        const double tol = st->tol;
-        bool finite = true, below = true;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const double nk = NORM_MAX ? acc[k] : sqrt(acc[k] / (double)(n_fluid > 0 ? n_fluid : 1));
-            if (!(nk < INFINITY)) finite = false;  // NaN or Inf
-            if (!(nk < tol)) below = false;
-            st->norms[k] = nk;
-        }
-        const int iters = st->iters + 1;
-        const bool bad = !finite || acc[4] > 0.0;
-        st->iters = iters;
-        st->cur = next_cur(st->cur, sc.smax);
-        if (bad) st->diverged = 1;
-        const bool converged = tol > 0.0 && below;
-        st->done = (bad || converged || iters >= st->max_pseudo) ? 1 : 0;
-        if (acc[5] < INFINITY) st->dtau_global = acc[5];  // reduced only when global
-    }
+    finalize_wave(load_tank(tanks + blockIdx.x), sc, threadIdx.x);
 }
 
 // Start of a real-time step (Algorithm 1) for tank blockIdx.y: with history the real-time levels
@@ -271,6 +213,7 @@ __global__ void __launch_bounds__(256)
         st->diverged = 0;
         st->max_pseudo = max_pseudo;
         st->tol = tol;
+        st->cur0 = cur;
         st->done = (max_pseudo <= 0) ? 1 : 0;
     }
 }
@@ -392,25 +335,23 @@ int launch_export_mixed(const TankDev &t, int cur, double *q, void *stream)
     return (int)hipGetLastError();
 }
 
-int launch_stage_direct_f64(const TankDev &t, const Scheme &sc, int stage, void *stream)
+int launch_stage_direct_f64(const TankDev &t, const Scheme &sc, int stage, const IterArgs &ia,
+                            void *stream)
 {
+    if (ia.fin) return (int)hipErrorInvalidValue;
     dim3 grid((t.nx + kDirectTX - 1) / kDirectTX, (t.ny + kDirectTY - 1) / kDirectTY);
     dim3 block(kDirectTX, kDirectTY);
     if (sc.norm_max)
-        hipLaunchKernelGGL(stage_direct_f64<true>, grid, block, 0, (hipStream_t)stream, t, sc, stage);
+        hipLaunchKernelGGL(stage_direct_f64<true>, grid, block, 0, (hipStream_t)stream, t, sc, stage, ia);
     else
-        hipLaunchKernelGGL(stage_direct_f64<false>, grid, block, 0, (hipStream_t)stream, t, sc, stage);
+        hipLaunchKernelGGL(stage_direct_f64<false>, grid, block, 0, (hipStream_t)stream, t, sc, stage, ia);
     return (int)hipGetLastError();
 }
 
 int launch_finalize_all(const TankDev *tanks_dev, int n_tanks, const Scheme &sc, void *stream)
 {
-    if (sc.norm_max)
-        hipLaunchKernelGGL(finalize_kernel<true>, dim3((unsigned)n_tanks), dim3(64), 0,
-                           (hipStream_t)stream, tanks_dev, sc);
-    else
-        hipLaunchKernelGGL(finalize_kernel<false>, dim3((unsigned)n_tanks), dim3(64), 0,
-                           (hipStream_t)stream, tanks_dev, sc);
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)n_tanks), dim3(64), 0, (hipStream_t)stream,
+                       tanks_dev, sc);
     return (int)hipGetLastError();
 }
 

@@ -169,6 +169,65 @@ __device__ __forceinline__ void block_reduce(double v[kPartialWidth])
     }
 }
 
+// Deterministic second pass of the residual and the pseudo-loop control of tank t (Algorithm 1),
+// by one whole wave: the tank's partials combined in a fixed order (lane-strided, then the wave
+// tree), then the norms, the stop flags, the buffer rotation and the global pseudo-time step
+// stored.  A stopped tank is left alone.
+__device__ __forceinline__ void finalize_wave(const TankDev &t, const Scheme &sc, int lane)
+{
+    Status *st = t.status;
+    const int n = t.n_partials;
+    const bool nm = sc.norm_max != 0;
+    // the partials are read before the stop flag is known (one memory round trip fewer)
+    double acc[kPartialWidth] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
+    constexpr int kBatch = 4;  // partials per lane whose loads are in flight together
+    for (int b0 = 0; b0 < n; b0 += kBatch * 64) {
+        double x[kBatch][kPartialWidth];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            const int b = min(b0 + q * 64 + lane, n - 1);
+#pragma unroll
+            for (int k = 0; k < kPartialWidth; ++k) x[q][k] = t.partials[(size_t)b * kPartialWidth + k];
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            if (b0 + q * 64 + lane >= n) continue;
+#pragma unroll
+            for (int k = 0; k < kPartialWidth; ++k)
+                acc[k] = (k == 5) ? fmin(acc[k], x[q][k])
+                                  : ((nm && k < 4) ? combine<true>(acc[k], x[q][k]) : acc[k] + x[q][k]);
+        }
+    }
+    auto sum = [](double a, double b) { return a + b; };
+    auto mx = [](double a, double b) { return combine<true>(a, b); };
+    auto mn = [](double a, double b) { return fmin(a, b); };
+#pragma unroll
+    for (int k = 0; k < kPartialWidth; ++k)
+        acc[k] = (k == 5) ? wave_reduce_to_lane63(acc[k], INFINITY, mn)
+                          : ((nm && k < 4) ? wave_reduce_to_lane63(acc[k], 0.0, mx)
+                                           : wave_reduce_to_lane63(acc[k], 0.0, sum));
+    if (st->done) return;
+    if (lane == 63) {
+        const double tol = st->tol;
+        bool finite = true, below = true;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double nk = nm ? acc[k] : sqrt(acc[k] / (double)(t.n_fluid > 0 ? t.n_fluid : 1));
+            if (!(nk < INFINITY)) finite = false;  // NaN or Inf
+            if (!(nk < tol)) below = false;
+            st->norms[k] = nk;
+        }
+        const int iters = st->iters + 1;
+        const bool bad = !finite || acc[4] > 0.0;
+        st->iters = iters;
+        st->cur = next_cur(st->cur, sc.smax);
+        if (bad) st->diverged = 1;
+        const bool converged = tol > 0.0 && below;
+        st->done = (bad || converged || iters >= st->max_pseudo) ? 1 : 0;
+        if (acc[5] < INFINITY) st->dtau_global = acc[5];  // reduced only when global
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Precision policies.  FP64: the state is stored as (rho, rho u, rho v, p) in FP64 and every step
 // runs in FP64.  Mixed: the state is stored in FP32 as the deviation from real-time level n

@@ -265,14 +265,22 @@ __device__ __forceinline__ Prim<R> ghost_state_gen(const TankDev &t, const Schem
 template <class P, bool NORM_MAX, int BDF, bool LAST, int WAVES, bool GEN>
 __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     stage_march(const TankDev *__restrict__ tanks, const MarchUnit *__restrict__ units, Scheme sc,
-                int stage)
+                int stage, IterArgs ia)
 {
     using R = typename P::Real;
     using S = typename P::Store;
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     const int lane = threadIdx.x % kLanes;
-    const MarchUnit un = units[blockIdx.x * (blockDim.x / kLanes) + wave];
+    int entry = blockIdx.x * (blockDim.x / kLanes) + wave;
+    if (ia.fin) {  // the waves in front of the unit table finalize the previous iteration
+        if (entry < ia.n_fin) {
+            if (entry < ia.n_tanks) finalize_wave(load_tank(tanks + entry), sc, lane);
+            return;
+        }
+        entry -= ia.n_fin;
+    }
+    const MarchUnit un = units[entry];
     if (un.tank < 0) return;  // padding (uniform per wave)
     const TankDev t = load_tank(tanks + un.tank);
     const Status *st = t.status;
@@ -286,7 +294,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     const int j0 = ch * t.chunk;
     const int j1 = min(j0 + t.chunk, t.ny);
 
-    const int cur = st->cur;
+    const int cur = iter_cur(st->cur0, ia.cur_off);
     const StageBuffers bufs = stage_buffers(cur, stage);
     const S *__restrict__ qprev = (const S *)state_buf(tanks + un.tank, bufs.in);
     const S *__restrict__ q0 = (const S *)state_buf(tanks + un.tank, cur);
@@ -610,47 +618,53 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
 
 template <class P, bool NM, int BDF, bool LS, bool GEN>
 void launch_t(const TankDev *tanks, const MarchUnit *units, dim3 g, dim3 b, int waves_simd,
-              const Scheme &sc, int stage, hipStream_t s)
+              const Scheme &sc, int stage, const IterArgs &ia, hipStream_t s)
 {
     if constexpr (!GEN) {
         if (waves_simd == 3) {
             hipLaunchKernelGGL((stage_march<P, NM, BDF, LS, 3, GEN>), g, b, 0, s, tanks, units, sc,
-                               stage);
+                               stage, ia);
             return;
         }
     }
-    hipLaunchKernelGGL((stage_march<P, NM, BDF, LS, 2, GEN>), g, b, 0, s, tanks, units, sc, stage);
+    hipLaunchKernelGGL((stage_march<P, NM, BDF, LS, 2, GEN>), g, b, 0, s, tanks, units, sc, stage, ia);
 }
 
 template <class P, int BDF, bool GEN>
 void launch_b(const TankDev *tanks, const MarchUnit *units, dim3 g, dim3 b, int waves_simd,
-              const Scheme &sc, int stage, hipStream_t s)
+              const Scheme &sc, int stage, const IterArgs &ia, hipStream_t s)
 {
     if (stage == sc.smax) {
-        if (sc.norm_max) launch_t<P, true, BDF, true, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
-        else launch_t<P, false, BDF, true, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+        if (sc.norm_max) launch_t<P, true, BDF, true, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
+        else launch_t<P, false, BDF, true, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
     } else {
-        launch_t<P, false, BDF, false, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+        launch_t<P, false, BDF, false, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
     }
 }
 
 // One stage over the unit table, for the scheme's precision and BDF order.
+// ia.fin (stage 1 only) puts workgroups in front of the unit table whose waves finalize the
+// previous iteration, one tank each: ceil(n_tanks / waves_per_block) rounded up to a multiple of 8.
 template <bool GEN>
 int launch(const TankDev *tanks, const MarchUnit *units, int n_entries, int waves_per_block,
-           const Scheme &sc, int stage, int waves_simd, void *stream)
+           const Scheme &sc, int stage, const IterArgs &ia_in, int waves_simd, void *stream)
 {
     if (waves_per_block < 1 || waves_per_block > kMaxWavesPerBlock || n_entries % waves_per_block)
         return (int)hipErrorInvalidValue;
-    const dim3 g(n_entries / waves_per_block), b(kLanes * waves_per_block);
+    if (ia_in.fin && (stage != 1 || ia_in.n_tanks < 1)) return (int)hipErrorInvalidValue;
+    IterArgs ia = ia_in;
+    const int fin_blocks = ia.fin ? ((ia.n_tanks + 8 * waves_per_block - 1) / (8 * waves_per_block)) * 8 : 0;
+    ia.n_fin = fin_blocks * waves_per_block;
+    const dim3 g(n_entries / waves_per_block + fin_blocks), b(kLanes * waves_per_block);
     hipStream_t s = (hipStream_t)stream;
     if (sc.mixed) {
-        if (sc.bdf >= 3) launch_b<PrecMixed, 3, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
-        else if (sc.bdf == 2) launch_b<PrecMixed, 2, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
-        else launch_b<PrecMixed, 1, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+        if (sc.bdf >= 3) launch_b<PrecMixed, 3, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
+        else if (sc.bdf == 2) launch_b<PrecMixed, 2, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
+        else launch_b<PrecMixed, 1, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
     } else {
-        if (sc.bdf >= 3) launch_b<PrecF64, 3, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
-        else if (sc.bdf == 2) launch_b<PrecF64, 2, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
-        else launch_b<PrecF64, 1, GEN>(tanks, units, g, b, waves_simd, sc, stage, s);
+        if (sc.bdf >= 3) launch_b<PrecF64, 3, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
+        else if (sc.bdf == 2) launch_b<PrecF64, 2, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
+        else launch_b<PrecF64, 1, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
     }
     return (int)hipGetLastError();
 }

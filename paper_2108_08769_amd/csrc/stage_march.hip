@@ -8,14 +8,14 @@ namespace vdac {
 int march_strips(int nx) { return (nx + march::kOut - 1) / march::kOut; }
 
 int launch_stage_march(const TankDev *tanks_dev, const MarchUnit *units, int n_entries,
-                       int waves_per_block, const Scheme &sc, int stage, int waves_simd,
-                       void *stream)
+                       int waves_per_block, const Scheme &sc, int stage, const IterArgs &ia,
+                       int waves_simd, void *stream)
 {
     if (sc.general)
-        return launch_stage_march_general(tanks_dev, units, n_entries, waves_per_block, sc, stage,
+        return launch_stage_march_general(tanks_dev, units, n_entries, waves_per_block, sc, stage, ia,
                                           stream);
-    return march::launch<false>(tanks_dev, units, n_entries, waves_per_block, sc, stage, waves_simd,
-                                stream);
+    return march::launch<false>(tanks_dev, units, n_entries, waves_per_block, sc, stage, ia,
+                                waves_simd, stream);
 }
 
 }  // namespace vdac

@@ -7,9 +7,10 @@
 namespace vdac {
 
 int launch_stage_march_general(const TankDev *tanks_dev, const MarchUnit *units, int n_entries,
-                               int waves_per_block, const Scheme &sc, int stage, void *stream)
+                               int waves_per_block, const Scheme &sc, int stage, const IterArgs &ia,
+                               void *stream)
 {
-    return march::launch<true>(tanks_dev, units, n_entries, waves_per_block, sc, stage, 2, stream);
+    return march::launch<true>(tanks_dev, units, n_entries, waves_per_block, sc, stage, ia, 2, stream);
 }
 
 }  // namespace vdac

@@ -133,7 +133,7 @@ __device__ __forceinline__ void tile_reduce_store(const double part[kPartialWidt
 // rounds, which shortens the critical path of small grids).
 template <int TX, int TY, int NT, bool NORM_MAX>
 __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int stage, int tiles_x,
-                                                     int n_tiles)
+                                                     int n_tiles, IterArgs ia)
 {
     constexpr int RX = TX + 4, RY = TY + 4, NR2 = RX * RY;  // primitives: tile + 2-cell halo
     constexpr int SX = TX + 2, SY = TY + 2, NR1 = SX * SY;  // flags: tile + 1-cell ring
@@ -149,10 +149,21 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     __shared__ double sXL[4][NFX], sXR[4][NFX];  // x-face states (then fluxes in sXL)
     __shared__ double sYL[4][NFY], sYU[4][NFY];  // y-face states (then fluxes in sYL)
 
+    // A stage-1 launch with ia.fin set puts 8 workgroups in front of the tiles (8 keeps each
+    // tile on the same XCD as in the other stages); the first finalizes the previous iteration,
+    // dispatched before any tile so that it does not trail the launch.
+    int bid = (int)blockIdx.x;
+    if (ia.fin) {
+        if (bid < 8) {
+            if (bid == 0 && threadIdx.x < 64) finalize_wave(t, sc, threadIdx.x);
+            return;
+        }
+        bid -= 8;
+    }
     // XCD-aware tile order: the hardware hands block b to XCD b % 8; each XCD gets a contiguous
     // run of tiles so that neighbouring tiles, which share halo cells, share an L2.
     const int per = (n_tiles + 7) >> 3;
-    const int tile = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+    const int tile = (bid & 7) * per + (bid >> 3);
     if (tile >= n_tiles) return;
     const int x0 = (tile % tiles_x) * TX;
     const int y0 = (tile / tiles_x) * TY;
@@ -191,7 +202,7 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
 
     const Status *st = t.status;
     if (st->done) return;
-    const int cur = st->cur;
+    const int cur = iter_cur(st->cur0, ia.cur_off);
     const StageBuffers bufs = stage_buffers(cur, stage);
     const double *qprev = (const double *)t.state[bufs.in];
     const double *q0 = (const double *)t.state[cur];
@@ -405,17 +416,17 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
 }
 
 template <int TX, int TY, int NT>
-int launch_tile(const TankDev &t, const Scheme &sc, int stage, void *stream)
+int launch_tile(const TankDev &t, const Scheme &sc, int stage, const IterArgs &ia, void *stream)
 {
     const int tiles_x = (t.nx + TX - 1) / TX, tiles_y = (t.ny + TY - 1) / TY;
     const int n_tiles = tiles_x * tiles_y;
-    const int blocks = ((n_tiles + 7) / 8) * 8;
+    const int blocks = ((n_tiles + 7) / 8) * 8 + (ia.fin ? 8 : 0);
     if (sc.norm_max)
         hipLaunchKernelGGL((stage_tile_f64<TX, TY, NT, true>), dim3(blocks), dim3(NT), 0,
-                           (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles);
+                           (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles, ia);
     else
         hipLaunchKernelGGL((stage_tile_f64<TX, TY, NT, false>), dim3(blocks), dim3(NT), 0,
-                           (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles);
+                           (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles, ia);
     return (int)hipGetLastError();
 }
 
@@ -438,13 +449,14 @@ int tile_count(const TankDev &t, int tile_x, int tile_y)
 }
 
 int launch_stage_tile_f64(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
-                          void *stream)
+                          const IterArgs &ia, void *stream)
 {
-    if (tile_x == 32 && tile_y == 8) return launch_tile<32, 8, 256>(t, sc, stage, stream);
-    if (tile_x == 16 && tile_y == 16) return launch_tile<16, 16, 256>(t, sc, stage, stream);
-    if (tile_x == 64 && tile_y == 4) return launch_tile<64, 4, 256>(t, sc, stage, stream);
-    if (tile_x == 3208 && tile_y == 2) return launch_tile<32, 8, 512>(t, sc, stage, stream);
-    if (tile_x == 1616 && tile_y == 2) return launch_tile<16, 16, 512>(t, sc, stage, stream);
+    if (ia.fin && stage != 1) return (int)hipErrorInvalidValue;
+    if (tile_x == 32 && tile_y == 8) return launch_tile<32, 8, 256>(t, sc, stage, ia, stream);
+    if (tile_x == 16 && tile_y == 16) return launch_tile<16, 16, 256>(t, sc, stage, ia, stream);
+    if (tile_x == 64 && tile_y == 4) return launch_tile<64, 4, 256>(t, sc, stage, ia, stream);
+    if (tile_x == 3208 && tile_y == 2) return launch_tile<32, 8, 512>(t, sc, stage, ia, stream);
+    if (tile_x == 1616 && tile_y == 2) return launch_tile<16, 16, 512>(t, sc, stage, ia, stream);
     return (int)hipErrorInvalidValue;
 }
 

@@ -83,9 +83,14 @@ struct vdac_grid {
     std::vector<Status> status_host;
     int hist;                           // completed real steps since set_state (capped at 2):
                                         // how many earlier real-time levels are valid
-    // captured pseudo-iterations, keyed by the number of iterations per graph
+    // captured pseudo-iterations, keyed by the number of iterations per graph and the first
+    // iteration's index mod 3 (which fixes the buffer rotation, IterArgs::cur_off)
     hipStream_t cap_stream;
-    std::vector<std::pair<int, hipGraphExec_t>> graphs;
+    struct Captured {
+        int iters, phase;
+        hipGraphExec_t exec;
+    };
+    std::vector<Captured> graphs;
     // stage-kernel timing (measurement only)
     bool timing;
     std::vector<hipEvent_t> ev_pool;
@@ -390,7 +395,7 @@ int read_status(const vdac_grid *g, int tank, Status *st)
 
 void drop_graphs(vdac_grid *g)
 {
-    for (auto &kv : g->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &cg : g->graphs) (void)hipGraphExecDestroy(cg.exec);
     g->graphs.clear();
 }
 
@@ -708,13 +713,19 @@ int set_state(vdac_grid *g, int32_t tank, const double *q)
 
 namespace {
 
-// One pseudo-iteration of every tank: s_max stage launches (one per stage for the whole grid
-// with the row-marching kernel, one per stage and tank otherwise) and the residual finalize of
-// all tanks.  With timing on, an event pair brackets each iteration's stage launches.
+// Pseudo-iterations first_iter .. first_iter + n_iter - 1 of every tank: s_max stage launches per
+// iteration (one per stage for the whole grid with the row-marching kernel, one per stage and tank
+// otherwise) and the residual finalize of all tanks.  The finalize of an iteration runs inside
+// the next iteration's stage-1 launch (extra waves, see IterArgs), except where stage 1 needs its
+// result (the global pseudo-time step) and with the plain kernel; the sequence's last iteration is
+// finalized by a launch of its own.  With timing on, an event pair brackets each iteration's stage
+// launches.
 int launch_iterations(vdac_grid *g, hipStream_t stream, int n_iter, int first_iter, size_t *ev_next)
 {
     const int nt = (int)g->tanks.size();
     const Plan &pl = g->plan;
+    const bool defer = !g->sc.global_dtau && pl.kind != KIND_DIRECT;
+    const int rot = 1 + ((g->sc.smax - 1) & 1);  // next_cur's step
     int rc;
     for (int it = 0; it < n_iter; ++it) {
         hipEvent_t e1 = nullptr;
@@ -726,38 +737,48 @@ int launch_iterations(vdac_grid *g, hipStream_t stream, int n_iter, int first_it
             *ev_next += 2;
             (void)hipEventRecord(e0, stream);
         }
+        IterArgs ia;
+        ia.cur_off = (int)(((long long)(first_iter + it) * rot) % 3);
+        ia.n_fin = 0;
+        ia.n_tanks = nt;
         for (int s = 1; s <= g->sc.smax; ++s) {
+            ia.fin = (defer && s == 1 && it > 0) ? 1 : 0;
             if (pl.kind == KIND_MARCH) {
-                rc = launch_stage_march(g->tanks_dev, g->units_dev, pl.n_entries, pl.wpb, g->sc, s,
+                rc = launch_stage_march(g->tanks_dev, g->units_dev, pl.n_entries, pl.wpb, g->sc, s, ia,
                                         pl.waves_simd, stream);
                 if (rc != 0) return hip_fail((hipError_t)rc, "stage launch");
                 continue;
             }
             for (int t = 0; t < nt; ++t) {
                 const TankDev &d = g->tanks[t].dev;
-                rc = pl.kind == KIND_DIRECT ? launch_stage_direct_f64(d, g->sc, s, stream)
-                                            : launch_stage_tile_f64(d, g->sc, s, pl.tile_x, pl.tile_y, stream);
+                IterArgs one = ia;
+                one.n_tanks = 1;
+                rc = pl.kind == KIND_DIRECT ? launch_stage_direct_f64(d, g->sc, s, one, stream)
+                                            : launch_stage_tile_f64(d, g->sc, s, pl.tile_x, pl.tile_y, one, stream);
                 if (rc != 0) return hip_fail((hipError_t)rc, "stage launch");
             }
         }
         if (e1) (void)hipEventRecord(e1, stream);
-        rc = launch_finalize_all(g->tanks_dev, nt, g->sc, stream);
-        if (rc != 0) return hip_fail((hipError_t)rc, "finalize launch");
+        if (!defer || it == n_iter - 1) {
+            rc = launch_finalize_all(g->tanks_dev, nt, g->sc, stream);
+            if (rc != 0) return hip_fail((hipError_t)rc, "finalize launch");
+        }
     }
     return VDAC_OK;
 }
 
-// The graph of k pseudo-iterations of every tank, captured on the private stream once.
-int graph_for(vdac_grid *g, int k, hipGraphExec_t *exec)
+// The graph of k pseudo-iterations of every tank whose first iteration index is phase mod 3,
+// captured on the private stream once.
+int graph_for(vdac_grid *g, int k, int phase, hipGraphExec_t *exec)
 {
-    for (auto &kv : g->graphs)
-        if (kv.first == k) {
-            *exec = kv.second;
+    for (auto &cg : g->graphs)
+        if (cg.iters == k && cg.phase == phase) {
+            *exec = cg.exec;
             return VDAC_OK;
         }
     hipError_t e = hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "beginning graph capture");
-    int rc = launch_iterations(g, g->cap_stream, k, 0, nullptr);
+    int rc = launch_iterations(g, g->cap_stream, k, phase, nullptr);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(g->cap_stream, &graph);
     if (rc != VDAC_OK) {
@@ -769,7 +790,7 @@ int graph_for(vdac_grid *g, int k, hipGraphExec_t *exec)
     e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail(e, "instantiating the pseudo-iteration graph");
-    g->graphs.push_back({k, ge});
+    g->graphs.push_back({k, phase, ge});
     *exec = ge;
     return VDAC_OK;
 }
@@ -815,7 +836,7 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
     for (int m = 0; m < max_pseudo && group > 0;) {
         if (use_graph) {
             hipGraphExec_t exec;
-            if ((rc = graph_for(g, group, &exec)) != VDAC_OK) return rc;
+            if ((rc = graph_for(g, group, m % 3, &exec)) != VDAC_OK) return rc;
             hipError_t e = hipGraphLaunch(exec, g->stream);
             if (e != hipSuccess) return hip_fail(e, "graph launch");
         } else {

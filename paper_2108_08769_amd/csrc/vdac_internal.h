@@ -34,11 +34,34 @@ struct Status {
     int32_t cur;         // index (0..2) of the state buffer holding the current state
     int32_t diverged;    // nonzero once a non-finite residual or rho <= 0 was seen
     int32_t max_pseudo;  // iteration limit of the current real step
-    int32_t pad;
+    int32_t cur0;        // `cur` at the start of the real step: the stage kernels of pseudo-iteration
+                         // m take their buffers from cur0 and m (IterArgs), never from `cur`
     double tol;          // <= 0: run exactly max_pseudo iterations
     double norms[4];     // residual norms of the last iteration (rho, rho u, rho v, p)
     double dtau_global;  // global pseudo-time step: the minimum local step of the current state
 };
+
+// Per-launch arguments of a stage kernel that change from one pseudo-iteration m to the next.
+//   cur_off   the iteration's stage-0 buffer is (cur0 + cur_off) mod 3, cur_off = m * r mod 3 with
+//             r = next_cur's rotation: the buffers do not depend on the status the deferred
+//             finalize (below) rewrites while the launch runs
+//   fin       stage 1 only: the launch also runs the finalize of iteration m - 1 (extra waves, one
+//             per tank, dispatched first); its stage-1 work for a tank that this finalize stops is
+//             discarded, as it goes to a buffer that is neither the result nor read again
+//   n_fin     row-marching launches: finalize waves in front of the unit table (a multiple of 8
+//             workgroups, so that every unit stays on the XCD the unit table assigns it)
+struct IterArgs {
+    int32_t cur_off;
+    int32_t fin;
+    int32_t n_fin;
+    int32_t n_tanks;
+};
+
+__host__ __device__ inline int iter_cur(int cur0, int cur_off)
+{
+    const int c = cur0 + cur_off;
+    return c >= 3 ? c - 3 : c;
+}
 
 // Real-time coefficients of the current real step (Table 1), in device memory so that a captured
 // pseudo-iteration graph stays valid from one step to the next.
@@ -130,14 +153,18 @@ int launch_begin_step_all(const TankDev *tanks_dev, int n_tanks, size_t max_plan
                           const StepParams &sp, int max_pseudo, double tol, int use_history,
                           void *stream);
 int launch_finalize_all(const TankDev *tanks_dev, int n_tanks, const Scheme &sc, void *stream);
-int launch_stage_direct_f64(const TankDev &t, const Scheme &sc, int stage, void *stream);
+// The per-tank stage launches: the plain kernel never finalizes (ia.fin must be 0); the tiled
+// kernel runs the finalize of its tank in one extra workgroup when ia.fin is set.
+int launch_stage_direct_f64(const TankDev &t, const Scheme &sc, int stage, const IterArgs &ia,
+                            void *stream);
 int launch_stage_tile_f64(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
-                          void *stream);
+                          const IterArgs &ia, void *stream);
 int launch_stage_march(const TankDev *tanks_dev, const MarchUnit *units, int n_entries,
-                       int waves_per_block, const Scheme &sc, int stage, int waves_simd,
-                       void *stream);
+                       int waves_per_block, const Scheme &sc, int stage, const IterArgs &ia,
+                       int waves_simd, void *stream);
 int launch_stage_march_general(const TankDev *tanks_dev, const MarchUnit *units, int n_entries,
-                               int waves_per_block, const Scheme &sc, int stage, void *stream);
+                               int waves_per_block, const Scheme &sc, int stage, const IterArgs &ia,
+                               void *stream);
 // Global real-time step of one tank (Sec. 2.2.4): per-workgroup minima of
 // CFL_t dx dy / (|u| dy + |v| dx) over the fluid cells of the current state into out[n_blocks].
 int launch_realtime_dt(const TankDev &t, int mixed, double cfl_t, double *out, int n_blocks,
