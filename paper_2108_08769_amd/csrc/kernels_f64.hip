@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
 {
     const Status *st = t.status;
     if (st->done) return;
-    const int cur = iter_cur(st->cur0, ia.cur_off);
+    const int cur = ia.cur_off;
     const StageBuffers b = stage_buffers(cur, stage);
     const double *qprev = (const double *)t.state[b.in];
     const double *q0 = (const double *)t.state[cur];
@@ -180,7 +180,8 @@ __global__ void __launch_bounds__(64) finalize_kernel(const TankDev *__restrict_
 // shift (n-2 <- n-1 <- n), else the kept earlier levels are set to the new level n; then level
 // n <- current state and a fresh pseudo-loop status; workgroup (0, 0) also stores the step's BDF
 // coefficients.  In the mixed form the new level n is level n plus the current deviation, which
-// then becomes zero.
+// then becomes zero.  The current state moves to buffer 0, where every step's pseudo-loop starts
+// (the status keeps naming the old buffer, which still holds it, until the first finalize).
 __global__ void __launch_bounds__(256)
     begin_step_kernel(const TankDev *__restrict__ tanks, StepParams sp, int max_pseudo, double tol,
                       int use_history, int mixed)
@@ -195,8 +196,11 @@ __global__ void __launch_bounds__(256)
         const double *q = (const double *)t.state[cur];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (k == 3 && !mixed) break;  // the FP64 form keeps no level-n pressure
             const size_t e = k * plane + c;
+            if (k == 3 && !mixed) {  // the FP64 form keeps no level-n pressure
+                if (cur != 0) ((double *)t.state[0])[e] = q[e];
+                break;
+            }
             const double old = t.level_n[e];
             const double nw = mixed ? old + (double)d[e] : q[e];
             if (k < 3) {
@@ -204,7 +208,13 @@ __global__ void __launch_bounds__(256)
                 if (t.level_nm1) t.level_nm1[e] = use_history ? old : nw;
             }
             t.level_n[e] = nw;
-            if (mixed) d[e] = 0.0f;
+            // the step starts from buffer 0: the state moves there (mixed: zero deviations)
+            if (mixed) {
+                d[e] = 0.0f;
+                if (cur != 0) ((float *)t.state[0])[e] = 0.0f;
+            } else if (cur != 0) {
+                ((double *)t.state[0])[e] = nw;
+            }
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -213,7 +223,6 @@ __global__ void __launch_bounds__(256)
         st->diverged = 0;
         st->max_pseudo = max_pseudo;
         st->tol = tol;
-        st->cur0 = cur;
         st->done = (max_pseudo <= 0) ? 1 : 0;
     }
 }

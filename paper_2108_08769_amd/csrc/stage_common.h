@@ -220,7 +220,7 @@ __device__ __forceinline__ void finalize_wave(const TankDev &t, const Scheme &sc
         const int iters = st->iters + 1;
         const bool bad = !finite || acc[4] > 0.0;
         st->iters = iters;
-        st->cur = next_cur(st->cur, sc.smax);
+        st->cur = cur_of_iter(iters, sc.smax);
         if (bad) st->diverged = 1;
         const bool converged = tol > 0.0 && below;
         st->done = (bad || converged || iters >= st->max_pseudo) ? 1 : 0;

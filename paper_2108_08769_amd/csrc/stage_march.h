@@ -284,7 +284,9 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     if (un.tank < 0) return;  // padding (uniform per wave)
     const TankDev t = load_tank(tanks + un.tank);
     const Status *st = t.status;
-    if (st->done) return;
+    // the buffers follow from the iteration (IterArgs); the stop flag is tested once the first
+    // rows' loads are in flight, so that its latency overlaps theirs
+    const int stopped = st->done;
 
     const int strip = un.local % t.n_strips, ch = un.local / t.n_strips;
     const int col = strip * kOut - 2 + lane;  // this lane's column (may lie outside the tank)
@@ -294,7 +296,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     const int j0 = ch * t.chunk;
     const int j1 = min(j0 + t.chunk, t.ny);
 
-    const int cur = iter_cur(st->cur0, ia.cur_off);
+    const int cur = ia.cur_off;
     const StageBuffers bufs = stage_buffers(cur, stage);
     const S *__restrict__ qprev = (const S *)state_buf(tanks + un.tank, bufs.in);
     const S *__restrict__ q0 = (const S *)state_buf(tanks + un.tank, cur);
@@ -336,6 +338,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     }
     InputLoad<P> in_ld = load_input<P>(t, qprev, have_col, gi, j0 + 1);             // row r+2
     SourceLoad<P> src_ld = load_sources<P, BDF>(t, q0, have_col, gi, j0 - 1);       // row r
+    if (stopped) return;
 
     // carries from row r-1:
     //  below      its state at its upper face, or, if that face is a wall, the face's flux

@@ -173,9 +173,7 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     const double k = sc.k;
 
     // ---- phase 1: every global load of the stage is issued here --------------------------
-    // Loads that do not depend on the pseudo-loop status go first, so that their latency
-    // overlaps the status read: the cell flags and the real-time levels of this thread's first
-    // phase-2 cell.
+    // The cell flags and the real-time levels of this thread's first phase-2 cell go first.
     constexpr int NFL = (NR1 + NT - 1) / NT;
     uint8_t fl[NFL];
 #pragma unroll
@@ -200,9 +198,10 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
         }
     }
 
-    const Status *st = t.status;
-    if (st->done) return;
-    const int cur = iter_cur(st->cur0, ia.cur_off);
+    // the buffers follow from the iteration (IterArgs); the stop flag is tested once the loads
+    // below are in flight, so that its latency overlaps theirs
+    const int stopped = t.status->done;
+    const int cur = ia.cur_off;
     const StageBuffers bufs = stage_buffers(cur, stage);
     const double *qprev = (const double *)t.state[bufs.in];
     const double *q0 = (const double *)t.state[cur];
@@ -227,6 +226,7 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
         src0.z2 = q0[2 * plane + own_c];
         if (tid < NC) own_p0 = q0[3 * plane + own_c];
     }
+    if (stopped) return;
 #pragma unroll
     for (int q = 0; q < NFL; ++q)
         if (tid + q * NT < NR1) sF[tid + q * NT] = fl[q];

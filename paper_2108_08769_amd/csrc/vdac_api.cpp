@@ -725,7 +725,6 @@ int launch_iterations(vdac_grid *g, hipStream_t stream, int n_iter, int first_it
     const int nt = (int)g->tanks.size();
     const Plan &pl = g->plan;
     const bool defer = !g->sc.global_dtau && pl.kind != KIND_DIRECT;
-    const int rot = 1 + ((g->sc.smax - 1) & 1);  // next_cur's step
     int rc;
     for (int it = 0; it < n_iter; ++it) {
         hipEvent_t e1 = nullptr;
@@ -738,7 +737,7 @@ int launch_iterations(vdac_grid *g, hipStream_t stream, int n_iter, int first_it
             (void)hipEventRecord(e0, stream);
         }
         IterArgs ia;
-        ia.cur_off = (int)(((long long)(first_iter + it) * rot) % 3);
+        ia.cur_off = cur_of_iter(first_iter + it, g->sc.smax);
         ia.n_fin = 0;
         ia.n_tanks = nt;
         for (int s = 1; s <= g->sc.smax; ++s) {

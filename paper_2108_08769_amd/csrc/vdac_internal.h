@@ -34,17 +34,16 @@ struct Status {
     int32_t cur;         // index (0..2) of the state buffer holding the current state
     int32_t diverged;    // nonzero once a non-finite residual or rho <= 0 was seen
     int32_t max_pseudo;  // iteration limit of the current real step
-    int32_t cur0;        // `cur` at the start of the real step: the stage kernels of pseudo-iteration
-                         // m take their buffers from cur0 and m (IterArgs), never from `cur`
+    int32_t pad;
     double tol;          // <= 0: run exactly max_pseudo iterations
     double norms[4];     // residual norms of the last iteration (rho, rho u, rho v, p)
     double dtau_global;  // global pseudo-time step: the minimum local step of the current state
 };
 
 // Per-launch arguments of a stage kernel that change from one pseudo-iteration m to the next.
-//   cur_off   the iteration's stage-0 buffer is (cur0 + cur_off) mod 3, cur_off = m * r mod 3 with
-//             r = next_cur's rotation: the buffers do not depend on the status the deferred
-//             finalize (below) rewrites while the launch runs
+//   cur_off   the iteration's stage-0 buffer, cur_of_iter(m): every real step starts from buffer 0
+//             (begin_step moves the state there), so the buffers follow from m alone and not from
+//             the status, which the deferred finalize (below) rewrites while the launch runs
 //   fin       stage 1 only: the launch also runs the finalize of iteration m - 1 (extra waves, one
 //             per tank, dispatched first); its stage-1 work for a tank that this finalize stops is
 //             discarded, as it goes to a buffer that is neither the result nor read again
@@ -57,11 +56,6 @@ struct IterArgs {
     int32_t n_tanks;
 };
 
-__host__ __device__ inline int iter_cur(int cur0, int cur_off)
-{
-    const int c = cur0 + cur_off;
-    return c >= 3 ? c - 3 : c;
-}
 
 // Real-time coefficients of the current real step (Table 1), in device memory so that a captured
 // pseudo-iteration graph stays valid from one step to the next.
@@ -89,6 +83,11 @@ __host__ __device__ inline StageBuffers stage_buffers(int cur, int s)
     return b;
 }
 __host__ __device__ inline int next_cur(int cur, int smax) { return (cur + 1 + ((smax - 1) & 1)) % 3; }
+// Buffer of the state after m pseudo-iterations of a real step (which starts from buffer 0).
+__host__ __device__ inline int cur_of_iter(long long m, int smax)
+{
+    return (int)((m * (1 + ((smax - 1) & 1))) % 3);
+}
 
 // Everything a stage kernel needs about one tank.
 struct TankDev {
