@@ -1,10 +1,11 @@
-// stage_tile.hip -- the Runge-Kutta stage kernel for gfx950 in its tiled form.
+// stage_tile.hip -- the Runge-Kutta stage kernel for gfx950 in its tiled form, FP64 or mixed
+// precision (the policies of stage_common.h).
 //
-// One 256-thread workgroup updates one TX x TY tile of cells in four phases separated by
-// workgroup barriers:
+// One workgroup of 256 or 512 threads updates one TX x TY tile of cells of a single tank in four
+// phases separated by workgroup barriers:
 //   1. the stage input Q^{s-1} of the tile and a two-cell halo is loaded once from memory and
-//      kept in LDS as primitives (rho, u, v, p), with the cell flags of the tile and a one-cell
-//      ring;
+//      kept in LDS as primitives (rho, u, v in the reconstruction precision, p in FP64), with the
+//      cell flags of the tile and a one-cell ring;
 //   2. every fluid cell of the tile and of the ring is reconstructed once: limited slopes of
 //      rho, u, v (Sec. 2.3.1), the stage-0 sources from Q^0 and level n, and the new pressure
 //      gradient (Sec. 2.3.2).  The cell writes its own state at each of its faces that belong to
@@ -13,8 +14,11 @@
 //      exactly one writer;
 //   3. every face of the tile is evaluated once with the Osher-Dumbser-Toro flux (Sec. 2.4.3);
 //      the flux overwrites the face's left/lower state slot;
-//   4. each tile cell forms the flux divergence, adds the frozen sources and applies the
+//   4. each tile cell forms the flux divergence in FP64, adds the frozen sources and applies the
 //      point-implicit update (eq. RK2), and the last stage accumulates the residual.
+// Mixed form: the state is stored as FP32 deviations from the FP64 level n; reconstruction and
+// fluxes run in FP32 with every face pressure expressed from the pressure of the face's
+// lower-index cell, and that reference (an FP64 difference) is added back in the divergence.
 // Periodic sides are handled by wrapping halo indices; cells outside a non-periodic side read
 // as non-fluid.
 #include <hip/hip_runtime.h>
@@ -65,7 +69,8 @@ __device__ __forceinline__ void ring_position(int pidx, int &i, int &j)
     }
 }
 
-// Stage-0 data of one cell: Q^0 (rho, rho u, rho v), level n and level n-1.
+// Stage-0 data of one cell: Q^0 (rho, rho u, rho v; the mixed form keeps its deviation from
+// level n), level n and level n-1.
 struct SourceData {
     double z0, z1, z2, n0, n1, n2, m0, m1, m2;
 };
@@ -86,68 +91,116 @@ __device__ __forceinline__ void load_levels(const TankDev &t, size_t c, bool bdf
     }
 }
 
-__device__ __forceinline__ SourceData load_source(const TankDev &t, const double *q0, size_t c,
-                                                  bool bdf2)
+template <class P>
+__device__ __forceinline__ SourceData load_source(const TankDev &t, const typename P::Store *q0,
+                                                  size_t c, bool bdf2)
 {
     const size_t plane = t.plane;
     SourceData s;
-    s.z0 = q0[c];
-    s.z1 = q0[plane + c];
-    s.z2 = q0[2 * plane + c];
+    s.z0 = (double)q0[c];
+    s.z1 = (double)q0[plane + c];
+    s.z2 = (double)q0[2 * plane + c];
     load_levels(t, c, bdf2, s);
     return s;
 }
 
-// Residual partial of one tile in a fixed order (deterministic): each tile cell's six values go
-// to LDS, then value k is combined by lanes 8k .. 8k+7 of wave 0, each over NC/8 cells, and a DPP
-// tree within those 8 lanes combines them; lane 8k+7 stores value k.  Only wave 0 works after the
-// barrier, and no lane exchange goes through LDS.
-template <bool NORM_MAX, int NC>
-__device__ __forceinline__ void tile_reduce_store(const double part[kPartialWidth], double *scratch,
-                                                  double *out)
+// Stage-0 quantities of a cell from its SourceData: absolute Q^0 (a0 .. a2) and the real-time
+// numerators B0 Q^0 + B1 Q^n + B2 Q^{n-1} (Table 1).  The mixed form uses B0 + B1 + B2 = 0:
+// B0 (Q^0 - Q^n) + B2 (Q^{n-1} - Q^n), with Q^0 - Q^n its stored deviation.
+template <class P>
+__device__ __forceinline__ void stage0_terms(const SourceData &sd, const StepParams &sp, bool bdf2,
+                                             double a[3], double num[3])
 {
-    static_assert(NC % 8 == 0, "eight lanes per value");
+    const double z[3] = {sd.z0, sd.z1, sd.z2}, n[3] = {sd.n0, sd.n1, sd.n2},
+                 m[3] = {sd.m0, sd.m1, sd.m2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if constexpr (P::kMixed) {
+            a[k] = n[k] + z[k];
+            num[k] = sp.b0 * z[k];
+            if (bdf2) num[k] = fma(sp.b2, m[k] - n[k], num[k]);
+        } else {
+            a[k] = z[k];
+            num[k] = fma(sp.b0, z[k], sp.b1 * n[k]);
+            if (bdf2) num[k] = fma(sp.b2, m[k], num[k]);
+        }
+    }
+}
+
+// Residual partial of one tile in a fixed order (deterministic): each wave holding tile cells
+// combines its lanes with the DPP tree (in VALU), then lane k of wave 0 combines the waves'
+// results for value k and stores it.
+template <bool NORM_MAX, int NC>
+__device__ __forceinline__ void tile_reduce_store(double part[kPartialWidth], double *out)
+{
+    static_assert(NC % 64 == 0, "tile cells fill whole waves");
+    __shared__ double red[NC / 64][kPartialWidth];
     const int tid = threadIdx.x;
-    if (tid < NC)
+    const int wave = tid >> 6, lane = tid & 63;
+    if (tid < NC) {
+        auto sum = [](double a, double b) { return a + b; };
+        auto mx = [](double a, double b) { return combine<true>(a, b); };
+        auto mn = [](double a, double b) { return fmin(a, b); };
 #pragma unroll
-        for (int k = 0; k < kPartialWidth; ++k) scratch[k * NC + tid] = part[k];
+        for (int k = 0; k < kPartialWidth; ++k) {
+            const double x = (k == 5) ? wave_reduce_to_lane63(part[k], INFINITY, mn)
+                                      : ((NORM_MAX && k < 4) ? wave_reduce_to_lane63(part[k], 0.0, mx)
+                                                             : wave_reduce_to_lane63(part[k], 0.0, sum));
+            if (lane == 63) red[wave][k] = x;
+        }
+    }
     __syncthreads();
-    if (tid < 8 * kPartialWidth) {
-        const int k = tid >> 3, l = tid & 7;
-        const bool mn = k == 5;               // minimum pseudo-time step
-        const bool mx = NORM_MAX && k < 4;    // maximum norm
-        const double id = mn ? INFINITY : 0.0;
-        auto op = [&](double a, double b) { return mn ? fmin(a, b) : (mx ? combine<true>(a, b) : a + b); };
-        double x = scratch[k * NC + l];
+    if (tid < kPartialWidth) {
+        const int k = tid;
+        double x = red[0][k];
 #pragma unroll
-        for (int j = 1; j < NC / 8; ++j) x = op(x, scratch[k * NC + l + 8 * j]);
-        // row shifts stay within rows of 16 lanes; lane 8k+7 only ever combines lanes 8k .. 8k+7
-        x = op(x, dpp_row_shr<1>(id, x));
-        x = op(x, dpp_row_shr<2>(id, x));
-        x = op(x, dpp_row_shr<4>(id, x));
-        if (l == 7) out[k] = x;
+        for (int w = 1; w < NC / 64; ++w)
+            x = (k == 5) ? fmin(x, red[w][k]) : ((NORM_MAX && k < 4) ? combine<true>(x, red[w][k]) : x + red[w][k]);
+        out[k] = x;
+    }
+}
+
+// Primitives of the stored cell c of a state buffer in the reconstruction precision, and its
+// absolute pressure in FP64 (mixed form: level n plus the FP32 deviation).
+template <class P>
+__device__ __forceinline__ void load_cell(const TankDev &t, const typename P::Store *q, size_t c,
+                                          Prim<typename P::Real> &w, double &p)
+{
+    const size_t plane = t.plane;
+    if constexpr (P::kMixed) {
+        const float r = (float)(t.level_n[c] + (double)q[c]);
+        const float m = (float)(t.level_n[plane + c] + (double)q[plane + c]);
+        const float n = (float)(t.level_n[2 * plane + c] + (double)q[2 * plane + c]);
+        const float ir = rcp_pos(r);
+        w = {r, m * ir, n * ir, 0.0f};
+        p = t.level_n[3 * plane + c] + (double)q[3 * plane + c];
+    } else {
+        w = load_prim(q, plane, c);
+        p = w.p;
     }
 }
 
 // NT threads per tile: 256 (one per tile cell) or 512 (every phase finishes in at most two
 // rounds, which shortens the critical path of small grids).
-template <int TX, int TY, int NT, bool NORM_MAX>
-__global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int stage, int tiles_x,
-                                                     int n_tiles, IterArgs ia)
+template <class P, int TX, int TY, int NT, bool NORM_MAX>
+__global__ void __launch_bounds__(NT) stage_tile(TankDev t, Scheme sc, int stage, int tiles_x,
+                                                 int n_tiles, IterArgs ia)
 {
+    using R = typename P::Real;
+    using S = typename P::Store;
     constexpr int RX = TX + 4, RY = TY + 4, NR2 = RX * RY;  // primitives: tile + 2-cell halo
     constexpr int SX = TX + 2, SY = TY + 2, NR1 = SX * SY;  // flags: tile + 1-cell ring
     constexpr int NC = TX * TY;
     static_assert(NC <= NT, "at most one tile cell per thread");
-    static_assert(kPartialWidth * NC <= 4 * NR2, "the residual reduction reuses the primitives' LDS");
     constexpr int NRING = 2 * (TX + TY);                    // ring positions without corners
     constexpr int NPOS = NC + NRING;
     constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
 
-    __shared__ double sW[4][NR2];
+    __shared__ R sW[3][NR2];      // rho, u, v
+    __shared__ double sP[NR2];    // absolute pressure
     __shared__ uint8_t sF[NR1];
-    __shared__ double sXL[4][NFX], sXR[4][NFX];  // x-face states (then fluxes in sXL)
-    __shared__ double sYL[4][NFY], sYU[4][NFY];  // y-face states (then fluxes in sYL)
+    __shared__ R sXL[4][NFX], sXR[4][NFX];  // x-face states (then fluxes in sXL)
+    __shared__ R sYL[4][NFY], sYU[4][NFY];  // y-face states (then fluxes in sYL)
 
     // A stage-1 launch with ia.fin set puts 8 workgroups in front of the tiles (8 keeps each
     // tile on the same XCD as in the other stages); the first finalizes the previous iteration,
@@ -170,7 +223,7 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     const int tid = threadIdx.x;
     const size_t plane = t.plane;
     const bool slip = sc.slip != 0;
-    const double k = sc.k;
+    const R k = (R)sc.k;
 
     // ---- phase 1: every global load of the stage is issued here --------------------------
     // The cell flags and the real-time levels of this thread's first phase-2 cell go first.
@@ -187,7 +240,7 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     }
     const StepParams sp = *t.step;
     const bool bdf2 = sp.b2 != 0.0;
-    SourceData src0 = {1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+    SourceData src0 = {P::kMixed ? 0.0 : 1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
     size_t own_c = ~(size_t)0;  // this thread's first phase-2 cell, if inside the tank
     if (tid < NPOS) {
         int i, j, gi, gj;
@@ -203,28 +256,30 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     const int stopped = t.status->done;
     const int cur = ia.cur_off;
     const StageBuffers bufs = stage_buffers(cur, stage);
-    const double *qprev = (const double *)t.state[bufs.in];
-    const double *q0 = (const double *)t.state[cur];
-    double *qout = (double *)t.state[bufs.out];
+    const S *qprev = (const S *)t.state[bufs.in];
+    const S *q0 = (const S *)t.state[cur];
+    S *qout = (S *)t.state[bufs.out];
 
     for (int r = tid; r < NR2; r += NT) {
         const int ri = r % RX, rj = r / RX;
         int gi, gj;
-        Prim<double> w = {1.0, 0.0, 0.0, 0.0};
+        Prim<R> w = {R(1), R(0), R(0), R(0)};
+        double p = 0.0;
         if (locate(x0 - 2 + ri, t.nx, t.per_x, gi) && locate(y0 - 2 + rj, t.ny, t.per_y, gj))
-            w = load_prim(qprev, plane, (size_t)gj * t.nx + gi);
+            load_cell<P>(t, qprev, (size_t)gj * t.nx + gi, w, p);
         sW[0][r] = w.r;
         sW[1][r] = w.u;
         sW[2][r] = w.v;
-        sW[3][r] = w.p;
+        sP[r] = p;
     }
-    // Q^0 of this thread's first phase-2 cell (and its pressure for the tile cell's update)
+    // Q^0 of this thread's first phase-2 cell (and its pressure, or pressure deviation, for the
+    // tile cell's update)
     double own_p0 = 0.0;
     if (own_c != ~(size_t)0) {
-        src0.z0 = q0[own_c];
-        src0.z1 = q0[plane + own_c];
-        src0.z2 = q0[2 * plane + own_c];
-        if (tid < NC) own_p0 = q0[3 * plane + own_c];
+        src0.z0 = (double)q0[own_c];
+        src0.z1 = (double)q0[plane + own_c];
+        src0.z2 = (double)q0[2 * plane + own_c];
+        if (tid < NC) own_p0 = (double)q0[3 * plane + own_c];
     }
     if (stopped) return;
 #pragma unroll
@@ -233,8 +288,10 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     __syncthreads();
 
     // ---- phase 2: reconstruction of the tile and ring cells --------------------------------
-    // The tile cell of this thread keeps its stage-0 data for phase 4.
-    double own_q0[3] = {1.0, 0.0, 0.0}, own_d[3] = {0.0, 0.0, 0.0};
+    // The tile cell of this thread keeps its stage-0 data for phase 4 (mixed form: also the
+    // references sx, sy of its left and lower faces, and its level-n density).
+    double own_a[3] = {1.0, 0.0, 0.0}, own_z[3] = {0.0, 0.0, 0.0}, own_d[3] = {0.0, 0.0, 0.0};
+    double own_sx = 0.0, own_sy = 0.0, own_lvl = 0.0;
 
     for (int pidx = tid; pidx < NPOS; pidx += NT) {
         int i, j;
@@ -242,67 +299,79 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
         const uint8_t f = sF[(j + 1) * SX + (i + 1)];
         if (f & FLAG_SOLID) continue;
         const int r = (j + 2) * RX + (i + 2);
-        CellRec rec;
-        rec.w = {sW[0][r], sW[1][r], sW[2][r], sW[3][r]};
+        CellRecT<R> rec;
+        rec.w = {sW[0][r], sW[1][r], sW[2][r], P::kMixed ? R(0) : (R)sP[r]};
         // a wall face shows the cell its own mirror image (Sec. 2.5)
-        const Prim<double> xm = (f & FLAG_WALL_XM) ? mirror(rec.w, 0, slip)
-                                                   : Prim<double>{sW[0][r - 1], sW[1][r - 1], sW[2][r - 1], 0.0};
-        const Prim<double> xp = (f & FLAG_WALL_XP) ? mirror(rec.w, 0, slip)
-                                                   : Prim<double>{sW[0][r + 1], sW[1][r + 1], sW[2][r + 1], 0.0};
-        const Prim<double> ym = (f & FLAG_WALL_YM) ? mirror(rec.w, 1, slip)
-                                                   : Prim<double>{sW[0][r - RX], sW[1][r - RX], sW[2][r - RX], 0.0};
-        const Prim<double> yp = (f & FLAG_WALL_YP) ? mirror(rec.w, 1, slip)
-                                                   : Prim<double>{sW[0][r + RX], sW[1][r + RX], sW[2][r + RX], 0.0};
-        rec.gx = slopes(xm, rec.w, xp, t.inv_dx, k);
-        rec.gy = slopes(ym, rec.w, yp, t.inv_dy, k);
+        const Prim<R> xm = (f & FLAG_WALL_XM) ? mirror(rec.w, 0, slip)
+                                              : Prim<R>{sW[0][r - 1], sW[1][r - 1], sW[2][r - 1], R(0)};
+        const Prim<R> xp = (f & FLAG_WALL_XP) ? mirror(rec.w, 0, slip)
+                                              : Prim<R>{sW[0][r + 1], sW[1][r + 1], sW[2][r + 1], R(0)};
+        const Prim<R> ym = (f & FLAG_WALL_YM) ? mirror(rec.w, 1, slip)
+                                              : Prim<R>{sW[0][r - RX], sW[1][r - RX], sW[2][r - RX], R(0)};
+        const Prim<R> yp = (f & FLAG_WALL_YP) ? mirror(rec.w, 1, slip)
+                                              : Prim<R>{sW[0][r + RX], sW[1][r + RX], sW[2][r + RX], R(0)};
+        rec.gx = slopes(xm, rec.w, xp, (R)t.inv_dx, k);
+        rec.gy = slopes(ym, rec.w, yp, (R)t.inv_dy, k);
 
-        // stage-0 sources: real-time term (B0 Q^0 + B1 Q^n + B2 Q^{n-1})/dt and rho^0
+        // stage-0 sources: real-time term and rho^0
         SourceData sd = src0;
         if (pidx != tid) {  // later rounds (256-thread tiles) load here
             int gi, gj;
             locate(x0 + i, t.nx, t.per_x, gi);
             locate(y0 + j, t.ny, t.per_y, gj);
-            sd = load_source(t, q0, (size_t)gj * t.nx + gi, bdf2);
+            sd = load_source<P>(t, q0, (size_t)gj * t.nx + gi, bdf2);
         }
-        double num0 = fma(sp.b0, sd.z0, sp.b1 * sd.n0);
-        double num1 = fma(sp.b0, sd.z1, sp.b1 * sd.n1);
-        double num2 = fma(sp.b0, sd.z2, sp.b1 * sd.n2);
-        if (bdf2) {
-            num0 = fma(sp.b2, sd.m0, num0);
-            num1 = fma(sp.b2, sd.m1, num1);
-            num2 = fma(sp.b2, sd.m2, num2);
+        double a[3], num[3];
+        stage0_terms<P>(sd, sp, bdf2, a, num);
+        const double d_r = num[0] * sp.inv_dt, d_ru = num[1] * sp.inv_dt, d_rv = num[2] * sp.inv_dt;
+        rec.d_r = (R)d_r;
+        rec.d_ru = (R)d_ru;
+        rec.d_rv = (R)d_rv;
+        rec.rho0 = (R)a[0];
+        // pressure each face state is expressed from: the cell's own p (FP64 form), or p minus
+        // the pressure of the face's lower-index cell (mixed form; sx, sy go back in in phase 4)
+        double sx = 0.0, sy = 0.0;
+        R pb_own = rec.w.p, pb_xl = rec.w.p, pb_yb = rec.w.p;
+        if constexpr (P::kMixed) {
+            sx = (f & FLAG_WALL_XM) ? 0.0 : sP[r] - sP[r - 1];
+            sy = (f & FLAG_WALL_YM) ? 0.0 : sP[r] - sP[r - RX];
+            pb_own = R(0);
+            pb_xl = (R)sx;
+            pb_yb = (R)sy;
         }
-        rec.d_r = num0 * sp.inv_dt;
-        rec.d_ru = num1 * sp.inv_dt;
-        rec.d_rv = num2 * sp.inv_dt;
-        rec.rho0 = sd.z0;
         if (pidx < NC) {
-            own_q0[0] = sd.z0;
-            own_q0[1] = sd.z1;
-            own_q0[2] = sd.z2;
-            own_d[0] = rec.d_r;
-            own_d[1] = rec.d_ru;
-            own_d[2] = rec.d_rv;
+            own_a[0] = a[0];
+            own_a[1] = a[1];
+            own_a[2] = a[2];
+            own_z[0] = sd.z0;
+            own_z[1] = sd.z1;
+            own_z[2] = sd.z2;
+            own_d[0] = d_r;
+            own_d[1] = d_ru;
+            own_d[2] = d_rv;
+            own_sx = sx;
+            own_sy = sy;
+            own_lvl = sd.n0;
         }
 
-        const FaceStates fs = face_states(t, rec);
+        const FaceStatesT<R> fs = face_states<R>(t, rec, pb_xl, pb_own, pb_yb, pb_own);
         const bool row_in = (j >= 0 && j < TY), col_in = (i >= 0 && i < TX);
         if (row_in) {
             if (i >= 0) {  // left face i of the tile's x-faces
                 const int fi = j * (TX + 1) + i;
-                const Prim<double> s = fs.xl;
+                const Prim<R> s = fs.xl;
                 sXR[0][fi] = s.r; sXR[1][fi] = s.u; sXR[2][fi] = s.v; sXR[3][fi] = s.p;
                 if (f & FLAG_WALL_XM) {
-                    const Prim<double> gs = ghost_state(t, rec, 0, -1, slip);
+                    const Prim<R> gs = ghost_state<R>(t, rec, 0, -1, slip, pb_own);
                     sXL[0][fi] = gs.r; sXL[1][fi] = gs.u; sXL[2][fi] = gs.v; sXL[3][fi] = gs.p;
                 }
             }
             if (i < TX) {  // right face i + 1
                 const int fi = j * (TX + 1) + i + 1;
-                const Prim<double> s = fs.xr;
+                const Prim<R> s = fs.xr;
                 sXL[0][fi] = s.r; sXL[1][fi] = s.u; sXL[2][fi] = s.v; sXL[3][fi] = s.p;
                 if (f & FLAG_WALL_XP) {
-                    const Prim<double> gs = ghost_state(t, rec, 0, +1, slip);
+                    const Prim<R> gs = ghost_state<R>(t, rec, 0, +1, slip, pb_own);
                     sXR[0][fi] = gs.r; sXR[1][fi] = gs.u; sXR[2][fi] = gs.v; sXR[3][fi] = gs.p;
                 }
             }
@@ -310,19 +379,19 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
         if (col_in) {
             if (j >= 0) {  // lower face j of the tile's y-faces
                 const int fi = j * TX + i;
-                const Prim<double> s = fs.yb;
+                const Prim<R> s = fs.yb;
                 sYU[0][fi] = s.r; sYU[1][fi] = s.u; sYU[2][fi] = s.v; sYU[3][fi] = s.p;
                 if (f & FLAG_WALL_YM) {
-                    const Prim<double> gs = ghost_state(t, rec, 1, -1, slip);
+                    const Prim<R> gs = ghost_state<R>(t, rec, 1, -1, slip, pb_own);
                     sYL[0][fi] = gs.r; sYL[1][fi] = gs.u; sYL[2][fi] = gs.v; sYL[3][fi] = gs.p;
                 }
             }
             if (j < TY) {  // upper face j + 1
                 const int fi = (j + 1) * TX + i;
-                const Prim<double> s = fs.yt;
+                const Prim<R> s = fs.yt;
                 sYL[0][fi] = s.r; sYL[1][fi] = s.u; sYL[2][fi] = s.v; sYL[3][fi] = s.p;
                 if (f & FLAG_WALL_YP) {
-                    const Prim<double> gs = ghost_state(t, rec, 1, +1, slip);
+                    const Prim<R> gs = ghost_state<R>(t, rec, 1, +1, slip, pb_own);
                     sYU[0][fi] = gs.r; sYU[1][fi] = gs.u; sYU[2][fi] = gs.v; sYU[3][fi] = gs.p;
                 }
             }
@@ -331,23 +400,24 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
     __syncthreads();
 
     // ---- phase 3: one Osher flux per face --------------------------------------------------
+    const R beta = (R)t.beta, inv_beta = (R)t.inv_beta;
     for (int fidx = tid; fidx < NFX + NFY; fidx += NT) {
         if (fidx < NFX) {
             const int fi = fidx % (TX + 1), j = fidx / (TX + 1);
-            const uint8_t fl = sF[(j + 1) * SX + fi], fr = sF[(j + 1) * SX + fi + 1];
-            if ((fl & FLAG_SOLID) && (fr & FLAG_SOLID)) continue;
-            const Prim<double> L = {sXL[0][fidx], sXL[1][fidx], sXL[2][fidx], sXL[3][fidx]};
-            const Prim<double> R = {sXR[0][fidx], sXR[1][fidx], sXR[2][fidx], sXR[3][fidx]};
-            const Vec4<double> F = osher_x(L, R, t.beta, t.inv_beta);
+            const uint8_t fl_ = sF[(j + 1) * SX + fi], fr = sF[(j + 1) * SX + fi + 1];
+            if ((fl_ & FLAG_SOLID) && (fr & FLAG_SOLID)) continue;
+            const Prim<R> L = {sXL[0][fidx], sXL[1][fidx], sXL[2][fidx], sXL[3][fidx]};
+            const Prim<R> Rt = {sXR[0][fidx], sXR[1][fidx], sXR[2][fidx], sXR[3][fidx]};
+            const Vec4<R> F = osher_x(L, Rt, beta, inv_beta);
             sXL[0][fidx] = F.a; sXL[1][fidx] = F.b; sXL[2][fidx] = F.c; sXL[3][fidx] = F.d;
         } else {
             const int q = fidx - NFX;
             const int i = q % TX, g = q / TX;
-            const uint8_t fl = sF[g * SX + i + 1], fu = sF[(g + 1) * SX + i + 1];
-            if ((fl & FLAG_SOLID) && (fu & FLAG_SOLID)) continue;
-            const Prim<double> L = {sYL[0][q], sYL[1][q], sYL[2][q], sYL[3][q]};
-            const Prim<double> U = {sYU[0][q], sYU[1][q], sYU[2][q], sYU[3][q]};
-            const Vec4<double> F = osher_y(L, U, t.beta, t.inv_beta);
+            const uint8_t fb = sF[g * SX + i + 1], fu = sF[(g + 1) * SX + i + 1];
+            if ((fb & FLAG_SOLID) && (fu & FLAG_SOLID)) continue;
+            const Prim<R> L = {sYL[0][q], sYL[1][q], sYL[2][q], sYL[3][q]};
+            const Prim<R> U = {sYU[0][q], sYU[1][q], sYU[2][q], sYU[3][q]};
+            const Vec4<R> F = osher_y(L, U, beta, inv_beta);
             sYL[0][q] = F.a; sYL[1][q] = F.b; sYL[2][q] = F.c; sYL[3][q] = F.d;
         }
     }
@@ -370,22 +440,26 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
             double R4[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const double div = (sXL[m][xm + 1] - sXL[m][xm]) * t.inv_dx
-                                   + (sYL[m][ym + TX] - sYL[m][ym]) * t.inv_dy;
+                const double div = ((double)sXL[m][xm + 1] - (double)sXL[m][xm]) * t.inv_dx
+                                   + ((double)sYL[m][ym + TX] - (double)sYL[m][ym]) * t.inv_dy;
                 R4[m] = -div;
             }
-            const double r0 = own_q0[0], m0 = own_q0[1], n0 = own_q0[2];
+            if constexpr (P::kMixed) {  // the face pressures' references
+                R4[1] = fma(-own_sx, t.inv_dx, R4[1]);
+                R4[2] = fma(-own_sy, t.inv_dy, R4[2]);
+            }
+            const double r0 = own_a[0];
             R4[0] += -own_d[0];
             R4[1] += -own_d[1] + r0 * t.gx;
             R4[2] += -own_d[2] + r0 * t.gy;
-            const double dtau = local_dtau(t, t.cfl, r0, m0, n0);
+            const double dtau = local_dtau(t, t.cfl, r0, own_a[1], own_a[2]);
             const double ad = alpha * dtau;
             const double api = 1.0 + sp.b0 * ad * sp.inv_dt;
             const double fac = ad * rcp_pos(api);
             out_c = c;
-            out[0] = r0 + fac * R4[0];
-            out[1] = m0 + fac * R4[1];
-            out[2] = n0 + fac * R4[2];
+            out[0] = own_z[0] + fac * R4[0];
+            out[1] = own_z[1] + fac * R4[1];
+            out[2] = own_z[2] + fac * R4[2];
             out[3] = own_p0 + t.beta * (ad * R4[3]);
             if (last) {
                 const double rp = t.beta * R4[3];
@@ -400,34 +474,47 @@ __global__ void __launch_bounds__(NT) stage_tile_f64(TankDev t, Scheme sc, int s
                     part[2] = R4[2] * R4[2];
                     part[3] = rp * rp;
                 }
-                part[4] = (out[0] > 0.0 && out[0] < INFINITY) ? 0.0 : 1.0;
+                const double rho_new = P::kMixed ? own_lvl + out[0] : out[0];
+                part[4] = (rho_new > 0.0 && rho_new < INFINITY) ? 0.0 : 1.0;
             }
         }
     }
     // the residual is reduced before the state is stored: the workgroup barrier of the reduction
     // would otherwise wait for the stores to complete
-    if (last) tile_reduce_store<NORM_MAX, NC>(part, &sW[0][0], t.partials + (size_t)tile * kPartialWidth);
+    if (last) tile_reduce_store<NORM_MAX, NC>(part, t.partials + (size_t)tile * kPartialWidth);
     if (out_c != kNoCell) {
-        qout[out_c] = out[0];
-        qout[plane + out_c] = out[1];
-        qout[2 * plane + out_c] = out[2];
-        qout[3 * plane + out_c] = out[3];
+        qout[out_c] = (S)out[0];
+        qout[plane + out_c] = (S)out[1];
+        qout[2 * plane + out_c] = (S)out[2];
+        qout[3 * plane + out_c] = (S)out[3];
     }
 }
 
-template <int TX, int TY, int NT>
+template <class P, int TX, int TY, int NT>
 int launch_tile(const TankDev &t, const Scheme &sc, int stage, const IterArgs &ia, void *stream)
 {
     const int tiles_x = (t.nx + TX - 1) / TX, tiles_y = (t.ny + TY - 1) / TY;
     const int n_tiles = tiles_x * tiles_y;
     const int blocks = ((n_tiles + 7) / 8) * 8 + (ia.fin ? 8 : 0);
     if (sc.norm_max)
-        hipLaunchKernelGGL((stage_tile_f64<TX, TY, NT, true>), dim3(blocks), dim3(NT), 0,
+        hipLaunchKernelGGL((stage_tile<P, TX, TY, NT, true>), dim3(blocks), dim3(NT), 0,
                            (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles, ia);
     else
-        hipLaunchKernelGGL((stage_tile_f64<TX, TY, NT, false>), dim3(blocks), dim3(NT), 0,
+        hipLaunchKernelGGL((stage_tile<P, TX, TY, NT, false>), dim3(blocks), dim3(NT), 0,
                            (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles, ia);
     return (int)hipGetLastError();
+}
+
+template <class P>
+int launch_tile_p(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
+                  const IterArgs &ia, void *stream)
+{
+    if (tile_x == 32 && tile_y == 8) return launch_tile<P, 32, 8, 256>(t, sc, stage, ia, stream);
+    if (tile_x == 16 && tile_y == 16) return launch_tile<P, 16, 16, 256>(t, sc, stage, ia, stream);
+    if (tile_x == 64 && tile_y == 4) return launch_tile<P, 64, 4, 256>(t, sc, stage, ia, stream);
+    if (tile_x == 3208 && tile_y == 2) return launch_tile<P, 32, 8, 512>(t, sc, stage, ia, stream);
+    if (tile_x == 1616 && tile_y == 2) return launch_tile<P, 16, 16, 512>(t, sc, stage, ia, stream);
+    return (int)hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -448,16 +535,13 @@ int tile_count(const TankDev &t, int tile_x, int tile_y)
     return ((t.nx + tile_x - 1) / tile_x) * ((t.ny + tile_y - 1) / tile_y);
 }
 
-int launch_stage_tile_f64(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
-                          const IterArgs &ia, void *stream)
+int launch_stage_tile(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
+                      const IterArgs &ia, void *stream)
 {
     if (ia.fin && stage != 1) return (int)hipErrorInvalidValue;
-    if (tile_x == 32 && tile_y == 8) return launch_tile<32, 8, 256>(t, sc, stage, ia, stream);
-    if (tile_x == 16 && tile_y == 16) return launch_tile<16, 16, 256>(t, sc, stage, ia, stream);
-    if (tile_x == 64 && tile_y == 4) return launch_tile<64, 4, 256>(t, sc, stage, ia, stream);
-    if (tile_x == 3208 && tile_y == 2) return launch_tile<32, 8, 512>(t, sc, stage, ia, stream);
-    if (tile_x == 1616 && tile_y == 2) return launch_tile<16, 16, 512>(t, sc, stage, ia, stream);
-    return (int)hipErrorInvalidValue;
+    if (sc.bdf > 2 || sc.general) return (int)hipErrorInvalidValue;
+    return sc.mixed ? launch_tile_p<PrecMixed>(t, sc, stage, tile_x, tile_y, ia, stream)
+                    : launch_tile_p<PrecF64>(t, sc, stage, tile_x, tile_y, ia, stream);
 }
 
 }  // namespace vdac

@@ -144,9 +144,9 @@ int check_options(const vdac_options *o)
         return fail(VDAC_E_INVALID, "tile %d x %d is not available (0 x 0 = automatic, 1 x 1 = "
                     "one thread per cell, -W x L (W = 1..3) = row marching in chunks of L rows, or 32 x 8, "
                     "16 x 16, 64 x 4)", o->tile_x, o->tile_y);
-    if (o->precision == VDAC_FP32_MIXED && !auto_tile && !march)
-        return fail(VDAC_E_INVALID, "the mixed precision form runs the row-marching kernel only "
-                    "(tile 0 x 0 or -W x L)");
+    if (o->precision == VDAC_FP32_MIXED && direct)
+        return fail(VDAC_E_INVALID, "the mixed precision form runs the row-marching or the tiled "
+                    "kernel (tile 0 x 0, -W x L or a 2D tile), not the one-thread-per-cell kernel");
     const bool general = o->flux != VDAC_FLUX_OSHER || o->pgrad != VDAC_PGRAD_NEW || o->local_dtau == 0;
     if ((general || o->bdf_order == 3) && !auto_tile && !march)
         return fail(VDAC_E_INVALID, "the Roe and exact fluxes, the limited pressure gradients, the "
@@ -753,7 +753,7 @@ int launch_iterations(vdac_grid *g, hipStream_t stream, int n_iter, int first_it
                 IterArgs one = ia;
                 one.n_tanks = 1;
                 rc = pl.kind == KIND_DIRECT ? launch_stage_direct_f64(d, g->sc, s, one, stream)
-                                            : launch_stage_tile_f64(d, g->sc, s, pl.tile_x, pl.tile_y, one, stream);
+                                            : launch_stage_tile(d, g->sc, s, pl.tile_x, pl.tile_y, one, stream);
                 if (rc != 0) return hip_fail((hipError_t)rc, "stage launch");
             }
         }
@@ -995,7 +995,7 @@ int autotune_tile(const vdac_tank *tanks, int32_t n_tanks, vdac_options *o, void
             if (c == 1 || c / 2 < max_ny) cand.push_back({-w, c});
     const bool march_only = base.flux != VDAC_FLUX_OSHER || base.pgrad != VDAC_PGRAD_NEW ||
                             base.local_dtau == 0 || base.bdf_order == 3 || has_open_side(&tanks[0]);
-    if (base.precision == VDAC_FP64 && n_tanks == 1 && !march_only)
+    if (n_tanks == 1 && !march_only)
         for (auto tl : {std::pair<int, int>{3208, 2}, {1616, 2}, {32, 8}, {16, 16}}) cand.push_back(tl);
 
     double best_ms = 0.0;

@@ -140,8 +140,9 @@ struct Scheme {
 
 // Launch wrappers.  All return hipError_t cast to int.
 //
-// Per-tank launches (FP64 only): tile (1, 1) runs the plain one-thread-per-cell kernel
-// (kernels_f64.hip), the supported 2D tiles the LDS-tiled kernel (stage_tile.hip).  Grid-wide
+// Per-tank launches: tile (1, 1) runs the plain one-thread-per-cell kernel (FP64 only,
+// kernels_f64.hip), the supported 2D tiles the LDS-tiled kernel (stage_tile.hip, FP64 or mixed,
+// default scheme, BDF order up to 2).  Grid-wide
 // launches: the row-marching kernel (stage_march.hip) runs every work unit of every tank from
 // the device unit table in one launch per stage, with `waves_per_block` table entries per
 // workgroup and a register budget of `waves_simd` (2 or 3) waves per SIMD; begin_step and
@@ -156,8 +157,8 @@ int launch_finalize_all(const TankDev *tanks_dev, int n_tanks, const Scheme &sc,
 // kernel runs the finalize of its tank in one extra workgroup when ia.fin is set.
 int launch_stage_direct_f64(const TankDev &t, const Scheme &sc, int stage, const IterArgs &ia,
                             void *stream);
-int launch_stage_tile_f64(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
-                          const IterArgs &ia, void *stream);
+int launch_stage_tile(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
+                      const IterArgs &ia, void *stream);
 int launch_stage_march(const TankDev *tanks_dev, const MarchUnit *units, int n_entries,
                        int waves_per_block, const Scheme &sc, int stage, const IterArgs &ia,
                        int waves_simd, void *stream);
