@@ -87,7 +87,10 @@ typedef struct {
     int32_t tile_x, tile_y; /* stage-kernel shape: 0 x 0 automatic; 1 x 1 one thread per cell;
                                -W x L row marching over 64-column strips in chunks of L rows,
                                W = 3 for a 3-waves-per-SIMD register budget, 1 or 2 otherwise;
-                               32 x 8, 16 x 16 or 64 x 4 two-dimensional LDS tiles */
+                               32 x 8, 16 x 16 or 64 x 4 two-dimensional LDS tiles (256
+                               threads), and 3208 x 2, 1616 x 2 for the 32 x 8 and 16 x 16 tiles
+                               with 512 threads; tiles take one tank, FP64 or mixed, BDF order up
+                               to 2; one thread per cell is FP64 only */
     int32_t graph_iters; /* pseudo-iterations captured per HIP graph and replayed on the stream:
                             0 automatic, K > 0 exactly K, -1 launch kernels one by one */
     int32_t flux;        /* VDAC_FLUX_* */
@@ -156,8 +159,9 @@ int stage_timing_read(const vdac_grid *g, double *kernel_ms, int64_t *launches,
 
 /* Autotuner of the stage-kernel shape.  For the tanks and options given (o's tile fields are
  * ignored on input), builds a scratch grid per candidate shape -- row marching with chunks of
- * 1..64 rows under a 2- and a 3-waves-per-SIMD register budget, and for a single FP64 tank also
- * the 2D LDS tiles -- runs one untimed and one timed real step of `iters` pseudo-iterations
+ * 1..64 rows under a 2- and a 3-waves-per-SIMD register budget, and for a single tank with the
+ * default scheme also the 2D LDS tiles -- runs one untimed and one timed real step of `iters`
+ * pseudo-iterations
  * (1..1000) from the initial rest state, and writes the shape with the least stage-kernel time
  * into o->tile_x, o->tile_y.  The result is cached for the life of the process, keyed by
  * precision, scheme and tank shapes, so later calls with the same key return at once.  Allocates

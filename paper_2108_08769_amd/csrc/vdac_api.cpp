@@ -143,7 +143,7 @@ int check_options(const vdac_options *o)
     if (!auto_tile && !direct && !march && !tile_supported(o->tile_x, o->tile_y))
         return fail(VDAC_E_INVALID, "tile %d x %d is not available (0 x 0 = automatic, 1 x 1 = "
                     "one thread per cell, -W x L (W = 1..3) = row marching in chunks of L rows, or 32 x 8, "
-                    "16 x 16, 64 x 4)", o->tile_x, o->tile_y);
+                    "16 x 16, 64 x 4, 3208 x 2, 1616 x 2)", o->tile_x, o->tile_y);
     if (o->precision == VDAC_FP32_MIXED && direct)
         return fail(VDAC_E_INVALID, "the mixed precision form runs the row-marching or the tiled "
                     "kernel (tile 0 x 0, -W x L or a 2D tile), not the one-thread-per-cell kernel");

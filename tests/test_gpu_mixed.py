@@ -364,14 +364,18 @@ def test_autotuner_picks_a_candidate_and_caches():
         shape = (tuned.tile_x, tuned.tile_y)
         print(f"[autotune] {prec}: {shape} in {first:.2f} s, cached call {second * 1e3:.2f} ms", flush=True)
         assert shape == (again.tile_x, again.tile_y)
-        assert shape[0] < 0 or (prec == "f64" and shape in [(3208, 2), (1616, 2), (32, 8), (16, 16)])
+        tiles = [(3208, 2), (1616, 2), (32, 8), (16, 16)]
+        assert shape[0] < 0 or shape in tiles, shape
         assert second < 0.05
-        # the tuned shape runs the same scheme: FP64 within the oracle bar, mixed bitwise equal
-        # to the heuristic shape (row marching only)
+        # the tuned shape runs the same scheme: FP64 within the oracle bar; mixed bitwise equal
+        # to the heuristic row-marching shape, or (a tile) within the tile/row-marching agreement
         got = run_gpu(wk, steps=2, max_pseudo=10, precision=prec, tile=shape)
         if prec == "f64":
             ref = run_oracle(wk, steps=2, max_pseudo=10)
             assert np.all(field_errors(got[0][0], ref[0][0], None, field_scales(t)) <= 1e-12)
         else:
             ref = run_gpu(wk, steps=2, max_pseudo=10, precision=prec, tile=(0, 0))
-            np.testing.assert_array_equal(got[0][0], ref[0][0])
+            if shape[0] < 0:
+                np.testing.assert_array_equal(got[0][0], ref[0][0])
+            else:
+                assert np.all(normwise(got[0][0], ref[0][0]) <= np.array([1e-8, 1e-6, 1e-6, 1e-6]))
