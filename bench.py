@@ -1,7 +1,7 @@
 """Benchmark: cell-updates per second per pseudo-time stage of the dual-time Godunov solver.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dam_break] [--precision f64]
-                    [--tile autotune|0x0|-WxL|TXxTY] [--unbatched] [--cpu-budget S]
+                    [--tile autotune|0x0|-WxL|TXxTY] [--unbatched] [--cpu-budget S] [--no-mixed]
 
 A step is one real-time step (Algorithm 1): level n <- state, then pseudo-iterations of
 s_max Runge-Kutta stages until the RMS residual is below the workload's tolerance or the
@@ -23,7 +23,9 @@ one, an event pair around each pseudo-iteration's s_max stage launches, so it in
 dispatch gaps between them).  traffic is the copy-calibrated FETCH_SIZE + WRITE_SIZE bytes per
 launch from the committed counter summaries in profiles/, reported only while the kernel
 sources still hash to what was profiled.  cpu_baseline times the serial FP64 oracle on a bounded
-sample of the same workload.
+sample of the same workload.  An FP64 line also reports mixed_form: the mixed-precision form on the
+same workload and steps, timed the same way after the FP64 measurement, with its speedup
+(--no-mixed skips it).
 """
 from __future__ import annotations
 
@@ -111,76 +113,11 @@ def cpu_baseline(wk, budget_s: float):
                       f"({cell_stages:.3g} cell-stages, {dt:.1f} s)"}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="dam_break")
-    ap.add_argument("--precision", default="f64")
-    ap.add_argument("--cpu-budget", type=float, default=12.0,
-                    help="seconds of oracle time for the CPU baseline (0 = skip)")
-    ap.add_argument("--no-stage-timing", action="store_true")
-    ap.add_argument("--tile", default="autotune",
-                    help="stage kernel shape: autotune (the library's autotuner), 0x0 (built-in "
-                         "heuristic), -WxL (row marching), or a 2D tile such as 3208x2")
-    ap.add_argument("--max-pseudo", type=int, default=0,
-                    help="override the workload's pseudo-iteration cap (short profiled runs)")
-    ap.add_argument("--graph-iters", type=int, default=0,
-                    help="pseudo-iterations per captured HIP graph (0 automatic, -1 no graphs)")
-    ap.add_argument("--unbatched", action="store_true",
-                    help="one grid per tank, stepped one after the other (the baseline of the "
-                         "batched form)")
-    ap.add_argument("--flux", default="osher", choices=["osher", "roe", "bassi"],
-                    help="Riemann solver (Sec. 2.4)")
-    ap.add_argument("--pgrad", default="new", choices=["new", "limiter", "split"],
-                    help="pressure gradient (Sec. 2.3.2)")
-    ap.add_argument("--pk", type=float, default=1.0, help="k of the limiter on p")
-    ap.add_argument("--global-dtau", action="store_true", help="one pseudo-time step per tank")
-    ap.add_argument("--bdf", type=int, default=0, help="BDF order (0: the workload's)")
-    ap.add_argument("--copy-probe", type=float, default=0.0,
-                    help="only copy this many MiB device to device 20 times and print the rate "
-                         "(calibrates the HBM byte counters of a profiler run)")
-    args = ap.parse_args()
-
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this solver has no multi-GPU path "
-              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    from paper_2108_08769_amd import vdac
-
-    if args.copy_probe > 0:
-        n = int(args.copy_probe * 2 ** 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(20):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        print(json.dumps({"copy_probe_bytes_each_way": 4 * n, "copies": 20,
-                          "GB_per_s_read_plus_write": 2 * 4 * n * 20 / dt / 1e9}), flush=True)
-        return
-
-    wk = build_workload(args.workload, args.precision)
-    if args.max_pseudo > 0:
-        wk.max_pseudo = args.max_pseudo
-    if args.bdf > 0:
-        wk.bdf = args.bdf
-    if args.global_dtau:
-        wk.local_dtau = False
-    flux = {"osher": vdac.FLUX_OSHER, "roe": vdac.FLUX_ROE, "bassi": vdac.FLUX_BASSI}[args.flux]
-    pgrad = {"new": vdac.PGRAD_NEW, "limiter": vdac.PGRAD_LIMITER, "split": vdac.PGRAD_SPLIT}[args.pgrad]
+def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
+    """Warm-up, then the timed region of exactly args.steps real steps of wk, then (timing) the
+    measurement pass for the roofline; returns the rate and what the JSON line reports."""
     tanks = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
                   solid=t.solid) for t in wk.tanks]
-    torch.cuda.set_device(0)
-    tune = args.tile == "autotune"
-    tile = (0, 0) if tune else tuple(int(v) for v in args.tile.lower().split("x"))
     opts = vdac.make_options(precision=wk.precision, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl,
                              k=wk.k, bdf=wk.bdf, tile=tile, graph_iters=args.graph_iters,
                              flux=flux, pgrad=pgrad, pk=args.pk, local_dtau=wk.local_dtau)
@@ -222,12 +159,11 @@ def main():
         cell_stages += cs
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    fluid = wk.fluid_cells
 
     # measurement pass: the same number of further steps, launched one by one, with a HIP event
     # pair around each pseudo-iteration's back-to-back stage kernels on the library's stream
     roofline = None
-    if not args.no_stage_timing:
+    if timing:
         for g in grids:
             g.stage_timing(True)
         for _ in range(args.steps):
@@ -249,9 +185,86 @@ def main():
                         "traffic_unit": "GB per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)",
                         "kernel": "stage", "avg_launch_us": round(avg_s * 1e6, 3),
                         "launches": launches, "bytes_per_launch": bytes_per_launch}
-    value = cell_stages / elapsed
     for g in grids:
         g.close()
+    return {"value": cell_stages / elapsed, "elapsed": elapsed, "iters": iters, "chosen": chosen,
+            "roofline": roofline}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dam_break")
+    ap.add_argument("--precision", default="f64")
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle time for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-stage-timing", action="store_true")
+    ap.add_argument("--tile", default="autotune",
+                    help="stage kernel shape: autotune (the library's autotuner), 0x0 (built-in "
+                         "heuristic), -WxL (row marching), or a 2D tile such as 3208x2")
+    ap.add_argument("--max-pseudo", type=int, default=0,
+                    help="override the workload's pseudo-iteration cap (short profiled runs)")
+    ap.add_argument("--graph-iters", type=int, default=0,
+                    help="pseudo-iterations per captured HIP graph (0 automatic, -1 no graphs)")
+    ap.add_argument("--unbatched", action="store_true",
+                    help="one grid per tank, stepped one after the other (the baseline of the "
+                         "batched form)")
+    ap.add_argument("--flux", default="osher", choices=["osher", "roe", "bassi"],
+                    help="Riemann solver (Sec. 2.4)")
+    ap.add_argument("--pgrad", default="new", choices=["new", "limiter", "split"],
+                    help="pressure gradient (Sec. 2.3.2)")
+    ap.add_argument("--pk", type=float, default=1.0, help="k of the limiter on p")
+    ap.add_argument("--global-dtau", action="store_true", help="one pseudo-time step per tank")
+    ap.add_argument("--bdf", type=int, default=0, help="BDF order (0: the workload's)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision run that an FP64 line reports beside it")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only copy this many MiB device to device 20 times and print the rate "
+                         "(calibrates the HBM byte counters of a profiler run)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this solver has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2108_08769_amd import vdac
+
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * 2 ** 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"copy_probe_bytes_each_way": 4 * n, "copies": 20,
+                          "GB_per_s_read_plus_write": 2 * 4 * n * 20 / dt / 1e9}), flush=True)
+        return
+
+    wk = build_workload(args.workload, args.precision)
+    if args.max_pseudo > 0:
+        wk.max_pseudo = args.max_pseudo
+    if args.bdf > 0:
+        wk.bdf = args.bdf
+    if args.global_dtau:
+        wk.local_dtau = False
+    flux = {"osher": vdac.FLUX_OSHER, "roe": vdac.FLUX_ROE, "bassi": vdac.FLUX_BASSI}[args.flux]
+    pgrad = {"new": vdac.PGRAD_NEW, "limiter": vdac.PGRAD_LIMITER, "split": vdac.PGRAD_SPLIT}[args.pgrad]
+    torch.cuda.set_device(0)
+    tune = args.tile == "autotune"
+    tile = (0, 0) if tune else tuple(int(v) for v in args.tile.lower().split("x"))
+    res = measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=not args.no_stage_timing)
+    value, elapsed, iters, chosen, roofline = (res[k] for k in ("value", "elapsed", "iters", "chosen",
+                                                                  "roofline"))
+    fluid = wk.fluid_cells
 
     line = {
         "metric": "cell-updates/s per pseudo-time stage",
@@ -275,6 +288,26 @@ def main():
                    "pgrad": args.pgrad, "local_dtau": bool(wk.local_dtau), "bdf": wk.bdf},
         "roofline": roofline,
     }
+    # the mixed form on the same workload, after the FP64 line's measurement (reported beside
+    # it: the headline metric compares the two forms)
+    if wk.precision == "f64" and not args.no_mixed:
+        wkm = build_workload(args.workload, "mixed")
+        if wkm.precision == "mixed":
+            if args.max_pseudo > 0:
+                wkm.max_pseudo = args.max_pseudo
+            if args.bdf > 0:
+                wkm.bdf = args.bdf
+            if args.global_dtau:
+                wkm.local_dtau = False
+            rm = measure(vdac, np, torch, wkm, args, tune, tile, flux, pgrad, timing=False)
+            line["mixed_form"] = {"value": rm["value"], "unit": line["unit"],
+                                  "ms_per_step": rm["elapsed"] * 1e3 / args.steps,
+                                  "speedup_vs_f64": rm["value"] / value, "dtype": "f32+f64",
+                                  "tile": rm["chosen"] + (" (autotuned)" if tune and not args.unbatched else ""),
+                                  "pseudo_iterations": rm["iters"],
+                                  "note": "same workload, steps and timing; FP32 storage as deviations "
+                                          "from FP64 level n, FP32 reconstruction and fluxes, FP64 "
+                                          "residual, sources and update"}
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(wk, args.cpu_budget)
     print(json.dumps(line), flush=True)
