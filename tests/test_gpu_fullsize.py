@@ -1,0 +1,126 @@
+"""Parity at the full sizes of the large benchmark workloads, in the launch configuration that
+bench.py times (the autotuned stage-kernel shape), on outputs the oracle can compute.
+
+* 4096 x 4096 obstacle dam break.  After one real step of P pseudo-iterations a cell's new state
+  depends only on the initial state within 2 cells per stage (a face's states need the slopes of
+  the two cells beside it, and each slope its two neighbours), so within R = 2 s_max P cells.  The
+  oracle runs a window of the initial state of radius R + 1 around each sampled cell, clipped at
+  the domain, where the domain's own walls apply.  The window's cut sides are walls in the
+  oracle, which can reach at most R cells inward, so the window's centre cell is exact.  Samples:
+  the obstacle's corners and top, the dam front, the layer interface, the four walls and corners,
+  and seeded interior cells.
+* 512-tank sloshing ensemble.  The whole batched launch runs; the oracle runs a sample of whole
+  tanks (the smallest, the largest and seeded ones).
+
+FP64 bar: |gpu - oracle| <= 1e-12 x the field's physical scale (as in the other parity tests).
+Mixed form: the mixed bar (rho 1e-6, rho u and rho v 1e-5, p 1e-4 of the same scales).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2108_08769_amd import vdac
+from paper_2108_08769_amd import workloads as wl
+from parity import gpu_options, oracle_problem, field_errors, field_scales
+
+pytestmark = pytest.mark.gpu
+
+FP64_BAR = np.array([1e-12, 1e-12, 1e-12, 1e-12])
+MIXED_BAR = np.array([1e-6, 1e-5, 1e-5, 1e-4])
+
+
+def tank_dict(t):
+    return dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
+                solid=t.solid)
+
+
+def run_tuned(wk, precision, pseudo):
+    """One real step of `pseudo` pseudo-iterations of every tank, in one grid, with the shape the
+    autotuner picks (as bench.py does); returns the states, the iteration counts and the shape."""
+    tanks = [tank_dict(t) for t in wk.tanks]
+    opts = vdac.autotune(tanks, gpu_options(wk, precision), iters=5)
+    shape = (opts.tile_x, opts.tile_y)
+    print(f"[fullsize] {wk.name} {precision}: autotuned shape {shape}", flush=True)
+    grid = vdac.Grid(tanks, opts)
+    try:
+        for i, t in enumerate(wk.tanks):
+            grid.set_state(i, t.q)
+        rc, done = grid.step(wk.dt, pseudo, 0.0, check=False)
+        assert rc == 0
+        states = [grid.get_state(i) for i in range(len(wk.tanks))]
+    finally:
+        grid.close()
+    return states, np.asarray(done), shape
+
+
+def obstacle_samples(t, n_random=10, seed=21):
+    n = t.nx
+    at = lambda x: min(n - 1, int(x / t.lx * n))  # cell containing coordinate x
+    pts = [(at(2.5) - 1, 0), (at(2.5) - 1, at(0.3)), (at(2.7) + 1, 2), (at(2.6), at(0.3) + 1),
+           (at(1.0), 5), (at(1.0) - 1, at(1.0)), (at(0.5), at(2.0)), (at(0.5), at(2.0) - 1),
+           (0, 0), (n - 1, 0), (0, n - 1), (n - 1, n - 1), (0, n // 2), (n - 1, n // 3),
+           (n // 2, 0), (n // 3, n - 1)]
+    rng = np.random.default_rng(seed)
+    pts += [(int(i), int(j)) for i, j in rng.integers(0, n, size=(n_random, 2))]
+    return [(i, j) for i, j in pts if not t.solid[j, i]]
+
+
+def window_oracle(wk, t, i, j, radius, pseudo):
+    """The oracle's state at cell (i, j) after one real step, from a window of the initial state."""
+    i0, i1 = max(0, i - radius), min(t.nx, i + radius + 1)
+    j0, j1 = max(0, j - radius), min(t.ny, j + radius + 1)
+    dx, dy = t.lx / t.nx, t.ly / t.ny
+    q = np.ascontiguousarray(t.q[:, j0:j1, i0:i1])
+    solid = np.ascontiguousarray(t.solid[j0:j1, i0:i1])
+    wt = wl.Tank(i1 - i0, j1 - j0, (i1 - i0) * dx, (j1 - j0) * dy, q, gx=t.gx, gy=t.gy,
+                 beta=t.beta, solid=solid)
+    pb = oracle_problem(wt, wk)
+    out, it, _, rc = oracle.step(pb, q, wk.dt, pseudo, 0.0, 0)
+    assert rc == 0 and it == pseudo
+    return out[:, j - j0, i - i0]
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_obstacle_4096_sampled_windows(precision):
+    pseudo = 2
+    wk = wl.obstacle_dam_break(n=4096, precision=precision)
+    t = wk.tanks[0]
+    states, done, _ = run_tuned(wk, precision, pseudo)
+    assert int(done[0]) == pseudo
+    got = states[0]
+    np.testing.assert_array_equal(got[:, t.solid == 1], t.q[:, t.solid == 1])
+    radius = 2 * wk.stages * pseudo + 1
+    scales = field_scales(t)
+    bar = FP64_BAR if precision == "f64" else MIXED_BAR
+    worst = np.zeros(4)
+    for i, j in obstacle_samples(t):
+        ref = window_oracle(wk, t, i, j, radius, pseudo)
+        err = np.abs(got[:, j, i] - ref) / scales
+        worst = np.maximum(worst, err)
+        assert np.all(err <= bar), ((i, j), err, got[:, j, i], ref)
+    print(f"[fullsize] obstacle 4096 {precision}: {len(obstacle_samples(t))} cells, worst scaled "
+          f"error per field {worst}", flush=True)
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_ensemble_512_sampled_tanks(precision):
+    pseudo = 5
+    wk = wl.sloshing_ensemble(precision=precision)
+    states, done, _ = run_tuned(wk, precision, pseudo)
+    assert np.all(done == pseudo)
+    cells = np.array([t.nx * t.ny for t in wk.tanks])
+    order = np.argsort(cells, kind="stable")
+    rng = np.random.default_rng(8)
+    picks = sorted(set(order[:2].tolist() + order[-2:].tolist()
+                       + rng.choice(len(wk.tanks), 4, replace=False).tolist()))
+    bar = FP64_BAR if precision == "f64" else MIXED_BAR
+    worst = np.zeros(4)
+    for k in picks:
+        t = wk.tanks[k]
+        pb = oracle_problem(t, wk)
+        ref, it, _, rc = oracle.step(pb, t.q, wk.dt, pseudo, 0.0, 0)
+        assert rc == 0 and it == pseudo
+        err = field_errors(states[k], ref, None, field_scales(t))
+        worst = np.maximum(worst, err)
+        assert np.all(err <= bar), (k, t.nx, t.ny, err)
+    print(f"[fullsize] ensemble {precision}: tanks {picks}, worst field error {worst}", flush=True)
