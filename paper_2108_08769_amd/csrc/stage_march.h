@@ -123,31 +123,40 @@ struct SourceLoad {
     uint8_t f;                         // cell flags (FLAG_SOLID if outside the tank)
 };
 
+// Row of a load: row r itself, wrapped across a periodic side, or (outside a non-periodic side)
+// the nearest row of the tank.  The cells outside the tank are not fluid (their flag reads
+// FLAG_SOLID), and every use of their values is guarded by that flag or by the wall flags of
+// their fluid neighbours, which take ghosts instead; loading a real cell there keeps the loads
+// unconditional and the values finite.
+__device__ __forceinline__ int load_row(const TankDev &t, int r, bool &inside)
+{
+    int gj;
+    inside = locate_axis(r, t.ny, t.per_y, gj);
+    return inside ? gj : (r < 0 ? 0 : t.ny - 1);
+}
+
+// gi: this lane's column, inside the tank (the nearest column where the lane lies outside).
 template <class P>
 __device__ __forceinline__ InputLoad<P> load_input(const TankDev &t,
                                                    const typename P::Store *__restrict__ qprev,
-                                                   bool have_col, int gi, int r)
+                                                   int gi, int r)
 {
-    using S = typename P::Store;
-    int gj;
+    bool inside;
+    const int gj = load_row(t, r, inside);
+    const size_t plane = t.plane;
+    const size_t c = (size_t)gj * t.nx + gi;
     InputLoad<P> L;
-    L.r = P::kMixed ? S(0) : S(1);
-    L.m = L.n = L.p = S(0);
-    L.lr = 1.0;
-    L.lm = L.ln = L.lp = 0.0;
-    if (have_col && locate_axis(r, t.ny, t.per_y, gj)) {
-        const size_t plane = t.plane;
-        const size_t c = (size_t)gj * t.nx + gi;
-        L.r = qprev[c];
-        L.m = qprev[plane + c];
-        L.n = qprev[2 * plane + c];
-        L.p = qprev[3 * plane + c];
-        if (P::kMixed) {
-            L.lr = t.level_n[c];
-            L.lm = t.level_n[plane + c];
-            L.ln = t.level_n[2 * plane + c];
-            L.lp = t.level_n[3 * plane + c];
-        }
+    L.r = qprev[c];
+    L.m = qprev[plane + c];
+    L.n = qprev[2 * plane + c];
+    L.p = qprev[3 * plane + c];
+    if (P::kMixed) {
+        L.lr = t.level_n[c];
+        L.lm = t.level_n[plane + c];
+        L.ln = t.level_n[2 * plane + c];
+        L.lp = t.level_n[3 * plane + c];
+    } else {
+        L.lr = L.lm = L.ln = L.lp = 0.0;
     }
     return L;
 }
@@ -157,37 +166,37 @@ __device__ __forceinline__ SourceLoad<P> load_sources(const TankDev &t,
                                                       const typename P::Store *__restrict__ q0,
                                                       bool have_col, int gi, int r)
 {
-    using S = typename P::Store;
-    int gj;
+    bool inside;
+    const int gj = load_row(t, r, inside);
+    const size_t plane = t.plane;
+    const size_t c = (size_t)gj * t.nx + gi;
     SourceLoad<P> L;
-    L.z0 = P::kMixed ? S(0) : S(1);
-    L.z1 = L.z2 = L.z3 = S(0);
-    L.n0 = L.m0 = L.k0 = 1.0;
-    L.n1 = L.n2 = L.m1 = L.m2 = L.k1 = L.k2 = 0.0;
-    L.f = FLAG_SOLID;
-    if (have_col && locate_axis(r, t.ny, t.per_y, gj)) {
-        const size_t plane = t.plane;
-        const size_t c = (size_t)gj * t.nx + gi;
-        L.f = t.flags[c];
-        L.z0 = q0[c];
-        L.z1 = q0[plane + c];
-        L.z2 = q0[2 * plane + c];
-        L.z3 = q0[3 * plane + c];
-        if (!P::kMixed) {  // the mixed form takes level n from the input row (it carries it)
-            L.n0 = t.level_n[c];
-            L.n1 = t.level_n[plane + c];
-            L.n2 = t.level_n[2 * plane + c];
-        }
-        if (BDF >= 2) {
-            L.m0 = t.level_nm1[c];
-            L.m1 = t.level_nm1[plane + c];
-            L.m2 = t.level_nm1[2 * plane + c];
-        }
-        if (BDF >= 3) {
-            L.k0 = t.level_nm2[c];
-            L.k1 = t.level_nm2[plane + c];
-            L.k2 = t.level_nm2[2 * plane + c];
-        }
+    const uint8_t f = t.flags[c];
+    L.f = (have_col && inside) ? f : (uint8_t)FLAG_SOLID;
+    L.z0 = q0[c];
+    L.z1 = q0[plane + c];
+    L.z2 = q0[2 * plane + c];
+    L.z3 = q0[3 * plane + c];
+    if (!P::kMixed) {  // the mixed form takes level n from the input row (it carries it)
+        L.n0 = t.level_n[c];
+        L.n1 = t.level_n[plane + c];
+        L.n2 = t.level_n[2 * plane + c];
+    } else {
+        L.n0 = L.n1 = L.n2 = 0.0;
+    }
+    if (BDF >= 2) {
+        L.m0 = t.level_nm1[c];
+        L.m1 = t.level_nm1[plane + c];
+        L.m2 = t.level_nm1[2 * plane + c];
+    } else {
+        L.m0 = L.m1 = L.m2 = 0.0;
+    }
+    if (BDF >= 3) {
+        L.k0 = t.level_nm2[c];
+        L.k1 = t.level_nm2[plane + c];
+        L.k2 = t.level_nm2[2 * plane + c];
+    } else {
+        L.k0 = L.k1 = L.k2 = 0.0;
     }
     return L;
 }
@@ -292,6 +301,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     const int col = strip * kOut - 2 + lane;  // this lane's column (may lie outside the tank)
     int gi = 0;
     const bool have_col = locate_axis(col, t.nx, t.per_x, gi);
+    if (!have_col) gi = col < 0 ? 0 : t.nx - 1;  // loads take the nearest column (see load_row)
     const bool out_lane = lane >= 2 && lane < 2 + kOut && col >= 0 && col < t.nx;
     const int j0 = ch * t.chunk;
     const int j1 = min(j0 + t.chunk, t.ny);
@@ -322,9 +332,9 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     double plo, pmid, phi;
     Vec4<double> lvl_mid = zero4<double>(), lvl_hi = zero4<double>();
     {
-        const InputLoad<P> a = load_input<P>(t, qprev, have_col, gi, j0 - 2);
-        const InputLoad<P> b = load_input<P>(t, qprev, have_col, gi, j0 - 1);
-        const InputLoad<P> c = load_input<P>(t, qprev, have_col, gi, j0);
+        const InputLoad<P> a = load_input<P>(t, qprev, gi, j0 - 2);
+        const InputLoad<P> b = load_input<P>(t, qprev, gi, j0 - 1);
+        const InputLoad<P> c = load_input<P>(t, qprev, gi, j0);
         lo = to_prim(a);
         mid = to_prim(b);
         hi = to_prim(c);
@@ -336,7 +346,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
             lvl_hi = {c.lr, c.lm, c.ln, 0.0};
         }
     }
-    InputLoad<P> in_ld = load_input<P>(t, qprev, have_col, gi, j0 + 1);             // row r+2
+    InputLoad<P> in_ld = load_input<P>(t, qprev, gi, j0 + 1);             // row r+2
     SourceLoad<P> src_ld = load_sources<P, BDF>(t, q0, have_col, gi, j0 - 1);       // row r
     if (stopped) return;
 
@@ -406,7 +416,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         const Prim<R> next_hi = to_prim(in_ld);
         const double next_phi = abs_p(in_ld);
         const Vec4<double> next_lvl = {in_ld.lr, in_ld.lm, in_ld.ln, 0.0};
-        in_ld = load_input<P>(t, qprev, have_col, gi, r + 3);
+        in_ld = load_input<P>(t, qprev, gi, r + 3);
         src_ld = load_sources<P, BDF>(t, q0, have_col, gi, r + 1);
 
         // ---- reconstruction of row r ------------------------------------------------------
