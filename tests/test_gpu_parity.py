@@ -155,11 +155,15 @@ def test_tile_variants_agree():
         assert np.all(field_errors(got, ref, None, field_scales(wk.tanks[0])) <= 1e-13)
 
 
+@pytest.mark.parametrize("kernel", [(0, 0), (3208, 2), (1, 1)], ids=["march", "tile", "plain"])
 @pytest.mark.parametrize("case", ["fixed", "tolerance", "multi_tank"])
-def test_graph_replay_matches_eager_launches(case):
+def test_graph_replay_matches_eager_launches(case, kernel):
     """Pseudo-iterations captured in HIP graphs and replayed (several replays per step, host
     synchronisations and state reads between steps) give bit-identical states, iteration
-    counts and norms to launching every kernel from the host."""
+    counts and norms to launching every kernel from the host.  Groups of 4 and 5 iterations
+    start at every iteration index mod 3 (the buffer rotation a captured graph is keyed by);
+    the row-marching and tiled kernels run each iteration's finalize inside the next
+    iteration's first stage, the plain kernel in launches of its own."""
     if case == "fixed":
         wk, steps, pseudo, tol = small_dam(70, 33), 3, 23, 0.0
     elif case == "tolerance":
@@ -169,9 +173,9 @@ def test_graph_replay_matches_eager_launches(case):
                          wl.random_state(nx, ny, seed=nx, rho_range=(1.0, 3.0), vel=0.2, p_scale=5.0),
                          gy=-9.81, beta=300.0) for nx, ny in [(20, 12), (7, 30), (33, 5)]]
         wk, steps, pseudo, tol = wl.Workload("multi", tanks, dt=1e-3, steps=1, max_pseudo=1), 2, 9, 0.0
-    ref = run_gpu(wk, steps, pseudo, tol, graph_iters=-1)
-    for gi in (0, 4):
-        got = run_gpu(wk, steps, pseudo, tol, graph_iters=gi)
+    ref = run_gpu(wk, steps, pseudo, tol, graph_iters=-1, tile=kernel)
+    for gi in (0, 4, 5):
+        got = run_gpu(wk, steps, pseudo, tol, graph_iters=gi, tile=kernel)
         for a, b in zip(got[0], ref[0]):
             np.testing.assert_array_equal(a, b)
         np.testing.assert_array_equal(got[1], ref[1])
