@@ -88,9 +88,10 @@ typedef struct {
                                -W x L row marching over 64-column strips in chunks of L rows,
                                W = 3 for a 3-waves-per-SIMD register budget, 1 or 2 otherwise;
                                32 x 8, 16 x 16 or 64 x 4 two-dimensional LDS tiles (256
-                               threads), and 3208 x 2, 1616 x 2 for the 32 x 8 and 16 x 16 tiles
-                               with 512 threads; tiles take one tank, FP64 or mixed, BDF order up
-                               to 2; one thread per cell is FP64 only */
+                               threads), 3208 x 2, 1616 x 2 for the 32 x 8 and 16 x 16 tiles
+                               with 512 threads, and 1608 x 2 for a 16 x 8 tile with 320 threads;
+                               tiles take one tank, FP64 or mixed, BDF order up to 2; one thread
+                               per cell is FP64 only */
     int32_t graph_iters; /* pseudo-iterations captured per HIP graph and replayed on the stream:
                             0 automatic, K > 0 exactly K, -1 launch kernels one by one */
     int32_t flux;        /* VDAC_FLUX_* */

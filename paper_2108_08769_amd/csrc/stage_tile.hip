@@ -182,9 +182,12 @@ __device__ __forceinline__ void load_cell(const TankDev &t, const typename P::St
 
 // NT threads per tile: 256 (one per tile cell) or 512 (every phase finishes in at most two
 // rounds, which shortens the critical path of small grids).
+// Launch bounds: NT threads, and for the 16 x 8 tile a register budget that fits four workgroups
+// (five waves per SIMD).
 template <class P, int TX, int TY, int NT, bool NORM_MAX>
-__global__ void __launch_bounds__(NT) stage_tile(TankDev t, Scheme sc, int stage, int tiles_x,
-                                                 int n_tiles, IterArgs ia)
+__global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankDev t, Scheme sc, int stage,
+                                                                          int tiles_x, int n_tiles,
+                                                                          IterArgs ia)
 {
     using R = typename P::Real;
     using S = typename P::Store;
@@ -514,24 +517,27 @@ int launch_tile_p(const TankDev &t, const Scheme &sc, int stage, int tile_x, int
     if (tile_x == 64 && tile_y == 4) return launch_tile<P, 64, 4, 256>(t, sc, stage, ia, stream);
     if (tile_x == 3208 && tile_y == 2) return launch_tile<P, 32, 8, 512>(t, sc, stage, ia, stream);
     if (tile_x == 1616 && tile_y == 2) return launch_tile<P, 16, 16, 512>(t, sc, stage, ia, stream);
+    if (tile_x == 1608 && tile_y == 2) return launch_tile<P, 16, 8, 320>(t, sc, stage, ia, stream);
     return (int)hipErrorInvalidValue;
 }
 
 }  // namespace
 
 // 32 x 8, 16 x 16 and 64 x 4 tiles run with 256 threads; 3208 and 1616 name the 32 x 8 and
-// 16 x 16 tiles run with 512 threads.
+// 16 x 16 tiles run with 512 threads, 1608 the 16 x 8 tile with 320 threads (tile_y 2 for all
+// three).
 bool tile_supported(int tile_x, int tile_y)
 {
     return (tile_x == 32 && tile_y == 8) || (tile_x == 16 && tile_y == 16) ||
            (tile_x == 64 && tile_y == 4) || (tile_x == 3208 && tile_y == 2) ||
-           (tile_x == 1616 && tile_y == 2);
+           (tile_x == 1616 && tile_y == 2) || (tile_x == 1608 && tile_y == 2);
 }
 
 int tile_count(const TankDev &t, int tile_x, int tile_y)
 {
     if (tile_x == 3208) tile_x = 32, tile_y = 8;
     if (tile_x == 1616) tile_x = 16, tile_y = 16;
+    if (tile_x == 1608) tile_x = 16, tile_y = 8;
     return ((t.nx + tile_x - 1) / tile_x) * ((t.ny + tile_y - 1) / tile_y);
 }
 

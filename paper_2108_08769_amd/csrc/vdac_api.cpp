@@ -143,7 +143,7 @@ int check_options(const vdac_options *o)
     if (!auto_tile && !direct && !march && !tile_supported(o->tile_x, o->tile_y))
         return fail(VDAC_E_INVALID, "tile %d x %d is not available (0 x 0 = automatic, 1 x 1 = "
                     "one thread per cell, -W x L (W = 1..3) = row marching in chunks of L rows, or 32 x 8, "
-                    "16 x 16, 64 x 4, 3208 x 2, 1616 x 2)", o->tile_x, o->tile_y);
+                    "16 x 16, 64 x 4, 3208 x 2, 1616 x 2, 1608 x 2)", o->tile_x, o->tile_y);
     if (o->precision == VDAC_FP32_MIXED && direct)
         return fail(VDAC_E_INVALID, "the mixed precision form runs the row-marching or the tiled "
                     "kernel (tile 0 x 0, -W x L or a 2D tile), not the one-thread-per-cell kernel");
@@ -996,7 +996,7 @@ int autotune_tile(const vdac_tank *tanks, int32_t n_tanks, vdac_options *o, void
     const bool march_only = base.flux != VDAC_FLUX_OSHER || base.pgrad != VDAC_PGRAD_NEW ||
                             base.local_dtau == 0 || base.bdf_order == 3 || has_open_side(&tanks[0]);
     if (n_tanks == 1 && !march_only)
-        for (auto tl : {std::pair<int, int>{3208, 2}, {1616, 2}, {32, 8}, {16, 16}}) cand.push_back(tl);
+        for (auto tl : {std::pair<int, int>{3208, 2}, {1616, 2}, {1608, 2}, {32, 8}, {16, 16}}) cand.push_back(tl);
 
     double best_ms = 0.0;
     std::pair<int, int> best = {0, 0};

@@ -129,7 +129,8 @@ def test_multi_tank_grid():
     check(wk, steps=2, pseudo=6)
 
 
-TILES = [(1, 1), (32, 8), (16, 16), (64, 4), (3208, 2), (1616, 2), (-1, 16), (-1, 7), (-3, 64), (-3, 5)]
+TILES = [(1, 1), (32, 8), (16, 16), (64, 4), (3208, 2), (1616, 2), (1608, 2), (-1, 16), (-1, 7),
+         (-3, 64), (-3, 5)]
 
 
 @pytest.mark.parametrize("tile", TILES)
