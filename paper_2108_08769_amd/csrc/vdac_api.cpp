@@ -81,6 +81,10 @@ struct vdac_grid {
     MarchUnit *units_dev;               // [plan.n_entries] (row marching only)
     double *staging;                    // [4][max_plane] (mixed form only)
     std::vector<Status> status_host;
+    // pinned snapshots of the statuses after a launch group, read while the next group runs
+    // (two slots: the snapshot in flight and the one being checked)
+    Status *status_snap = nullptr;      // [2][n_tanks]
+    hipEvent_t snap_ev[2] = {nullptr, nullptr};
     int hist;                           // completed real steps since set_state (capped at 2):
                                         // how many earlier real-time levels are valid
     // captured pseudo-iterations, keyed by the number of iterations per graph and the first
@@ -686,6 +690,12 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         destroy_grid(g);
         return hip_fail(ec, "creating the capture stream");
     }
+    ec = hipHostMalloc((void **)&g->status_snap, 2 * (size_t)n_tanks * sizeof(Status), hipHostMallocDefault);
+    for (int k = 0; k < 2 && ec == hipSuccess; ++k) ec = hipEventCreateWithFlags(&g->snap_ev[k], hipEventDisableTiming);
+    if (ec != hipSuccess) {
+        destroy_grid(g);
+        return hip_fail(ec, "allocating the status snapshots");
+    }
     *out = g;
     return VDAC_OK;
 }
@@ -820,8 +830,11 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
                                use_history, g->stream);
     if (rc != 0) return hip_fail((hipError_t)rc, "begin_step launch");
     std::vector<int> before(nt, 0);
-    // iterations per launch group: with a tolerance, the host checks the stop flags after each
-    // group (the kernels of stopped tanks return at once); without, groups cover max_pseudo.
+    // iterations per launch group: with a tolerance, the host checks the stop flags between
+    // groups (the kernels of stopped tanks return at once); without, groups cover max_pseudo.
+    // The check is pipelined: after group k is queued, the host reads the status snapshot taken
+    // after group k-1, so the GPU never waits for the host; a step that has converged runs at
+    // most one group of returning kernels more.
     int group;
     if (tol > 0.0) {
         group = max_pseudo < 10 ? max_pseudo : 10;
@@ -832,7 +845,7 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
     const bool use_graph = g->opt.graph_iters >= 0 && !g->timing;
     if (use_graph && g->opt.graph_iters > 0) group = g->opt.graph_iters;
     size_t ev_next = 0;
-    for (int m = 0; m < max_pseudo && group > 0;) {
+    for (int m = 0, k = 0; m < max_pseudo && group > 0;) {
         if (use_graph) {
             hipGraphExec_t exec;
             if ((rc = graph_for(g, group, m % 3, &exec)) != VDAC_OK) return rc;
@@ -845,11 +858,21 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
         }
         m += group;
         if (m < max_pseudo && tol > 0.0) {
-            if ((rc = read_statuses(g)) != VDAC_OK) return rc;
-            bool all_done = true;
-            for (int t = 0; t < nt && all_done; ++t) all_done = g->status_host[t].done != 0;
-            if (all_done) break;
+            const int slot = k & 1;
+            hipError_t e = hipMemcpyAsync(g->status_snap + slot * nt, g->status_dev, nt * sizeof(Status),
+                                          hipMemcpyDeviceToHost, g->stream);
+            if (e == hipSuccess) e = hipEventRecord(g->snap_ev[slot], g->stream);
+            if (e != hipSuccess) return hip_fail(e, "reading the statuses");
+            if (k >= 1) {
+                const int prev = slot ^ 1;
+                e = hipEventSynchronize(g->snap_ev[prev]);
+                if (e != hipSuccess) return hip_fail(e, "reading the statuses");
+                bool all_done = true;
+                for (int t = 0; t < nt && all_done; ++t) all_done = g->status_snap[prev * nt + t].done != 0;
+                if (all_done) break;
+            }
         }
+        ++k;
     }
     if ((rc = read_statuses(g)) != VDAC_OK) return rc;
     int status = VDAC_OK;
@@ -1037,6 +1060,9 @@ void destroy_grid(vdac_grid *g)
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     else (void)hipDeviceSynchronize();
     for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : g->snap_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (g->status_snap) (void)hipHostFree(g->status_snap);
     drop_graphs(g);
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     if (g->own_ws && g->ws) (void)hipFree(g->ws);
