@@ -1,14 +1,16 @@
 """Parity at the full sizes of the large benchmark workloads, in the launch configuration that
 bench.py times (the autotuned stage-kernel shape), on outputs the oracle can compute.
 
-* 4096 x 4096 obstacle dam break.  After one real step of P pseudo-iterations a cell's new state
+* 64 x 64 hydrostatic tank (the first benchmark configuration) in full: 10 real steps of exactly
+  200 pseudo-iterations, every step compared (the error is printed against the step).
+* 4096 x 4096 obstacle dam break.  After real steps totalling N pseudo-iterations a cell's state
   depends only on the initial state within 2 cells per stage (a face's states need the slopes of
-  the two cells beside it, and each slope its two neighbours), so within R = 2 s_max P cells.  The
-  oracle runs a window of the initial state of radius R + 1 around each sampled cell, clipped at
-  the domain, where the domain's own walls apply.  The window's cut sides are walls in the
-  oracle, which can reach at most R cells inward, so the window's centre cell is exact.  Samples:
-  the obstacle's corners and top, the dam front, the layer interface, the four walls and corners,
-  and seeded interior cells.
+  the two cells beside it, and each slope its two neighbours; the real-time levels are the
+  cell's own), so within R = 2 s_max N cells.  The oracle runs a window of the initial state of
+  radius R + 1 around each sampled cell, clipped at the domain, where the domain's own walls
+  apply.  The window's cut sides are walls in the oracle, which can reach at most R cells inward,
+  so the window's centre cell is exact.  Samples: the obstacle's corners and top, the dam front,
+  the layer interface, the four walls and corners, and seeded interior cells.
 * 512-tank sloshing ensemble.  The whole batched launch runs; the oracle runs a sample of whole
   tanks (the smallest, the largest and seeded ones).
 
@@ -34,9 +36,10 @@ def tank_dict(t):
                 solid=t.solid)
 
 
-def run_tuned(wk, precision, pseudo):
-    """One real step of `pseudo` pseudo-iterations of every tank, in one grid, with the shape the
-    autotuner picks (as bench.py does); returns the states, the iteration counts and the shape."""
+def run_tuned(wk, precision, pseudo, steps=1):
+    """`steps` real steps of `pseudo` pseudo-iterations of every tank, in one grid, with the shape
+    the autotuner picks (as bench.py does); returns the states, the iteration counts of the last
+    step and the shape."""
     tanks = [tank_dict(t) for t in wk.tanks]
     opts = vdac.autotune(tanks, gpu_options(wk, precision), iters=5)
     shape = (opts.tile_x, opts.tile_y)
@@ -45,8 +48,9 @@ def run_tuned(wk, precision, pseudo):
     try:
         for i, t in enumerate(wk.tanks):
             grid.set_state(i, t.q)
-        rc, done = grid.step(wk.dt, pseudo, 0.0, check=False)
-        assert rc == 0
+        for _ in range(steps):
+            rc, done = grid.step(wk.dt, pseudo, 0.0, check=False)
+            assert rc == 0
         states = [grid.get_state(i) for i in range(len(wk.tanks))]
     finally:
         grid.close()
@@ -65,8 +69,9 @@ def obstacle_samples(t, n_random=10, seed=21):
     return [(i, j) for i, j in pts if not t.solid[j, i]]
 
 
-def window_oracle(wk, t, i, j, radius, pseudo):
-    """The oracle's state at cell (i, j) after one real step, from a window of the initial state."""
+def window_oracle(wk, t, i, j, radius, pseudo, steps=1):
+    """The oracle's state at cell (i, j) after `steps` real steps, from a window of the initial
+    state."""
     i0, i1 = max(0, i - radius), min(t.nx, i + radius + 1)
     j0, j1 = max(0, j - radius), min(t.ny, j + radius + 1)
     dx, dy = t.lx / t.nx, t.ly / t.ny
@@ -75,26 +80,52 @@ def window_oracle(wk, t, i, j, radius, pseudo):
     wt = wl.Tank(i1 - i0, j1 - j0, (i1 - i0) * dx, (j1 - j0) * dy, q, gx=t.gx, gy=t.gy,
                  beta=t.beta, solid=solid)
     pb = oracle_problem(wt, wk)
-    out, it, _, rc = oracle.step(pb, q, wk.dt, pseudo, 0.0, 0)
-    assert rc == 0 and it == pseudo
+    out = q
+    for _ in range(steps):
+        out, it, _, rc = oracle.step(pb, out, wk.dt, pseudo, 0.0, 0)
+        assert rc == 0 and it == pseudo
     return out[:, j - j0, i - i0]
+
+
+def test_hydrostatic_64_in_full_every_step():
+    """The first benchmark configuration in full: 10 real steps of exactly 200 pseudo-iterations
+    in the autotuned shape, each step's state against the oracle's."""
+    wk = wl.hydrostatic()
+    t = wk.tanks[0]
+    tanks = [tank_dict(t)]
+    opts = vdac.autotune(tanks, gpu_options(wk, "f64"), iters=5)
+    print(f"[fullsize] {wk.name}: autotuned shape {(opts.tile_x, opts.tile_y)}", flush=True)
+    pb = oracle_problem(t, wk)
+    grid = vdac.Grid(tanks, opts)
+    try:
+        grid.set_state(0, t.q)
+        ref = t.q
+        for step in range(wk.steps):
+            rc, done = grid.step(wk.dt, wk.max_pseudo, 0.0, check=False)
+            ref, it, _, orc = oracle.step(pb, ref, wk.dt, wk.max_pseudo, 0.0, 0)
+            assert rc == 0 and orc == 0 and int(done[0]) == it == wk.max_pseudo
+            err = field_errors(grid.get_state(0), ref, None, field_scales(t))
+            print(f"[fullsize] hydrostatic step {step + 1}: field errors {err}", flush=True)
+            assert np.all(err <= FP64_BAR), (step, err)
+    finally:
+        grid.close()
 
 
 @pytest.mark.parametrize("precision", ["f64", "mixed"])
 def test_obstacle_4096_sampled_windows(precision):
-    pseudo = 2
+    pseudo, steps = 2, 2
     wk = wl.obstacle_dam_break(n=4096, precision=precision)
     t = wk.tanks[0]
-    states, done, _ = run_tuned(wk, precision, pseudo)
+    states, done, _ = run_tuned(wk, precision, pseudo, steps)
     assert int(done[0]) == pseudo
     got = states[0]
     np.testing.assert_array_equal(got[:, t.solid == 1], t.q[:, t.solid == 1])
-    radius = 2 * wk.stages * pseudo + 1
+    radius = 2 * wk.stages * pseudo * steps + 1
     scales = field_scales(t)
     bar = FP64_BAR if precision == "f64" else MIXED_BAR
     worst = np.zeros(4)
     for i, j in obstacle_samples(t):
-        ref = window_oracle(wk, t, i, j, radius, pseudo)
+        ref = window_oracle(wk, t, i, j, radius, pseudo, steps)
         err = np.abs(got[:, j, i] - ref) / scales
         worst = np.maximum(worst, err)
         assert np.all(err <= bar), ((i, j), err, got[:, j, i], ref)

@@ -185,12 +185,12 @@ def test_graph_replay_matches_eager_launches(case, kernel):
 
 
 def test_full_size_dam_break_512x256():
-    """The benchmark workload at its full size, truncated to a few pseudo-iterations."""
-    check(wl.dam_break(), steps=1, pseudo=4)
+    """The benchmark workload at its full size, truncated to 2 real steps of 5 pseudo-iterations."""
+    check(wl.dam_break(), steps=2, pseudo=5)
 
 
 def test_full_size_rayleigh_taylor_256x1024():
-    check(wl.rayleigh_taylor(precision="f64"), steps=1, pseudo=2)
+    check(wl.rayleigh_taylor(precision="f64"), steps=2, pseudo=3)
 
 
 def test_deterministic_repeat():

@@ -1,7 +1,7 @@
 """The window argument the full-size GPU parity tests rest on, checked on the CPU with the oracle
-alone: after one real step of P pseudo-iterations, a cell's state computed from a window of the
-initial state of radius 2 s_max P + 1 around it (cut sides as walls, the domain's own walls where
-the window reaches them) equals the cell's state from the whole tank."""
+alone: after real steps totalling N pseudo-iterations, a cell's state computed from a window of
+the initial state of radius 2 s_max N + 1 around it (cut sides as walls, the domain's own walls
+where the window reaches them) equals the cell's state from the whole tank."""
 import numpy as np
 
 import oracle
@@ -9,7 +9,7 @@ from paper_2108_08769_amd import workloads as wl
 from parity import oracle_problem
 
 
-def window_state(wk, t, i, j, radius, pseudo):
+def window_state(wk, t, i, j, radius, pseudo, steps):
     i0, i1 = max(0, i - radius), min(t.nx, i + radius + 1)
     j0, j1 = max(0, j - radius), min(t.ny, j + radius + 1)
     dx, dy = t.lx / t.nx, t.ly / t.ny
@@ -17,18 +17,24 @@ def window_state(wk, t, i, j, radius, pseudo):
     solid = np.ascontiguousarray(t.solid[j0:j1, i0:i1])
     wt = wl.Tank(i1 - i0, j1 - j0, (i1 - i0) * dx, (j1 - j0) * dy, q, gx=t.gx, gy=t.gy,
                  beta=t.beta, solid=solid)
-    out, it, _, rc = oracle.step(oracle_problem(wt, wk), q, wk.dt, pseudo, 0.0, 0)
-    assert rc == 0 and it == pseudo
+    pb = oracle_problem(wt, wk)
+    out = q
+    for _ in range(steps):
+        out, it, _, rc = oracle.step(pb, out, wk.dt, pseudo, 0.0, 0)
+        assert rc == 0 and it == pseudo
     return out[:, j - j0, i - i0]
 
 
-def test_window_of_radius_2_smax_P_plus_1_reproduces_the_whole_tank():
-    pseudo = 2
+def test_window_of_radius_2_smax_N_plus_1_reproduces_the_whole_tank():
+    pseudo, steps = 2, 2
     wk = wl.obstacle_dam_break(n=128)
     t = wk.tanks[0]
-    full, it, _, rc = oracle.step(oracle_problem(t, wk), t.q, wk.dt, pseudo, 0.0, 0)
-    assert rc == 0 and it == pseudo
-    radius = 2 * wk.stages * pseudo + 1
+    pb = oracle_problem(t, wk)
+    full = t.q
+    for _ in range(steps):
+        full, it, _, rc = oracle.step(pb, full, wk.dt, pseudo, 0.0, 0)
+        assert rc == 0 and it == pseudo
+    radius = 2 * wk.stages * pseudo * steps + 1
     rng = np.random.default_rng(5)
     pts = [(0, 0), (127, 127), (80, 0), (79, 9), (87, 10), (32, 40), (31, 64), (16, 63)]
     pts += [tuple(int(v) for v in p) for p in rng.integers(0, 128, size=(12, 2))]
@@ -37,11 +43,11 @@ def test_window_of_radius_2_smax_P_plus_1_reproduces_the_whole_tank():
     for i, j in pts:
         if t.solid[j, i]:
             continue
-        err = np.abs(window_state(wk, t, i, j, radius, pseudo) - full[:, j, i]) / scale
+        err = np.abs(window_state(wk, t, i, j, radius, pseudo, steps) - full[:, j, i]) / scale
         worst = max(worst, float(err.max()))
         assert np.all(err <= 1e-14), ((i, j), err)
     # a window much shorter than the reach changes the result next to the dam front and the
     # layer interface, where the state varies (the comparison above has teeth)
-    short = [np.abs(window_state(wk, t, i, j, 2, pseudo) - full[:, j, i]).max()
+    short = [np.abs(window_state(wk, t, i, j, 2, pseudo, steps) - full[:, j, i]).max()
              for i, j in [(34, 20), (29, 20), (20, 66)]]
     assert min(short) > 0.0, short
