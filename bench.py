@@ -23,7 +23,8 @@ one, an event pair around each pseudo-iteration's s_max stage launches, so it in
 dispatch gaps between them).  traffic is the copy-calibrated FETCH_SIZE + WRITE_SIZE bytes per
 launch from the committed counter summaries in profiles/, reported only while the kernel
 sources still hash to what was profiled.  cpu_baseline times the serial FP64 oracle on a bounded
-sample of the same workload.  An FP64 line also reports mixed_form: the mixed-precision form on the
+sample of the same workload, cpu_baseline_all_cores the same source built with -fopenmp on all
+the host's threads.  An FP64 line also reports mixed_form: the mixed-precision form on the
 same workload and steps, timed the same way after the FP64 measurement, with its speedup
 (--no-mixed skips it).
 """
@@ -90,27 +91,47 @@ def build_workload(name: str, precision: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(wk, budget_s: float):
-    """The oracle as it stands (serial FP64 C), timed on a bounded sample of the workload: the
-    first real step with as many pseudo-iterations as fit the budget (estimated from one)."""
-    import numpy as np
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wk, budget_s: float, omp: bool = False):
+    """The oracle (FP64 C) timed on a bounded sample of the workload: real steps from the initial
+    state, each with as many pseudo-iterations as the budget allows (up to the workload's cap),
+    until the budget is used.  omp=False is the oracle as it stands (serial); omp=True the same
+    source built with -fopenmp on all host threads (same results)."""
     import oracle
     t = wk.tanks[0]
     pb = oracle.Problem(t.nx, t.ny, t.lx, t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
                         solid=t.solid, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl, k=wk.k,
                         local_dtau=wk.local_dtau, bdf=1)
     t0 = time.perf_counter()
-    oracle.step(pb, t.q, wk.dt, 1, 0.0)
+    oracle.step(pb, t.q, wk.dt, 1, 0.0, omp=omp)
     one = time.perf_counter() - t0
     iters = int(max(1, min(wk.max_pseudo, budget_s / max(one, 1e-6))))
+    q, total_it, steps = t.q, 0, 0
     t0 = time.perf_counter()
-    _, it, _, rc = oracle.step(pb, t.q, wk.dt, iters, 0.0)
+    while True:
+        q, it, _, rc = oracle.step(pb, q, wk.dt, iters, 0.0, omp=omp)
+        total_it += it
+        steps += 1
+        if rc != 0 or time.perf_counter() - t0 >= budget_s:
+            break
     dt = time.perf_counter() - t0
-    cell_stages = t.fluid_cells * wk.stages * it
+    cell_stages = t.fluid_cells * wk.stages * total_it
+    threads = oracle.threads(omp)
     return {"value": cell_stages / dt, "unit": "cell-updates/s per pseudo-time stage",
-            "cores": 1, "kind": "oracle",
-            "sample": f"{wk.name}: first real step, {it} pseudo-iterations x {wk.stages} stages "
-                      f"({cell_stages:.3g} cell-stages, {dt:.1f} s)"}
+            "cores": threads, "kind": "oracle" if not omp else "oracle, -fopenmp build of the same source",
+            "cpu": cpu_model(), "host_threads": os.cpu_count(),
+            "sample": f"{wk.name}: {steps} real step(s) of {iters} pseudo-iterations x {wk.stages} "
+                      f"stages ({cell_stages:.3g} cell-stages, {dt:.1f} s, {threads} thread(s))"}
 
 
 def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
@@ -310,6 +331,7 @@ def main():
                                           "residual, sources and update"}
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(wk, args.cpu_budget)
+        line["cpu_baseline_all_cores"] = cpu_baseline(wk, args.cpu_budget, omp=True)
     print(json.dumps(line), flush=True)
 
 

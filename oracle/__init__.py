@@ -20,6 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vdac_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 BC_WALL = 0
 BC_PERIODIC = 1
@@ -29,12 +30,14 @@ PGRAD_NEW, PGRAD_LIMITER, PGRAD_SPLIT = 0, 1, 2
 
 
 def build() -> str:
-    """Compile the oracle (plain C99, -O2, no contraction, no fast-math)."""
-    tmp = _LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-Wall",
-           "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB)
+    """Compile the oracle (plain C99, -O2, no contraction, no fast-math), serial, and the same
+    source with -fopenmp (its row loops on all host threads; used only to time the oracle)."""
+    for lib_path, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        tmp = lib_path + ".tmp"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-Wall", *extra,
+               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, lib_path)
     return _LIB
 
 
@@ -64,15 +67,16 @@ class _Detail(ctypes.Structure):
                 for name in ("prim", "grad", "fx", "fy", "resid", "dtau")]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def lib(omp: bool = False):
+    """The serial oracle, or (omp=True) the same source built with -fopenmp."""
+    path = _LIB_OMP if omp else _LIB
+    if path not in _libs:
+        if not os.path.exists(path):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         L.orc_limiter.restype = ctypes.c_double
         L.orc_limiter.argtypes = [ctypes.c_double] * 3
@@ -96,8 +100,15 @@ def lib():
         L.orc_step.restype = ctypes.c_int
         L.orc_step.argtypes = [ctypes.POINTER(_Problem), dp, dp, dp, ctypes.c_double, ctypes.c_int,
                                ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
-        _lib = L
-    return _lib
+        L.orc_threads.restype = ctypes.c_int
+        L.orc_threads.argtypes = []
+        _libs[path] = L
+    return _libs[path]
+
+
+def threads(omp: bool = False) -> int:
+    """Host threads the oracle's row loops run on (1 for the serial build)."""
+    return int(lib(omp).orc_threads())
 
 
 def _ptr(a: np.ndarray | None):
@@ -252,8 +263,9 @@ def stage(pb: Problem, qprev, q0, qn, dt, s, qnm1=None, qnm2=None):
     return out, det
 
 
-def step(pb: Problem, q, dt, max_pseudo, tol=0.0, norm=0, qnm1=None, qnm2=None):
-    """One real-time step.  Returns (q_new, iterations, norms[4], status)."""
+def step(pb: Problem, q, dt, max_pseudo, tol=0.0, norm=0, qnm1=None, qnm2=None, omp=False):
+    """One real-time step.  Returns (q_new, iterations, norms[4], status).  omp=True runs the
+    -fopenmp build of the same source (same results; for timing on all host threads)."""
     q = np.array(q, dtype=np.float64, order="C", copy=True)
     assert q.shape == (4, pb.ny, pb.nx)
     qm = None if qnm1 is None else np.ascontiguousarray(qnm1, dtype=np.float64)
@@ -261,8 +273,8 @@ def step(pb: Problem, q, dt, max_pseudo, tol=0.0, norm=0, qnm1=None, qnm2=None):
     it = ctypes.c_int(0)
     res = np.zeros(4)
     st = pb.c_struct()
-    rc = lib().orc_step(ctypes.byref(st), _ptr(q), _ptr(qm), _ptr(qm2), dt, int(max_pseudo),
-                        float(tol), int(norm), ctypes.byref(it), _ptr(res))
+    rc = lib(omp).orc_step(ctypes.byref(st), _ptr(q), _ptr(qm), _ptr(qm2), dt, int(max_pseudo),
+                           float(tol), int(norm), ctypes.byref(it), _ptr(res))
     if rc == -1:
         raise ValueError("orc_step: invalid arguments")
     return q, it.value, res, rc

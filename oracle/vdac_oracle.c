@@ -9,6 +9,11 @@
  * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the benchmark's CPU-baseline
  * leg; never by the product path.  It shares no code with the GPU library.
  *
+ * Built serial for the tests.  A second build with -fopenmp (for the all-cores CPU baseline only)
+ * runs the row loops of a stage on all host threads; every cell's arithmetic is the same, and the
+ * only reduction inside them is a minimum, so that build's results are bit for bit the serial
+ * ones.
+ *
  * Written for a reader holding the paper: every step follows the definition it cites, in the
  * paper's order and notation, with no blocking, fusion or reordering.  Build with
  * -O2 -ffp-contract=off (no fused multiply-add, no fast-math).
@@ -60,6 +65,16 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#define ORC_PRAGMA(x) _Pragma(#x)
+#define ORC_ROWS _Pragma("omp parallel for schedule(static)")
+#define ORC_ROWS_MIN(v) ORC_PRAGMA(omp parallel for schedule(static) reduction(min : v))
+#else
+#define ORC_ROWS
+#define ORC_ROWS_MIN(v)
+#endif
 
 /* ------------------------------------------------------------------------------------------ */
 /* Single-point pieces                                                                        */
@@ -572,6 +587,7 @@ static void freeze_sources(const geom *g, const double *Q0, const double *Qn, co
         B[3] = -1.0 / 3.0;
     }
     double dmin = INFINITY;
+    ORC_ROWS_MIN(dmin)
     for (int j = 0; j < g->ny; ++j)
         for (int i = 0; i < g->nx; ++i) {
             size_t c = at(g, i, j);
@@ -623,6 +639,7 @@ static void stage_internal(const geom *g, const double *Qprev, const double *Q0,
     size_t nfx = (size_t)ny * (size_t)(nx + 1), nfy = (size_t)(ny + 1) * (size_t)nx;
 
     /* primitives of the stage input */
+    ORC_ROWS
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t c = at(g, i, j);
@@ -634,6 +651,7 @@ static void stage_internal(const geom *g, const double *Qprev, const double *Q0,
         }
 
     /* limited gradients and the new pressure gradient of every fluid cell */
+    ORC_ROWS
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t c = at(g, i, j);
@@ -647,6 +665,7 @@ static void stage_internal(const geom *g, const double *Qprev, const double *Q0,
         }
 
     /* x-faces: face i is the left face of cell i, between cells i-1 and i */
+    ORC_ROWS
     for (int j = 0; j < ny; ++j)
         for (int f = 0; f <= nx; ++f) {
             int il = f - 1, ir = f;
@@ -677,6 +696,7 @@ static void stage_internal(const geom *g, const double *Qprev, const double *Q0,
         }
 
     /* y-faces: face j is the lower face of cell row j, between rows j-1 and j */
+    ORC_ROWS
     for (int f = 0; f <= ny; ++f)
         for (int i = 0; i < nx; ++i) {
             int jl = f - 1, jr = f;
@@ -708,6 +728,7 @@ static void stage_internal(const geom *g, const double *Qprev, const double *Q0,
 
     /* bracket of eq. RK2 and the update */
     double alpha = pb->alpha[s - 1];
+    ORC_ROWS
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t c = at(g, i, j);
@@ -927,6 +948,16 @@ int orc_step(const orc_problem *pb, double *q, const double *qnm1, const double 
     free(fz.rho0);
     free(fz.dtau);
     return status;
+}
+
+/* Threads the row loops run on: 1 in the serial build. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Sec. 2.2.4: dt = min over fluid cells of CFL_t |Omega| / (|u| dS_x + |v| dS_y), dS_x = dy and

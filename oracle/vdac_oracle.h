@@ -125,6 +125,10 @@ int orc_stage(const orc_problem *pb, const double *qprev, const double *q0, cons
 int orc_step(const orc_problem *pb, double *q, const double *qnm1, const double *qnm2, double dt,
              int max_pseudo, double tol, int norm_kind, int *iters, double res[4]);
 
+/* Threads the row loops run on: 1 in the serial build, the OpenMP thread count in the build
+ * made with -fopenmp (used only to time the oracle on all host cores). */
+int orc_threads(void);
+
 #ifdef __cplusplus
 }
 #endif
