@@ -122,7 +122,8 @@ def cpu_baseline(wk, budget_s: float, omp: bool = False):
         q, it, _, rc = oracle.step(pb, q, wk.dt, iters, 0.0, omp=omp)
         total_it += it
         steps += 1
-        if rc != 0 or time.perf_counter() - t0 >= budget_s:
+        spent = time.perf_counter() - t0
+        if rc != 0 or spent + spent / steps > budget_s:  # the next step would not fit the budget
             break
     dt = time.perf_counter() - t0
     cell_stages = t.fluid_cells * wk.stages * total_it

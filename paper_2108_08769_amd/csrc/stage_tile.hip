@@ -182,6 +182,15 @@ __device__ __forceinline__ void load_cell(const TankDev &t, const typename P::St
 
 // NT threads per tile: 256 (one per tile cell) or 512 (every phase finishes in at most two
 // rounds, which shortens the critical path of small grids).
+// Whether the last wave of an NT-thread workgroup is idle in phases 1 and 2 (no primitive, flag
+// or phase-2 position falls to it), so that it can run the deferred finalize there.
+template <int TX, int TY, int NT>
+__host__ __device__ constexpr bool fin_in_block()
+{
+    return NT == 512 && (TX + 4) * (TY + 4) <= NT - 64 && (TX + 2) * (TY + 2) <= NT - 64 &&
+           TX * TY + 2 * (TX + TY) <= NT - 64;
+}
+
 // Launch bounds: NT threads, and for the 16 x 8 tile a register budget that fits four workgroups
 // (five waves per SIMD).
 template <class P, int TX, int TY, int NT, bool NORM_MAX>
@@ -205,11 +214,14 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
     __shared__ R sXL[4][NFX], sXR[4][NFX];  // x-face states (then fluxes in sXL)
     __shared__ R sYL[4][NFY], sYU[4][NFY];  // y-face states (then fluxes in sYL)
 
-    // A stage-1 launch with ia.fin set puts 8 workgroups in front of the tiles (8 keeps each
-    // tile on the same XCD as in the other stages); the first finalizes the previous iteration,
-    // dispatched before any tile so that it does not trail the launch.
+    // The finalize of the previous iteration (stage-1 launches with ia.fin set): where the last
+    // wave has no work in phases 1 and 2 (512 threads), that wave of workgroup 0 runs it between
+    // the first two barriers; otherwise 8 workgroups go in front of the tiles (8 keeps each tile
+    // on the same XCD as in the other stages), the first of which runs it, dispatched before any
+    // tile so that it does not trail the launch.
+    constexpr bool kFinInBlock = fin_in_block<TX, TY, NT>();
     int bid = (int)blockIdx.x;
-    if (ia.fin) {
+    if (ia.fin && !kFinInBlock) {
         if (bid < 8) {
             if (bid == 0 && threadIdx.x < 64) finalize_wave(t, sc, threadIdx.x);
             return;
@@ -289,6 +301,9 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
     for (int q = 0; q < NFL; ++q)
         if (tid + q * NT < NR1) sF[tid + q * NT] = fl[q];
     __syncthreads();
+    if constexpr (kFinInBlock) {
+        if (ia.fin && bid == 0 && tid >= NT - 64) finalize_wave(t, sc, tid - (NT - 64));
+    }
 
     // ---- phase 2: reconstruction of the tile and ring cells --------------------------------
     // The tile cell of this thread keeps its stage-0 data for phase 4 (mixed form: also the
@@ -498,7 +513,7 @@ int launch_tile(const TankDev &t, const Scheme &sc, int stage, const IterArgs &i
 {
     const int tiles_x = (t.nx + TX - 1) / TX, tiles_y = (t.ny + TY - 1) / TY;
     const int n_tiles = tiles_x * tiles_y;
-    const int blocks = ((n_tiles + 7) / 8) * 8 + (ia.fin ? 8 : 0);
+    const int blocks = ((n_tiles + 7) / 8) * 8 + (ia.fin && !fin_in_block<TX, TY, NT>() ? 8 : 0);
     if (sc.norm_max)
         hipLaunchKernelGGL((stage_tile<P, TX, TY, NT, true>), dim3(blocks), dim3(NT), 0,
                            (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles, ia);
