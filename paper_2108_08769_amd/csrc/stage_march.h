@@ -365,7 +365,14 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     bool fluid_lo = false;
     double part0 = 0.0, part1 = 0.0, part2 = 0.0, part3 = 0.0, part4 = 0.0, part5 = INFINITY;
 
-    for (int r = j0 - 1; r <= j1; ++r) {
+    // One row step (row r's reconstruction, its faces, and the update of row r-1).  The window
+    // (primitives, FP64 pressures and, mixed form, level n of rows r-1, r, r+1) comes in by
+    // reference; the step writes row r+2 into the slots of row r-1, so that consecutive steps
+    // rotate the slots' roles instead of copying them.
+    auto row_step = [&](int r, Prim<R> &lo, Prim<R> &mid, Prim<R> &hi, double &plo, double &pmid,
+                        double &phi, Vec4<double> &lvl_lo, Vec4<double> &lvl_mid,
+                        Vec4<double> &lvl_hi) __attribute__((always_inline)) {
+        (void)lvl_hi;
         // sources of row r (loaded one step ahead), then the next loads
         const uint8_t f = src_ld.f;
         const bool fluid = !(f & FLAG_SOLID);
@@ -601,15 +608,38 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
             }
         }
         fluid_lo = fluid;
+        lo = next_hi;
+        plo = next_phi;
+        if constexpr (P::kMixed) lvl_lo = next_lvl;
+    };
+
+    // rows j0-1 .. j1.  Mixed form (bound by its arithmetic): three steps per trip with the
+    // slots' roles rotated, then the last 0..2 rows.  FP64 (bound by memory; the larger loop
+    // body measured slower): one step per trip.  A single step moves the roles back into place.
+    Vec4<double> lvl_lo = zero4<double>();
+    int r = j0 - 1;
+    if constexpr (P::kMixed) {
+        for (; r + 2 <= j1; r += 3) {
+            row_step(r, lo, mid, hi, plo, pmid, phi, lvl_lo, lvl_mid, lvl_hi);
+            row_step(r + 1, mid, hi, lo, pmid, phi, plo, lvl_mid, lvl_hi, lvl_lo);
+            row_step(r + 2, hi, lo, mid, phi, plo, pmid, lvl_hi, lvl_lo, lvl_mid);
+        }
+    }
+    for (; r <= j1; ++r) {
+        row_step(r, lo, mid, hi, plo, pmid, phi, lvl_lo, lvl_mid, lvl_hi);
+        const Prim<R> w = lo;
         lo = mid;
         mid = hi;
-        hi = next_hi;
+        hi = w;
+        const double pw = plo;
         plo = pmid;
         pmid = phi;
-        phi = next_phi;
+        phi = pw;
         if constexpr (P::kMixed) {
+            const Vec4<double> lw = lvl_lo;
+            lvl_lo = lvl_mid;
             lvl_mid = lvl_hi;
-            lvl_hi = next_lvl;
+            lvl_hi = lw;
         }
     }
 
