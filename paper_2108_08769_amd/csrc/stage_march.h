@@ -423,8 +423,10 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         const Prim<R> next_hi = to_prim(in_ld);
         const double next_phi = abs_p(in_ld);
         const Vec4<double> next_lvl = {in_ld.lr, in_ld.lm, in_ld.ln, 0.0};
-        in_ld = load_input<P>(t, qprev, gi, r + 3);
-        src_ld = load_sources<P, BDF>(t, q0, have_col, gi, r + 1);
+        // the chunk reconstructs rows up to j1 from inputs up to row j1 + 1: past those rows the
+        // loads repeat the last needed row (a cache hit), with no branch around them
+        in_ld = load_input<P>(t, qprev, gi, min(r + 3, j1 + 1));
+        src_ld = load_sources<P, BDF>(t, q0, have_col, gi, min(r + 1, j1));
 
         // ---- reconstruction of row r ------------------------------------------------------
         const Prim<R> wl = prim_from_left(mid);
