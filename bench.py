@@ -22,7 +22,9 @@ in a measurement pass of K further steps right after the timed region (kernels l
 one, an event pair around each pseudo-iteration's s_max stage launches, so it includes the
 dispatch gaps between them).  traffic is the copy-calibrated FETCH_SIZE + WRITE_SIZE bytes per
 launch from the committed counter summaries in profiles/, reported only while the kernel
-sources still hash to what was profiled.  cpu_baseline times the serial FP64 oracle on a bounded
+sources still hash to what was profiled.  stream_reference sets the achieved rate beside the
+best rate of a plain plane-stream kernel of the library on the same device (the FP64 stage's
+11 planes in, 4 out, and a copy).  cpu_baseline times the serial FP64 oracle on a bounded
 sample of the same workload, cpu_baseline_all_cores the same source built with -fopenmp on all
 the host's threads.  An FP64 line also reports mixed_form: the mixed-precision form on the
 same workload and steps, timed the same way after the FP64 measurement, with its speedup
@@ -213,6 +215,35 @@ def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
             "roofline": roofline}
 
 
+def stream_reference(vdac, torch, n=16 << 20, reps=5):
+    """Best rate, GB/s read + write, of the library's plane-stream kernel over three launch
+    shapes: 11 FP64 planes of n cells read and 4 written (the FP64 stage's mix), and a plain
+    copy of 4n doubles; 1.9 GB and 1 GB touched, well beyond the 256 MB last-level cache."""
+    inp = torch.zeros(11 * n, dtype=torch.float64, device="cuda")
+    out = torch.empty(4 * n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for n_in, n_out, cells, name in [(11, 4, n, "gbps"), (1, 1, 4 * n, "copy_gbps")]:
+        best = 0.0
+        for blocks in (0, 1024, 4096):
+            launch = lambda: vdac.stream_probe(n_in, n_out, cells, blocks, inp.data_ptr(),
+                                               out.data_ptr(), stream.cuda_stream)
+            launch()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                launch()
+            e1.record(stream)
+            e1.synchronize()
+            sec = e0.elapsed_time(e1) / 1e3 / reps
+            best = max(best, (n_in + n_out) * 8.0 * cells / sec / 1e9)
+        res[name] = round(best, 1)
+    del inp, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,6 +341,13 @@ def main():
                    "pgrad": args.pgrad, "local_dtau": bool(wk.local_dtau), "bdf": wk.bdf},
         "roofline": roofline,
     }
+    if roofline is not None:
+        ref = stream_reference(vdac, torch)
+        roofline["stream_reference"] = {
+            "kernel": "plane stream: 11 FP64 planes read, 4 written, one cell per lane "
+                      "(include/vdac_probe.h)",
+            "gbps": ref["gbps"], "copy_gbps": ref["copy_gbps"],
+            "frac": round(roofline["achieved"] / ref["gbps"], 4)}
     # the mixed form on the same workload, after the FP64 line's measurement (reported beside
     # it: the headline metric compares the two forms)
     if wk.precision == "f64" and not args.no_mixed:

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libvdac.so")
 OBJDIR = os.path.join(PKG, "_build")
 
 SOURCES = ["kernels_f64.hip", "stage_tile.hip", "stage_march.hip", "stage_march_gen.hip",
-           "vdac_api.cpp"]
+           "stream_probe.hip", "vdac_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", INCLUDE, "-I", CSRC,

@@ -15,6 +15,7 @@
 
 #include "vdac.h"
 #include "vdac_internal.h"
+#include "vdac_probe.h"
 
 using namespace vdac;
 
@@ -1070,5 +1071,18 @@ void destroy_grid(vdac_grid *g)
 }
 
 const char *last_error(void) { return g_error.c_str(); }
+
+int vdac_stream_probe(int32_t n_in, int32_t n_out, uint64_t n, int32_t blocks, const double *in,
+                      double *out, void *hip_stream)
+{
+    const bool pair_ok = (n_in == 1 && (n_out == 0 || n_out == 1)) || (n_in == 11 && n_out == 4);
+    if (!pair_ok) return fail(VDAC_E_INVALID, "stream probe: unsupported planes (%d in, %d out)",
+                              n_in, n_out);
+    if (n == 0 || blocks < 0 || blocks > (1 << 24) || in == nullptr || out == nullptr)
+        return fail(VDAC_E_INVALID, "stream probe: bad size, block count or pointer");
+    const int rc = launch_stream_probe(n_in, n_out, (size_t)n, blocks, in, out, hip_stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "stream probe launch");
+    return VDAC_OK;
+}
 
 }  // extern "C"

@@ -173,6 +173,10 @@ int launch_realtime_dt(const TankDev &t, int mixed, double cfl_t, double *out, i
 // device memory and the mixed form's storage (cur = 0 after import).
 int launch_import_mixed(const TankDev &t, const double *q, void *stream);
 int launch_export_mixed(const TankDev &t, int cur, double *q, void *stream);
+// Plane-stream bandwidth reference (n_in, n_out) in {(1, 0), (1, 1), (11, 4)}; blocks = 0: one
+// element per lane.
+int launch_stream_probe(int n_in, int n_out, size_t n, int blocks, const double *in, double *out,
+                        void *stream);
 int march_strips(int nx);
 int direct_blocks(const TankDev &t);
 int tile_count(const TankDev &t, int tile_x, int tile_y);

@@ -110,6 +110,9 @@ def lib():
         L.destroy_grid.restype = None
         L.last_error.argtypes = []
         L.last_error.restype = ctypes.c_char_p
+        L.vdac_stream_probe.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                        ctypes.c_int32, vp, vp, vp]
+        L.vdac_stream_probe.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -117,6 +120,12 @@ def lib():
 def _check(rc: int):
     if rc != VDAC_OK:
         raise VdacError(rc, lib().last_error().decode())
+
+
+def stream_probe(n_in: int, n_out: int, n: int, blocks: int, in_ptr: int, out_ptr: int,
+                 stream: int = 0):
+    """One pass of the plane-stream bandwidth reference (include/vdac_probe.h) on `stream`."""
+    _check(lib().vdac_stream_probe(n_in, n_out, n, blocks, in_ptr, out_ptr, stream or None))
 
 
 def default_options() -> Options:

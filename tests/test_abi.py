@@ -12,26 +12,46 @@ from paper_2108_08769_amd import vdac
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    text = open(os.path.join(ROOT, "include", "vdac.h")).read()
+def declared_functions(header="vdac.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, re.M)
     return sorted(set(n for n in names if n not in ("sizeof",)))
 
 
+def all_headers():
+    return sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+
+
 def test_header_lists_the_boundary():
     assert set(vdac.EXPORTS) == set(declared_functions())
+    assert declared_functions("vdac_probe.h") == ["vdac_stream_probe"]
 
 
-def test_library_exports_every_declared_symbol():
+@pytest.mark.parametrize("header", all_headers())
+def test_library_exports_every_declared_symbol(header):
     lib = vdac.lib()
-    for name in declared_functions():
+    names = declared_functions(header)
+    assert names
+    for name in names:
         assert hasattr(lib, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", vdac.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
     exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
-    for name in declared_functions():
+    for name in names:
         assert name in exported, name
+
+
+@pytest.mark.parametrize("n_in,n_out,n,blocks,null", [(2, 1, 10, 0, False), (11, 3, 10, 0, False),
+                                                      (1, 1, 0, 0, False), (1, 1, 10, -1, False),
+                                                      (1, 1, 10, 0, True)])
+def test_stream_probe_rejects_bad_arguments(n_in, n_out, n, blocks, null):
+    """Argument checks run before any device call."""
+    buf = ctypes.create_string_buffer(64)
+    ptr = None if null else ctypes.addressof(buf)
+    with pytest.raises(vdac.VdacError) as e:
+        vdac.stream_probe(n_in, n_out, n, blocks, ptr or 0, ptr or 0)
+    assert e.value.code == vdac.VDAC_E_INVALID
 
 
 def test_default_options():
