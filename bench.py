@@ -22,9 +22,12 @@ in a measurement pass of K further steps right after the timed region (kernels l
 one, an event pair around each pseudo-iteration's s_max stage launches, so it includes the
 dispatch gaps between them).  traffic is the copy-calibrated FETCH_SIZE + WRITE_SIZE bytes per
 launch from the committed counter summaries in profiles/, reported only while the kernel
-sources still hash to what was profiled.  stream_reference sets the achieved rate beside the
-best rate of a plain plane-stream kernel of the library on the same device (the FP64 stage's
-11 planes in, 4 out, and a copy).  cpu_baseline times the serial FP64 oracle on a bounded
+sources still hash to what was profiled.  valu is, from the same summaries, the stage kernel's
+VALU instructions (SQ_INSTS_VALU x 64 lanes) per fluid cell-stage and their issue rate against
+the chip's 39.3 T lane-instructions/s.  regime says whether the grid's planes exceed the 256 MB
+last-level cache (below it, achieved is an effective rate, not HBM traffic).  stream_reference
+sets the achieved rate beside the best rate of a plain plane-stream kernel of the library on the
+same device (the FP64 stage's 11 planes in, 4 out, and a copy).  cpu_baseline times the serial FP64 oracle on a bounded
 sample of the same workload, cpu_baseline_all_cores the same source built with -fopenmp on all
 the host's threads.  An FP64 line also reports mixed_form: the mixed-precision form on the
 same workload and steps, timed the same way after the FP64 measurement, with its speedup
@@ -42,6 +45,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+LLC_BYTES = 256e6              # MI355X last-level (Infinity) cache
+# VALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64 instruction takes 4 cycles;
+# FP64 FMA issues at this rate, and so does unpacked FP32)
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+# bytes per cell of the grid's planes: three state buffers, level n, the flag byte (each further
+# BDF level adds 32)
+PLANE_BYTES = {"f64": 3 * 32 + 32 + 1, "mixed": 3 * 16 + 32 + 1}
 BYTES_PER_CELL_STAGE = {       # algorithmic bytes per fluid cell per stage, three-stage mean
     "f64": (88.0 + 120.0 + 120.0) / 3.0,      # Q^{s-1} 32 + Q^0 32 + level n 24 + out 32
     "mixed": (64.0 + 80.0 + 80.0) / 3.0,      # deviations 16 + 16, level n 32, out 16
@@ -60,21 +70,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload: str, precision: str, tile: str):
-    """HBM bytes per stage launch from the committed counter summaries (profiles/*.md, copy-
-    calibrated FETCH_SIZE + WRITE_SIZE), or None if no summary covers this workload, precision and
-    tile or the kernel sources changed since it was taken."""
+def profiled(kind: str, workload: str, precision: str, tile: str):
+    """A per-launch figure of the stage kernel from the committed counter summaries
+    (profiles/*.md): kind "traffic" gives HBM bytes (copy-calibrated FETCH_SIZE + WRITE_SIZE),
+    kind "valu" wave-level VALU instructions (SQ_INSTS_VALU).  None if no summary covers this
+    workload, precision and tile, or the kernel sources changed since it was taken."""
     import glob
     src = kernel_source_hash()
+    field = {"traffic": "bytes_per_launch", "valu": "insts_per_launch"}[kind]
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(f) as fh:
             for line in fh:
-                if not line.startswith("traffic:"):
+                if not line.startswith(kind + ":"):
                     continue
                 kv = dict(x.split("=", 1) for x in line.split()[1:])
                 if (kv.get("workload") == workload and kv.get("precision") == precision
                         and kv.get("tile") == tile and kv.get("source") == src):
-                    return float(kv["bytes_per_launch"])
+                    return float(kv[field])
     return None
 
 
@@ -202,13 +214,27 @@ def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
             avg_s = kms / 1e3 / launches
             bytes_per_launch = bpc * kcs / launches
             achieved = bytes_per_launch / avg_s / 1e9
-            traffic = profiled_traffic(wk.name, wk.precision, chosen)
+            traffic = profiled("traffic", wk.name, wk.precision, chosen)
+            valu = profiled("valu", wk.name, wk.precision, chosen)
+            cells = kcs / launches
+            grid_cells = sum(t.nx * t.ny for t in wk.tanks)
+            plane_bytes = grid_cells * (PLANE_BYTES[wk.precision] + 32 * (wk.bdf - 1))
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                         "traffic": None if traffic is None else round(traffic / 1e9, 6),
                         "traffic_unit": "GB per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)",
                         "kernel": "stage", "avg_launch_us": round(avg_s * 1e6, 3),
-                        "launches": launches, "bytes_per_launch": bytes_per_launch}
+                        "launches": launches, "bytes_per_launch": bytes_per_launch,
+                        "regime": ("HBM-resident" if plane_bytes > LLC_BYTES else
+                                   "cache-resident: the grid's planes (%.0f MB) fit the 256 MB "
+                                   "last-level cache, so achieved is an effective rate (algorithmic "
+                                   "bytes / launch time), not HBM traffic" % (plane_bytes / 1e6)),
+                        "valu": None if valu is None else {
+                            "insts_per_cell_stage": round(valu * 64 / cells, 1),
+                            "achieved": round(valu * 64 / avg_s / 1e12, 2),
+                            "peak": VALU_PEAK_T, "unit": "T lane-instructions/s",
+                            "frac": round(valu * 64 / avg_s / 1e12 / VALU_PEAK_T, 4),
+                            "source": "SQ_INSTS_VALU per launch (profiles/)"}}
     for g in grids:
         g.close()
     return {"value": cell_stages / elapsed, "elapsed": elapsed, "iters": iters, "chosen": chosen,
