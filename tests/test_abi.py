@@ -121,3 +121,20 @@ def test_null_handles_are_rejected():
     assert L.get_state(None, 0, q) == vdac.VDAC_E_INVALID
     assert L.residual_norm(None, 0, q) == vdac.VDAC_E_INVALID
     L.destroy_grid(None)
+
+
+@pytest.mark.parametrize("offset,short,code,needle", [(0, 1, vdac.VDAC_E_NOMEM, "smaller than"),
+                                                      (8, 0, vdac.VDAC_E_INVALID, "aligned")])
+def test_create_grid_checks_a_borrowed_workspace(offset, short, code, needle):
+    """A caller's workspace that is smaller than workspace_bytes, or not 256-byte aligned, is
+    rejected before any device call (the pointer is never dereferenced)."""
+    o = vdac.default_options()
+    t, _ = vdac.make_tank(40, 24, 2.0, 1.0)
+    need = vdac.workspace_bytes([t], o)
+    arr = (vdac.Tank * 1)(t)
+    h = ctypes.c_void_p()
+    fake = 0x10000000 + offset  # never touched
+    rc = vdac.lib().create_grid(arr, 1, ctypes.byref(o), ctypes.c_void_p(fake), need - short, None,
+                                ctypes.byref(h))
+    assert rc == code and needle in vdac.lib().last_error().decode()
+    assert not h.value

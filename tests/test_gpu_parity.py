@@ -11,7 +11,7 @@ import pytest
 
 from paper_2108_08769_amd import vdac
 from paper_2108_08769_amd import workloads as wl
-from parity import run_gpu, run_oracle, field_errors, field_scales
+from parity import run_gpu, run_oracle, field_errors, field_scales, gpu_options
 
 pytestmark = pytest.mark.gpu
 
@@ -191,6 +191,40 @@ def test_full_size_dam_break_512x256():
 
 def test_full_size_rayleigh_taylor_256x1024():
     check(wl.rayleigh_taylor(precision="f64"), steps=2, pseudo=3)
+
+
+def _run_grid(wk, steps, pseudo, tol=0.0, **grid_kw):
+    t = wk.tanks[0]
+    tank = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
+                 solid=t.solid)]
+    grid = vdac.Grid(tank, gpu_options(wk), **grid_kw)
+    try:
+        grid.set_state(0, t.q)
+        its = []
+        for _ in range(steps):
+            its.append(int(grid.step(wk.dt, pseudo, tol)[1][0]))
+        return grid.get_state(0), its, grid.residual_norm(0)
+    finally:
+        grid.close()
+
+
+def test_library_owned_workspace_and_side_stream():
+    """create_grid with no workspace (the library allocates and frees its own) and on a stream
+    other than the default one gives bit-identical states, iteration counts and norms to a grid
+    on a caller-owned workspace and the current stream."""
+    import torch
+    wk = small_dam(45, 27)
+    ref = _run_grid(wk, 2, 300, tol=1e-3)
+    own = _run_grid(wk, 2, 300, tol=1e-3, own_workspace=True)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        alt = _run_grid(wk, 2, 300, tol=1e-3, stream=side)
+    torch.cuda.synchronize()
+    for got in (own, alt):
+        np.testing.assert_array_equal(got[0], ref[0])
+        assert got[1] == ref[1]
+        np.testing.assert_array_equal(got[2], ref[2])
+    print(f"[parity] workspace/stream variants: iterations {ref[1]}", flush=True)
 
 
 def test_deterministic_repeat():
