@@ -18,7 +18,8 @@ extern "C" {
  * without waiting.  For every i < n the kernel reads in[k * n + i] for k < n_in, and writes their
  * sum to out[k * n + i] for k < n_out (n_out = 0: reads only).  Supported (n_in, n_out): (1, 0) read only, (1, 1) copy, (11, 4) the
  * FP64 stage's plane mix (Q^{s-1}, Q^0 and three planes of level n in, Q^s out).  `blocks`
- * 256-thread workgroups stride over i (blocks = 0: one element per lane).
+ * 256-thread workgroups stride over i (blocks = 0: one element per lane, up to 2^24
+ * workgroups).
  *
  * in, out: device pointers to n_in * n and max(n_out, 1) * n doubles, caller-owned (with
  * n_out = 0, out[i] is written only where the sum is NaN).  Returns 0, 1 (VDAC_E_INVALID: an

@@ -37,8 +37,9 @@ int launch_stream_probe(int n_in, int n_out, size_t n, int blocks, const double 
                         void *stream_)
 {
     const hipStream_t stream = (hipStream_t)stream_;
-    const size_t lanes = (n + 255) / 256;
-    const unsigned grid = blocks > 0 ? (unsigned)blocks : (unsigned)lanes;
+    // one element per lane unless that needs more than 2^24 workgroups (the loop strides on)
+    const size_t wgs = (n + 255) / 256;
+    const unsigned grid = blocks > 0 ? (unsigned)blocks : (unsigned)(wgs < (1u << 24) ? wgs : (1u << 24));
     if (n_in == 1 && n_out == 0)
         hipLaunchKernelGGL((stream_planes<1, 0>), dim3(grid), dim3(256), 0, stream, in, out, n);
     else if (n_in == 1 && n_out == 1)
