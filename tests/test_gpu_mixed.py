@@ -138,6 +138,18 @@ def test_mixed_ragged_dam_vs_oracle():
     check_mixed(small_dam(37, 23), steps=3, pseudo=20, ref="oracle")
 
 
+@pytest.mark.parametrize("tile", [(0, 0), (3208, 2), (1608, 2)], ids=["march", "tile32x8", "tile16x8"])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 7), (7, 1), (2, 2), (3, 3), (16, 16), (17, 15),
+                                   (33, 2)])
+def test_mixed_tiny_and_ragged_tanks(nx, ny, tile):
+    """Tanks narrower or shorter than the stencil, a tile or a strip, in the mixed form, against
+    the oracle (random states of unit scale)."""
+    q = wl.random_state(nx, ny, seed=nx * 100 + ny, rho_range=(1.0, 3.0), vel=0.2, p_scale=5.0)
+    wk = wl.Workload("tiny", [wl.Tank(nx, ny, 0.1 * nx, 0.13 * ny, q, gx=0.3, gy=-9.81, beta=300.0)],
+                     dt=1e-3, steps=1, max_pseudo=1)
+    check_mixed(wk, steps=2, pseudo=4, ref="oracle", tile=tile)
+
+
 @pytest.mark.parametrize("opt", ["bdf2", "slip", "superbee", "max_norm"])
 def test_mixed_options_vs_fp64(opt):
     wk = small_dam(96, 48)
