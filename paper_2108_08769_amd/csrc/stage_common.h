@@ -96,6 +96,23 @@ __device__ __forceinline__ double local_dtau(const TankDev &t, double cfl, doubl
     return cfl * (t.dx * t.dy) * rcp_pos(lx + ly);
 }
 
+// The same step in FP32 with the hardware reciprocal and reciprocal-square-root estimates, for
+// the mixed form: the step only scales the pseudo-time update (the converged state does not
+// depend on it), so it needs no more precision than the fluxes it multiplies.
+__device__ __forceinline__ double local_dtau_f32(const TankDev &t, double cfl, double rho, double m,
+                                                 double n)
+{
+    const float ir = rcp_pos((float)rho);
+    const float u = (float)m * ir, v = (float)n * ir;
+    const float fb = 4.0f * (float)t.beta * ir;
+    const float cx2 = fmaf(u, u, fb), cy2 = fmaf(v, v, fb);
+    const float cx = cx2 * rsqrt_pos(cx2);
+    const float cy = cy2 * rsqrt_pos(cy2);
+    const float lx = 0.5f * (fabsf(u) + cx) * (float)t.dy;
+    const float ly = 0.5f * (fabsf(v) + cy) * (float)t.dx;
+    return (double)((float)(cfl * (t.dx * t.dy)) * rcp_pos(lx + ly));
+}
+
 template <bool NORM_MAX>
 __device__ __forceinline__ double combine(double a, double b)
 {

@@ -589,7 +589,9 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
             below = {syt.r, syt.u, syt.v, syt.p};
         }
         if (fluid && r >= j0 && r < j1) {
-            const double dtau = use_glob ? dtau_glob : local_dtau(t, t.cfl, a0, a1, a2);
+            const double dtau = use_glob ? dtau_glob
+                                : (P::kMixed ? local_dtau_f32(t, t.cfl, a0, a1, a2)
+                                             : local_dtau(t, t.cfl, a0, a1, a2));
             const double ad = alpha * dtau;
             const double fc = ad * rcp_pos(fma(sp.b0 * ad, sp.inv_dt, 1.0));
             if (LAST) {

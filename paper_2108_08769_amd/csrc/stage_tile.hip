@@ -470,7 +470,8 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
             R4[0] += -own_d[0];
             R4[1] += -own_d[1] + r0 * t.gx;
             R4[2] += -own_d[2] + r0 * t.gy;
-            const double dtau = local_dtau(t, t.cfl, r0, own_a[1], own_a[2]);
+            const double dtau = P::kMixed ? local_dtau_f32(t, t.cfl, r0, own_a[1], own_a[2])
+                                          : local_dtau(t, t.cfl, r0, own_a[1], own_a[2]);
             const double ad = alpha * dtau;
             const double api = 1.0 + sp.b0 * ad * sp.inv_dt;
             const double fac = ad * rcp_pos(api);
