@@ -16,8 +16,9 @@ extern "C" {
 
 /* Launches one pass of the plane stream on `hip_stream` (NULL: the default stream) and returns
  * without waiting.  For every i < n the kernel reads in[k * n + i] for k < n_in, and writes their
- * sum to out[k * n + i] for k < n_out (n_out = 0: reads only).  Supported (n_in, n_out): (1, 0) read only, (1, 1) copy, (11, 4) the
- * FP64 stage's plane mix (Q^{s-1}, Q^0 and three planes of level n in, Q^s out).  `blocks`
+ * sum to out[k * n + i] for k < n_out (n_out = 0: reads only).  Supported (n_in, n_out):
+ * (1, 0) read only, (1, 1) copy, (11, 4) the FP64 stage's plane mix (Q^{s-1}, Q^0 and three
+ * planes of level n in, Q^s out).  `blocks`
  * 256-thread workgroups stride over i (blocks = 0: one element per lane, up to 2^24
  * workgroups).
  *
