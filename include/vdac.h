@@ -57,6 +57,10 @@ enum { VDAC_FLUX_OSHER = 0, VDAC_FLUX_ROE = 1, VDAC_FLUX_BASSI = 2 };
  * limiting, restored after). */
 enum { VDAC_PGRAD_NEW = 0, VDAC_PGRAD_LIMITER = 1, VDAC_PGRAD_SPLIT = 2 };
 
+/* Precision of the stage: FP64 throughout, or mixed (the state stored as FP32 deviations from an
+ * FP64 level n; reconstruction, Riemann fluxes and the local pseudo-time step in FP32; sources,
+ * flux divergence, update and residual norm in FP64).  The state crosses the boundary in FP64
+ * either way. */
 enum { VDAC_FP64 = 0, VDAC_FP32_MIXED = 1 };
 enum { VDAC_NORM_RMS = 0, VDAC_NORM_MAX = 1 };
 
