@@ -301,6 +301,46 @@ def test_divergence_is_reported():
     assert iters[0, 0] < 50
 
 
+def wild_tank():
+    """A tank whose density goes negative (finite) in its third pseudo-iteration at the standard
+    pseudo-time Courant number (the oracle finds the same)."""
+    q = wl.random_state(12, 10, seed=6, rho_range=(0.01, 10.0), vel=2.0, p_scale=5.0)
+    return wl.Tank(12, 10, 1.2, 1.0, q, gy=-9.81, beta=300.0)
+
+
+@pytest.mark.parametrize("precision,tile", [("f64", (0, 0)), ("f64", (3208, 2)), ("f64", (1, 1)),
+                                            ("mixed", (0, 0)), ("mixed", (3208, 2))],
+                         ids=["f64-march", "f64-tile", "f64-plain", "mixed-march", "mixed-tile"])
+def test_divergence_stops_only_the_failing_tank(precision, tile):
+    """A tank whose density goes negative stops at the iteration the oracle stops at, with the
+    oracle's state after that iteration (FP64), and the step reports VDAC_E_DIVERGED.  On the
+    row-marching kernel it shares the launch with a healthy tank, which runs all its iterations
+    and ends bit for bit as it does alone."""
+    wild = wild_tank()
+    calm = small_dam(24, 12).tanks[0]
+    batch = tile == (0, 0)
+    tanks = [calm, wild] if batch else [wild]
+    wk = wl.Workload("diverging", tanks, dt=1e-3, steps=1, max_pseudo=1)
+    states, iters, _, codes = run_gpu(wk, 1, 50, precision=precision, tile=tile)
+    assert codes == [vdac.VDAC_E_DIVERGED]
+    ref, it, _, orc = oracle.step(oracle_problem(wild, wk), wild.q, wk.dt, 50, 0.0, 0)
+    assert orc != 0 and it == 3
+    assert int(iters[0, -1]) == it
+    got = states[-1]
+    assert got[0].min() <= 0.0
+    if precision == "f64":
+        err = field_errors(got, ref, None, field_scales(wild))
+        assert np.all(err <= TOL), err
+    if batch:
+        assert int(iters[0, 0]) == 50
+        solo = run_gpu(wl.Workload("calm", [calm], dt=1e-3, steps=1, max_pseudo=1), 1, 50,
+                       precision=precision, tile=tile)
+        np.testing.assert_array_equal(states[0], solo[0][0])
+        assert solo[3] == [0]
+    print(f"[parity] divergence {precision} {tile}: stopped at iteration {int(iters[0, -1])}, "
+          f"min rho {got[0].min():.3e}", flush=True)
+
+
 def test_set_state_rejects_bad_density():
     grid = vdac.Grid([dict(nx=4, ny=4, lx=1.0, ly=1.0)])
     try:
