@@ -14,7 +14,9 @@ stays resident in HBM for the whole timed region; nothing crosses PCIe inside it
 per-step status read.
 
 value = fluid cells x stages executed / seconds over exactly K timed steps (kernels replayed
-from captured HIP graphs).  The roofline entry is the Runge-Kutta stage kernel: algorithmic
+from captured HIP graphs).  K defaults to the workload's own step count (500 for the dam
+break), and the timed steps start from the initial state (it is set again after the W warmup
+steps), so the timed region is the workload's whole run.  The roofline entry is the Runge-Kutta stage kernel: algorithmic
 bytes per launch (per fluid cell-stage 109.3 B for FP64, the mean of 88 B at stage 1 and 120 B
 at later stages of a three-stage scheme; 74.7 B for the mixed form, 64 and 80 B) divided by its
 mean launch duration.  That duration is measured live with HIP events on the library's stream,
@@ -185,6 +187,11 @@ def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
 
     for _ in range(args.warmup):
         step_all()
+    # back to the initial state (outside the timed region), so that the timed steps are the
+    # workload's own run from its start
+    for g, tl in zip(grids, [[t] for t in wk.tanks] if args.unbatched else [wk.tanks]):
+        for i, t in enumerate(tl):
+            g.set_state(i, t.q)
     torch.cuda.synchronize()
 
     # timed region: exactly K steps, kernels replayed from captured graphs, no instrumentation
@@ -276,7 +283,9 @@ def stream_reference(vdac, torch, n=16 << 20, reps=5):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=0,
+                    help="timed real steps (0: the workload's own step count, e.g. 500 for the "
+                         "dam break)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dam_break")
     ap.add_argument("--precision", default="f64")
@@ -332,6 +341,8 @@ def main():
         return
 
     wk = build_workload(args.workload, args.precision)
+    if args.steps <= 0:
+        args.steps = wk.steps
     if args.max_pseudo > 0:
         wk.max_pseudo = args.max_pseudo
     if args.bdf > 0:
