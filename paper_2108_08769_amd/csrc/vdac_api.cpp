@@ -60,7 +60,8 @@ struct Plan {
 };
 
 struct TankHost {
-    vdac_tank desc;
+    vdac_tank desc;               // as stored (see stored_tanks)
+    bool transposed;              // stored with x and y exchanged
     std::vector<uint8_t> flags;
     TankDev dev;
 };
@@ -274,6 +275,80 @@ bool has_open_side(const vdac_tank *t)
     for (int s = 0; s < 4; ++s)
         if (t->bc[s] == VDAC_BC_TRANSMISSIVE) return true;
     return false;
+}
+
+// Stored orientation.  In a batch (more than one tank) on the row-marching kernel, a tank is
+// stored with x and y exchanged when that leaves fewer lanes without a cell: a 64-lane strip
+// covers 60 columns, so a tank nx wide takes ceil(nx / 60) strips per row.  Batches of small
+// tanks are bound by VALU issue, where idle lanes cost time (a 512-tank ensemble of 32..256-cell
+// sides: 8% fewer lane-rows, 6% faster in the mixed form); a single large tank gained nothing
+// and lost 5-10% on the 256 x 1024 Rayleigh-Taylor tank, so single tanks keep the caller's
+// orientation, as do the tiled and per-cell kernels.  The scheme is the same under the exchange
+// (per-axis slopes and limiters, the flux rotated to each face, the pressure gradient's x and y
+// forms, the pseudo-time step), so the stored problem is the caller's tank reflected about its
+// diagonal: nx <-> ny, lx <-> ly, gx <-> gy, the x sides <-> the y sides, rho u <-> rho v.
+bool stored_transposed(const vdac_tank *t, int n_tanks, const vdac_options *o)
+{
+    if (o->tile_x > 0 || n_tanks < 2) return false;
+    return (long)march_strips(t->ny) * t->nx < (long)march_strips(t->nx) * t->ny;
+}
+
+struct StoredTanks {
+    std::vector<vdac_tank> t;
+    std::vector<std::vector<uint8_t>> solid;  // transposed solid masks
+    std::vector<char> transposed;
+};
+
+StoredTanks stored_tanks(const vdac_tank *tanks, int n_tanks, const vdac_options *o)
+{
+    StoredTanks S;
+    S.t.assign(tanks, tanks + n_tanks);
+    S.solid.resize(n_tanks);
+    S.transposed.assign(n_tanks, 0);
+    for (int k = 0; k < n_tanks; ++k) {
+        const vdac_tank &a = tanks[k];
+        if (!stored_transposed(&a, n_tanks, o)) continue;
+        vdac_tank &b = S.t[k];
+        b.nx = a.ny;
+        b.ny = a.nx;
+        b.lx = a.ly;
+        b.ly = a.lx;
+        b.gx = a.gy;
+        b.gy = a.gx;
+        b.bc[0] = a.bc[2];
+        b.bc[1] = a.bc[3];
+        b.bc[2] = a.bc[0];
+        b.bc[3] = a.bc[1];
+        if (a.solid) {
+            std::vector<uint8_t> &m = S.solid[k];
+            m.resize((size_t)a.nx * a.ny);
+            for (int j = 0; j < a.ny; ++j)
+                for (int i = 0; i < a.nx; ++i) m[(size_t)i * a.ny + j] = a.solid[(size_t)j * a.nx + i];
+            b.solid = m.data();
+        }
+        S.transposed[k] = 1;
+    }
+    return S;
+}
+
+// A state [4][ny][nx] in the caller's orientation to the stored one (forward) or back: each
+// plane transposed, rho u and rho v exchanged.
+void transpose_state(const double *in, double *out, int nx, int ny, bool forward)
+{
+    // forward: in is [ny][nx] (caller), out is [nx][ny]; backward: in is [nx][ny], out [ny][nx]
+    const size_t plane = (size_t)nx * ny;
+    static const int field_of[4] = {0, 2, 1, 3};
+    for (int k = 0; k < 4; ++k) {
+        const double *src = in + (size_t)field_of[k] * plane;
+        double *dst = out + (size_t)k * plane;
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                if (forward)
+                    dst[(size_t)i * ny + j] = src[(size_t)j * nx + i];
+                else
+                    dst[(size_t)j * nx + i] = src[(size_t)i * ny + j];
+            }
+    }
 }
 
 // Options a tank's sides restrict: zero-gradient sides run on the row-marching kernel, not with
@@ -523,9 +598,10 @@ size_t workspace_bytes(const vdac_tank *tanks, int32_t n_tanks, const vdac_optio
     if (!tanks || n_tanks < 1 || check_options(o) != VDAC_OK) return 0;
     for (int t = 0; t < n_tanks; ++t)
         if (check_tank(&tanks[t], t) != VDAC_OK) return 0;
-    const Plan p = plan_for(tanks, n_tanks, o);
+    const StoredTanks S = stored_tanks(tanks, n_tanks, o);
+    const Plan p = plan_for(S.t.data(), n_tanks, o);
     size_t total = 0;
-    for (int t = 0; t < n_tanks; ++t) total += layout_of(&tanks[t], o, p.n_partials[t]).end;
+    for (int t = 0; t < n_tanks; ++t) total += layout_of(&S.t[t], o, p.n_partials[t]).end;
     return total + grid_block(n_tanks, p, o).end;
 }
 
@@ -548,11 +624,14 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         if ((rc = check_tank_options(&tanks[t], t, o)) != VDAC_OK) return rc;
     }
     const size_t need = workspace_bytes(tanks, n_tanks, o);
+    // the tanks as stored (some transposed; see stored_tanks)
+    const StoredTanks S = stored_tanks(tanks, n_tanks, o);
+    const vdac_tank *st = S.t.data();
 
     vdac_grid *g = new (std::nothrow) vdac_grid();
     if (!g) return fail(VDAC_E_NOMEM, "host allocation failed");
     g->opt = *o;
-    g->plan = plan_for(tanks, n_tanks, o);
+    g->plan = plan_for(st, n_tanks, o);
     g->stream = (hipStream_t)hip_stream;
     g->cap_stream = nullptr;
     if (device_workspace) {
@@ -593,7 +672,7 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
     sc.global_dtau = o->local_dtau == 0;
     sc.general = sc.flux != VDAC_FLUX_OSHER || sc.pgrad != VDAC_PGRAD_NEW || sc.global_dtau;
     for (int t = 0; t < n_tanks; ++t)
-        if (has_open_side(&tanks[t])) sc.general = 1;
+        if (has_open_side(&st[t])) sc.general = 1;
 
     const Plan &pl = g->plan;
     g->tanks.resize(n_tanks);
@@ -604,7 +683,7 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
     g->t_launches = 0;
     g->t_cell_stages = 0.0;
     size_t base = 0;
-    for (int t = 0; t < n_tanks; ++t) base += layout_of(&tanks[t], o, pl.n_partials[t]).end;
+    for (int t = 0; t < n_tanks; ++t) base += layout_of(&st[t], o, pl.n_partials[t]).end;
     const GridBlock B = grid_block(n_tanks, pl, o);
     g->status_dev = (Status *)(g->ws + base + B.status);
     g->step_dev = (StepParams *)(g->ws + base + B.step);
@@ -615,27 +694,28 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
     std::vector<TankDev> devs(n_tanks);
     for (int t = 0; t < n_tanks; ++t) {
         TankHost &th = g->tanks[t];
-        th.desc = tanks[t];
+        th.desc = st[t];
         th.desc.solid = nullptr;
+        th.transposed = S.transposed[t] != 0;
         int n_fluid = 0;
-        build_flags(&tanks[t], th.flags, &n_fluid);
-        const TankLayout L = layout_of(&tanks[t], o, pl.n_partials[t]);
+        build_flags(&st[t], th.flags, &n_fluid);
+        const TankLayout L = layout_of(&st[t], o, pl.n_partials[t]);
         TankDev &d = th.dev;
         std::memset(&d, 0, sizeof d);
-        d.nx = tanks[t].nx;
-        d.ny = tanks[t].ny;
-        d.per_x = tanks[t].bc[0] == VDAC_BC_PERIODIC;
-        d.per_y = tanks[t].bc[2] == VDAC_BC_PERIODIC;
-        d.dx = tanks[t].lx / tanks[t].nx;
-        d.dy = tanks[t].ly / tanks[t].ny;
+        d.nx = st[t].nx;
+        d.ny = st[t].ny;
+        d.per_x = st[t].bc[0] == VDAC_BC_PERIODIC;
+        d.per_y = st[t].bc[2] == VDAC_BC_PERIODIC;
+        d.dx = st[t].lx / st[t].nx;
+        d.dy = st[t].ly / st[t].ny;
         d.inv_dx = 1.0 / d.dx;
         d.inv_dy = 1.0 / d.dy;
         d.half_dx = 0.5 * d.dx;
         d.half_dy = 0.5 * d.dy;
-        d.gx = tanks[t].gx;
-        d.gy = tanks[t].gy;
-        d.beta = tanks[t].beta;
-        d.inv_beta = 1.0 / tanks[t].beta;
+        d.gx = st[t].gx;
+        d.gy = st[t].gy;
+        d.beta = st[t].beta;
+        d.inv_beta = 1.0 / st[t].beta;
         d.cfl = o->cfl_tau;
         d.plane = (size_t)d.nx * d.ny;
         for (int b = 0; b < 3; ++b) d.state[b] = (void *)(g->ws + base + L.state[b]);
@@ -652,7 +732,7 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         d.chunk = pl.chunk[t] > 0 ? pl.chunk[t] : 1;
         d.open = 0;
         for (int side = 0; side < 4; ++side)
-            if (tanks[t].bc[side] == VDAC_BC_TRANSMISSIVE) d.open |= 1 << side;
+            if (st[t].bc[side] == VDAC_BC_TRANSMISSIVE) d.open |= 1 << side;
         devs[t] = d;
         base += L.end;
     }
@@ -660,7 +740,7 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
                                   hipMemcpyHostToDevice, g->stream);
     std::vector<MarchUnit> tab;
     if (e == hipSuccess && pl.kind == KIND_MARCH) {
-        tab = unit_table(pl, tanks, n_tanks);
+        tab = unit_table(pl, st, n_tanks);
         e = hipMemcpyAsync(g->units_dev, tab.data(), tab.size() * sizeof(MarchUnit),
                            hipMemcpyHostToDevice, g->stream);
     }
@@ -708,6 +788,12 @@ int set_state(vdac_grid *g, int32_t tank, const double *q)
     if (tank < 0 || tank >= (int)g->tanks.size()) return fail(VDAC_E_INVALID, "no tank %d", tank);
     TankHost &th = g->tanks[tank];
     const TankDev &d = th.dev;
+    std::vector<double> stored;  // the state in the stored orientation
+    if (th.transposed) {
+        stored.resize(4 * d.plane);
+        transpose_state(q, stored.data(), d.ny, d.nx, true);
+        q = stored.data();
+    }
     for (size_t c = 0; c < d.plane; ++c) {
         if (th.flags[c] & FLAG_SOLID) continue;
         if (!(q[c] > 0.0) || !std::isfinite(q[c]))
@@ -942,6 +1028,7 @@ int residual_norm(const vdac_grid *g, int32_t tank, double out[4])
     int rc = read_status(g, tank, &st);
     if (rc != VDAC_OK) return rc;
     for (int k = 0; k < 4; ++k) out[k] = st.norms[k];
+    if (g->tanks[tank].transposed) std::swap(out[1], out[2]);  // rho u, rho v of the stored tank
     return VDAC_OK;
 }
 
@@ -953,18 +1040,26 @@ int get_state(const vdac_grid *g, int32_t tank, double *q)
     Status st;
     int rc = read_status(g, tank, &st);
     if (rc != VDAC_OK) return rc;
-    const TankDev &d = g->tanks[tank].dev;
+    const TankHost &th = g->tanks[tank];
+    const TankDev &d = th.dev;
+    std::vector<double> stored;  // the stored orientation, transposed back below
+    double *dst = q;
+    if (th.transposed) {
+        stored.resize(4 * d.plane);
+        dst = stored.data();
+    }
     hipError_t e;
     if (g->sc.mixed) {
         e = (hipError_t)launch_export_mixed(d, st.cur, g->staging, g->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(q, g->staging, 4 * d.plane * sizeof(double), hipMemcpyDeviceToHost, g->stream);
+            e = hipMemcpyAsync(dst, g->staging, 4 * d.plane * sizeof(double), hipMemcpyDeviceToHost, g->stream);
     } else {
-        e = hipMemcpyAsync(q, d.state[st.cur], 4 * d.plane * sizeof(double), hipMemcpyDeviceToHost,
+        e = hipMemcpyAsync(dst, d.state[st.cur], 4 * d.plane * sizeof(double), hipMemcpyDeviceToHost,
                            g->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "get_state");
+    if (th.transposed) transpose_state(dst, q, d.ny, d.nx, false);
     return VDAC_OK;
 }
 

@@ -93,3 +93,25 @@ def field_errors(a: np.ndarray, b: np.ndarray, solid=None, scales=None) -> np.nd
             s = max(s, scales[k])
         out[k] = d / s if s > 0 else d
     return out
+
+
+def strips(w):
+    return -(-w // 60)  # 64-lane strips of 60 columns
+
+
+def stored_transposed_in_batch(t):
+    """The library's rule: in a batch, a tank is stored with x and y exchanged when that needs
+    fewer strip-rows."""
+    return strips(t.ny) * t.nx < strips(t.nx) * t.ny
+
+
+def reflect(t):
+    """The tank reflected about its diagonal (x <-> y, rho u <-> rho v)."""
+    q = np.ascontiguousarray(t.q[[0, 2, 1, 3]].transpose(0, 2, 1))
+    solid = None if t.solid is None else np.ascontiguousarray(t.solid.T)
+    bc = (t.bc[2], t.bc[3], t.bc[0], t.bc[1])
+    return wl.Tank(t.ny, t.nx, t.ly, t.lx, q, gx=t.gy, gy=t.gx, beta=t.beta, bc=bc, solid=solid)
+
+
+def unreflect_state(q):
+    return np.ascontiguousarray(q[[0, 2, 1, 3]].transpose(0, 2, 1))

@@ -19,7 +19,8 @@ import pytest
 
 from paper_2108_08769_amd import vdac
 from paper_2108_08769_amd import workloads as wl
-from parity import run_gpu, run_oracle, field_errors, field_scales, gpu_options
+from parity import (run_gpu, run_oracle, field_errors, field_scales, gpu_options, reflect,
+                    stored_transposed_in_batch, unreflect_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -148,6 +149,14 @@ def test_mixed_tiny_and_ragged_tanks(nx, ny, tile):
     wk = wl.Workload("tiny", [wl.Tank(nx, ny, 0.1 * nx, 0.13 * ny, q, gx=0.3, gy=-9.81, beta=300.0)],
                      dt=1e-3, steps=1, max_pseudo=1)
     check_mixed(wk, steps=2, pseudo=4, ref="oracle", tile=tile)
+
+
+@pytest.mark.parametrize("case", ["walls", "periodic_x", "obstacle"])
+def test_mixed_transposed_storage_vs_oracle(case):
+    """Tall tanks that the row-marching kernel stores with x and y exchanged, mixed form, against
+    the oracle in the caller's orientation."""
+    from test_gpu_parity import tall_tank
+    check_mixed(tall_tank(case, "mixed"), steps=2, pseudo=12, ref="oracle")
 
 
 @pytest.mark.parametrize("opt", ["bdf2", "slip", "superbee", "max_norm"])
@@ -346,17 +355,28 @@ def ensemble_subset(n, precision="f64", seed=4):
 
 def test_batched_equals_single_tank_grids():
     """Every tank of a 24-tank grid comes out bit for bit as in a grid of its own (same row chunk,
-    so that the residual partials, and with them the norms, are summed alike)."""
+    so that the residual partials, and with them the norms, are summed alike).  A batch stores
+    some tanks with x and y exchanged; such a tank is compared with a grid of its own holding the
+    reflected tank (which a single grid stores as given), reflected back, so the test also shows
+    that the library's reflection is exact."""
     wk = ensemble_subset(24)
     print(f"[batched] sizes {[(t.nx, t.ny) for t in wk.tanks]}", flush=True)
     b_states, b_it, b_norms, _ = run_gpu(wk, steps=2, max_pseudo=6, precision="f64", tile=(-2, 8))
+    n_tr = 0
     for i, t in enumerate(wk.tanks):
-        one = wl.Workload("one", [t], dt=wk.dt, steps=1, max_pseudo=1, stages=wk.stages,
-                          alpha=wk.alpha, cfl=wk.cfl, k=wk.k, bdf=wk.bdf)
+        tr = stored_transposed_in_batch(t)
+        n_tr += tr
+        one = wl.Workload("one", [reflect(t) if tr else t], dt=wk.dt, steps=1, max_pseudo=1,
+                          stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl, k=wk.k, bdf=wk.bdf)
         s_states, s_it, s_norms, _ = run_gpu(one, steps=2, max_pseudo=6, precision="f64",
                                              tile=(-2, 8))
-        np.testing.assert_array_equal(b_states[i], s_states[0], err_msg=f"tank {i}")
-        np.testing.assert_array_equal(b_norms[i], s_norms[0])
+        got, norms = s_states[0], s_norms[0]
+        if tr:
+            got, norms = unreflect_state(got), norms[[0, 2, 1, 3]]
+        np.testing.assert_array_equal(b_states[i], got, err_msg=f"tank {i} (transposed {tr})")
+        np.testing.assert_array_equal(b_norms[i], norms)
+    assert 0 < n_tr < len(wk.tanks)
+    print(f"[batched] {n_tr} of {len(wk.tanks)} tanks stored transposed", flush=True)
 
 
 def test_batched_vs_oracle():

@@ -16,7 +16,8 @@ import pytest
 
 from paper_2108_08769_amd import vdac
 from paper_2108_08769_amd import workloads as wl
-from parity import run_gpu, run_oracle, field_errors, field_scales
+from parity import (run_gpu, run_oracle, field_errors, field_scales, reflect,
+                    stored_transposed_in_batch, unreflect_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -231,6 +232,10 @@ def test_general_kernel_batch_equals_single_tanks():
     wk = wl.Workload("mixed_sides", tanks, dt=1e-3, steps=1, max_pseudo=1)
     batch = run_gpu(wk, 2, 8, flux=ROE, pgrad=LIMITER, tile=(-2, 8))
     for i, t in enumerate(tanks):
-        one = wl.Workload("one", [t], dt=1e-3, steps=1, max_pseudo=1)
+        # the batch stores the 29 x 31 tank with x and y exchanged: compare with its reflection
+        tr = stored_transposed_in_batch(t)
+        one = wl.Workload("one", [reflect(t) if tr else t], dt=1e-3, steps=1, max_pseudo=1)
         single = run_gpu(one, 2, 8, flux=ROE, pgrad=LIMITER, tile=(-2, 8))
-        np.testing.assert_array_equal(batch[0][i], single[0][0], err_msg=f"tank {i}")
+        got = unreflect_state(single[0][0]) if tr else single[0][0]
+        np.testing.assert_array_equal(batch[0][i], got, err_msg=f"tank {i} (transposed {tr})")
+    assert [stored_transposed_in_batch(t) for t in tanks] == [False, False, True]

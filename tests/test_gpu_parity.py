@@ -262,6 +262,55 @@ def test_fp64_error_against_step(case):
     print(f"[parity] {case}: worst over 20 steps {worst:.3e}", flush=True)
 
 
+def tall_tank(case, precision="f64"):
+    """A 20 x 90 tank with a small companion tank in one batch: the row-marching kernel stores
+    the tall tank transposed (2 strips of 20 rows instead of 1 strip of 90 rows; batches only),
+    so every case runs the reflected problem and is compared in the caller's orientation.  The
+    6 x 5 companion keeps its orientation."""
+    nx, ny, lx, ly = 20, 90, 0.5, 2.25
+    xc = (np.arange(nx) + 0.5) * lx / nx
+    yc = (np.arange(ny) + 0.5) * ly / ny
+    q = np.zeros((4, ny, nx))
+    q[0] = np.where((xc[None, :] < 0.2) & (yc[:, None] < 1.0), 1000.0, 1.0)
+    rng = np.random.default_rng(42)
+    q[1] = rng.uniform(-0.05, 0.05, (ny, nx)) * q[0]
+    q[2] = rng.uniform(-0.02, 0.02, (ny, nx)) * q[0]
+    kw = dict(gx=0.7, gy=-9.81, beta=1100.0)
+    if case == "periodic_x":
+        kw["bc"] = (vdac.BC_PERIODIC, vdac.BC_PERIODIC, vdac.BC_WALL, vdac.BC_WALL)
+    elif case == "open_top":
+        kw["bc"] = (vdac.BC_WALL, vdac.BC_WALL, vdac.BC_WALL, vdac.BC_TRANSMISSIVE)
+    elif case == "obstacle":
+        solid = np.zeros((ny, nx), np.uint8)
+        solid[10:14, 12:17] = 1  # off the diagonal: a wrong transposition moves it
+        kw["solid"] = solid
+    t = wl.Tank(nx, ny, lx, ly, q, **kw)
+    qc = wl.random_state(6, 5, seed=3, rho_range=(1.0, 3.0), vel=0.2, p_scale=5.0)
+    companion = wl.Tank(6, 5, 0.3, 0.25, qc, gx=0.7, gy=-9.81, beta=300.0)
+    wk = wl.Workload(f"tall_{case}", [t, companion], dt=1e-3, steps=1, max_pseudo=1,
+                     precision=precision)
+    if case == "bdf2":
+        wk.bdf = 2
+    return wk
+
+
+@pytest.mark.parametrize("case", ["walls", "periodic_x", "open_top", "obstacle", "bdf2"])
+def test_transposed_storage_matches_oracle(case):
+    """Tanks stored with x and y exchanged give the oracle's states, iteration counts and norms
+    (rho u and rho v in the caller's order) in the caller's orientation."""
+    check(tall_tank(case), steps=3, pseudo=12)
+
+
+def test_transposed_storage_tolerance_and_batch():
+    """A tolerance-stopped step and a batch that mixes stored orientations (the tall tank with a
+    wide one) against the oracle."""
+    wk = tall_tank("walls")
+    check(wk, steps=2, pseudo=3000, tol=5.0)
+    wide = small_dam(70, 21).tanks[0]  # a batch with the tall tank alone besides it
+    both = wl.Workload("mixed_orientations", [wk.tanks[0], wide], dt=1e-3, steps=1, max_pseudo=1)
+    check(both, steps=2, pseudo=10)
+
+
 def test_deterministic_repeat():
     wk = small_dam(64, 32)
     a = run_gpu(wk, 2, 10)
