@@ -118,7 +118,11 @@ size_t workspace_bytes(const vdac_tank *tanks, int32_t n_tanks, const vdac_optio
  * not NULL, is a device buffer of at least ws_bytes >= workspace_bytes(...) bytes that the
  * library borrows until destroy_grid (the caller keeps it alive); if NULL the library allocates
  * and frees its own.  hip_stream is a hipStream_t (NULL = the null stream).  The initial state
- * of every tank is rho = 1, zero velocity and pressure until set_state is called. */
+ * of every tank is rho = 1, zero velocity and pressure until set_state is called.
+ * In a grid of more than one tank on the row-marching kernel, the library may store a tank
+ * reflected about its diagonal (x and y exchanged) when that leaves fewer SIMD lanes idle; the
+ * scheme is the same under the reflection, and every call of this interface (set_state,
+ * get_state, residual_norm, realtime_dt) takes and returns the caller's orientation. */
 int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
                 void *device_workspace, size_t ws_bytes, void *hip_stream, vdac_grid **out);
 
