@@ -311,6 +311,34 @@ def test_transposed_storage_tolerance_and_batch():
     check(both, steps=2, pseudo=10)
 
 
+def test_transposed_storage_realtime_dt_and_norms():
+    """realtime_dt and residual_norm of a tank stored transposed (in a batch) against the
+    oracle on the same state, in the caller's orientation (the norms' rho u and rho v order)."""
+    wk = tall_tank("walls")
+    t = wk.tanks[0]
+    tanks = [dict(nx=x.nx, ny=x.ny, lx=x.lx, ly=x.ly, gx=x.gx, gy=x.gy, beta=x.beta, bc=x.bc)
+             for x in wk.tanks]
+    grid = vdac.Grid(tanks, gpu_options(wk))
+    try:
+        for i, x in enumerate(wk.tanks):
+            grid.set_state(i, x.q)
+        grid.step(wk.dt, 10)
+        q = grid.get_state(0)
+        got_dt = grid.realtime_dt(0, 0.45)
+        got_norms = grid.residual_norm(0)
+    finally:
+        grid.close()
+    pb = oracle_problem(t, wk)
+    ref_dt = oracle.realtime_dt(pb, q, 0.45)
+    _, it, ref_norms, rc = oracle.step(pb, t.q, wk.dt, 10, 0.0, 0)
+    assert rc == 0 and it == 10
+    print(f"[parity] transposed tank: realtime dt {got_dt:.6e} (oracle {ref_dt:.6e}), norms "
+          f"{got_norms} (oracle {ref_norms})", flush=True)
+    assert got_dt == pytest.approx(ref_dt, rel=1e-14)
+    np.testing.assert_allclose(got_norms, ref_norms, rtol=1e-7, atol=1e-12)
+    assert abs(got_norms[1] - got_norms[2]) > 1e-3 * max(got_norms[1], got_norms[2])
+
+
 def test_deterministic_repeat():
     wk = small_dam(64, 32)
     a = run_gpu(wk, 2, 10)
