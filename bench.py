@@ -123,8 +123,8 @@ def cpu_model() -> str:
 
 def cpu_baseline(wk, budget_s: float, omp: bool = False):
     """The oracle (FP64 C) timed on a bounded sample of the workload: real steps from the initial
-    state, each with as many pseudo-iterations as the budget allows (up to the workload's cap),
-    until the budget is used.  omp=False is the oracle as it stands (serial); omp=True the same
+    state of its first tank (the only tank, except in the ensemble), each with as many
+    pseudo-iterations as the budget allows (up to the workload's cap), until the budget is used.  omp=False is the oracle as it stands (serial); omp=True the same
     source built with -fopenmp on all host threads (same results)."""
     import oracle
     t = wk.tanks[0]
@@ -147,11 +147,13 @@ def cpu_baseline(wk, budget_s: float, omp: bool = False):
     dt = time.perf_counter() - t0
     cell_stages = t.fluid_cells * wk.stages * total_it
     threads = oracle.threads(omp)
+    what = f" (its first tank, {t.nx}x{t.ny})" if len(wk.tanks) > 1 else ""
     return {"value": cell_stages / dt, "unit": "cell-updates/s per pseudo-time stage",
             "cores": threads, "kind": "oracle" if not omp else "oracle, -fopenmp build of the same source",
             "cpu": cpu_model(), "host_threads": os.cpu_count(),
-            "sample": f"{wk.name}: {steps} real step(s) of {iters} pseudo-iterations x {wk.stages} "
-                      f"stages ({cell_stages:.3g} cell-stages, {dt:.1f} s, {threads} thread(s))"}
+            "sample": f"{wk.name}{what}: {steps} real step(s) of {iters} pseudo-iterations x "
+                      f"{wk.stages} stages ({cell_stages:.3g} cell-stages, {dt:.1f} s, "
+                      f"{threads} thread(s))"}
 
 
 def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
