@@ -6,12 +6,12 @@
  *
  * One call of step_dual_time advances every tank of a grid by one real-time step (Algorithm 1,
  * Sec. 2.2.2): level n <- current state, then explicit Runge-Kutta pseudo-time iterations
- * (eqs. RK1-RK2) until every residual norm is below the tolerance.  Each Runge-Kutta stage runs,
+ * (eqs. 23-24) until every residual norm is below the tolerance.  Each Runge-Kutta stage runs,
  * on the GPU and per cell: limited MUSCL gradients of rho, u, v (Sec. 2.3.1), the new pressure
  * gradient from the rearranged momentum equation (Sec. 2.3.2), face states, the
  * Osher-Dumbser-Toro flux (Sec. 2.4.3) rotated to each face (Sec. 2.4), the flux divergence,
  * the real-time and body-force sources frozen at stage 0 and the point-implicit update
- * (eq. point_implicit), with the local pseudo-time step of Sec. 2.2.3.  Walls are ghost cells
+ * (coefficient of eq. 27), with the local pseudo-time step of Sec. 2.2.3.  Walls are ghost cells
  * with zero-gradient rho and p, mirrored velocity and reversed gravity (Sec. 2.5).
  *
  * Conventions shared by every entry point

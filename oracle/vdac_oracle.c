@@ -624,7 +624,7 @@ static void side_entities(const geom *g, const prim *W, const entity *E, const f
     }
 }
 
-/* One Runge-Kutta stage (eq. RK2) on internal-form arrays.  R (nullable) receives the bracket
+/* One Runge-Kutta stage (eq. 24) on internal-form arrays.  R (nullable) receives the bracket
  * [4][n] with the p row as beta*R_(p/beta). */
 static void stage_internal(const geom *g, const double *Qprev, const double *Q0, const frozen *fz,
                            double dt, int s, double *Qout, double *R, orc_detail *det)
@@ -726,7 +726,7 @@ static void stage_internal(const geom *g, const double *Qprev, const double *Q0,
             }
         }
 
-    /* bracket of eq. RK2 and the update */
+    /* bracket of eq. 24 and the update */
     double alpha = pb->alpha[s - 1];
     ORC_ROWS
     for (int j = 0; j < ny; ++j)
@@ -908,7 +908,7 @@ int orc_step(const orc_problem *pb, double *q, const double *qnm1, const double 
     memcpy(Qn, Q, 4 * n * sizeof(double)); /* Algorithm 1: Q^n <- Q */
 
     for (m = 0; m < max_pseudo;) {
-        memcpy(Q0, Q, 4 * n * sizeof(double)); /* Q^m <- Q (eq. RK1) */
+        memcpy(Q0, Q, 4 * n * sizeof(double)); /* Q^m <- Q (eq. 23) */
         freeze_sources(&g, Q0, Qn, Qm, Qm2, dt, &fz);
         const double *prev = Q0;
         for (int s = 1; s <= pb->stages; ++s) {

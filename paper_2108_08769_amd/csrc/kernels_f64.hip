@@ -35,7 +35,7 @@ __device__ __forceinline__ void reconstruct(const TankDev &t, const Scheme &sc,
                                          : load_prim(qprev, plane, (size_t)wrap(j + 1, t.ny) * t.nx + i);
     rec.gx = slopes(xm, rec.w, xp, t.inv_dx, sc.k);
     rec.gy = slopes(ym, rec.w, yp, t.inv_dy, sc.k);
-    // real-time term (B0 Q^0 + B1 Q^n + B2 Q^{n-1})/dt on rho, rho u, rho v (eq. bdf)
+    // real-time term (B0 Q^0 + B1 Q^n + B2 Q^{n-1})/dt on rho, rho u, rho v (eq. 26)
     const double *qn = t.level_n;
     double num[3];
 #pragma unroll
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
                 }
                 Fyp = osher_y(L, R, t.beta, t.inv_beta);
             }
-            // bracket of eq. RK2 and the point-implicit update (eq. point_implicit)
+            // bracket of eq. 24 and the point-implicit update (coefficient of eq. 27)
             const double r0 = q0[c], m0 = q0[plane + c], n0 = q0[2 * plane + c];
             const double p0 = q0[3 * plane + c];
             const double dtau = local_dtau(t, t.cfl, r0, m0, n0);

@@ -22,7 +22,7 @@
 //      whose left face is a wall evaluates that face itself from its own ghost (Sec. 2.5);
 //   3. evaluates the y-face between rows r-1 and r (rotated, Sec. 2.4); a face with a wall above
 //      row r is evaluated with row r's ghost and carried to the next row;
-//   4. completes row r-1: flux divergence, frozen sources, point-implicit update (eq. RK2), and
+//   4. completes row r-1: flux divergence, frozen sources, point-implicit update (eq. 24), and
 //      on the last stage the residual partial.
 // Each face is evaluated once.  Periodic sides wrap indices; cells outside a non-periodic side
 // read as non-fluid.

@@ -15,7 +15,7 @@
 //   3. every face of the tile is evaluated once with the Osher-Dumbser-Toro flux (Sec. 2.4.3);
 //      the flux overwrites the face's left/lower state slot;
 //   4. each tile cell forms the flux divergence in FP64, adds the frozen sources and applies the
-//      point-implicit update (eq. RK2), and the last stage accumulates the residual.
+//      point-implicit update (eq. 24), and the last stage accumulates the residual.
 // Mixed form: the state is stored as FP32 deviations from the FP64 level n; reconstruction and
 // fluxes run in FP32 with every face pressure expressed from the pressure of the face's
 // lower-index cell, and that reference (an FP64 difference) is added back in the divergence.

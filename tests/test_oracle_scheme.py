@@ -100,8 +100,8 @@ def test_uniform_relaxation_closed_form(bdf):
     """A spatially uniform state on a fully periodic grid has zero flux divergence (all faces
     alike), so each pseudo-iteration solves dQ/dtau = -I_C dQ/dt + rho^0 g point-implicitly:
     Q^{m+1} = Q^m + dtau/alpha_PI (-(B0 Q^m + B1 Q^n + B2 Q^{n-1})/dt + rho^m g),
-    alpha_PI = 1 + B0 dtau/dt on rho, rho u, rho v and 1 on p/beta (eqs. RK2, bdf,
-    point_implicit; Table 1), with the local dtau of Sec. 2.2.3.  Two iterations, so that Q^0
+    alpha_PI = 1 + B0 dtau/dt on rho, rho u, rho v and 1 on p/beta (eqs. 24, 26,
+    27; Table 1), with the local dtau of Sec. 2.2.3.  Two iterations, so that Q^0
     differs from Q^n and every coefficient enters."""
     B0, B1, B2, _ = read_bdf_table()["backward_euler" if bdf == 1 else "bdf2"]
     nx, ny, lx, ly, beta, gx, gy, dt, cfl = 4, 3, 2.0, 1.5, 700.0, 1.3, -9.81, 2e-3, 0.48
@@ -239,7 +239,7 @@ def developed_dam(nx, ny, lx, ly, dt, slip):
 
 @pytest.mark.parametrize("slip", [False, True])
 def test_flux_divergence_telescopes(slip):
-    """Each face flux enters its two cells with opposite signs (eq. AC_rearranged), so summed
+    """Each face flux enters its two cells with opposite signs (eq. 22), so summed
     over the tank the divergence reduces to the boundary fluxes:
     sum_i R_i |Omega| = -sum_i D_i |Omega| + sum_i B_i |Omega| - (net outward boundary flux)."""
     nx, ny, lx, ly, dt = 16, 8, 4.0, 2.0, 1e-3
