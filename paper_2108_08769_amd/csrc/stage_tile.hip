@@ -1,7 +1,7 @@
 // stage_tile.hip -- the Runge-Kutta stage kernel for gfx950 in its tiled form, FP64 or mixed
 // precision (the policies of stage_common.h).
 //
-// One workgroup of 256 or 512 threads updates one TX x TY tile of cells of a single tank in four
+// One workgroup of 256, 320 or 512 threads updates one TX x TY tile of cells of a single tank in four
 // phases separated by workgroup barriers:
 //   1. the stage input Q^{s-1} of the tile and a two-cell halo is loaded once from memory and
 //      kept in LDS as primitives (rho, u, v in the reconstruction precision, p in FP64), with the

@@ -5,9 +5,12 @@
 //              FP64.  Mixed form: FP32 deviations rho - rho^n, rho*u - (rho*u)^n,
 //              rho*v - (rho*v)^n, p - p^n from real-time level n.  The current state, the
 //              stage-0 state of the running pseudo-iteration and the stage outputs rotate among
-//              them (see stage_buffers below), so no state is ever copied.
+//              them (see stage_buffers below) without copies; begin_step moves the state into
+//              buffer 0 once per real step.
 //   level_n    real-time level n in FP64: 3 planes (rho, rho*u, rho*v) in the FP64 form, 4 (and
-//              p) in the mixed form; level_nm1 3 planes for BDF2.
+//              p) in the mixed form; level_nm1 (BDF2, BDF3) and level_nm2 (BDF3) 3 planes each.
+// A tank of a batch may be stored reflected about its diagonal (x and y exchanged); the host
+// reflects states and norms at the C ABI, and the kernels see an ordinary tank.
 //   flags      one byte per cell: which faces are walls (domain wall or solid neighbour) and
 //              whether the cell itself is solid.
 //   partials   per-work-unit residual partial sums of the last Runge-Kutta stage.
