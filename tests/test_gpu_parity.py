@@ -289,16 +289,21 @@ def tall_tank(case, precision="f64"):
     companion = wl.Tank(6, 5, 0.3, 0.25, qc, gx=0.7, gy=-9.81, beta=300.0)
     wk = wl.Workload(f"tall_{case}", [t, companion], dt=1e-3, steps=1, max_pseudo=1,
                      precision=precision)
-    if case == "bdf2":
-        wk.bdf = 2
+    if case in ("bdf2", "bdf3"):
+        wk.bdf = int(case[-1])
+    if case == "superbee_slip":
+        wk.k = 2.0
     return wk
 
 
-@pytest.mark.parametrize("case", ["walls", "periodic_x", "open_top", "obstacle", "bdf2"])
+@pytest.mark.parametrize("case", ["walls", "periodic_x", "open_top", "obstacle", "bdf2", "bdf3",
+                                  "superbee_slip"])
 def test_transposed_storage_matches_oracle(case):
     """Tanks stored with x and y exchanged give the oracle's states, iteration counts and norms
-    (rho u and rho v in the caller's order) in the caller's orientation."""
-    check(tall_tank(case), steps=3, pseudo=12)
+    (rho u and rho v in the caller's order) in the caller's orientation.  Free-slip walls flip
+    only the normal velocity, so they also check that the sides' axes are exchanged."""
+    kw = {"wall_slip": True} if case == "superbee_slip" else {}
+    check(tall_tank(case), steps=3, pseudo=12, **kw)
 
 
 def test_transposed_storage_tolerance_and_batch():
