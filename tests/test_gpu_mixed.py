@@ -159,6 +159,14 @@ def test_mixed_transposed_storage_vs_oracle(case):
     check_mixed(tall_tank(case, "mixed"), steps=2, pseudo=12, ref="oracle")
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_mixed_random_batches_vs_oracle(seed):
+    """Seeded random batches (shapes, sides, obstacles, gravity, states; some tanks stored
+    transposed), mixed form, every tank against the oracle."""
+    from test_gpu_parity import random_batch
+    check_mixed(random_batch(seed, "mixed"), steps=2, pseudo=8, ref="oracle")
+
+
 @pytest.mark.parametrize("opt", ["bdf2", "slip", "superbee", "max_norm"])
 def test_mixed_options_vs_fp64(opt):
     wk = small_dam(96, 48)

@@ -344,6 +344,52 @@ def test_transposed_storage_realtime_dt_and_norms():
     assert abs(got_norms[1] - got_norms[2]) > 1e-3 * max(got_norms[1], got_norms[2])
 
 
+def random_batch(seed, precision="f64"):
+    """A seeded batch of 6 tanks: sides 1..70 cells, random side kinds (periodic sides paired,
+    zero-gradient sides allowed), a random solid block in some, random gravity components, random
+    state of unit scale.  Several tanks are stored transposed (tall and narrow)."""
+    rng = np.random.default_rng(seed)
+    tanks = []
+    for k in range(6):
+        nx, ny = int(rng.integers(1, 71)), int(rng.integers(1, 71))
+        if k == 0:
+            nx, ny = int(rng.integers(8, 20)), int(rng.integers(61, 71))  # stored transposed
+        q = wl.random_state(nx, ny, seed=seed * 10 + k, rho_range=(1.0, 3.0), vel=0.2, p_scale=5.0)
+        sides = []
+        for axis in range(2):
+            kind = rng.choice(["wall", "periodic", "open", "mixed"])
+            if kind == "periodic":
+                sides += [vdac.BC_PERIODIC, vdac.BC_PERIODIC]
+            elif kind == "open":
+                sides += [vdac.BC_TRANSMISSIVE, vdac.BC_TRANSMISSIVE]
+            elif kind == "mixed":
+                sides += [vdac.BC_WALL, vdac.BC_TRANSMISSIVE]
+            else:
+                sides += [vdac.BC_WALL, vdac.BC_WALL]
+        solid = None
+        if nx >= 6 and ny >= 6 and rng.random() < 0.5:
+            solid = np.zeros((ny, nx), np.uint8)
+            i0, j0 = int(rng.integers(1, nx - 3)), int(rng.integers(1, ny - 3))
+            solid[j0:j0 + 2, i0:i0 + 3] = 1
+        tanks.append(wl.Tank(nx, ny, 0.05 * nx, 0.04 * ny, q, gx=float(rng.uniform(-2, 2)),
+                             gy=float(rng.uniform(-10, -1)), beta=float(rng.uniform(100, 1000)),
+                             bc=tuple(sides), solid=solid))
+    return wl.Workload(f"random_batch_{seed}", tanks, dt=1e-3, steps=1, max_pseudo=1,
+                       precision=precision)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_random_batches_against_oracle(seed):
+    """Seeded random batches (shapes, sides, obstacles, gravity, states) on the row-marching
+    kernel, every tank against the oracle; some tanks are stored transposed."""
+    from parity import stored_transposed_in_batch
+    wk = random_batch(seed)
+    print(f"[parity] random batch {seed}: {[(t.nx, t.ny, t.bc) for t in wk.tanks]}, transposed "
+          f"{[stored_transposed_in_batch(t) for t in wk.tanks]}", flush=True)
+    assert stored_transposed_in_batch(wk.tanks[0])
+    check(wk, steps=2, pseudo=8)
+
+
 def test_deterministic_repeat():
     wk = small_dam(64, 32)
     a = run_gpu(wk, 2, 10)
