@@ -147,6 +147,32 @@ def test_tile_variants_periodic_and_obstacle(tile):
     check(wl.obstacle_dam_break(n=80), steps=1, pseudo=12, tile=tile)
 
 
+def random_single_tank(seed):
+    """A seeded tank for the single-tank kernels: sides 1..90 cells, walls or periodic sides, a
+    random solid block in some, random gravity components and state of unit scale."""
+    rng = np.random.default_rng(100 + seed)
+    nx, ny = int(rng.integers(1, 91)), int(rng.integers(1, 91))
+    q = wl.random_state(nx, ny, seed=200 + seed, rho_range=(1.0, 3.0), vel=0.2, p_scale=5.0)
+    px, py = rng.random() < 0.4, rng.random() < 0.4
+    bc = ((vdac.BC_PERIODIC,) * 2 if px else (vdac.BC_WALL,) * 2) + \
+         ((vdac.BC_PERIODIC,) * 2 if py else (vdac.BC_WALL,) * 2)
+    solid = None
+    if nx >= 6 and ny >= 6 and rng.random() < 0.6:
+        solid = np.zeros((ny, nx), np.uint8)
+        i0, j0 = int(rng.integers(1, nx - 3)), int(rng.integers(1, ny - 3))
+        solid[j0:j0 + 3, i0:i0 + 2] = 1
+    t = wl.Tank(nx, ny, 0.05 * nx, 0.04 * ny, q, gx=float(rng.uniform(-2, 2)),
+                gy=float(rng.uniform(-10, -1)), beta=float(rng.uniform(100, 1000)), bc=bc, solid=solid)
+    return wl.Workload(f"random_tank_{seed}", [t], dt=1e-3, steps=1, max_pseudo=1)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("tile", TILES)
+def test_tile_variants_random_tanks(tile, seed):
+    """Every stage-kernel shape on seeded random single tanks against the oracle."""
+    check(random_single_tank(seed), steps=2, pseudo=6, tile=tile)
+
+
 def test_tile_variants_agree():
     """The tiled kernels evaluate every face once and the plain kernel twice per face; all agree
     to rounding."""
