@@ -159,6 +159,18 @@ def test_mixed_transposed_storage_vs_oracle(case):
     check_mixed(tall_tank(case, "mixed"), steps=2, pseudo=12, ref="oracle")
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("tile", [(0, 0), (-3, 5), (32, 8), (16, 16), (3208, 2), (1616, 2),
+                                  (1608, 2)])
+def test_mixed_kernel_shapes_random_tanks_vs_oracle(tile, seed):
+    """The mixed form in every kernel shape on seeded random single tanks (periodic sides,
+    obstacles, random gravity), against the oracle."""
+    from test_gpu_parity import random_single_tank
+    wk = random_single_tank(seed)
+    wk.precision = "mixed"
+    check_mixed(wk, steps=2, pseudo=6, ref="oracle", tile=tile)
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3, 4])
 def test_mixed_random_batches_vs_oracle(seed):
     """Seeded random batches (shapes, sides, obstacles, gravity, states; some tanks stored
