@@ -161,7 +161,8 @@ __device__ __forceinline__ InputLoad<P> load_input(const TankDev &t,
     return L;
 }
 
-template <class P, int BDF>
+// Z = false leaves out Q^0 (stage 1 of the FP64 form takes it from the input rows instead).
+template <class P, int BDF, bool Z = true>
 __device__ __forceinline__ SourceLoad<P> load_sources(const TankDev &t,
                                                       const typename P::Store *__restrict__ q0,
                                                       bool have_col, int gi, int r)
@@ -173,10 +174,14 @@ __device__ __forceinline__ SourceLoad<P> load_sources(const TankDev &t,
     SourceLoad<P> L;
     const uint8_t f = t.flags[c];
     L.f = (have_col && inside) ? f : (uint8_t)FLAG_SOLID;
-    L.z0 = q0[c];
-    L.z1 = q0[plane + c];
-    L.z2 = q0[2 * plane + c];
-    L.z3 = q0[3 * plane + c];
+    if constexpr (Z) {
+        L.z0 = q0[c];
+        L.z1 = q0[plane + c];
+        L.z2 = q0[2 * plane + c];
+        L.z3 = q0[3 * plane + c];
+    } else {
+        L.z0 = L.z1 = L.z2 = L.z3 = 0;
+    }
     if (!P::kMixed) {  // the mixed form takes level n from the input row (it carries it)
         L.n0 = t.level_n[c];
         L.n1 = t.level_n[plane + c];
@@ -271,7 +276,9 @@ __device__ __forceinline__ Prim<R> ghost_state_gen(const TankDev &t, const Schem
 
 // WAVES: the register budget as waves per SIMD (2: up to 256 VGPRs per lane, 3: up to 168).
 // BDF: the highest real-time order of the grid (levels n-1, n-2 read); GEN: general options.
-template <class P, bool NORM_MAX, int BDF, bool LAST, int WAVES, bool GEN>
+// FIRST (FP64 form, stage 1 of more than one): Q^{s-1} is Q^0, so Q^0 of a row is taken from
+// the input rows the window already holds (the same values) instead of being read again.
+template <class P, bool NORM_MAX, int BDF, bool LAST, int WAVES, bool GEN, bool FIRST = false>
 __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     stage_march(const TankDev *__restrict__ tanks, const MarchUnit *__restrict__ units, Scheme sc,
                 int stage, IterArgs ia)
@@ -328,8 +335,10 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     // (plo, pmid, phi: their absolute pressures in FP64)
     // (mixed form: lvl_mid, lvl_hi carry level n of rho, rho u, rho v of rows r and r+1, which
     // the input loads fetched, so that the sources need not fetch it again)
+    static_assert(!FIRST || (!P::kMixed && !LAST), "FIRST is the FP64 form's stage 1");
     Prim<R> lo, mid, hi;
     double plo, pmid, phi;
+    double mlo = 0.0, mmid = 0.0, mhi = 0.0, nlo = 0.0, nmid = 0.0, nhi = 0.0;  // FIRST: rho u, rho v
     Vec4<double> lvl_mid = zero4<double>(), lvl_hi = zero4<double>();
     {
         const InputLoad<P> a = load_input<P>(t, qprev, gi, j0 - 2);
@@ -341,13 +350,17 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         plo = abs_p(a);
         pmid = abs_p(b);
         phi = abs_p(c);
+        if constexpr (FIRST) {
+            mlo = a.m; mmid = b.m; mhi = c.m;
+            nlo = a.n; nmid = b.n; nhi = c.n;
+        }
         if constexpr (P::kMixed) {
             lvl_mid = {b.lr, b.lm, b.ln, 0.0};
             lvl_hi = {c.lr, c.lm, c.ln, 0.0};
         }
     }
     InputLoad<P> in_ld = load_input<P>(t, qprev, gi, j0 + 1);             // row r+2
-    SourceLoad<P> src_ld = load_sources<P, BDF>(t, q0, have_col, gi, j0 - 1);       // row r
+    SourceLoad<P> src_ld = load_sources<P, BDF, !FIRST>(t, q0, have_col, gi, j0 - 1); // row r
     if (stopped) return;
 
     // carries from row r-1:
@@ -377,8 +390,9 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         const uint8_t f = src_ld.f;
         const bool fluid = !(f & FLAG_SOLID);
         // z: the base of the update (Q^0, or its deviation and p^0); a0..a2: absolute Q^0
-        const Vec4<double> z = {(double)src_ld.z0, (double)src_ld.z1, (double)src_ld.z2,
-                                (double)src_ld.z3};
+        const Vec4<double> z = FIRST ? Vec4<double>{(double)mid.r, mmid, nmid, pmid}
+                                     : Vec4<double>{(double)src_ld.z0, (double)src_ld.z1,
+                                                    (double)src_ld.z2, (double)src_ld.z3};
         double a0, a1, a2, num0, num1, num2;
         double lvl_r;  // level-n density of row r
         if constexpr (P::kMixed) {
@@ -422,11 +436,12 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         const double d_r = num0 * sp.inv_dt, d_ru = num1 * sp.inv_dt, d_rv = num2 * sp.inv_dt;
         const Prim<R> next_hi = to_prim(in_ld);
         const double next_phi = abs_p(in_ld);
+        const double next_m = FIRST ? (double)in_ld.m : 0.0, next_n = FIRST ? (double)in_ld.n : 0.0;
         const Vec4<double> next_lvl = {in_ld.lr, in_ld.lm, in_ld.ln, 0.0};
         // the chunk reconstructs rows up to j1 from inputs up to row j1 + 1: past those rows the
         // loads repeat the last needed row (a cache hit), with no branch around them
         in_ld = load_input<P>(t, qprev, gi, min(r + 3, j1 + 1));
-        src_ld = load_sources<P, BDF>(t, q0, have_col, gi, min(r + 1, j1));
+        src_ld = load_sources<P, BDF, !FIRST>(t, q0, have_col, gi, min(r + 1, j1));
 
         // ---- reconstruction of row r ------------------------------------------------------
         const Prim<R> wl = prim_from_left(mid);
@@ -614,6 +629,10 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         fluid_lo = fluid;
         lo = next_hi;
         plo = next_phi;
+        if constexpr (FIRST) {
+            mlo = next_m;
+            nlo = next_n;
+        }
         if constexpr (P::kMixed) lvl_lo = next_lvl;
     };
 
@@ -639,6 +658,15 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         plo = pmid;
         pmid = phi;
         phi = pw;
+        if constexpr (FIRST) {
+            const double mw = mlo, nw = nlo;
+            mlo = mmid;
+            mmid = mhi;
+            mhi = mw;
+            nlo = nmid;
+            nmid = nhi;
+            nhi = nw;
+        }
         if constexpr (P::kMixed) {
             const Vec4<double> lw = lvl_lo;
             lvl_lo = lvl_mid;
@@ -663,18 +691,19 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     }
 }
 
-template <class P, bool NM, int BDF, bool LS, bool GEN>
+template <class P, bool NM, int BDF, bool LS, bool GEN, bool FIRST = false>
 void launch_t(const TankDev *tanks, const MarchUnit *units, dim3 g, dim3 b, int waves_simd,
               const Scheme &sc, int stage, const IterArgs &ia, hipStream_t s)
 {
     if constexpr (!GEN) {
         if (waves_simd == 3) {
-            hipLaunchKernelGGL((stage_march<P, NM, BDF, LS, 3, GEN>), g, b, 0, s, tanks, units, sc,
-                               stage, ia);
+            hipLaunchKernelGGL((stage_march<P, NM, BDF, LS, 3, GEN, FIRST>), g, b, 0, s, tanks,
+                               units, sc, stage, ia);
             return;
         }
     }
-    hipLaunchKernelGGL((stage_march<P, NM, BDF, LS, 2, GEN>), g, b, 0, s, tanks, units, sc, stage, ia);
+    hipLaunchKernelGGL((stage_march<P, NM, BDF, LS, 2, GEN, FIRST>), g, b, 0, s, tanks, units, sc,
+                       stage, ia);
 }
 
 template <class P, int BDF, bool GEN>
@@ -685,6 +714,13 @@ void launch_b(const TankDev *tanks, const MarchUnit *units, dim3 g, dim3 b, int 
         if (sc.norm_max) launch_t<P, true, BDF, true, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
         else launch_t<P, false, BDF, true, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
     } else {
+        if constexpr (!P::kMixed && !GEN) {
+            if (stage == 1) {
+                launch_t<P, false, BDF, false, GEN, true>(tanks, units, g, b, waves_simd, sc, stage,
+                                                          ia, s);
+                return;
+            }
+        }
         launch_t<P, false, BDF, false, GEN>(tanks, units, g, b, waves_simd, sc, stage, ia, s);
     }
 }
