@@ -114,7 +114,9 @@ void vdac_default_options(vdac_options *o);
 /* Device bytes create_grid needs for these tanks and options (0 on invalid arguments). */
 size_t workspace_bytes(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o);
 
-/* Builds a grid of n_tanks independent tanks.  o may be NULL (defaults).  device_workspace, if
+/* Builds a grid of n_tanks independent tanks: the problem statement the paper's tests give (the
+ * domain and its cells, gravity, beta, the walls of Sec. 2.5, the scheme of Sec. 2.2-2.4), one
+ * tank per problem.  o may be NULL (defaults).  device_workspace, if
  * not NULL, is a device buffer of at least ws_bytes >= workspace_bytes(...) bytes that the
  * library borrows until destroy_grid (the caller keeps it alive); if NULL the library allocates
  * and frees its own.  hip_stream is a hipStream_t (NULL = the null stream).  The initial state
@@ -127,8 +129,9 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
                 void *device_workspace, size_t ws_bytes, void *hip_stream, vdac_grid **out);
 
 /* Sets the state of one tank from a host array q [4][ny][nx] (rho, rho*u, rho*v, p).  Also
- * sets level n to q and discards the BDF2 history, so the next step uses backward Euler
- * (Sec. 2.2.2).  rho must be finite and > 0 in every fluid cell, else VDAC_E_INVALID. */
+ * sets level n to q and discards this tank's earlier real-time levels, so its next step uses
+ * backward Euler (Sec. 2.2.2); the other tanks of the grid keep theirs.  rho must be finite and
+ * > 0 in every fluid cell, else VDAC_E_INVALID. */
 int set_state(vdac_grid *g, int32_t tank, const double *q);
 
 /* One real-time step of size dt > 0 for every tank (Algorithm 1); dt = +infinity switches the
@@ -142,11 +145,27 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol,
                    int32_t *pseudo_done);
 
 /* Residual norms (rho, rho*u, rho*v, p) of the last pseudo-iteration of one tank: the norm of
- * the last Runge-Kutta stage's bracket, the p row as beta times the p/beta row (= dp/dtau). */
+ * the last Runge-Kutta stage's bracket of eq. 24 (the pseudo-time derivative dQ/dtau that the
+ * convergence test of Algorithm 1 measures), the p row as beta times the p/beta row (= dp/dtau);
+ * RMS or maximum over the fluid cells (options.norm). */
 int residual_norm(const vdac_grid *g, int32_t tank, double out[4]);
 
-/* Copies one tank's state to the host array q [4][ny][nx] (rho, rho*u, rho*v, p). */
+/* Copies one tank's state to the host array q [4][ny][nx]: the conserved variables of Sec. 2.1.2
+ * (rho, rho*u, rho*v) and the pressure p itself (not p/beta). */
 int get_state(const vdac_grid *g, int32_t tank, double *q);
+
+/* Real-time history of one tank, for an exact restart of a BDF2 or BDF3 run (Table 1: a step of
+ * order k needs the states at the k - 1 earlier real times besides the current one).
+ * get_history writes to the host array levels [2][3][ny][nx] the states (rho, rho*u, rho*v) at
+ * the starts of the last and of the one but last completed real steps (the pressure has no
+ * real-time term), and to *count how many of them the next step of this grid would use:
+ * min(real steps completed since set_state, bdf_order - 1); levels[1] is written only when
+ * *count is 2.  set_history, called after set_state on a grid with the same options and tank,
+ * restores them, so that the next step_dual_time continues the run bit for bit: count 0..2 and at
+ * most bdf_order - 1, else VDAC_E_INVALID; levels[1] is read only when count is 2.  Host arrays are
+ * owned by the caller and copied synchronously.  A later set_state discards the restored levels. */
+int get_history(const vdac_grid *g, int32_t tank, double *levels, int32_t *count);
+int set_history(vdac_grid *g, int32_t tank, const double *levels, int32_t count);
 
 /* Global real-time step of one tank from its current state (Sec. 2.2.4):
  * *dt = min over fluid cells of cfl_t dx dy / (|u| dy + |v| dx), +infinity at rest. */

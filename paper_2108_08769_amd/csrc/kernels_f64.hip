@@ -1,7 +1,7 @@
 // kernels_f64.hip -- kernels of one real-time step on gfx950 other than the row-marching stage:
 // begin-of-step bookkeeping and the deterministic residual finalize (all tanks in one launch each),
-// the conversions of the mixed-precision storage, the real-time step bound, and the plain FP64
-// stage kernel.
+// the conversions of the mixed-precision storage, the tank-wide minima (real-time step bound,
+// smallest pseudo-time step), and the plain FP64 stage kernel.
 //
 // stage_direct_f64 is the plain form of a stage: one thread per cell, which reconstructs itself
 // and its four neighbours and evaluates all four of its faces.  Every face is therefore computed
@@ -176,19 +176,20 @@ __global__ void __launch_bounds__(64) finalize_kernel(const TankDev *__restrict_
     finalize_wave(load_tank(tanks + blockIdx.x), sc, threadIdx.x);
 }
 
-// Start of a real-time step (Algorithm 1) for tank blockIdx.y: with history the real-time levels
-// shift (n-2 <- n-1 <- n), else the kept earlier levels are set to the new level n; then level
-// n <- current state and a fresh pseudo-loop status; workgroup (0, 0) also stores the step's BDF
-// coefficients.  In the mixed form the new level n is level n plus the current deviation, which
-// then becomes zero.  The current state moves to buffer 0, where every step's pseudo-loop starts
-// (the status keeps naming the old buffer, which still holds it, until the first finalize).
+// Start of a real-time step (Algorithm 1) for tank blockIdx.y, by the tank's StepParams (which
+// the host has stored before the launch): with HISTORY_SHIFT the real-time levels shift
+// (n-2 <- n-1 <- n), with HISTORY_RESET the kept earlier levels are set to the new level n, with
+// HISTORY_KEEP they stay as restored; then level n <- current state and a fresh pseudo-loop
+// status.  In the mixed form the new level n is level n plus the current deviation, which then
+// becomes zero.  The current state moves to buffer 0, where every step's pseudo-loop starts (the
+// status keeps naming the old buffer, which still holds it, until the first finalize).
 __global__ void __launch_bounds__(256)
-    begin_step_kernel(const TankDev *__restrict__ tanks, StepParams sp, int max_pseudo, double tol,
-                      int use_history, int mixed)
+    begin_step_kernel(const TankDev *__restrict__ tanks, int max_pseudo, double tol, int mixed)
 {
     const TankDev &t = tanks[blockIdx.y];
     Status *st = t.status;
     const int cur = st->cur;
+    const int history = t.step->history;
     const size_t plane = t.plane;
     for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < plane;
          c += (size_t)gridDim.x * 256) {
@@ -203,9 +204,10 @@ __global__ void __launch_bounds__(256)
             }
             const double old = t.level_n[e];
             const double nw = mixed ? old + (double)d[e] : q[e];
-            if (k < 3) {
-                if (t.level_nm2) t.level_nm2[e] = use_history ? t.level_nm1[e] : nw;
-                if (t.level_nm1) t.level_nm1[e] = use_history ? old : nw;
+            if (k < 3 && history != HISTORY_KEEP) {
+                const bool shift = history == HISTORY_SHIFT;
+                if (t.level_nm2) t.level_nm2[e] = shift ? t.level_nm1[e] : nw;
+                if (t.level_nm1) t.level_nm1[e] = shift ? old : nw;
             }
             t.level_n[e] = nw;
             // the step starts from buffer 0: the state moves there (mixed: zero deviations)
@@ -218,7 +220,6 @@ __global__ void __launch_bounds__(256)
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (blockIdx.y == 0) *const_cast<StepParams *>(t.step) = sp;
         st->iters = 0;
         st->diverged = 0;
         st->max_pseudo = max_pseudo;
@@ -263,11 +264,16 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// Global real-time step (Sec. 2.2.4): per-workgroup minima over fluid cells of
-// CFL_t dx dy / (|u| dy + |v| dx) of the current state (infinity at rest).
+// Per-workgroup minima over the fluid cells of the current state of tank first + blockIdx.y into
+// scratch[blockIdx.y * gridDim.x + blockIdx.x]: kind MIN_REALTIME_DT, the global real-time step of
+// Sec. 2.2.4, CFL_t dx dy / (|u| dy + |v| dx) (infinity at rest); kind MIN_PSEUDO_DTAU, the local
+// pseudo-time step of Sec. 2.2.3 (the function the stage kernels use, so that the minimum is the
+// one the last stage reduces).  Every workgroup writes its slot (infinity if it has no cell).
 __global__ void __launch_bounds__(256)
-    realtime_dt_kernel(TankDev t, int mixed, double cfl_t, double *__restrict__ out)
+    tanks_min_kernel(const TankDev *__restrict__ tanks, int first, int mixed, int kind, double cfl,
+                     double *__restrict__ scratch)
 {
+    const TankDev &t = tanks[first + blockIdx.y];
     const Status *st = t.status;
     const int cur = st->cur;
     const size_t plane = t.plane;
@@ -287,14 +293,35 @@ __global__ void __launch_bounds__(256)
             mu = q[plane + c];
             mv = q[2 * plane + c];
         }
-        const double lam = (fabs(mu) * t.dy + fabs(mv) * t.dx) / r;
-        m = fmin(m, cfl_t * (t.dx * t.dy) / lam);
+        if (kind == MIN_PSEUDO_DTAU) {
+            m = fmin(m, local_dtau(t, t.cfl, r, mu, mv));
+        } else {
+            const double lam = (fabs(mu) * t.dy + fabs(mv) * t.dx) / r;
+            m = fmin(m, cfl * (t.dx * t.dy) / lam);
+        }
     }
-    for (int off = 32; off >= 1; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+    m = wave_reduce_to_lane63(m, INFINITY, [](double a, double b) { return fmin(a, b); });
     __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) out[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+    if (threadIdx.x == 0)
+        scratch[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
+// out[blockIdx.x * out_stride] = the minimum of scratch[blockIdx.x * n .. + n) (one workgroup per
+// tank; each thread strides over its row, then the tree).
+__global__ void __launch_bounds__(256) min_rows_kernel(const double *__restrict__ scratch, int n,
+                                                       double *__restrict__ out, int out_stride)
+{
+    const double *row = scratch + (size_t)blockIdx.x * n;
+    double m = INFINITY;
+    for (int i = threadIdx.x; i < n; i += 256) m = fmin(m, row[i]);
+    m = wave_reduce_to_lane63(m, INFINITY, [](double a, double b) { return fmin(a, b); });
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        out[(size_t)blockIdx.x * out_stride] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
 unsigned cell_blocks(size_t plane)
@@ -313,20 +340,26 @@ int direct_blocks(const TankDev &t)
 }
 
 int launch_begin_step_all(const TankDev *tanks_dev, int n_tanks, size_t max_plane, const Scheme &sc,
-                          const StepParams &sp, int max_pseudo, double tol, int use_history,
-                          void *stream)
+                          int max_pseudo, double tol, void *stream)
 {
     const dim3 grid(cell_blocks(max_plane), (unsigned)n_tanks);
-    hipLaunchKernelGGL(begin_step_kernel, grid, dim3(256), 0, (hipStream_t)stream, tanks_dev, sp,
-                       max_pseudo, tol, use_history, sc.mixed);
+    hipLaunchKernelGGL(begin_step_kernel, grid, dim3(256), 0, (hipStream_t)stream, tanks_dev,
+                       max_pseudo, tol, sc.mixed);
     return (int)hipGetLastError();
 }
 
-int launch_realtime_dt(const TankDev &t, int mixed, double cfl_t, double *out, int n_blocks,
-                       void *stream)
+int launch_tanks_min(const TankDev *tanks_dev, int first, int n_tanks, int mixed, int kind,
+                     double cfl, double *scratch, int blocks_per_tank, double *out, int out_stride,
+                     void *stream)
 {
-    hipLaunchKernelGGL(realtime_dt_kernel, dim3((unsigned)n_blocks), dim3(256), 0,
-                       (hipStream_t)stream, t, mixed, cfl_t, out);
+    if (n_tanks < 1 || blocks_per_tank < 1 || blocks_per_tank > kMinBlocksMax || !scratch || !out)
+        return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(tanks_min_kernel, dim3((unsigned)blocks_per_tank, (unsigned)n_tanks), dim3(256),
+                       0, (hipStream_t)stream, tanks_dev, first, mixed, kind, cfl, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(min_rows_kernel, dim3((unsigned)n_tanks), dim3(256), 0, (hipStream_t)stream,
+                       (const double *)scratch, blocks_per_tank, out, out_stride);
     return (int)hipGetLastError();
 }
 

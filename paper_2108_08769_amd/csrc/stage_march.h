@@ -734,7 +734,9 @@ int launch(const TankDev *tanks, const MarchUnit *units, int n_entries, int wave
 {
     if (waves_per_block < 1 || waves_per_block > kMaxWavesPerBlock || n_entries % waves_per_block)
         return (int)hipErrorInvalidValue;
-    if (ia_in.fin && (stage != 1 || ia_in.n_tanks < 1)) return (int)hipErrorInvalidValue;
+    // the finalize waves read the partials of the previous iteration's last stage: stage 1 must
+    // not be that stage, as its units write the partials in the same launch
+    if (ia_in.fin && (stage != 1 || stage == sc.smax || ia_in.n_tanks < 1)) return (int)hipErrorInvalidValue;
     IterArgs ia = ia_in;
     const int fin_blocks = ia.fin ? ((ia.n_tanks + 8 * waves_per_block - 1) / (8 * waves_per_block)) * 8 : 0;
     ia.n_fin = fin_blocks * waves_per_block;

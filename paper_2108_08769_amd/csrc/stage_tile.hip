@@ -560,7 +560,9 @@ int tile_count(const TankDev &t, int tile_x, int tile_y)
 int launch_stage_tile(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
                       const IterArgs &ia, void *stream)
 {
-    if (ia.fin && stage != 1) return (int)hipErrorInvalidValue;
+    // the finalize reads the partials of the previous iteration's last stage, which stage 1 would
+    // overwrite in the same launch if it were the last stage
+    if (ia.fin && (stage != 1 || stage == sc.smax)) return (int)hipErrorInvalidValue;
     if (sc.bdf > 2 || sc.general) return (int)hipErrorInvalidValue;
     return sc.mixed ? launch_tile_p<PrecMixed>(t, sc, stage, tile_x, tile_y, ia, stream)
                     : launch_tile_p<PrecF64>(t, sc, stage, tile_x, tile_y, ia, stream);

@@ -74,11 +74,13 @@ struct vdac_grid {
     Scheme sc;
     Plan plan;
     hipStream_t stream;
+    int device;                         // the HIP device current at create_grid
     char *ws;
     bool own_ws;
     size_t ws_bytes;
     Status *status_dev;                 // [n_tanks], contiguous
-    StepParams *step_dev;
+    StepParams *step_dev;               // [n_tanks]
+    StepParams *step_host = nullptr;    // [n_tanks], pinned: the next step's coefficients
     TankDev *tanks_dev;                 // [n_tanks]
     MarchUnit *units_dev;               // [plan.n_entries] (row marching only)
     double *staging;                    // [4][max_plane] (mixed form only)
@@ -87,8 +89,11 @@ struct vdac_grid {
     // (two slots: the snapshot in flight and the one being checked)
     Status *status_snap = nullptr;      // [2][n_tanks]
     hipEvent_t snap_ev[2] = {nullptr, nullptr};
-    int hist;                           // completed real steps since set_state (capped at 2):
-                                        // how many earlier real-time levels are valid
+    // per tank: earlier real-time levels held (completed real steps since set_state, capped at
+    // 2, or the count set_history restored) and whether set_history restored them for the next
+    // step (begin_step must then keep levels n-1 and n-2 as they are)
+    std::vector<int> hist;
+    std::vector<char> restored;
     // captured pseudo-iterations, keyed by the number of iterations per graph and the first
     // iteration's index mod 3 (which fixes the buffer rotation, IterArgs::cur_off)
     hipStream_t cap_stream;
@@ -101,8 +106,8 @@ struct vdac_grid {
     bool timing;
     std::vector<hipEvent_t> ev_pool;
     struct PendingTiming {
-        int start, stop;  // indices into ev_pool, around one iteration's stage launches
-        int iter;         // pseudo-iteration (within the step)
+        int start, stop;  // indices into ev_pool, around the stage launches of iterations
+        int iter, n_iter; // pseudo-iterations [iter, iter + n_iter) of the step
     };
     std::vector<PendingTiming> ev_pending;
     double t_ms;
@@ -331,14 +336,15 @@ StoredTanks stored_tanks(const vdac_tank *tanks, int n_tanks, const vdac_options
     return S;
 }
 
-// A state [4][ny][nx] in the caller's orientation to the stored one (forward) or back: each
-// plane transposed, rho u and rho v exchanged.
-void transpose_state(const double *in, double *out, int nx, int ny, bool forward)
+// A state [nf][ny][nx] (nf = 4: rho, rho u, rho v, p; nf = 3: a real-time level without p) in the
+// caller's orientation to the stored one (forward) or back: each plane transposed, rho u and
+// rho v exchanged.
+void transpose_state(const double *in, double *out, int nx, int ny, bool forward, int nf = 4)
 {
     // forward: in is [ny][nx] (caller), out is [nx][ny]; backward: in is [nx][ny], out [ny][nx]
     const size_t plane = (size_t)nx * ny;
     static const int field_of[4] = {0, 2, 1, 3};
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < nf; ++k) {
         const double *src = in + (size_t)field_of[k] * plane;
         double *dst = out + (size_t)k * plane;
         for (int j = 0; j < ny; ++j)
@@ -403,7 +409,7 @@ GridBlock grid_block(int n_tanks, const Plan &p, const vdac_options *o)
     B.status = off;
     off += align256((size_t)n_tanks * sizeof(Status));
     B.step = off;
-    off += align256(sizeof(StepParams));
+    off += align256((size_t)n_tanks * sizeof(StepParams));
     B.tanks = off;
     off += align256((size_t)n_tanks * sizeof(TankDev));
     B.units = off;
@@ -489,49 +495,55 @@ hipEvent_t pool_event(vdac_grid *g, size_t idx)
     return g->ev_pool[idx];
 }
 
-// Collects the elapsed time of every bracketed pseudo-iteration of the finished step.  An
-// iteration counts if some tank was still running in it; its launches and cell-stages count the
-// tanks that were.
+// Collects the elapsed time of every bracket of the finished step: one pseudo-iteration's stage
+// launches (kernels launched one by one), or one replayed graph of several iterations.  A
+// bracket counts if some tank was still running in one of its iterations; its launches and
+// cell-stages count, per iteration, the tanks that were (a graph's time also holds the kernels
+// of stopped tanks, which return at once, and the finalize launch at its end).
 int collect_timing(vdac_grid *g, const std::vector<int> &iters_before, const std::vector<int> &iters_after)
 {
     const size_t nt = g->tanks.size();
     for (auto &pr : g->ev_pending) {
-        int active = 0;
+        int active_iters = 0;
+        int64_t launches = 0;
         double cells = 0.0;
-        for (size_t t = 0; t < nt; ++t)
-            if (pr.iter < iters_after[t] - iters_before[t]) {
-                ++active;
-                cells += g->tanks[t].dev.n_fluid;
-            }
-        if (active == 0) continue;
+        for (int m = pr.iter; m < pr.iter + pr.n_iter; ++m) {
+            int active = 0;
+            for (size_t t = 0; t < nt; ++t)
+                if (m < iters_after[t] - iters_before[t]) {
+                    ++active;
+                    cells += g->tanks[t].dev.n_fluid;
+                }
+            if (active == 0) continue;
+            ++active_iters;
+            launches += (int64_t)g->sc.smax * (g->plan.kind == KIND_MARCH ? 1 : active);
+        }
+        if (active_iters == 0) continue;
         hipError_t e = hipEventSynchronize(g->ev_pool[pr.stop]);
         if (e != hipSuccess) return hip_fail(e, "stage timing");
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, g->ev_pool[pr.start], g->ev_pool[pr.stop]);
         if (e != hipSuccess) return hip_fail(e, "stage timing");
-        g->t_ms += ms;  // s_max back-to-back stage launches
-        g->t_launches += (int64_t)g->sc.smax * (g->plan.kind == KIND_MARCH ? 1 : active);
+        g->t_ms += ms;
+        g->t_launches += launches;
         g->t_cell_stages += cells * g->sc.smax;
     }
     g->ev_pending.clear();
     return VDAC_OK;
 }
 
-// The smallest local pseudo-time step (Sec. 2.2.3) of a host state over the tank's fluid cells:
-// the global step of the first pseudo-iteration after set_state (later ones come from the
-// final stage of the previous iteration).
-double min_local_dtau(const TankHost &th, const double *q)
+// The smallest local pseudo-time step of the tank's current state into its status (the global
+// pseudo-time step of the first iteration after set_state; the final stage of each iteration
+// reduces it for the next), on the device: the tank's residual partials serve as the
+// per-workgroup minima (no stage is running).
+int init_dtau_global(vdac_grid *g, int t)
 {
-    const TankDev &d = th.dev;
-    double m = INFINITY;
-    for (size_t c = 0; c < d.plane; ++c) {
-        if (th.flags[c] & FLAG_SOLID) continue;
-        const double r = q[c], u = q[d.plane + c] / r, v = q[2 * d.plane + c] / r;
-        const double cx = std::sqrt(u * u + 4.0 * d.beta / r), cy = std::sqrt(v * v + 4.0 * d.beta / r);
-        const double dt = d.cfl * (d.dx * d.dy) / (0.5 * (std::fabs(u) + cx) * d.dy + 0.5 * (std::fabs(v) + cy) * d.dx);
-        m = std::min(m, dt);
-    }
-    return m;
+    const TankDev &d = g->tanks[t].dev;
+    const int n_blocks = (int)std::max<size_t>(1, std::min<size_t>(
+        {(size_t)d.n_partials * kPartialWidth, (size_t)kMinBlocksMax, (d.plane + 255) / 256}));
+    double *out = (double *)((char *)d.status + offsetof(Status, dtau_global));
+    return launch_tanks_min(g->tanks_dev, t, 1, g->sc.mixed, MIN_PSEUDO_DTAU, 0.0, d.partials,
+                            n_blocks, out, 1, g->stream);
 }
 
 // Uploads an FP64 state [4][plane] into tank t: plain copies into the three state buffers and
@@ -556,8 +568,9 @@ int upload_state(vdac_grid *g, int t, const double *q)
     Status st;
     std::memset(&st, 0, sizeof st);
     st.done = 1;  // cur = 0
-    st.dtau_global = min_local_dtau(g->tanks[t], q);
+    st.dtau_global = INFINITY;
     if (e == hipSuccess) e = hipMemcpyAsync(d.status, &st, sizeof st, hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess && g->sc.global_dtau) e = (hipError_t)init_dtau_global(g, t);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "uploading the state");
     return VDAC_OK;
@@ -634,6 +647,7 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
     g->plan = plan_for(st, n_tanks, o);
     g->stream = (hipStream_t)hip_stream;
     g->cap_stream = nullptr;
+    g->device = 0;
     if (device_workspace) {
         if (ws_bytes < need) {
             delete g;
@@ -656,6 +670,11 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         g->own_ws = true;
     }
     g->ws_bytes = need;
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        if (g->own_ws) (void)hipFree(g->ws);
+        delete g;
+        return fail(VDAC_E_DEVICE, "no current HIP device");
+    }
 
     Scheme &sc = g->sc;
     std::memset(&sc, 0, sizeof sc);
@@ -677,7 +696,8 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
     const Plan &pl = g->plan;
     g->tanks.resize(n_tanks);
     g->status_host.assign(n_tanks, Status());
-    g->hist = 0;
+    g->hist.assign(n_tanks, 0);
+    g->restored.assign(n_tanks, 0);
     g->timing = false;
     g->t_ms = 0.0;
     g->t_launches = 0;
@@ -725,7 +745,7 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         d.flags = (const uint8_t *)(g->ws + base + L.flags);
         d.partials = (double *)(g->ws + base + L.partials);
         d.status = g->status_dev + t;
-        d.step = g->step_dev;
+        d.step = g->step_dev + t;
         d.n_fluid = n_fluid;
         d.n_partials = pl.n_partials[t];
         d.n_strips = march_strips(d.nx);
@@ -772,6 +792,8 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         return hip_fail(ec, "creating the capture stream");
     }
     ec = hipHostMalloc((void **)&g->status_snap, 2 * (size_t)n_tanks * sizeof(Status), hipHostMallocDefault);
+    if (ec == hipSuccess)
+        ec = hipHostMalloc((void **)&g->step_host, (size_t)n_tanks * sizeof(StepParams), hipHostMallocDefault);
     for (int k = 0; k < 2 && ec == hipSuccess; ++k) ec = hipEventCreateWithFlags(&g->snap_ev[k], hipEventDisableTiming);
     if (ec != hipSuccess) {
         destroy_grid(g);
@@ -804,7 +826,8 @@ int set_state(vdac_grid *g, int32_t tank, const double *q)
     }
     const int rc = upload_state(g, tank, q);
     if (rc != VDAC_OK) return rc;
-    g->hist = 0;
+    g->hist[tank] = 0;
+    g->restored[tank] = 0;
     return VDAC_OK;
 }
 
@@ -814,14 +837,15 @@ namespace {
 // iteration (one per stage for the whole grid with the row-marching kernel, one per stage and tank
 // otherwise) and the residual finalize of all tanks.  The finalize of an iteration runs inside
 // the next iteration's stage-1 launch (extra waves, see IterArgs), except where stage 1 needs its
-// result (the global pseudo-time step) and with the plain kernel; the sequence's last iteration is
-// finalized by a launch of its own.  With timing on, an event pair brackets each iteration's stage
-// launches.
+// result (the global pseudo-time step), where stage 1 is also the last stage (one stage per
+// iteration: that launch writes the partials the finalize would read), and with the plain
+// kernel; the sequence's last iteration is finalized by a launch of its own.  With timing on, an
+// event pair brackets each iteration's stage launches.
 int launch_iterations(vdac_grid *g, hipStream_t stream, int n_iter, int first_iter, size_t *ev_next)
 {
     const int nt = (int)g->tanks.size();
     const Plan &pl = g->plan;
-    const bool defer = !g->sc.global_dtau && pl.kind != KIND_DIRECT;
+    const bool defer = !g->sc.global_dtau && pl.kind != KIND_DIRECT && g->sc.smax > 1;
     int rc;
     for (int it = 0; it < n_iter; ++it) {
         hipEvent_t e1 = nullptr;
@@ -829,7 +853,7 @@ int launch_iterations(vdac_grid *g, hipStream_t stream, int n_iter, int first_it
             hipEvent_t e0 = pool_event(g, *ev_next);
             e1 = pool_event(g, *ev_next + 1);
             if (!e0 || !e1) return fail(VDAC_E_DEVICE, "creating timing events failed");
-            g->ev_pending.push_back({(int)*ev_next, (int)*ev_next + 1, first_iter + it});
+            g->ev_pending.push_back({(int)*ev_next, (int)*ev_next + 1, first_iter + it, 1});
             *ev_next += 2;
             (void)hipEventRecord(e0, stream);
         }
@@ -902,19 +926,24 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
     if (std::isnan(tol)) return fail(VDAC_E_INVALID, "tol is NaN");
     const int nt = (int)g->tanks.size();
     int rc;
-    // Table 1: the order is the grid's, limited by the earlier real-time levels available (the
-    // first step after set_state is backward Euler, the second at most BDF2); dt = +infinity
+    // Table 1: the order is the grid's, limited per tank by the earlier real-time levels it holds
+    // (the first step after set_state is backward Euler, the second at most BDF2); dt = +infinity
     // switches the real-time term off (1/dt = 0: no source, alpha_PI = 1)
-    const int order = std::min(g->sc.bdf, 1 + g->hist);
-    StepParams sp;
-    sp.inv_dt = std::isfinite(dt) ? 1.0 / dt : 0.0;
-    sp.b0 = order == 3 ? 11.0 / 6.0 : (order == 2 ? 1.5 : 1.0);
-    sp.b1 = order == 3 ? -3.0 : (order == 2 ? -2.0 : -1.0);
-    sp.b2 = order == 3 ? 1.5 : (order == 2 ? 0.5 : 0.0);
-    sp.b3 = order == 3 ? -1.0 / 3.0 : 0.0;
-    const int use_history = g->hist > 0;
-    rc = launch_begin_step_all(g->tanks_dev, nt, g->plan.max_plane, g->sc, sp, max_pseudo, tol,
-                               use_history, g->stream);
+    for (int t = 0; t < nt; ++t) {
+        const int order = std::min(g->sc.bdf, 1 + g->hist[t]);
+        StepParams &sp = g->step_host[t];
+        std::memset(&sp, 0, sizeof sp);
+        sp.inv_dt = std::isfinite(dt) ? 1.0 / dt : 0.0;
+        sp.b0 = order == 3 ? 11.0 / 6.0 : (order == 2 ? 1.5 : 1.0);
+        sp.b1 = order == 3 ? -3.0 : (order == 2 ? -2.0 : -1.0);
+        sp.b2 = order == 3 ? 1.5 : (order == 2 ? 0.5 : 0.0);
+        sp.b3 = order == 3 ? -1.0 / 3.0 : 0.0;
+        sp.history = g->restored[t] ? HISTORY_KEEP : (g->hist[t] > 0 ? HISTORY_SHIFT : HISTORY_RESET);
+    }
+    hipError_t e0 = hipMemcpyAsync(g->step_dev, g->step_host, nt * sizeof(StepParams),
+                                   hipMemcpyHostToDevice, g->stream);
+    if (e0 != hipSuccess) return hip_fail(e0, "storing the step's coefficients");
+    rc = launch_begin_step_all(g->tanks_dev, nt, g->plan.max_plane, g->sc, max_pseudo, tol, g->stream);
     if (rc != 0) return hip_fail((hipError_t)rc, "begin_step launch");
     std::vector<int> before(nt, 0);
     // iterations per launch group: with a tolerance, the host checks the stop flags between
@@ -929,15 +958,26 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
         const int n_groups = (max_pseudo + 19) / 20;
         group = n_groups > 0 ? (max_pseudo + n_groups - 1) / n_groups : 0;
     }
-    const bool use_graph = g->opt.graph_iters >= 0 && !g->timing;
+    const bool use_graph = g->opt.graph_iters >= 0;
     if (use_graph && g->opt.graph_iters > 0) group = g->opt.graph_iters;
     size_t ev_next = 0;
     for (int m = 0, k = 0; m < max_pseudo && group > 0;) {
         if (use_graph) {
             hipGraphExec_t exec;
             if ((rc = graph_for(g, group, m % 3, &exec)) != VDAC_OK) return rc;
+            hipEvent_t t0 = nullptr, t1 = nullptr;
+            if (g->timing) {  // an event pair around the replayed graph
+                t0 = pool_event(g, ev_next);
+                t1 = pool_event(g, ev_next + 1);
+                if (!t0 || !t1) return fail(VDAC_E_DEVICE, "creating timing events failed");
+                g->ev_pending.push_back({(int)ev_next, (int)ev_next + 1, m, group});
+                ev_next += 2;
+                hipError_t e = hipEventRecord(t0, g->stream);
+                if (e != hipSuccess) return hip_fail(e, "stage timing");
+            }
             hipError_t e = hipGraphLaunch(exec, g->stream);
             if (e != hipSuccess) return hip_fail(e, "graph launch");
+            if (t1 && (e = hipEventRecord(t1, g->stream)) != hipSuccess) return hip_fail(e, "stage timing");
         } else {
             const int n = (max_pseudo - m < group) ? (max_pseudo - m) : group;
             if ((rc = launch_iterations(g, g->stream, n, m, g->timing ? &ev_next : nullptr)) != VDAC_OK)
@@ -971,7 +1011,10 @@ int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int3
         if (st.diverged && status == VDAC_OK)
             status = fail(VDAC_E_DIVERGED, "tank %d diverged at pseudo-iteration %d", t, st.iters);
     }
-    g->hist = std::min(g->hist + 1, 2);
+    for (int t = 0; t < nt; ++t) {
+        g->hist[t] = std::min(g->hist[t] + 1, 2);
+        g->restored[t] = 0;
+    }
     if (g->timing && (rc = collect_timing(g, before, after)) != VDAC_OK) return rc;
     return status;
 }
@@ -983,16 +1026,18 @@ int realtime_dt(const vdac_grid *g, int32_t tank, double cfl_t, double *dt)
     if (tank < 0 || tank >= (int)g->tanks.size()) return fail(VDAC_E_INVALID, "no tank %d", tank);
     if (!(cfl_t > 0.0) || !std::isfinite(cfl_t)) return fail(VDAC_E_INVALID, "cfl_t must be finite and > 0");
     const TankDev &d = g->tanks[tank].dev;
-    // the tank's residual partials serve as the per-workgroup minima (no stage is running)
-    const int n_blocks = std::max(1, std::min(d.n_partials * kPartialWidth, 1024));
-    hipError_t e = (hipError_t)launch_realtime_dt(d, g->sc.mixed, cfl_t, d.partials, n_blocks, g->stream);
-    std::vector<double> mins(n_blocks);
+    // the tank's residual partials serve as the per-workgroup minima and the result (no stage is
+    // running); the minimum is taken on the device and one double is read back
+    const int n_blocks = (int)std::max<size_t>(1, std::min<size_t>(
+        {(size_t)d.n_partials * kPartialWidth - 1, (size_t)kMinBlocksMax, (d.plane + 255) / 256}));
+    hipError_t e = (hipError_t)launch_tanks_min(g->tanks_dev, tank, 1, g->sc.mixed, MIN_REALTIME_DT,
+                                                cfl_t, d.partials, n_blocks, d.partials + n_blocks, 1,
+                                                g->stream);
+    double m = INFINITY;
     if (e == hipSuccess)
-        e = hipMemcpyAsync(mins.data(), d.partials, n_blocks * sizeof(double), hipMemcpyDeviceToHost, g->stream);
+        e = hipMemcpyAsync(&m, d.partials + n_blocks, sizeof(double), hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "realtime_dt");
-    double m = INFINITY;
-    for (double x : mins) m = std::min(m, x);
     *dt = m;
     return VDAC_OK;
 }
@@ -1060,6 +1105,70 @@ int get_state(const vdac_grid *g, int32_t tank, double *q)
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "get_state");
     if (th.transposed) transpose_state(dst, q, d.ny, d.nx, false);
+    return VDAC_OK;
+}
+
+int get_history(const vdac_grid *g, int32_t tank, double *levels, int32_t *count)
+{
+    g_error.clear();
+    if (!g || !levels || !count) return fail(VDAC_E_INVALID, "grid, levels or count is NULL");
+    if (tank < 0 || tank >= (int)g->tanks.size()) return fail(VDAC_E_INVALID, "no tank %d", tank);
+    const TankHost &th = g->tanks[tank];
+    const TankDev &d = th.dev;
+    // after a completed step, level n holds the state at its start and level n-1 the one before;
+    // levels restored by set_history and not yet stepped on sit one slot further (n-1, n-2)
+    const bool restored = g->restored[tank] != 0;
+    const int n = restored ? g->hist[tank] : std::min(g->hist[tank], g->sc.bdf - 1);
+    const double *src[2] = {restored ? d.level_nm1 : d.level_n, restored ? d.level_nm2 : d.level_nm1};
+    const size_t bytes = 3 * d.plane * sizeof(double);
+    std::vector<double> stored;  // the stored orientation, transposed back below
+    if (th.transposed) stored.resize(3 * d.plane);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+        double *dst = th.transposed ? stored.data() : levels + (size_t)k * 3 * d.plane;
+        e = hipMemcpyAsync(dst, src[k], bytes, hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e == hipSuccess && th.transposed)
+            transpose_state(stored.data(), levels + (size_t)k * 3 * d.plane, d.ny, d.nx, false, 3);
+    }
+    if (e != hipSuccess) return hip_fail(e, "get_history");
+    *count = n;
+    return VDAC_OK;
+}
+
+int set_history(vdac_grid *g, int32_t tank, const double *levels, int32_t count)
+{
+    g_error.clear();
+    if (!g) return fail(VDAC_E_INVALID, "grid is NULL");
+    if (tank < 0 || tank >= (int)g->tanks.size()) return fail(VDAC_E_INVALID, "no tank %d", tank);
+    if (count < 0 || count > 2 || count > g->sc.bdf - 1)
+        return fail(VDAC_E_INVALID, "count must lie in 0..%d for a grid of BDF order %d (got %d)",
+                    std::min(2, g->sc.bdf - 1), g->sc.bdf, count);
+    if (count > 0 && !levels) return fail(VDAC_E_INVALID, "levels is NULL");
+    TankHost &th = g->tanks[tank];
+    const TankDev &d = th.dev;
+    std::vector<double> stored(th.transposed ? 3 * d.plane : 0);
+    double *dst[2] = {d.level_nm1, d.level_nm2};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < count; ++k) {
+        const double *lv = levels + (size_t)k * 3 * d.plane;
+        if (th.transposed) {
+            transpose_state(lv, stored.data(), d.ny, d.nx, true, 3);
+            lv = stored.data();
+        }
+        for (size_t c = 0; c < d.plane; ++c) {
+            if (th.flags[c] & FLAG_SOLID) continue;
+            if (!(lv[c] > 0.0) || !std::isfinite(lv[c]) || !std::isfinite(lv[d.plane + c]) ||
+                !std::isfinite(lv[2 * d.plane + c]))
+                return fail(VDAC_E_INVALID, "tank %d: level %d must be finite with rho > 0 (cell %zu)",
+                            tank, k, c);
+        }
+        e = hipMemcpyAsync(dst[k], lv, 3 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) return hip_fail(e, "set_history");
+    }
+    g->hist[tank] = count;
+    g->restored[tank] = count > 0 ? 1 : 0;
     return VDAC_OK;
 }
 
@@ -1159,6 +1268,7 @@ void destroy_grid(vdac_grid *g)
     for (hipEvent_t e : g->snap_ev)
         if (e) (void)hipEventDestroy(e);
     if (g->status_snap) (void)hipHostFree(g->status_snap);
+    if (g->step_host) (void)hipHostFree(g->step_host);
     drop_graphs(g);
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     if (g->own_ws && g->ws) (void)hipFree(g->ws);

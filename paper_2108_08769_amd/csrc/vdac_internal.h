@@ -60,11 +60,20 @@ struct IterArgs {
 };
 
 
-// Real-time coefficients of the current real step (Table 1), in device memory so that a captured
-// pseudo-iteration graph stays valid from one step to the next.
+// Real-time coefficients of one tank's current real step (Table 1), in device memory so that a
+// captured pseudo-iteration graph stays valid from one step to the next.  Each tank has its own:
+// its BDF order follows the earlier levels it holds, which set_state and set_history change per
+// tank.
+enum : int32_t {
+    HISTORY_RESET = 0,  // begin_step sets the kept earlier levels to the new level n
+    HISTORY_SHIFT = 1,  // begin_step shifts the levels: n-2 <- n-1 <- n
+    HISTORY_KEEP = 2,   // the earlier levels were restored (set_history): begin_step keeps them
+};
 struct StepParams {
     double inv_dt;          // 1/dt (0: pseudo-time only)
     double b0, b1, b2, b3;  // BDF coefficients: dQ/dt = (b0 Q^0 + b1 Q^n + b2 Q^{n-1} + b3 Q^{n-2})/dt
+    int32_t history;        // HISTORY_*: what begin_step does with levels n-1 and n-2
+    int32_t pad;
 };
 
 // Number of doubles per work unit in the residual partials: four field sums (or maxima), the
@@ -110,7 +119,7 @@ struct TankDev {
     const uint8_t *flags;
     double *partials;         // [n_partials][kPartialWidth]
     Status *status;
-    const StepParams *step;
+    const StepParams *step;   // this tank's coefficients of the current real step
     int32_t n_fluid;
     int32_t n_partials;       // residual partials one stage launch writes for this tank
     int32_t n_strips;         // row-marching kernel: 64-column strips across the tank
@@ -150,11 +159,10 @@ struct Scheme {
 // the device unit table in one launch per stage, with `waves_per_block` table entries per
 // workgroup and a register budget of `waves_simd` (2 or 3) waves per SIMD; begin_step and
 // finalize cover all tanks in one launch each.
-// begin_step: use_history = 1 moves level n to level n-1 (BDF2 after a completed step); 0 sets
-// level n-1 (if kept) to the new level n.
+// begin_step: each tank's StepParams (in device memory before the launch) give its BDF
+// coefficients and what happens to its earlier levels (HISTORY_*).
 int launch_begin_step_all(const TankDev *tanks_dev, int n_tanks, size_t max_plane, const Scheme &sc,
-                          const StepParams &sp, int max_pseudo, double tol, int use_history,
-                          void *stream);
+                          int max_pseudo, double tol, void *stream);
 int launch_finalize_all(const TankDev *tanks_dev, int n_tanks, const Scheme &sc, void *stream);
 // The per-tank stage launches: the plain kernel never finalizes (ia.fin must be 0); the tiled
 // kernel runs the finalize of its tank in one extra workgroup when ia.fin is set.
@@ -168,10 +176,18 @@ int launch_stage_march(const TankDev *tanks_dev, const MarchUnit *units, int n_e
 int launch_stage_march_general(const TankDev *tanks_dev, const MarchUnit *units, int n_entries,
                                int waves_per_block, const Scheme &sc, int stage, const IterArgs &ia,
                                void *stream);
-// Global real-time step of one tank (Sec. 2.2.4): per-workgroup minima of
-// CFL_t dx dy / (|u| dy + |v| dx) over the fluid cells of the current state into out[n_blocks].
-int launch_realtime_dt(const TankDev &t, int mixed, double cfl_t, double *out, int n_blocks,
-                       void *stream);
+// Minima over the fluid cells of the current states of tanks first .. first + n_tanks - 1 (device
+// table), in two launches: blocks_per_tank per-workgroup minima per tank into
+// scratch[n_tanks][blocks_per_tank], then each tank's minimum (fixed order) into
+// out[k * out_stride].  kind MIN_REALTIME_DT: the global real-time step of Sec. 2.2.4,
+// CFL_t dx dy / (|u| dy + |v| dx) with CFL_t = cfl (infinity at rest); kind MIN_PSEUDO_DTAU: the
+// smallest local pseudo-time step of Sec. 2.2.3 (the tank's own CFL_tau; cfl unused).
+// blocks_per_tank in 1..kMinBlocksMax; every scratch slot is written before it is read.
+enum { MIN_REALTIME_DT = 0, MIN_PSEUDO_DTAU = 1 };
+constexpr int kMinBlocksMax = 1024;
+int launch_tanks_min(const TankDev *tanks_dev, int first, int n_tanks, int mixed, int kind,
+                     double cfl, double *scratch, int blocks_per_tank, double *out, int out_stride,
+                     void *stream);
 // Conversions between the caller's FP64 conserved state [4][ny][nx] (rho, rho u, rho v, p) in
 // device memory and the mixed form's storage (cur = 0 after import).
 int launch_import_mixed(const TankDev &t, const double *q, void *stream);

@@ -22,8 +22,9 @@ FP64, FP32_MIXED = 0, 1
 NORM_RMS, NORM_MAX = 0, 1
 
 EXPORTS = ("vdac_default_options", "workspace_bytes", "create_grid", "set_state",
-           "step_dual_time", "residual_norm", "get_state", "stage_timing", "stage_timing_read",
-           "autotune_tile", "realtime_dt", "destroy_grid", "last_error")
+           "step_dual_time", "residual_norm", "get_state", "get_history", "set_history",
+           "stage_timing", "stage_timing_read", "autotune_tile", "realtime_dt", "destroy_grid",
+           "last_error")
 
 
 class VdacError(RuntimeError):
@@ -97,6 +98,10 @@ def lib():
         L.residual_norm.restype = ctypes.c_int
         L.get_state.argtypes = [vp, ctypes.c_int32, dp]
         L.get_state.restype = ctypes.c_int
+        L.get_history.argtypes = [vp, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int32)]
+        L.get_history.restype = ctypes.c_int
+        L.set_history.argtypes = [vp, ctypes.c_int32, dp, ctypes.c_int32]
+        L.set_history.restype = ctypes.c_int
         L.stage_timing.argtypes = [vp, ctypes.c_int32]
         L.stage_timing.restype = ctypes.c_int
         L.stage_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp]
@@ -285,3 +290,23 @@ class Grid:
         q = np.zeros((4, ny, nx))
         _check(self._lib.get_state(self._h, tank, q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return q
+
+    def get_history(self, tank: int = 0) -> np.ndarray:
+        """The earlier real-time levels [count, 3, ny, nx] (rho, rho u, rho v) the next step would
+        use (Table 1), newest first."""
+        ny, nx = self._shapes[tank]
+        lv = np.zeros((2, 3, ny, nx))
+        n = ctypes.c_int32()
+        _check(self._lib.get_history(self._h, tank, lv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     ctypes.byref(n)))
+        return lv[:n.value].copy()
+
+    def set_history(self, tank: int, levels: np.ndarray):
+        """Restores earlier real-time levels [count, 3, ny, nx] after set_state."""
+        ny, nx = self._shapes[tank]
+        lv = np.zeros((2, 3, ny, nx))
+        n = int(len(levels))
+        if n:
+            lv[:n] = np.asarray(levels, dtype=np.float64)
+        _check(self._lib.set_history(self._h, tank, lv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     n))
