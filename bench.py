@@ -1,39 +1,45 @@
 """Benchmark: cell-updates per second per pseudo-time stage of the dual-time Godunov solver.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dam_break] [--precision f64]
-                    [--tile autotune|0x0|-WxL|TXxTY] [--unbatched] [--cpu-budget S] [--no-mixed]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload obstacle_dam_break]
+                    [--precision f64] [--tile autotune|0x0|-WxL|TXxTY] [--unbatched]
+                    [--cpu-budget S] [--no-mixed] [--no-extra]
 
 A step is one real-time step (Algorithm 1): level n <- state, then pseudo-iterations of
 s_max Runge-Kutta stages until the RMS residual is below the workload's tolerance or the
-iteration cap is reached.  The default workload is the 512 x 256 dam break (water column
-x < 1, y < 1 in a 4 x 2 walled tank, beta = 1100, dt = 1e-4, up to 100 pseudo-iterations to an
-RMS residual of 1e-6) in FP64, synthetic initial data; other workloads: hydrostatic,
-rayleigh_taylor, obstacle_dam_break (4096 x 4096), sloshing_ensemble (512 tanks).  The
-stage-kernel shape comes from the library's autotuner (untimed, before the warmup).  The state
-stays resident in HBM for the whole timed region; nothing crosses PCIe inside it except the
-per-step status read.
+iteration cap is reached.  The default workload is the largest single-GPU configuration, the
+4096 x 4096 dam break with a rectangular obstacle (4 x 4 walled tank, water at x < 1, y < 2,
+solid cells at 2.5 < x < 2.7, y < 0.3, density ratio 1000:1, beta = 1100, dt = 2e-5, exactly 50
+pseudo-iterations per step) in FP64, synthetic initial data; its planes (about 2 GB) exceed the
+256 MB last-level cache, so the stage kernel streams from HBM.  Other workloads: hydrostatic,
+dam_break (512 x 256), rayleigh_taylor, sloshing_ensemble (512 tanks).  The stage-kernel shape
+comes from the library's autotuner (untimed, before the warmup).  The state stays resident in
+HBM for the whole timed region; nothing crosses PCIe inside it except the per-step status read.
 
 value = fluid cells x stages executed / seconds over exactly K timed steps (kernels replayed
-from captured HIP graphs).  K defaults to the workload's own step count (500 for the dam
-break), and the timed steps start from the initial state (it is set again after the W warmup
-steps), so the timed region is the workload's whole run.  The roofline entry is the Runge-Kutta stage kernel: algorithmic
-bytes per launch (per fluid cell-stage 109.3 B for FP64, the mean of 88 B at stage 1 and 120 B
-at later stages of a three-stage scheme; 74.7 B for the mixed form, 64 and 80 B) divided by its
-mean launch duration.  That duration is measured live with HIP events on the library's stream,
-in a measurement pass of K further steps right after the timed region (kernels launched one by
-one, an event pair around each pseudo-iteration's s_max stage launches, so it includes the
-dispatch gaps between them).  traffic is the copy-calibrated FETCH_SIZE + WRITE_SIZE bytes per
+from captured HIP graphs).  K defaults to the workload's own step count (200 for the obstacle
+case), and the timed steps start from the initial state (it is set again after the W warmup
+steps), so the timed region is the workload's whole run.  The roofline entry is the Runge-Kutta
+stage kernel: algorithmic bytes per launch (per fluid cell-stage 109.3 B for FP64, the mean of
+88 B at stage 1 and 120 B at later stages of a three-stage scheme; 74.7 B for the mixed form, 64
+and 80 B) divided by its mean launch duration.  That duration is measured live inside the timed
+region with HIP events on the library's stream: an event pair around every replayed graph of
+pseudo-iterations, whose time divided by its stage launches is the mean (it includes the
+dispatch gaps between the launches, the graph's one finalize launch and, with a tolerance, the
+kernels of stopped tanks, which return at once; launches x mean <= the timed region).  traffic
+is the copy-calibrated FETCH_SIZE + WRITE_SIZE bytes per
 launch from the committed counter summaries in profiles/, reported only while the kernel
 sources still hash to what was profiled.  valu is, from the same summaries, the stage kernel's
 VALU instructions (SQ_INSTS_VALU x 64 lanes) per fluid cell-stage and their issue rate against
 the chip's 39.3 T lane-instructions/s.  regime says whether the grid's planes exceed the 256 MB
 last-level cache (below it, achieved is an effective rate, not HBM traffic).  stream_reference
 sets the achieved rate beside the best rate of a plain plane-stream kernel of the library on the
-same device (the FP64 stage's 11 planes in, 4 out, and a copy).  cpu_baseline times the serial FP64 oracle on a bounded
-sample of the same workload, cpu_baseline_all_cores the same source built with -fopenmp on all
-the host's threads.  An FP64 line also reports mixed_form: the mixed-precision form on the
-same workload and steps, timed the same way after the FP64 measurement, with its speedup
-(--no-mixed skips it).
+same device (the FP64 stage's 11 planes in, 4 out, and a copy).  cpu_baseline times the serial
+FP64 oracle on a bounded sample of the same workload (for the 4096^2 case a 2048 x 512 window of
+the tank with the dam front and the obstacle), cpu_baseline_all_cores the same source built with
+-fopenmp on all the host's threads.  An FP64 line also reports mixed_form: the mixed-precision
+form on the same workload and steps, timed the same way after the FP64 measurement, with its
+speedup (--no-mixed skips it).  The default line also carries extra_workloads: the 512 x 256 dam
+break (cache-resident) in both forms, K of its steps (--no-extra skips it).
 """
 from __future__ import annotations
 
@@ -121,13 +127,39 @@ def cpu_model() -> str:
     return "unknown"
 
 
+# The CPU baseline's sample of the 4096^2 obstacle case: columns 896..2943 and rows 0..511 of the
+# tank (the dam front at x = 1, the obstacle at 2.5 < x < 2.7, y < 0.3), walls around the window.
+# One oracle pseudo-iteration of the whole tank takes about 20 s on one core; the window's takes
+# about 1.3 s, with the same work per cell.
+CPU_WINDOW = {"obstacle_dam_break_4096x4096": (896, 2944, 0, 512)}
+
+
+def sample_tank(wk):
+    """The tank the CPU baseline times: the first tank (the only one, except in the ensemble), or
+    its window for the 4096^2 case; and a phrase saying which."""
+    import numpy as np
+    from paper_2108_08769_amd import workloads as wl
+    t = wk.tanks[0]
+    if wk.name in CPU_WINDOW:
+        i0, i1, j0, j1 = CPU_WINDOW[wk.name]
+        dx, dy = t.lx / t.nx, t.ly / t.ny
+        solid = None if t.solid is None else np.ascontiguousarray(t.solid[j0:j1, i0:i1])
+        w = wl.Tank(i1 - i0, j1 - j0, (i1 - i0) * dx, (j1 - j0) * dy,
+                    np.ascontiguousarray(t.q[:, j0:j1, i0:i1]), gx=t.gx, gy=t.gy, beta=t.beta,
+                    bc=t.bc, solid=solid)
+        return w, (f" (a {w.nx}x{w.ny} window of the tank: columns {i0}..{i1 - 1}, rows "
+                   f"{j0}..{j1 - 1}, walls around it)")
+    return t, (f" (its first tank, {t.nx}x{t.ny})" if len(wk.tanks) > 1 else "")
+
+
 def cpu_baseline(wk, budget_s: float, omp: bool = False):
     """The oracle (FP64 C) timed on a bounded sample of the workload: real steps from the initial
-    state of its first tank (the only tank, except in the ensemble), each with as many
-    pseudo-iterations as the budget allows (up to the workload's cap), until the budget is used.  omp=False is the oracle as it stands (serial); omp=True the same
-    source built with -fopenmp on all host threads (same results)."""
+    state of its sample tank (sample_tank), each with as many pseudo-iterations as the budget
+    allows (up to the workload's cap), until the budget is used.  omp=False is the oracle as it
+    stands (serial); omp=True the same source built with -fopenmp on all host threads (same
+    results)."""
     import oracle
-    t = wk.tanks[0]
+    t, what = sample_tank(wk)
     pb = oracle.Problem(t.nx, t.ny, t.lx, t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
                         solid=t.solid, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl, k=wk.k,
                         local_dtau=wk.local_dtau, bdf=1)
@@ -147,7 +179,6 @@ def cpu_baseline(wk, budget_s: float, omp: bool = False):
     dt = time.perf_counter() - t0
     cell_stages = t.fluid_cells * wk.stages * total_it
     threads = oracle.threads(omp)
-    what = f" (its first tank, {t.nx}x{t.ny})" if len(wk.tanks) > 1 else ""
     return {"value": cell_stages / dt, "unit": "cell-updates/s per pseudo-time stage",
             "cores": threads, "kind": "oracle" if not omp else "oracle, -fopenmp build of the same source",
             "cpu": cpu_model(), "host_threads": os.cpu_count(),
@@ -157,8 +188,9 @@ def cpu_baseline(wk, budget_s: float, omp: bool = False):
 
 
 def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
-    """Warm-up, then the timed region of exactly args.steps real steps of wk, then (timing) the
-    measurement pass for the roofline; returns the rate and what the JSON line reports."""
+    """Warm-up, then the timed region of exactly args.steps real steps of wk (with timing, the
+    stage-kernel events inside it give the roofline); returns the rate and what the JSON line
+    reports."""
     tanks = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
                   solid=t.solid) for t in wk.tanks]
     opts = vdac.make_options(precision=wk.precision, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl,
@@ -196,7 +228,11 @@ def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
             g.set_state(i, t.q)
     torch.cuda.synchronize()
 
-    # timed region: exactly K steps, kernels replayed from captured graphs, no instrumentation
+    # timed region: exactly K steps, kernels replayed from captured graphs, with an event pair
+    # around each replayed graph on the library's stream (the stage-kernel time)
+    if timing:
+        for g in grids:
+            g.stage_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = 0
@@ -208,14 +244,8 @@ def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
-    # measurement pass: the same number of further steps, launched one by one, with a HIP event
-    # pair around each pseudo-iteration's back-to-back stage kernels on the library's stream
     roofline = None
     if timing:
-        for g in grids:
-            g.stage_timing(True)
-        for _ in range(args.steps):
-            step_all()
         kms, launches, kcs = 0.0, 0, 0.0
         for g in grids:
             a, b, c = g.stage_timing_read()
@@ -231,13 +261,18 @@ def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
             cells = kcs / launches
             grid_cells = sum(t.nx * t.ny for t in wk.tanks)
             plane_bytes = grid_cells * (PLANE_BYTES[wk.precision] + 32 * (wk.bdf - 1))
-            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            resident = plane_bytes > LLC_BYTES
+            roofline = {"bound": "hbm" if resident else "llc",
+                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                         "traffic": None if traffic is None else round(traffic / 1e9, 6),
                         "traffic_unit": "GB per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)",
                         "kernel": "stage", "avg_launch_us": round(avg_s * 1e6, 3),
                         "launches": launches, "bytes_per_launch": bytes_per_launch,
-                        "regime": ("HBM-resident" if plane_bytes > LLC_BYTES else
+                        "timed_ms_in_brackets": round(kms, 3),
+                        "timed_region_ms": round(elapsed * 1e3, 3),
+                        "regime": ("HBM-resident: the grid's planes (%.2f GB) exceed the 256 MB "
+                                   "last-level cache" % (plane_bytes / 1e9) if resident else
                                    "cache-resident: the grid's planes (%.0f MB) fit the 256 MB "
                                    "last-level cache, so achieved is an effective rate (algorithmic "
                                    "bytes / launch time), not HBM traffic" % (plane_bytes / 1e6)),
@@ -289,7 +324,7 @@ def main():
                     help="timed real steps (0: the workload's own step count, e.g. 500 for the "
                          "dam break)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="dam_break")
+    ap.add_argument("--workload", default="obstacle_dam_break")
     ap.add_argument("--precision", default="f64")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
@@ -313,6 +348,8 @@ def main():
     ap.add_argument("--bdf", type=int, default=0, help="BDF order (0: the workload's)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run that an FP64 line reports beside it")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 512 x 256 dam break that the default line reports beside it")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only copy this many MiB device to device 20 times and print the rate "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -401,7 +438,8 @@ def main():
                 wkm.bdf = args.bdf
             if args.global_dtau:
                 wkm.local_dtau = False
-            rm = measure(vdac, np, torch, wkm, args, tune, tile, flux, pgrad, timing=False)
+            rm = measure(vdac, np, torch, wkm, args, tune, tile, flux, pgrad,
+                         timing=not args.no_stage_timing)
             line["mixed_form"] = {"value": rm["value"], "unit": line["unit"],
                                   "ms_per_step": rm["elapsed"] * 1e3 / args.steps,
                                   "speedup_vs_f64": rm["value"] / value, "dtype": "f32+f64",
@@ -409,7 +447,23 @@ def main():
                                   "pseudo_iterations": rm["iters"],
                                   "note": "same workload, steps and timing; FP32 storage as deviations "
                                           "from FP64 level n, FP32 reconstruction and fluxes, FP64 "
-                                          "residual, sources and update"}
+                                          "residual, sources and update",
+                                  "roofline": rm["roofline"]}
+    # the cache-resident 512 x 256 dam break beside the default workload (both forms, K steps)
+    if args.workload == "obstacle_dam_break" and not args.no_extra and not args.unbatched:
+        extra = {}
+        for prec in ("f64", "mixed"):
+            wke = build_workload("dam_break", prec)
+            re_ = measure(vdac, np, torch, wke, args, tune, (0, 0) if tune else tile, flux, pgrad,
+                          timing=False)
+            extra[prec] = {"value": re_["value"], "ms_per_step": re_["elapsed"] * 1e3 / args.steps,
+                           "tile": re_["chosen"] + (" (autotuned)" if tune else ""),
+                           "pseudo_iterations": re_["iters"]}
+        extra["f64"]["unit"] = line["unit"]
+        extra["mixed_speedup_vs_f64"] = extra["mixed"]["value"] / extra["f64"]["value"]
+        extra["note"] = ("dam break 512 x 256 (water x < 1, y < 1 in a 4 x 2 tank, dt = 1e-4, up "
+                         "to 100 pseudo-iterations to 1e-6), its first K steps; cache-resident")
+        line["extra_workloads"] = {wke.name: extra}
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(wk, args.cpu_budget)
         line["cpu_baseline_all_cores"] = cpu_baseline(wk, args.cpu_budget, omp=True)
