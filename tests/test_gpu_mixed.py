@@ -10,6 +10,13 @@ L-infinity error max |mixed - fp64| / max |fp64| over fluid cells must stay with
 and rho within 1e-6; rho v, near zero early in a dam break, is held to 1e-5 against its physical
 scale (rho_max sqrt(|g| L)).  Every case prints its per-field errors.
 
+Where a tank has barely left rest (the sloshing ensemble's small-tilt tanks after two steps,
+Rayleigh-Taylor in its first ~0.05 s), max |rho u| falls to ~1e-4 of its physical scale and the
+plain normwise rho u error exceeds the 1e-5 target (measured up to 1.04e-5 and 1.8e-5) while the
+absolute difference stays near 1e-8.  Those tests hold the floored error (denominator at least 1%
+of the physical scale) to 1e-5, and the plain figure to the level measured there (2e-5 for the
+ensemble, 3e-5 over time), and print both: the target is missed literally in these two cases.
+
 Batched form: a grid of many tanks runs every stage of every tank in one launch from a unit
 table; each tank must come out bit for bit as it does in a grid of its own, and match the oracle
 at the FP64 bar (1e-12).
@@ -37,10 +44,11 @@ def normwise(a, b, solid=None):
     return out
 
 
-def check_mixed(wk, steps, pseudo, ref="gpu", floor=0.0, **kw):
+def check_mixed(wk, steps, pseudo, ref="gpu", floor=0.0, plain_rho_u=None, **kw):
     """Runs wk in the mixed form and in FP64 (GPU or oracle) and applies BAR.  floor > 0 floors
     the normwise denominator of each field at floor x its physical scale (for tanks that have
-    barely left rest, where max |field| is not a meaningful scale)."""
+    barely left rest, where max |field| is not a meaningful scale); the plain normwise rho u
+    error is then held to plain_rho_u and printed as well."""
     print(f"[mixed] {wk.name} tanks={len(wk.tanks)} steps={steps} pseudo={pseudo} ref={ref} {kw}",
           flush=True)
     m_states, m_it, _, m_codes = run_gpu(wk, steps, pseudo, precision="mixed", **kw)
@@ -51,11 +59,15 @@ def check_mixed(wk, steps, pseudo, ref="gpu", floor=0.0, **kw):
     assert all(c == 0 for c in m_codes) and all(c == 0 for c in r_codes), (m_codes, r_codes)
     np.testing.assert_array_equal(m_it, r_it)
     worst = np.zeros(4)
+    worst_plain = 0.0
     for t, a, b in zip(wk.tanks, m_states, r_states):
         nw = normwise(a, b, t.solid)
+        plain = nw[1]
+        worst_plain = max(worst_plain, plain)
         sc = field_errors(a, b, t.solid, field_scales(t))
         if floor > 0:
             nw = field_errors(a, b, t.solid, floor * field_scales(t))
+            assert plain_rho_u is not None and plain <= plain_rho_u, (t.nx, t.ny, plain)
         if nw[1] > 0.5 * BAR["rho_u"]:
             print(f"[mixed]   tank {t.nx}x{t.ny}: max|rho u| {np.abs(b[1]).max():.3e}, "
                   f"normwise {nw}, scaled {sc}", flush=True)
@@ -65,7 +77,8 @@ def check_mixed(wk, steps, pseudo, ref="gpu", floor=0.0, **kw):
         assert sc[2] <= BAR["rho_v"], (t.nx, t.ny, sc)
         assert nw[3] <= BAR["p"], (t.nx, t.ny, nw)
     print(f"[mixed]   worst normwise error rho {worst[0]:.2e} rho_u {worst[1]:.2e} "
-          f"rho_v(scaled) {worst[2]:.2e} p {worst[3]:.2e}", flush=True)
+          f"rho_v(scaled) {worst[2]:.2e} p {worst[3]:.2e}; plain normwise rho_u {worst_plain:.2e}",
+          flush=True)
     return worst
 
 
@@ -98,16 +111,19 @@ def test_mixed_error_vs_time(name, steps):
     a physical scale of 6) while the absolute difference stays near 1e-8, so the plain normwise
     error of rho u peaks near 2e-5 without any loss of accuracy.  The bar therefore floors each
     field's normwise denominator at 1% of its physical scale (as for the ensemble); the plain
-    normwise error is printed beside it."""
+    normwise error is printed beside it and held to 3e-5, the level measured there (the 1e-5
+    target is missed literally while the flow is that close to rest)."""
     wk = getattr(wl, name)()
     t = wk.tanks[0]
     tank = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc)]
     grids = {p: vdac.Grid(tank, gpu_options(wk, p)) for p in ("mixed", "f64")}
     bar = np.array([BAR["rho"], BAR["rho_u"], BAR["rho_v"], BAR["p"]])
+    plain_bar = 3e-5
     try:
         for g in grids.values():
             g.set_state(0, t.q)
         worst = np.zeros(4)
+        worst_plain = 0.0
         for step in range(1, steps + 1):
             its = {}
             for p, g in grids.items():
@@ -117,18 +133,21 @@ def test_mixed_error_vs_time(name, steps):
             a, b = grids["mixed"].get_state(0), grids["f64"].get_state(0)
             fl = field_errors(a, b, None, 0.01 * field_scales(t))
             worst = np.maximum(worst, fl)
+            nw = normwise(a, b)
+            worst_plain = max(worst_plain, nw[1])
             if step % 10 == 0 or step == 1:
-                nw = normwise(a, b)
                 print(f"[mixed] {wk.name} t={step * wk.dt:.4f} iterations {its['mixed']}/"
                       f"{its['f64']} max|rho u| {np.abs(b[1]).max():.2e} error (floored) "
                       f"{fl[0]:.1e} {fl[1]:.1e} {fl[2]:.1e} {fl[3]:.1e} (plain normwise "
                       f"{nw[0]:.1e} {nw[1]:.1e} {nw[2]:.1e} {nw[3]:.1e})", flush=True)
             assert abs(its["mixed"] - its["f64"]) <= 1, (step, its)
             assert np.all(fl <= bar), (step, fl)
+            assert nw[1] <= plain_bar, (step, nw)
     finally:
         for g in grids.values():
             g.close()
-    print(f"[mixed]   {wk.name} worst (floored) over {steps} steps: {worst}", flush=True)
+    print(f"[mixed]   {wk.name} worst (floored) over {steps} steps: {worst}; plain normwise "
+          f"rho u {worst_plain:.2e}", flush=True)
 
 
 def test_mixed_obstacle_vs_fp64():
@@ -436,8 +455,9 @@ def test_batched_mixed_vs_fp64_full_ensemble():
     """All 512 tanks, two real steps of the configured 50 pseudo-iterations.  Tanks with a small
     drawn tilt are still close to rest then (max |rho u| down to ~1e-6 of rho_max sqrt(|g| L)),
     where the normwise ratio measures rounding against a vanishing denominator; the denominator
-    is therefore floored at 1% of each field's physical scale."""
-    check_mixed(wl.sloshing_ensemble(), steps=2, pseudo=50, floor=0.01)
+    is therefore floored at 1% of each field's physical scale.  The plain normwise rho u error,
+    the target's own figure, reached 1.04e-5 on one tank (112 x 240) and is held to 2e-5."""
+    check_mixed(wl.sloshing_ensemble(), steps=2, pseudo=50, floor=0.01, plain_rho_u=2e-5)
 
 
 # ---- autotuner ------------------------------------------------------------------------------
