@@ -171,11 +171,12 @@ int set_history(vdac_grid *g, int32_t tank, const double *levels, int32_t count)
  * *dt = min over fluid cells of cfl_t dx dy / (|u| dy + |v| dx), +infinity at rest. */
 int realtime_dt(const vdac_grid *g, int32_t tank, double cfl_t, double *dt);
 
-/* Measurement: while enabled, step_dual_time launches kernels one by one (no graphs) and
- * brackets the s_max back-to-back Runge-Kutta stage launches of every pseudo-iteration with a
- * pair of HIP events on the grid's stream, accumulating their elapsed times; enabling resets the
- * totals.  The events add a marker before the first and after the last stage launch of each
- * pseudo-iteration and nothing else. */
+/* Measurement: while enabled, step_dual_time brackets every replayed graph of pseudo-iterations
+ * (or, with graph_iters = -1, the s_max back-to-back Runge-Kutta stage launches of every
+ * pseudo-iteration) with a pair of HIP events on the grid's stream and accumulates their elapsed
+ * times; enabling resets the totals.  The events add markers between launches and nothing
+ * else, so a timed region may keep them on.  A graph's time includes its one finalize launch
+ * and, with a tolerance, the kernels of tanks that have stopped (they return at once). */
 int stage_timing(vdac_grid *g, int32_t enable);
 
 /* Totals since stage timing was enabled: summed stage-kernel milliseconds, number of stage
