@@ -106,6 +106,30 @@ __device__ __forceinline__ Vec4<T> cast4(const Vec4<U> &a)
     return {(T)a.a, (T)a.b, (T)a.c, (T)a.d};
 }
 
+// Loads and stores at a 32-bit byte offset from a wave-uniform base in the global address space:
+// the base stays in scalar registers and one vector register holds the offset, shared by every
+// plane of a row (a plane holds fewer than 2^29 cells, so its byte offsets fit 32 bits).
+template <typename T>
+__device__ __forceinline__ T gld(const T *base, uint32_t off)
+{
+    using GC = __attribute__((address_space(1))) const char;
+    using GT = __attribute__((address_space(1))) const T;
+    return *(GT *)((GC *)base + off);
+}
+template <typename T>
+__device__ __forceinline__ void gst(T *base, uint32_t off, T v)
+{
+    using GC = __attribute__((address_space(1))) char;
+    using GT = __attribute__((address_space(1))) T;
+    *(GT *)((GC *)base + off) = v;
+}
+
+// Byte offsets of this lane's column within a row: in the state's element type, in FP64 (the
+// real-time levels) and in bytes (the flags).
+struct LaneOff {
+    uint32_t s, d, f;
+};
+
 // Loads of one row, issued one step ahead of their use: the stage input is fetched two rows
 // ahead (it is the upper neighbour of the next row), the stage-0 state, level n (and level
 // n-1) and the flags one row ahead.
@@ -127,34 +151,35 @@ struct SourceLoad {
 // the nearest row of the tank.  The cells outside the tank are not fluid (their flag reads
 // FLAG_SOLID), and every use of their values is guarded by that flag or by the wall flags of
 // their fluid neighbours, which take ghosts instead; loading a real cell there keeps the loads
-// unconditional and the values finite.
+// unconditional and the values finite.  r is wave-uniform, and so is the result.
 __device__ __forceinline__ int load_row(const TankDev &t, int r, bool &inside)
 {
     int gj;
     inside = locate_axis(r, t.ny, t.per_y, gj);
-    return inside ? gj : (r < 0 ? 0 : t.ny - 1);
+    return uni(inside ? gj : (r < 0 ? 0 : t.ny - 1));
 }
 
-// gi: this lane's column, inside the tank (the nearest column where the lane lies outside).
 template <class P>
 __device__ __forceinline__ InputLoad<P> load_input(const TankDev &t,
                                                    const typename P::Store *__restrict__ qprev,
-                                                   int gi, int r)
+                                                   const LaneOff &lo, int r)
 {
+    using S = typename P::Store;
     bool inside;
-    const int gj = load_row(t, r, inside);
+    const uint32_t row = (uint32_t)load_row(t, r, inside) * (uint32_t)t.nx;
+    const uint32_t os = row * (uint32_t)sizeof(S) + lo.s;
     const size_t plane = t.plane;
-    const size_t c = (size_t)gj * t.nx + gi;
     InputLoad<P> L;
-    L.r = qprev[c];
-    L.m = qprev[plane + c];
-    L.n = qprev[2 * plane + c];
-    L.p = qprev[3 * plane + c];
+    L.r = gld(qprev, os);
+    L.m = gld(qprev + plane, os);
+    L.n = gld(qprev + 2 * plane, os);
+    L.p = gld(qprev + 3 * plane, os);
     if (P::kMixed) {
-        L.lr = t.level_n[c];
-        L.lm = t.level_n[plane + c];
-        L.ln = t.level_n[2 * plane + c];
-        L.lp = t.level_n[3 * plane + c];
+        const uint32_t od = row * 8u + lo.d;
+        L.lr = gld(t.level_n, od);
+        L.lm = gld(t.level_n + plane, od);
+        L.ln = gld(t.level_n + 2 * plane, od);
+        L.lp = gld(t.level_n + 3 * plane, od);
     } else {
         L.lr = L.lm = L.ln = L.lp = 0.0;
     }
@@ -165,41 +190,42 @@ __device__ __forceinline__ InputLoad<P> load_input(const TankDev &t,
 template <class P, int BDF, bool Z = true>
 __device__ __forceinline__ SourceLoad<P> load_sources(const TankDev &t,
                                                       const typename P::Store *__restrict__ q0,
-                                                      bool have_col, int gi, int r)
+                                                      bool have_col, const LaneOff &lo, int r)
 {
+    using S = typename P::Store;
     bool inside;
-    const int gj = load_row(t, r, inside);
+    const uint32_t row = (uint32_t)load_row(t, r, inside) * (uint32_t)t.nx;
+    const uint32_t os = row * (uint32_t)sizeof(S) + lo.s, od = row * 8u + lo.d;
     const size_t plane = t.plane;
-    const size_t c = (size_t)gj * t.nx + gi;
     SourceLoad<P> L;
-    const uint8_t f = t.flags[c];
+    const uint8_t f = gld(t.flags, row + lo.f);
     L.f = (have_col && inside) ? f : (uint8_t)FLAG_SOLID;
     if constexpr (Z) {
-        L.z0 = q0[c];
-        L.z1 = q0[plane + c];
-        L.z2 = q0[2 * plane + c];
-        L.z3 = q0[3 * plane + c];
+        L.z0 = gld(q0, os);
+        L.z1 = gld(q0 + plane, os);
+        L.z2 = gld(q0 + 2 * plane, os);
+        L.z3 = gld(q0 + 3 * plane, os);
     } else {
         L.z0 = L.z1 = L.z2 = L.z3 = 0;
     }
     if (!P::kMixed) {  // the mixed form takes level n from the input row (it carries it)
-        L.n0 = t.level_n[c];
-        L.n1 = t.level_n[plane + c];
-        L.n2 = t.level_n[2 * plane + c];
+        L.n0 = gld((const double *)t.level_n, od);
+        L.n1 = gld((const double *)t.level_n + plane, od);
+        L.n2 = gld((const double *)t.level_n + 2 * plane, od);
     } else {
         L.n0 = L.n1 = L.n2 = 0.0;
     }
     if (BDF >= 2) {
-        L.m0 = t.level_nm1[c];
-        L.m1 = t.level_nm1[plane + c];
-        L.m2 = t.level_nm1[2 * plane + c];
+        L.m0 = gld((const double *)t.level_nm1, od);
+        L.m1 = gld((const double *)t.level_nm1 + plane, od);
+        L.m2 = gld((const double *)t.level_nm1 + 2 * plane, od);
     } else {
         L.m0 = L.m1 = L.m2 = 0.0;
     }
     if (BDF >= 3) {
-        L.k0 = t.level_nm2[c];
-        L.k1 = t.level_nm2[plane + c];
-        L.k2 = t.level_nm2[2 * plane + c];
+        L.k0 = gld((const double *)t.level_nm2, od);
+        L.k1 = gld((const double *)t.level_nm2 + plane, od);
+        L.k2 = gld((const double *)t.level_nm2 + 2 * plane, od);
     } else {
         L.k0 = L.k1 = L.k2 = 0.0;
     }
@@ -312,6 +338,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     const bool out_lane = lane >= 2 && lane < 2 + kOut && col >= 0 && col < t.nx;
     const int j0 = ch * t.chunk;
     const int j1 = min(j0 + t.chunk, t.ny);
+    const LaneOff lof = {(uint32_t)gi * (uint32_t)sizeof(S), (uint32_t)gi * 8u, (uint32_t)gi};
 
     const int cur = ia.cur_off;
     const StageBuffers bufs = stage_buffers(cur, stage);
@@ -341,9 +368,9 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     double mlo = 0.0, mmid = 0.0, mhi = 0.0, nlo = 0.0, nmid = 0.0, nhi = 0.0;  // FIRST: rho u, rho v
     Vec4<double> lvl_mid = zero4<double>(), lvl_hi = zero4<double>();
     {
-        const InputLoad<P> a = load_input<P>(t, qprev, gi, j0 - 2);
-        const InputLoad<P> b = load_input<P>(t, qprev, gi, j0 - 1);
-        const InputLoad<P> c = load_input<P>(t, qprev, gi, j0);
+        const InputLoad<P> a = load_input<P>(t, qprev, lof, j0 - 2);
+        const InputLoad<P> b = load_input<P>(t, qprev, lof, j0 - 1);
+        const InputLoad<P> c = load_input<P>(t, qprev, lof, j0);
         lo = to_prim(a);
         mid = to_prim(b);
         hi = to_prim(c);
@@ -359,8 +386,8 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
             lvl_hi = {c.lr, c.lm, c.ln, 0.0};
         }
     }
-    InputLoad<P> in_ld = load_input<P>(t, qprev, gi, j0 + 1);             // row r+2
-    SourceLoad<P> src_ld = load_sources<P, BDF, !FIRST>(t, q0, have_col, gi, j0 - 1); // row r
+    InputLoad<P> in_ld = load_input<P>(t, qprev, lof, j0 + 1);              // row r+2
+    SourceLoad<P> src_ld = load_sources<P, BDF, !FIRST>(t, q0, have_col, lof, j0 - 1); // row r
     if (stopped) return;
 
     // carries from row r-1:
@@ -440,8 +467,8 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         const Vec4<double> next_lvl = {in_ld.lr, in_ld.lm, in_ld.ln, 0.0};
         // the chunk reconstructs rows up to j1 from inputs up to row j1 + 1: past those rows the
         // loads repeat the last needed row (a cache hit), with no branch around them
-        in_ld = load_input<P>(t, qprev, gi, min(r + 3, j1 + 1));
-        src_ld = load_sources<P, BDF, !FIRST>(t, q0, have_col, gi, min(r + 1, j1));
+        in_ld = load_input<P>(t, qprev, lof, min(r + 3, j1 + 1));
+        src_ld = load_sources<P, BDF, !FIRST>(t, q0, have_col, lof, min(r + 1, j1));
 
         // ---- reconstruction of row r ------------------------------------------------------
         const Prim<R> wl = prim_from_left(mid);
@@ -457,8 +484,10 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         const bool open_yp = GEN && r == t.ny - 1 && (t.open & 8);
         const double pright = GEN ? from_right(pmid) : 0.0;  // shuffles: every lane takes part
         const double pleft_g = GEN ? from_left(pmid) : 0.0;
-        R px = R(0), py = R(0);
-        if (fluid) {
+        // every lane reconstructs (no branch): the values of a lane that holds no fluid cell are
+        // finite and never used, since its fluid neighbours see a wall there and take ghosts
+        R px, py;
+        {
             const Prim<R> xm = (f & FLAG_WALL_XM) ? (open_xm ? mid : mirror(mid, 0, slip)) : wl;
             const Prim<R> xp = (f & FLAG_WALL_XP) ? (open_xp ? mid : mirror(mid, 0, slip)) : wr;
             const Prim<R> ym = (f & FLAG_WALL_YM) ? (open_ym ? mid : mirror(mid, 1, slip)) : lo;
@@ -479,9 +508,6 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
                 px = cell_gradp_x(t, rec);
                 py = cell_gradp_y(t, rec);
             }
-        } else {
-            rec.gx = {R(0), R(0), R(0)};
-            rec.gy = {R(0), R(0), R(0)};
         }
         // pressure each face state is expressed from: the absolute p (FP64 form), or p minus
         // the pressure of the face's lower-index cell (mixed form); sx, sy add that reference
@@ -498,21 +524,16 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         }
 
         // ---- y-face between rows r-1 and r ------------------------------------------------
-        Vec4<R> gb = zero4<R>();
-        if (r >= j0) {
-            if (fluid) {
-                Prim<R> L;
-                if (fluid_lo)
-                    L = Prim<R>{below.a, below.b, below.c, below.d};
-                else if (GEN)
-                    L = ghost_state_gen(t, sc, rec, 1, -1, open_ym, py, pb_own);
-                else
-                    L = ghost_state(t, rec, 1, -1, slip, pb_own);
-                const Prim<R> Rs = state_at(mid, rec.gy, py, -hy, pb_yb);
-                gb = GEN ? flux_y(sc.flux, L, Rs, beta, inv_beta) : osher_y(L, Rs, beta, inv_beta);
-            } else if (fluid_lo) {
-                gb = below;  // evaluated with row r-1's ghost
-            }
+        // (a fluid row r-1 below a cell without fluid carries the face's flux, evaluated with its
+        // ghost, in below; the value of gb where neither is fluid is never used)
+        Vec4<R> gb = below;
+        if (r >= j0 && fluid) {
+            Prim<R> L = Prim<R>{below.a, below.b, below.c, below.d};
+            if (!fluid_lo)
+                L = GEN ? ghost_state_gen(t, sc, rec, 1, -1, open_ym, py, pb_own)
+                        : ghost_state(t, rec, 1, -1, slip, pb_own);
+            const Prim<R> Rs = state_at(mid, rec.gy, py, -hy, pb_yb);
+            gb = GEN ? flux_y(sc.flux, L, Rs, beta, inv_beta) : osher_y(L, Rs, beta, inv_beta);
         }
         const Vec4<double> gbd = cast4<double>(gb);
 
@@ -520,17 +541,17 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
         if (r - 1 >= j0 && out_lane && fluid_lo) {
             int gj;
             locate_axis(r - 1, t.ny, t.per_y, gj);
-            const size_t c = (size_t)gj * t.nx + gi;
+            const uint32_t os = (uint32_t)uni(gj) * (uint32_t)t.nx * (uint32_t)sizeof(S) + lof.s;
             if (LAST) {
                 const double R0 = fma(-gbd.a, t.inv_dy, rpart.a);
                 const double R1 = fma(-gbd.b, t.inv_dy, rpart.b);
                 const double R2 = fma(-gbd.c, t.inv_dy, rpart.c);
                 const double R3 = fma(-gbd.d, t.inv_dy, rpart.d);
                 const double rn = fma(fac, R0, pre.a);
-                qout[c] = (S)rn;
-                qout[plane + c] = (S)fma(fac, R1, pre.b);
-                qout[2 * plane + c] = (S)fma(fac, R2, pre.c);
-                qout[3 * plane + c] = (S)fma(t.beta, adt * R3, pre.d);
+                gst(qout, os, (S)rn);
+                gst(qout + plane, os, (S)fma(fac, R1, pre.b));
+                gst(qout + 2 * plane, os, (S)fma(fac, R2, pre.c));
+                gst(qout + 3 * plane, os, (S)fma(t.beta, adt * R3, pre.d));
                 const double rp = t.beta * R3;
                 if (NORM_MAX) {
                     part0 = combine<true>(part0, fabs(R0));
@@ -553,27 +574,24 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
                 }
             } else {
                 // fac and adt already carry 1/dy here
-                qout[c] = (S)fma(-fac, gbd.a, pre.a);
-                qout[plane + c] = (S)fma(-fac, gbd.b, pre.b);
-                qout[2 * plane + c] = (S)fma(-fac, gbd.c, pre.c);
-                qout[3 * plane + c] = (S)fma(-adt, gbd.d, pre.d);
+                gst(qout, os, (S)fma(-fac, gbd.a, pre.a));
+                gst(qout + plane, os, (S)fma(-fac, gbd.b, pre.b));
+                gst(qout + 2 * plane, os, (S)fma(-fac, gbd.c, pre.c));
+                gst(qout + 3 * plane, os, (S)fma(-adt, gbd.d, pre.d));
             }
         }
 
-        // ---- x-faces of row r and its residual without the upper y-face ------------------
-        Vec4<double> rp4 = zero4<double>();
+        // ---- x-faces of row r, its residual without the upper y-face, its carries ----------
         if (r >= j0 && r < j1) {
+            // every lane evaluates its right face (no branch); a lane without fluid produces a
+            // value that no fluid neighbour reads (that neighbour has a wall there)
             const Prim<R> sxl = state_at(mid, rec.gx, px, -hx, pb_xl);
-            const Prim<R> partner = prim_from_right(sxl);  // right neighbour's left state
-            Vec4<R> fr = zero4<R>();
-            if (fluid) {
-                Prim<R> Rs = partner;
-                if (f & FLAG_WALL_XP)
-                    Rs = GEN ? ghost_state_gen(t, sc, rec, 0, +1, open_xp, px, pb_own)
-                             : ghost_state(t, rec, 0, +1, slip, pb_own);
-                const Prim<R> Ls = state_at(mid, rec.gx, px, hx, pb_own);
-                fr = GEN ? flux_x(sc.flux, Ls, Rs, beta, inv_beta) : osher_x(Ls, Rs, beta, inv_beta);
-            }
+            Prim<R> Rs = prim_from_right(sxl);  // right neighbour's left state
+            if (f & FLAG_WALL_XP)
+                Rs = GEN ? ghost_state_gen(t, sc, rec, 0, +1, open_xp, px, pb_own)
+                         : ghost_state(t, rec, 0, +1, slip, pb_own);
+            const Prim<R> Ls = state_at(mid, rec.gx, px, hx, pb_own);
+            const Vec4<R> fr = GEN ? flux_x(sc.flux, Ls, Rs, beta, inv_beta) : osher_x(Ls, Rs, beta, inv_beta);
             Vec4<R> fl = {from_left(fr.a), from_left(fr.b), from_left(fr.c), from_left(fr.d)};
             if (fluid && (f & FLAG_WALL_XM)) {
                 const Prim<R> Lg = GEN ? ghost_state_gen(t, sc, rec, 0, -1, open_xm, px, pb_own)
@@ -582,6 +600,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
             }
             const Vec4<double> frd = cast4<double>(fr), fld = cast4<double>(fl);
             // -(x-divergence) + lower flux / dy - real-time term + body force
+            Vec4<double> rp4;
             rp4.a = fma(gbd.a, t.inv_dy, -((frd.a - fld.a) * t.inv_dx)) - d_r;
             rp4.b = fma(gbd.b, t.inv_dy, -((frd.b - fld.b) * t.inv_dx)) + fma(a0, t.gx, -d_ru);
             rp4.c = fma(gbd.c, t.inv_dy, -((frd.c - fld.c) * t.inv_dx)) + fma(a0, t.gy, -d_rv);
@@ -590,20 +609,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
                 rp4.b = fma(-sx, t.inv_dx, rp4.b);
                 rp4.c = fma(-sy, t.inv_dy, rp4.c);
             }
-        }
-
-        // ---- carries of row r -------------------------------------------------------------
-        const Prim<R> syt = state_at(mid, rec.gy, py, hy, pb_own);
-        if (fluid && (f & FLAG_WALL_YP) && r < j1) {  // a wall above row r: that face's flux now
-            if (GEN)
-                below = flux_y(sc.flux, syt, ghost_state_gen(t, sc, rec, 1, +1, open_yp, py, pb_own),
-                               beta, inv_beta);
-            else
-                below = osher_y(syt, ghost_state(t, rec, 1, +1, slip, pb_own), beta, inv_beta);
-        } else {
-            below = {syt.r, syt.u, syt.v, syt.p};
-        }
-        if (fluid && r >= j0 && r < j1) {
+            // carries of row r (read by the update of row r in the next step, fluid lanes only)
             const double dtau = use_glob ? dtau_glob
                                 : (P::kMixed ? local_dtau_f32(t, t.cfl, a0, a1, a2)
                                              : local_dtau(t, t.cfl, a0, a1, a2));
@@ -626,6 +632,12 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
                 adt = t.beta * ad * t.inv_dy;
             }
         }
+        const Prim<R> syt = state_at(mid, rec.gy, py, hy, pb_own);
+        below = {syt.r, syt.u, syt.v, syt.p};
+        if (fluid && (f & FLAG_WALL_YP) && r < j1)  // a wall above row r: that face's flux now
+            below = GEN ? flux_y(sc.flux, syt, ghost_state_gen(t, sc, rec, 1, +1, open_yp, py, pb_own),
+                                 beta, inv_beta)
+                        : osher_y(syt, ghost_state(t, rec, 1, +1, slip, pb_own), beta, inv_beta);
         fluid_lo = fluid;
         lo = next_hi;
         plo = next_phi;

@@ -74,25 +74,27 @@ __device__ __forceinline__ T limiter(T a, T b, T k)
 }
 
 // k = 1: minmod(a, b) = sgn(b) min(|a|, |b|) when a and b share a sign, else 0 -- the same value
-// as limiter(a, b, 1) (up to the sign of a zero result).
-template <typename T>
-__device__ __forceinline__ T minmod(T a, T b)
+// as limiter(a, b, 1) (up to the sign of a zero result).  It is the median of a, b and 0: the
+// smaller of the two when both are positive, the larger when both are negative, else zero.  In
+// FP32 that is one median instruction; in FP64, max(min(a, b), min(max(a, b), 0)).
+__device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+__device__ __forceinline__ double minmod(double a, double b)
 {
-    const T m = fmin(fabs(a), fabs(b));
-    return (a * b > T(0)) ? copysign(m, b) : T(0);
+    return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
 }
 
 // Limited one-sided slopes of rho, u, v at a cell from its two neighbours along one axis:
-// G((W_{i+1} - W_i)/h, (W_i - W_{i-1})/h).
+// G((W_{i+1} - W_i)/h, (W_i - W_{i-1})/h).  With minmod the scale 1/h > 0 is applied after the
+// limiter: rounding is monotonic, so minmod(a/h, b/h) and minmod(a, b)/h are the same number.
 template <typename T>
 __device__ __forceinline__ Slope<T> slopes(const Prim<T> &m, const Prim<T> &c, const Prim<T> &p,
                                            T inv_h, T k)
 {
     Slope<T> g;
     if (k == T(1)) {
-        g.r = minmod((p.r - c.r) * inv_h, (c.r - m.r) * inv_h);
-        g.u = minmod((p.u - c.u) * inv_h, (c.u - m.u) * inv_h);
-        g.v = minmod((p.v - c.v) * inv_h, (c.v - m.v) * inv_h);
+        g.r = minmod(p.r - c.r, c.r - m.r) * inv_h;
+        g.u = minmod(p.u - c.u, c.u - m.u) * inv_h;
+        g.v = minmod(p.v - c.v, c.v - m.v) * inv_h;
     } else {
         g.r = limiter((p.r - c.r) * inv_h, (c.r - m.r) * inv_h, k);
         g.u = limiter((p.u - c.u) * inv_h, (c.u - m.u) * inv_h, k);
@@ -152,35 +154,39 @@ struct AbsAAcc {
 };
 
 // Adds the point (rho, u, v), 1/rho = ir, with half weight wj (and wjb = wj / beta) to acc, for
-// the jump (dr, dm, dn, dp) in (rho, rho u, rho v, p):
+// the jump (dr, dm, dp) in (rho, rho u, p):
 //   |A| dQ = |u| dQ + (lambda_4 - |u|)(l_4 . dQ) r_4 + (-lambda_5 - |u|)(l_5 . dQ) r_5,
 // where, with a = (d(rho u) - u d(rho))/beta and dq = d(p/beta),
 //   l_4 . dQ =  (rho/c)(lambda_4 a + dq),   l_5 . dQ = -(rho/c)(lambda_5 a + dq),
 //   r_4 = (lambda_4, u lambda_4 + beta/rho, v lambda_4, -lambda_5/rho),
 //   r_5 = (lambda_5, u lambda_5 + beta/rho, v lambda_5, -lambda_4/rho).
-// The weight is folded into k4 and k5; with a' = beta a and dp = beta dq,
-//   k4 = (lambda_4 - |u|)(w/(2 beta))(rho/c)(lambda_4 a' + dp), k5 alike; component 1 is kept
-// as sum u s + beta sum (k4 + k5)/rho.
+// With a' = beta a, dp = beta dq and g = w/(2 beta c), the weighted terms are rho g K4 r_4 and
+// rho g K5 r_5 with K4 = (lambda_4 - |u|)(lambda_4 a' + dp), K5 = (lambda_5 + |u|)(lambda_5 a' + dp).
+// Their components 0, 1 (its u part) and 2 share s = K4 lambda_4 + K5 lambda_5 times rho g, u rho g
+// = m g and v rho g = n g; components 1 (its beta/rho part, kept apart as a1b) and 3 carry 1/rho,
+// which cancels rho: g (K4 + K5) and -g (K4 lambda_5 + K5 lambda_4).  So neither v nor rho g
+// itself is formed.
 template <typename T>
-__device__ __forceinline__ void absA_point(AbsAAcc<T> &acc, T rho, T ir, T u, T v, T wj, T wjb,
+__device__ __forceinline__ void absA_point(AbsAAcc<T> &acc, T rho, T ir, T m, T n, T wj, T wjb,
                                            T four_beta, T dr, T dm, T dp)
 {
+    const T u = m * ir;
     const T c2 = fma(u, u, four_beta * ir);
     const T y = rsqrt_pos(c2);          // 1/c
     const T hc = T(0.5) * (c2 * y);     // c/2
-    const T rcw = wjb * rho * y;        // (w/2) rho / (beta c)
+    const T g = wjb * y;                // w / (2 beta c)
     const T l4 = fma(T(0.5), u, hc), l5 = fma(T(0.5), u, -hc);
     const T au = fabs(u);
     acc.sau = fma(wj, au, acc.sau);
     const T a = fma(-u, dr, dm);
-    const T k4 = (l4 - au) * rcw * fma(l4, a, dp);
-    const T k5 = (l5 + au) * rcw * fma(l5, a, dp);
-    const T s = fma(k4, l4, k5 * l5);
-    acc.a0 += s;
-    acc.a1u = fma(u, s, acc.a1u);
-    acc.a1b = fma(ir, k4 + k5, acc.a1b);
-    acc.a2 = fma(v, s, acc.a2);
-    acc.a3 = fma(-ir, fma(k4, l5, k5 * l4), acc.a3);
+    const T K4 = (l4 - au) * fma(l4, a, dp);
+    const T K5 = (l5 + au) * fma(l5, a, dp);
+    const T sg = g * fma(K4, l4, K5 * l5);
+    acc.a0 = fma(rho, sg, acc.a0);
+    acc.a1u = fma(m, sg, acc.a1u);
+    acc.a1b = fma(g, K4 + K5, acc.a1b);
+    acc.a2 = fma(n, sg, acc.a2);
+    acc.a3 = fma(-g, fma(K4, l5, K5 * l4), acc.a3);
 }
 
 // F = (F(Q_L) + F(Q_R) - acc)/2 with acc = sum_j (w_j/2) |A_j| dQ.
@@ -223,7 +229,7 @@ __device__ __forceinline__ Vec4<T> osher_x(const Prim<T> &L, const Prim<T> &R, T
         const T m = fma(dm, t, mL);
         const T n = fma(dn, t, nL);
         const T ir = rcp_pos(rho);
-        absA_point(acc, rho, ir, m * ir, n * ir, wj, wjb, four_beta, dr, dm, dp);
+        absA_point(acc, rho, ir, m, n, wj, wjb, four_beta, dr, dm, dp);
     }
     return upwind_flux(L, R, mL, mR, dr, dm, dn, dp, beta, inv_beta, acc);
 }
@@ -244,7 +250,7 @@ __device__ __forceinline__ Vec4<T> roe_x(const Prim<T> &L, const Prim<T> &R, T b
     const T ut = fma(sl, L.u, sr * R.u) * iw;
     const T vt = fma(sl, L.v, sr * R.v) * iw;
     AbsAAcc<T> acc = {T(0), T(0), T(0), T(0), T(0), T(0)};
-    absA_point(acc, rho, rcp_pos(rho), ut, vt, T(1), inv_beta, T(4) * beta, dr, dm, dp);
+    absA_point(acc, rho, rcp_pos(rho), rho * ut, rho * vt, T(1), inv_beta, T(4) * beta, dr, dm, dp);
     return upwind_flux(L, R, mL, mR, dr, dm, dn, dp, beta, inv_beta, acc);
 }
 
