@@ -64,7 +64,7 @@ enum { VDAC_PGRAD_NEW = 0, VDAC_PGRAD_LIMITER = 1, VDAC_PGRAD_SPLIT = 2 };
 enum { VDAC_FP64 = 0, VDAC_FP32_MIXED = 1 };
 enum { VDAC_NORM_RMS = 0, VDAC_NORM_MAX = 1 };
 
-/* One tank: a rectangle of nx * ny cells of size (lx/nx) x (ly/ny). */
+/* One tank: a rectangle of nx * ny cells of size (lx/nx) x (ly/ny), at most 2^29 cells. */
 typedef struct {
     int32_t nx, ny;
     double lx, ly;

@@ -170,8 +170,9 @@ int check_tank(const vdac_tank *t, int idx)
 {
     if (t->nx < 1 || t->ny < 1)
         return fail(VDAC_E_INVALID, "tank %d: nx and ny must be >= 1", idx);
-    if ((long long)t->nx * (long long)t->ny > (1LL << 30))
-        return fail(VDAC_E_INVALID, "tank %d: more than 2^30 cells", idx);
+    // the row-marching kernel addresses a plane with 32-bit byte offsets (8-byte elements)
+    if ((long long)t->nx * (long long)t->ny > (1LL << 29))
+        return fail(VDAC_E_INVALID, "tank %d: more than 2^29 cells", idx);
     if (!(t->lx > 0.0) || !(t->ly > 0.0) || !std::isfinite(t->lx) || !std::isfinite(t->ly))
         return fail(VDAC_E_INVALID, "tank %d: lx and ly must be finite and > 0", idx);
     if (!(t->beta > 0.0) || !std::isfinite(t->beta))
@@ -831,6 +832,8 @@ int set_state(vdac_grid *g, int32_t tank, const double *q)
     return VDAC_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Pseudo-iterations first_iter .. first_iter + n_iter - 1 of every tank: s_max stage launches per
@@ -916,6 +919,8 @@ int graph_for(vdac_grid *g, int k, int phase, hipGraphExec_t *exec)
 }
 
 }  // namespace
+
+extern "C" {
 
 int step_dual_time(vdac_grid *g, double dt, int32_t max_pseudo, double tol, int32_t *pseudo_done)
 {
@@ -1172,6 +1177,9 @@ int set_history(vdac_grid *g, int32_t tank, const double *levels, int32_t count)
     return VDAC_OK;
 }
 
+
+}  // extern "C"
+
 namespace {
 
 std::mutex g_tune_mutex;
@@ -1191,6 +1199,8 @@ std::string tune_key(const vdac_tank *tanks, int n_tanks, const vdac_options *o)
 }
 
 }  // namespace
+
+extern "C" {
 
 int autotune_tile(const vdac_tank *tanks, int32_t n_tanks, vdac_options *o, void *hip_stream,
                   int32_t iters)

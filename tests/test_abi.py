@@ -42,6 +42,19 @@ def test_library_exports_every_declared_symbol(header):
         assert name in exported, name
 
 
+def test_library_exports_no_other_c_symbols():
+    """The unmangled (C-linkage) functions the library exports are exactly those its headers
+    declare: no helper leaks into the boundary."""
+    out = subprocess.run(["nm", "-D", "--defined-only", vdac.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    c_names = {n for n in exported if not n.startswith("_Z")}
+    declared = set()
+    for h in all_headers():
+        declared |= set(declared_functions(h))
+    assert c_names == declared, (sorted(c_names - declared), sorted(declared - c_names))
+
+
 @pytest.mark.parametrize("n_in,n_out,n,blocks,null", [(2, 1, 10, 0, False), (11, 3, 10, 0, False),
                                                       (1, 1, 0, 0, False), (1, 1, 10, -1, False),
                                                       (1, 1, 10, 0, True)])
