@@ -171,6 +171,22 @@ int set_history(vdac_grid *g, int32_t tank, const double *levels, int32_t count)
  * *dt = min over fluid cells of cfl_t dx dy / (|u| dy + |v| dx), +infinity at rest. */
 int realtime_dt(const vdac_grid *g, int32_t tank, double cfl_t, double *dt);
 
+/* For callers that cannot allocate device memory or synchronise with the host: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The same global
+ * real-time steps as realtime_dt, for tanks first_tank .. first_tank + n_tanks - 1, written to
+ * the caller's device array dt_device[n_tanks] (FP64, in the caller's orientation; +infinity
+ * for a tank at rest) by kernels queued on the grid's stream; the call returns without waiting
+ * for them.  It allocates nothing: the per-workgroup minima go to a fixed device array of the
+ * library, 8192 doubles (64 KiB) on each GPU it runs on, held until the process ends.  A tank
+ * takes min(256, ceil(nx ny / 256)) of them (the range: the largest tank's count times
+ * n_tanks); a range that needs more than 8192 is rejected with VDAC_E_INVALID (split it).
+ * Every minimum is written before it is read, so nothing needs clearing between calls.  All
+ * calls on one GPU share that array: calls that overlap in time on one GPU (other streams,
+ * other threads, other grids) race and must be ordered by the caller.  The current device must
+ * be the one create_grid ran on (else VDAC_E_INVALID). */
+int realtime_dt_device(const vdac_grid *g, int32_t first_tank, int32_t n_tanks, double cfl_t,
+                       double *dt_device);
+
 /* Measurement: while enabled, step_dual_time brackets every replayed graph of pseudo-iterations
  * (or, with graph_iters = -1, the s_max back-to-back Runge-Kutta stage launches of every
  * pseudo-iteration) with a pair of HIP events on the grid's stream and accumulates their elapsed

@@ -1177,6 +1177,70 @@ int set_history(vdac_grid *g, int32_t tank, const double *levels, int32_t count)
     return VDAC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The allocation-free entry point's scratch: per-workgroup minima of realtime_dt_device, a fixed
+// array of kNoAllocScratch doubles (64 KiB) that every GPU the library runs on holds until the
+// process ends.  In host code `scratch` only names the symbol: its device address on each GPU
+// comes from hipGetSymbolAddress, taken once per device (with that device current) and kept in
+// g_scratch_ptr, which is what kernels receive.
+constexpr int kNoAllocScratch = 8192;
+constexpr int kNoAllocBlocksPerTank = 256;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kNoAllocScratch];
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_on_device(int dev, double **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(VDAC_E_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "locating the fixed scratch array");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return VDAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int realtime_dt_device(const vdac_grid *g, int32_t first_tank, int32_t n_tanks, double cfl_t,
+                       double *dt_device)
+{
+    g_error.clear();
+    if (!g || !dt_device) return fail(VDAC_E_INVALID, "grid or dt_device is NULL");
+    if (n_tanks < 1 || first_tank < 0 || first_tank > (int)g->tanks.size() - n_tanks)
+        return fail(VDAC_E_INVALID, "tanks %d..%d are not in the grid (%d tanks)", first_tank,
+                    first_tank + n_tanks - 1, (int)g->tanks.size());
+    if (!(cfl_t > 0.0) || !std::isfinite(cfl_t)) return fail(VDAC_E_INVALID, "cfl_t must be finite and > 0");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "realtime_dt_device");
+    if (dev != g->device)
+        return fail(VDAC_E_INVALID, "the current device (%d) is not the grid's (%d)", dev, g->device);
+    size_t max_plane = 1;
+    for (int t = first_tank; t < first_tank + n_tanks; ++t)
+        max_plane = std::max(max_plane, g->tanks[t].dev.plane);
+    const int bpt = (int)std::min<size_t>(kNoAllocBlocksPerTank, (max_plane + 255) / 256);
+    if ((size_t)bpt * (size_t)n_tanks > (size_t)kNoAllocScratch)
+        return fail(VDAC_E_INVALID, "%d tanks of up to %zu cells need %zu scratch minima, more than the "
+                    "%d of the fixed scratch array: split the range", n_tanks, max_plane,
+                    (size_t)bpt * n_tanks, kNoAllocScratch);
+    double *s = nullptr;
+    int rc = scratch_on_device(dev, &s);
+    if (rc != VDAC_OK) return rc;
+    rc = launch_tanks_min(g->tanks_dev, first_tank, n_tanks, g->sc.mixed, MIN_REALTIME_DT, cfl_t, s,
+                          bpt, dt_device, 1, g->stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "realtime_dt_device launch");
+    return VDAC_OK;
+}
 
 }  // extern "C"
 

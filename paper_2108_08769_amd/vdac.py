@@ -23,8 +23,8 @@ NORM_RMS, NORM_MAX = 0, 1
 
 EXPORTS = ("vdac_default_options", "workspace_bytes", "create_grid", "set_state",
            "step_dual_time", "residual_norm", "get_state", "get_history", "set_history",
-           "stage_timing", "stage_timing_read", "autotune_tile", "realtime_dt", "destroy_grid",
-           "last_error")
+           "stage_timing", "stage_timing_read", "autotune_tile", "realtime_dt",
+           "realtime_dt_device", "destroy_grid", "last_error")
 
 
 class VdacError(RuntimeError):
@@ -111,6 +111,8 @@ def lib():
         L.autotune_tile.restype = ctypes.c_int
         L.realtime_dt.argtypes = [vp, ctypes.c_int32, ctypes.c_double, dp]
         L.realtime_dt.restype = ctypes.c_int
+        L.realtime_dt_device.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, vp]
+        L.realtime_dt_device.restype = ctypes.c_int
         L.destroy_grid.argtypes = [vp]
         L.destroy_grid.restype = None
         L.last_error.argtypes = []
@@ -284,6 +286,12 @@ class Grid:
         dt = ctypes.c_double()
         _check(self._lib.realtime_dt(self._h, tank, float(cfl_t), ctypes.byref(dt)))
         return dt.value
+
+    def realtime_dt_device(self, first_tank: int, n_tanks: int, cfl_t: float, out_ptr: int):
+        """Queues the global real-time steps of n_tanks tanks into the device array at out_ptr
+        (n_tanks doubles) on the grid's stream; allocates nothing and does not wait."""
+        _check(self._lib.realtime_dt_device(self._h, int(first_tank), int(n_tanks), float(cfl_t),
+                                            ctypes.c_void_p(out_ptr)))
 
     def get_state(self, tank: int = 0) -> np.ndarray:
         ny, nx = self._shapes[tank]
