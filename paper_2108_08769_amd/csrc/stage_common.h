@@ -96,6 +96,27 @@ __device__ __forceinline__ double local_dtau(const TankDev &t, double cfl, doubl
     return cfl * (t.dx * t.dy) * rcp_pos(lx + ly);
 }
 
+// The pseudo-time step scaled by alpha_s, ad = alpha_s dtau, and the point-implicit factor
+// fc = ad / (1 + B0 ad / dt) (eq. 27) of a cell with stage-0 state (rho, m, n), in FP64 with two
+// reciprocal-square-root estimates and one reciprocal.  With u = m/rho, c_x = sqrt(u^2 + 4 beta/rho)
+// = sqrt(m^2 + 4 beta rho)/rho, so the denominator of Sec. 2.2.3 is D'/rho with
+//   D' = (|m| + sqrt(m^2 + 4 beta rho)) dy/2 + (|n| + sqrt(n^2 + 4 beta rho)) dx/2,
+// and ad = a rho / D', fc = a rho / (D' + kappa rho) with a = alpha_s CFL dx dy and
+// kappa = B0 a / dt; both reciprocals come from one of their product.
+__device__ __forceinline__ void dtau_factors(const TankDev &t, double a, double kappa, double rho,
+                                             double m, double n, double &ad, double &fc)
+{
+    const double fb = 4.0 * t.beta * rho;
+    const double sx2 = fma(m, m, fb), sy2 = fma(n, n, fb);
+    const double sx = sx2 * rsqrt_pos(sx2), sy = sy2 * rsqrt_pos(sy2);
+    const double d = 0.5 * fma(fabs(m) + sx, t.dy, (fabs(n) + sy) * t.dx);
+    const double e = fma(kappa, rho, d);
+    const double ip = rcp_pos(d * e);
+    const double ar = a * rho;
+    ad = ar * (e * ip);
+    fc = ar * (d * ip);
+}
+
 // The same step in FP32 with the hardware reciprocal and reciprocal-square-root estimates, for
 // the mixed form: the step only scales the pseudo-time update (the converged state does not
 // depend on it), so it needs no more precision than the fluxes it multiplies.

@@ -349,6 +349,8 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     const bool slip = sc.slip != 0;
     const R kl = (R)sc.k;
     const double alpha = sc.alpha[stage - 1];
+    const double a_dtau = alpha * (t.cfl * (t.dx * t.dy));  // alpha_s CFL dx dy
+    const double kappa = sp.b0 * a_dtau * sp.inv_dt;
     const size_t plane = t.plane;
     const R hx = (R)t.half_dx, hy = (R)t.half_dy;
     const R beta = (R)t.beta, inv_beta = (R)t.inv_beta;
@@ -610,11 +612,14 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
                 rp4.c = fma(-sy, t.inv_dy, rp4.c);
             }
             // carries of row r (read by the update of row r in the next step, fluid lanes only)
-            const double dtau = use_glob ? dtau_glob
-                                : (P::kMixed ? local_dtau_f32(t, t.cfl, a0, a1, a2)
-                                             : local_dtau(t, t.cfl, a0, a1, a2));
-            const double ad = alpha * dtau;
-            const double fc = ad * rcp_pos(fma(sp.b0 * ad, sp.inv_dt, 1.0));
+            double ad, fc;
+            if (!P::kMixed && !use_glob) {
+                dtau_factors(t, a_dtau, kappa, a0, a1, a2, ad, fc);
+            } else {
+                const double dtau = use_glob ? dtau_glob : local_dtau_f32(t, t.cfl, a0, a1, a2);
+                ad = alpha * dtau;
+                fc = ad * rcp_pos(fma(sp.b0 * ad, sp.inv_dt, 1.0));
+            }
             if (LAST) {
                 pre = z;
                 rpart = rp4;

@@ -1289,9 +1289,29 @@ int autotune_tile(const vdac_tank *tanks, int32_t n_tanks, vdac_options *o, void
         }
     }
     int max_ny = 1;
-    for (int t = 0; t < n_tanks; ++t) max_ny = std::max(max_ny, tanks[t].ny);
+    long strip_rows = 0;
+    for (int t = 0; t < n_tanks; ++t) {
+        max_ny = std::max(max_ny, tanks[t].ny);
+        strip_rows += (long)march_strips(tanks[t].nx) * tanks[t].ny;
+    }
     std::vector<std::pair<int, int>> cand;
-    const int chunks[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+    std::vector<int> chunks = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+    // chunks whose units fill the chip's wave slots a whole number of times (1..3) with two or
+    // three waves per SIMD, so that the last round of waves is not a partial one
+    auto units_of = [&](long c) {
+        long u = 0;
+        for (int t = 0; t < n_tanks; ++t)
+            u += (long)march_strips(tanks[t].nx) * ((tanks[t].ny + c - 1) / c);
+        return u;
+    };
+    for (long slots : {kWaveSlots, kWaveSlots * 3 / 2})
+        for (long r = 1; r <= 3; ++r) {
+            long c = std::max(1L, (strip_rows + r * slots - 1) / (r * slots));
+            while (c <= max_ny && units_of(c) > r * slots) ++c;
+            if (c > 64 && c <= max_ny) chunks.push_back((int)c);
+        }
+    std::sort(chunks.begin(), chunks.end());
+    chunks.erase(std::unique(chunks.begin(), chunks.end()), chunks.end());
     for (int w : {2, 3})
         for (int c : chunks)
             if (c == 1 || c / 2 < max_ny) cand.push_back({-w, c});
