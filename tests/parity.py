@@ -95,6 +95,19 @@ def field_errors(a: np.ndarray, b: np.ndarray, solid=None, scales=None) -> np.nd
     return out
 
 
+def plain_errors(a: np.ndarray, b: np.ndarray, solid=None, scales=None, floor=1e-3) -> np.ndarray:
+    """Per-field max |a - b| / max |b| over fluid cells, the plain relative error, for the fields
+    whose max |b| is at least floor x their physical scale (nan for the others, where the plain
+    ratio measures rounding against a vanishing denominator)."""
+    mask = np.ones(a.shape[1:], bool) if solid is None else solid == 0
+    out = np.full(4, np.nan)
+    for k in range(4):
+        s = np.abs(b[k][mask]).max()
+        if scales is None or s >= floor * scales[k]:
+            out[k] = np.abs(a[k][mask] - b[k][mask]).max() / s if s > 0 else 0.0
+    return out
+
+
 def strips(w):
     return -(-w // 60)  # 64-lane strips of 60 columns
 

@@ -16,7 +16,7 @@ import pytest
 
 from paper_2108_08769_amd import vdac
 from paper_2108_08769_amd import workloads as wl
-from parity import (run_gpu, run_oracle, field_errors, field_scales, reflect,
+from parity import (run_gpu, run_oracle, field_errors, field_scales, plain_errors, reflect,
                     stored_transposed_in_batch, unreflect_state)
 
 pytestmark = pytest.mark.gpu
@@ -36,9 +36,13 @@ def check(wk, steps, pseudo, bar=TOL, scales=None, **kw):
     np.testing.assert_array_equal(g[1], o[1])
     worst = 0.0
     for t, a, b in zip(wk.tanks, g[0], o[0]):
-        err = field_errors(a, b, t.solid, field_scales(t) if scales is None else scales)
+        sc = field_scales(t) if scales is None else scales
+        err = field_errors(a, b, t.solid, sc)
         worst = max(worst, err.max())
         assert np.all(err <= bar), (t.nx, t.ny, err)
+        plain = plain_errors(a, b, t.solid, sc)
+        ok = ~np.isnan(plain)
+        assert np.all(plain[ok] <= bar), (t.nx, t.ny, plain)
     for a, b in zip(g[2], o[2]):
         # norms agree to rtol 1e-7 above the rounding floor of the flux divergence: the kernel
         # sums face fluxes scaled by 1/h, so a field whose fluxes cancel (v = 0 in a 1D problem)

@@ -12,7 +12,8 @@ import pytest
 from paper_2108_08769_amd import vdac
 from paper_2108_08769_amd import workloads as wl
 import oracle
-from parity import run_gpu, run_oracle, field_errors, field_scales, gpu_options, oracle_problem
+from parity import (run_gpu, run_oracle, field_errors, field_scales, gpu_options, oracle_problem,
+                    plain_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -26,16 +27,22 @@ def check(wk, steps, pseudo, tol=0.0, bar=TOL, **kw):
     o_states, o_it, o_norms, o_codes = run_oracle(wk, steps, pseudo, tol, **kw)
     assert all(c == 0 for c in g_codes) and all(c == 0 for c in o_codes), (g_codes, o_codes)
     np.testing.assert_array_equal(g_it, o_it)
-    worst = 0.0
+    worst, worst_plain = 0.0, 0.0
     for t, a, b in zip(wk.tanks, g_states, o_states):
         err = field_errors(a, b, t.solid, field_scales(t))
         worst = max(worst, err.max())
         assert np.all(err <= bar), (t.nx, t.ny, err)
+        # the plain max |a - b| / max |b| as well, wherever max |b| is not negligible
+        plain = plain_errors(a, b, t.solid, field_scales(t))
+        ok = ~np.isnan(plain)
+        worst_plain = max(worst_plain, plain[ok].max() if ok.any() else 0.0)
+        assert np.all(plain[ok] <= bar), (t.nx, t.ny, plain)
         if t.solid is not None:
             np.testing.assert_array_equal(a[:, t.solid == 1], t.q[:, t.solid == 1])
     for a, b in zip(g_norms, o_norms):
         np.testing.assert_allclose(a, b, rtol=1e-7, atol=1e-12)
-    print(f"[parity]   worst field error {worst:.3e}", flush=True)
+    print(f"[parity]   worst field error {worst:.3e} (plain max|a-b|/max|b| {worst_plain:.3e})",
+          flush=True)
     return worst
 
 

@@ -51,3 +51,35 @@ def test_window_of_radius_2_smax_N_plus_1_reproduces_the_whole_tank():
     short = [np.abs(window_state(wk, t, i, j, 2, pseudo, steps) - full[:, j, i]).max()
              for i, j in [(34, 20), (29, 20), (20, 66)]]
     assert min(short) > 0.0, short
+
+
+def test_window_reproduces_the_whole_tank_after_20_iterations():
+    """The reach the 4096^2 GPU check uses: two real steps of 10 pseudo-iterations (radius 121),
+    on a 256^2 obstacle tank; windows run on the oracle's -fopenmp build (bitwise the serial
+    one's results)."""
+    pseudo, steps = 10, 2
+    wk = wl.obstacle_dam_break(n=256)
+    t = wk.tanks[0]
+    pb = oracle_problem(t, wk)
+    full = t.q
+    for _ in range(steps):
+        full, it, _, rc = oracle.step(pb, full, wk.dt, pseudo, 0.0, 0, omp=True)
+        assert rc == 0 and it == pseudo
+    radius = 2 * wk.stages * pseudo * steps + 1
+    scale = np.array([1000.0, 1000.0 * np.sqrt(9.81 * 4), 1000.0 * np.sqrt(9.81 * 4), 1000.0 * 9.81 * 4])
+    for i, j in [(64, 128), (159, 18), (255, 255), (200, 100), (127, 60)]:
+        assert not t.solid[j, i]
+        i0, i1 = max(0, i - radius), min(t.nx, i + radius + 1)
+        j0, j1 = max(0, j - radius), min(t.ny, j + radius + 1)
+        dx, dy = t.lx / t.nx, t.ly / t.ny
+        q = np.ascontiguousarray(t.q[:, j0:j1, i0:i1])
+        solid = np.ascontiguousarray(t.solid[j0:j1, i0:i1])
+        wt = wl.Tank(i1 - i0, j1 - j0, (i1 - i0) * dx, (j1 - j0) * dy, q, gx=t.gx, gy=t.gy,
+                     beta=t.beta, solid=solid)
+        wpb = oracle_problem(wt, wk)
+        out = q
+        for _ in range(steps):
+            out, it, _, rc = oracle.step(wpb, out, wk.dt, pseudo, 0.0, 0, omp=True)
+            assert rc == 0
+        err = np.abs(out[:, j - j0, i - i0] - full[:, j, i]) / scale
+        assert np.all(err <= 1e-14), ((i, j), err)
