@@ -134,6 +134,23 @@ __device__ __forceinline__ double local_dtau_f32(const TankDev &t, double cfl, d
     return (double)((float)(cfl * (t.dx * t.dy)) * rcp_pos(lx + ly));
 }
 
+// dtau_factors in FP32 with the hardware estimates, for the mixed form, whose pseudo-time step is
+// an FP32 step size (it scales the update; the converged state does not depend on it).
+__device__ __forceinline__ void dtau_factors_f32(const TankDev &t, float a, float kappa, double rho_d,
+                                                 double m_d, double n_d, double &ad, double &fc)
+{
+    const float rho = (float)rho_d, m = (float)m_d, n = (float)n_d;
+    const float fb = 4.0f * (float)t.beta * rho;
+    const float sx2 = fmaf(m, m, fb), sy2 = fmaf(n, n, fb);
+    const float sx = sx2 * rsqrt_pos(sx2), sy = sy2 * rsqrt_pos(sy2);
+    const float d = 0.5f * fmaf(fabsf(m) + sx, (float)t.dy, (fabsf(n) + sy) * (float)t.dx);
+    const float e = fmaf(kappa, rho, d);
+    const float ip = rcp_pos(d * e);
+    const float ar = a * rho;
+    ad = (double)(ar * (e * ip));
+    fc = (double)(ar * (d * ip));
+}
+
 template <bool NORM_MAX>
 __device__ __forceinline__ double combine(double a, double b)
 {

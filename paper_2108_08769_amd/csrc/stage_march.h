@@ -613,12 +613,13 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
             }
             // carries of row r (read by the update of row r in the next step, fluid lanes only)
             double ad, fc;
-            if (!P::kMixed && !use_glob) {
-                dtau_factors(t, a_dtau, kappa, a0, a1, a2, ad, fc);
-            } else {
-                const double dtau = use_glob ? dtau_glob : local_dtau_f32(t, t.cfl, a0, a1, a2);
-                ad = alpha * dtau;
+            if (use_glob) {
+                ad = alpha * dtau_glob;
                 fc = ad * rcp_pos(fma(sp.b0 * ad, sp.inv_dt, 1.0));
+            } else if (P::kMixed) {
+                dtau_factors_f32(t, (float)a_dtau, (float)kappa, a0, a1, a2, ad, fc);
+            } else {
+                dtau_factors(t, a_dtau, kappa, a0, a1, a2, ad, fc);
             }
             if (LAST) {
                 pre = z;
