@@ -288,14 +288,30 @@ def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
             "roofline": roofline}
 
 
-def stream_reference(vdac, torch, n=16 << 20, reps=5):
+def stream_reference(vdac, torch, n=16 << 20, reps=5, march=None):
     """Best rate, GB/s read + write, of the library's plane-stream kernel over three launch
     shapes: 11 FP64 planes of n cells read and 4 written (the FP64 stage's mix), and a plain
-    copy of 4n doubles; 1.9 GB and 1 GB touched, well beyond the 256 MB last-level cache."""
+    copy of 4n doubles; 1.9 GB and 1 GB touched, well beyond the 256 MB last-level cache.
+    march = (nx, ny, chunk): also the same plane mix in the row-marching stage kernel's access
+    pattern on that tank (include/vdac_probe.h), as algorithmic GB/s (120 B per cell)."""
     inp = torch.zeros(11 * n, dtype=torch.float64, device="cuda")
     out = torch.empty(4 * n, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     res = {}
+    if march is not None and march[0] * march[1] <= n:
+        nx, ny, chunk = march
+        launch = lambda: vdac.march_probe(nx, ny, chunk, inp.data_ptr(), out.data_ptr(),
+                                          stream.cuda_stream)
+        launch()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            launch()
+        e1.record(stream)
+        e1.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        res["march_gbps"] = round(120.0 * nx * ny / sec / 1e9, 1)
     for n_in, n_out, cells, name in [(11, 4, n, "gbps"), (1, 1, 4 * n, "copy_gbps")]:
         best = 0.0
         for blocks in (0, 1024, 4096):
@@ -421,12 +437,22 @@ def main():
         "roofline": roofline,
     }
     if roofline is not None:
-        ref = stream_reference(vdac, torch)
+        march = None
+        if len(wk.tanks) == 1 and chosen.startswith("-"):
+            march = (wk.tanks[0].nx, wk.tanks[0].ny, int(chosen.split("x")[1]))
+        ref = stream_reference(vdac, torch, march=march)
         roofline["stream_reference"] = {
             "kernel": "plane stream: 11 FP64 planes read, 4 written, one cell per lane "
                       "(include/vdac_probe.h)",
             "gbps": ref["gbps"], "copy_gbps": ref["copy_gbps"],
             "frac": round(roofline["achieved"] / ref["gbps"], 4)}
+        if "march_gbps" in ref:
+            roofline["march_reference"] = {
+                "kernel": "the same 11-in, 4-out plane mix in the stage kernel's row-marching "
+                          "pattern on this tank and chunk, no arithmetic (include/vdac_probe.h); "
+                          "algorithmic GB/s at 120 B per cell",
+                "gbps": ref["march_gbps"],
+                "frac": round(roofline["achieved"] / ref["march_gbps"], 4)}
     # the mixed form on the same workload, after the FP64 line's measurement (reported beside
     # it: the headline metric compares the two forms)
     if wk.precision == "f64" and not args.no_mixed:

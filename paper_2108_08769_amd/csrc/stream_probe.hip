@@ -31,7 +31,61 @@ __global__ void __launch_bounds__(256) stream_planes(const double *__restrict__ 
     }
 }
 
+// The FP64 stage's plane mix in the row-marching stage kernel's access pattern: each wave owns a
+// strip of 64 columns (60 written, 2 halo columns each side) and walks a chunk of rows upward,
+// reading input rows j0-2 .. j1+1 (planes 0-3), source rows j0-1 .. j1 (planes 4-10) and writing
+// rows j0 .. j1-1 (4 planes); 4 waves per workgroup, workgroup b running on XCD b % 8 with a
+// contiguous eighth of the units.  Only sums, no stencil arithmetic.
+__global__ void __launch_bounds__(256) march_planes(const double *__restrict__ in,
+                                                    double *__restrict__ out, int nx, int ny,
+                                                    int chunk, int n_units, int n_blocks)
+{
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x;
+    const int per = (n_blocks + 7) / 8;
+    const int k = (b % 8) * per + b / 8;  // this workgroup's place in the natural order
+    const int unit = k * 4 + (int)(threadIdx.x >> 6);
+    if (unit >= n_units) return;
+    const size_t plane = (size_t)nx * ny;
+    const int strips = (nx + 59) / 60;
+    const int strip = unit % strips, ch = unit / strips;
+    int col = strip * 60 - 2 + lane;
+    const bool out_lane = lane >= 2 && lane < 62 && col >= 0 && col < nx;
+    col = col < 0 ? 0 : (col >= nx ? nx - 1 : col);
+    const int j0 = ch * chunk, j1 = min(j0 + chunk, ny);
+    double carry = 0.0;
+    for (int r = j0 - 2; r <= j1 + 1; ++r) {
+        const int row = r < 0 ? 0 : (r >= ny ? ny - 1 : r);
+        const size_t c = (size_t)row * nx + col;
+        double acc = carry;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += in[q * plane + c];
+        if (r >= j0 - 1 && r <= j1) {
+#pragma unroll
+            for (int q = 4; q < 11; ++q) acc += in[q * plane + c];
+        }
+        carry = 0.5 * acc;
+        if (out_lane && r >= j0 && r < j1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out[q * plane + c] = acc;
+        }
+    }
+}
+
 }  // namespace
+
+extern "C" int vdac_march_probe(int32_t nx, int32_t ny, int32_t chunk, const double *in, double *out,
+                                void *hip_stream)
+{
+    if (nx < 1 || ny < 1 || chunk < 1 || (long long)nx * ny > (1LL << 29) || !in || !out) return 1;
+    const long long strips = (nx + 59) / 60, chunks = (ny + chunk - 1) / chunk;
+    const long long units = strips * chunks;
+    if (units > (1LL << 28)) return 1;
+    const int n_blocks = (int)((units + 3) / 4);
+    hipLaunchKernelGGL(march_planes, dim3((unsigned)n_blocks), dim3(256), 0, (hipStream_t)hip_stream,
+                       in, out, (int)nx, (int)ny, (int)chunk, (int)units, n_blocks);
+    return hipGetLastError() == hipSuccess ? 0 : 3;
+}
 
 int launch_stream_probe(int n_in, int n_out, size_t n, int blocks, const double *in, double *out,
                         void *stream_)

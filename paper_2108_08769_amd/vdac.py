@@ -120,6 +120,8 @@ def lib():
         L.vdac_stream_probe.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                         ctypes.c_int32, vp, vp, vp]
         L.vdac_stream_probe.restype = ctypes.c_int
+        L.vdac_march_probe.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+        L.vdac_march_probe.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -133,6 +135,13 @@ def stream_probe(n_in: int, n_out: int, n: int, blocks: int, in_ptr: int, out_pt
                  stream: int = 0):
     """One pass of the plane-stream bandwidth reference (include/vdac_probe.h) on `stream`."""
     _check(lib().vdac_stream_probe(n_in, n_out, n, blocks, in_ptr, out_ptr, stream or None))
+
+
+def march_probe(nx: int, ny: int, chunk: int, in_ptr: int, out_ptr: int, stream: int = 0):
+    """One pass of the row-marching bandwidth reference (include/vdac_probe.h) on `stream`."""
+    rc = lib().vdac_march_probe(nx, ny, chunk, in_ptr, out_ptr, stream or None)
+    if rc != VDAC_OK:
+        raise VdacError(rc, "march probe: bad size or pointer, or the launch failed")
 
 
 def default_options() -> Options:

@@ -25,7 +25,7 @@ def all_headers():
 
 def test_header_lists_the_boundary():
     assert set(vdac.EXPORTS) == set(declared_functions())
-    assert declared_functions("vdac_probe.h") == ["vdac_stream_probe"]
+    assert declared_functions("vdac_probe.h") == ["vdac_march_probe", "vdac_stream_probe"]
 
 
 @pytest.mark.parametrize("header", all_headers())
@@ -64,6 +64,17 @@ def test_stream_probe_rejects_bad_arguments(n_in, n_out, n, blocks, null):
     ptr = None if null else ctypes.addressof(buf)
     with pytest.raises(vdac.VdacError) as e:
         vdac.stream_probe(n_in, n_out, n, blocks, ptr or 0, ptr or 0)
+    assert e.value.code == vdac.VDAC_E_INVALID
+
+
+@pytest.mark.parametrize("nx,ny,chunk,null", [(0, 10, 4, False), (10, 0, 4, False), (10, 10, 0, False),
+                                               (1 << 15, 1 << 15, 4, False), (10, 10, 4, True)])
+def test_march_probe_rejects_bad_arguments(nx, ny, chunk, null):
+    """Argument checks run before any device call."""
+    buf = ctypes.create_string_buffer(64)
+    ptr = None if null else ctypes.addressof(buf)
+    with pytest.raises(vdac.VdacError) as e:
+        vdac.march_probe(nx, ny, chunk, ptr or 0, ptr or 0)
     assert e.value.code == vdac.VDAC_E_INVALID
 
 
