@@ -12,10 +12,11 @@ scale (rho_max sqrt(|g| L)).  Every case prints its per-field errors.
 
 Where a tank has barely left rest (the sloshing ensemble's small-tilt tanks after two steps,
 Rayleigh-Taylor in its first ~0.05 s), max |rho u| falls to ~1e-4 of its physical scale and the
-plain normwise rho u error exceeds the 1e-5 target (measured up to 1.04e-5 and 1.8e-5) while the
+plain normwise rho u error exceeds the 1e-5 target (measured up to 1.35e-5 and 2.4e-5) while the
 absolute difference stays near 1e-8.  Those tests hold the floored error (denominator at least 1%
-of the physical scale) to 1e-5, and the plain figure to the level measured there (2e-5 for the
-ensemble, 3e-5 over time), and print both: the target is missed literally in these two cases.
+of the physical scale) to 1e-5, and the plain figure to 3e-5, above the level measured there
+(1.35e-5 on the ensemble's tanks with max |rho u| at least 1e-4 of its scale, 2.4e-5 over time),
+and print both: the target is missed literally in these two cases.
 
 Batched form: a grid of many tanks runs every stage of every tank in one launch from a unit
 table; each tank must come out bit for bit as it does in a grid of its own, and match the oracle
@@ -44,11 +45,12 @@ def normwise(a, b, solid=None):
     return out
 
 
-def check_mixed(wk, steps, pseudo, ref="gpu", floor=0.0, plain_rho_u=None, **kw):
+def check_mixed(wk, steps, pseudo, ref="gpu", floor=0.0, plain_rho_u=None, plain_level=1e-4, **kw):
     """Runs wk in the mixed form and in FP64 (GPU or oracle) and applies BAR.  floor > 0 floors
     the normwise denominator of each field at floor x its physical scale (for tanks that have
     barely left rest, where max |field| is not a meaningful scale); the plain normwise rho u
-    error is then held to plain_rho_u and printed as well."""
+    error is then held to plain_rho_u on every tank whose max |rho u| is at least plain_level x
+    its physical scale, and printed for all."""
     print(f"[mixed] {wk.name} tanks={len(wk.tanks)} steps={steps} pseudo={pseudo} ref={ref} {kw}",
           flush=True)
     m_states, m_it, _, m_codes = run_gpu(wk, steps, pseudo, precision="mixed", **kw)
@@ -71,7 +73,7 @@ def check_mixed(wk, steps, pseudo, ref="gpu", floor=0.0, plain_rho_u=None, **kw)
         if floor > 0:
             nw = field_errors(a, b, t.solid, floor * field_scales(t))
             # the plain figure is held where max |rho u| is not negligible against its scale
-            if level >= 1e-3:
+            if level >= plain_level:
                 worst_plain = max(worst_plain, plain)
                 assert plain_rho_u is not None and plain <= plain_rho_u, (t.nx, t.ny, level, plain)
         else:
@@ -120,9 +122,9 @@ def test_mixed_error_vs_time(name, steps):
     side for `steps` real steps, compared after every step and printed every 10.  Rayleigh-
     Taylor starts from rest with p = 0: for its first ~0.05 s max |rho u| falls to ~4e-4 (against
     a physical scale of 6) while the absolute difference stays near 1e-8, so the plain normwise
-    error of rho u peaks near 2e-5 without any loss of accuracy.  The bar therefore floors each
+    error of rho u peaks near 2.4e-5 without any loss of accuracy.  The bar therefore floors each
     field's normwise denominator at 1% of its physical scale (as for the ensemble); the plain
-    normwise error is printed beside it and held to 3e-5, the level measured there (the 1e-5
+    normwise error is printed beside it and held to 3e-5, above the 2.4e-5 measured (the 1e-5
     target is missed literally while the flow is that close to rest)."""
     wk = getattr(wl, name)()
     t = wk.tanks[0]
@@ -467,10 +469,12 @@ def test_batched_mixed_vs_fp64_full_ensemble():
     drawn tilt are still close to rest then (max |rho u| down to ~1e-6 of rho_max sqrt(|g| L)),
     where the normwise ratio measures rounding against a vanishing denominator; the denominator
     is therefore floored at 1% of each field's physical scale.  The plain normwise rho u error,
-    the target's own figure, is held to 2e-5 where max |rho u| is at least 1e-3 of its scale (it
-    reached 1.04e-5 on one tank, 112 x 240); below that (a tank at rest to within rounding has
-    plain error up to 1) it is printed by decade of max |rho u| / scale."""
-    check_mixed(wl.sloshing_ensemble(), steps=2, pseudo=50, floor=0.01, plain_rho_u=2e-5)
+    the target's own figure, is held to 3e-5 on every tank whose max |rho u| is at least 1e-4 of
+    its scale (measured: 1.35e-5 at most there, above the 1e-5 target); below that (a tank at
+    rest to within rounding has plain error up to 1) it is printed by decade of
+    max |rho u| / scale."""
+    check_mixed(wl.sloshing_ensemble(), steps=2, pseudo=50, floor=0.01, plain_rho_u=3e-5,
+                plain_level=1e-4)
 
 
 # ---- autotuner ------------------------------------------------------------------------------
