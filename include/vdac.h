@@ -94,8 +94,8 @@ typedef struct {
                                32 x 8, 16 x 16 or 64 x 4 two-dimensional LDS tiles (256
                                threads), 3208 x 2, 1616 x 2 for the 32 x 8 and 16 x 16 tiles
                                with 512 threads, and 1608 x 2 for a 16 x 8 tile with 320 threads;
-                               tiles take one tank, FP64 or mixed, BDF order up to 2; one thread
-                               per cell is FP64 only */
+                               tiles take one tank, FP64 or mixed; one thread per cell is FP64
+                               with the default scheme only */
     int32_t graph_iters; /* pseudo-iterations captured per HIP graph and replayed on the stream:
                             0 automatic, K > 0 exactly K, -1 launch kernels one by one */
     int32_t flux;        /* VDAC_FLUX_* */
@@ -103,8 +103,8 @@ typedef struct {
     double p_limiter_k;  /* k of the limiter on p for VDAC_PGRAD_LIMITER / _SPLIT, in [1, 2] */
 } vdac_options;
 /* Options other than the defaults of flux, pgrad and local_dtau, BDF3 and zero-gradient sides
- * run on the row-marching stage kernel only (tile 0 x 0 or -W x L); the split limiter is not
- * available with zero-gradient sides. */
+ * run on the row-marching and tiled stage kernels, not on the one-thread-per-cell kernel (tile
+ * 1 x 1); the split limiter is not available with zero-gradient sides. */
 
 /* Fills o with the defaults: FP64, 3 stages alpha = (1/3, 1/2, 1), CFL_tau 0.48, minmod,
  * local dtau, backward Euler, RMS norm, no-slip walls, automatic tiles, automatic graphs, Osher

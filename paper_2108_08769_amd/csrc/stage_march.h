@@ -256,50 +256,6 @@ __device__ __forceinline__ double abs_p(const InputLoad<P> &L)
     return P::kMixed ? L.lp + (double)L.p : (double)L.p;
 }
 
-// Pressure gradient along one axis by the k-limiter on p (pgrad 1) or the split limiter
-// (pgrad 2, Sec. 2.3.2): from the pressure differences dpr = p_{i+1} - p_i, dpl = p_i - p_{i-1}
-// (FP64), the densities of the stencil and the gravity component g along the axis.
-__device__ __forceinline__ double pgrad_limited(int pgrad, double pk, double dpr, double dpl,
-                                               double inv_h, double rl, double rc, double rr,
-                                               double g)
-{
-    if (pgrad == 1) return limiter(dpr * inv_h, dpl * inv_h, pk);
-    const double kr = fma(dpr, inv_h, -0.5 * (rc + rr) * g);
-    const double kl = fma(dpl, inv_h, -0.5 * (rl + rc) * g);
-    return fma(rc, g, limiter(kr, kl, pk));
-}
-
-// Ghost of a reconstructed cell for the general kernel: across a wall (open = false) or a
-// zero-gradient side (open = true: no velocity sign change, gravity kept, sources kept).  Its
-// normal p-slope: the new method evaluates the rearranged momentum equation in the ghost; the
-// k-limiter on p gives zero at such a face on both sides; the split limiter gives minus the
-// cell's (the wall ghost's stencil is the cell's reflected, with gravity reversed).
-template <typename R>
-__device__ __forceinline__ Prim<R> ghost_state_gen(const TankDev &t, const Scheme &sc,
-                                                   const CellRecT<R> &c, int axis, int sd,
-                                                   bool open, R p_own_slope, R pbase)
-{
-    const bool slip = sc.slip != 0;
-    const R su = (open || (slip && axis == 1)) ? R(1) : R(-1);
-    const R sv = (open || (slip && axis == 0)) ? R(1) : R(-1);
-    const R gs = open ? R(1) : R(-1);
-    const Prim<R> w = {c.w.r, su * c.w.u, sv * c.w.v, c.w.p};
-    if (axis == 0) {
-        const Slope<R> gx = c.gx;
-        const Slope<R> gy = {c.gy.r, su * c.gy.u, sv * c.gy.v};
-        const R px = sc.pgrad == 0 ? gradp_x(w, gx, gy, su * c.d_ru, gs * (c.rho0 * (R)t.gx))
-                                   : (sc.pgrad == 1 ? p_own_slope : -p_own_slope);
-        const R h = sd > 0 ? -(R)t.half_dx : (R)t.half_dx;
-        return state_at(w, gx, px, h, pbase);
-    }
-    const Slope<R> gy = c.gy;
-    const Slope<R> gx = {c.gx.r, su * c.gx.u, sv * c.gx.v};
-    const R py = sc.pgrad == 0 ? gradp_y(w, gx, gy, sv * c.d_rv, gs * (c.rho0 * (R)t.gy))
-                               : (sc.pgrad == 1 ? p_own_slope : -p_own_slope);
-    const R h = sd > 0 ? -(R)t.half_dy : (R)t.half_dy;
-    return state_at(w, gy, py, h, pbase);
-}
-
 // WAVES: the register budget as waves per SIMD (2: up to 256 VGPRs per lane, 3: up to 168).
 // BDF: the highest real-time order of the grid (levels n-1, n-2 read); GEN: general options.
 // FIRST (FP64 form, stage 1 of more than one): Q^{s-1} is Q^0, so Q^0 of a row is taken from

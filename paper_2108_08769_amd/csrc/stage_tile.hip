@@ -21,6 +21,10 @@
 // lower-index cell, and that reference (an FP64 difference) is added back in the divergence.
 // Periodic sides are handled by wrapping halo indices; cells outside a non-periodic side read
 // as non-fluid.
+// GEN (the general options): the Roe or exact flux in place of Osher's (Sec. 2.4), the k-limiter
+// or split limiter on p in place of the new pressure gradient (Sec. 2.3.2), zero-gradient sides
+// (Sec. 3.1), one pseudo-time step per tank (the minimum local step, from the previous iteration's
+// last stage), and BDF3 (Table 1).
 #include <hip/hip_runtime.h>
 
 #include "stage_common.h"
@@ -70,13 +74,15 @@ __device__ __forceinline__ void ring_position(int pidx, int &i, int &j)
 }
 
 // Stage-0 data of one cell: Q^0 (rho, rho u, rho v; the mixed form keeps its deviation from
-// level n), level n and level n-1.
+// level n), level n, level n-1 and level n-2.
 struct SourceData {
-    double z0, z1, z2, n0, n1, n2, m0, m1, m2;
+    double z0, z1, z2, n0, n1, n2, m0, m1, m2, k0, k1, k2;
 };
 
-// Level n (and n-1 with BDF2) of cell c; these do not depend on the pseudo-loop status.
-__device__ __forceinline__ void load_levels(const TankDev &t, size_t c, bool bdf2, SourceData &s)
+// Level n (and n-1 with BDF2, n-2 with BDF3) of cell c; these do not depend on the pseudo-loop
+// status.
+__device__ __forceinline__ void load_levels(const TankDev &t, size_t c, bool bdf2, bool bdf3,
+                                            SourceData &s)
 {
     const size_t plane = t.plane;
     s.n0 = t.level_n[c];
@@ -89,40 +95,50 @@ __device__ __forceinline__ void load_levels(const TankDev &t, size_t c, bool bdf
     } else {
         s.m0 = s.m1 = s.m2 = 0.0;
     }
+    if (bdf3) {
+        s.k0 = t.level_nm2[c];
+        s.k1 = t.level_nm2[plane + c];
+        s.k2 = t.level_nm2[2 * plane + c];
+    } else {
+        s.k0 = s.k1 = s.k2 = 0.0;
+    }
 }
 
 template <class P>
 __device__ __forceinline__ SourceData load_source(const TankDev &t, const typename P::Store *q0,
-                                                  size_t c, bool bdf2)
+                                                  size_t c, bool bdf2, bool bdf3)
 {
     const size_t plane = t.plane;
     SourceData s;
     s.z0 = (double)q0[c];
     s.z1 = (double)q0[plane + c];
     s.z2 = (double)q0[2 * plane + c];
-    load_levels(t, c, bdf2, s);
+    load_levels(t, c, bdf2, bdf3, s);
     return s;
 }
 
 // Stage-0 quantities of a cell from its SourceData: absolute Q^0 (a0 .. a2) and the real-time
-// numerators B0 Q^0 + B1 Q^n + B2 Q^{n-1} (Table 1).  The mixed form uses B0 + B1 + B2 = 0:
-// B0 (Q^0 - Q^n) + B2 (Q^{n-1} - Q^n), with Q^0 - Q^n its stored deviation.
+// numerators B0 Q^0 + B1 Q^n + B2 Q^{n-1} + B3 Q^{n-2} (Table 1).  The mixed form uses
+// B0 + B1 + B2 + B3 = 0: B0 (Q^0 - Q^n) + B2 (Q^{n-1} - Q^n) + B3 (Q^{n-2} - Q^n), with
+// Q^0 - Q^n its stored deviation.
 template <class P>
 __device__ __forceinline__ void stage0_terms(const SourceData &sd, const StepParams &sp, bool bdf2,
-                                             double a[3], double num[3])
+                                             bool bdf3, double a[3], double num[3])
 {
     const double z[3] = {sd.z0, sd.z1, sd.z2}, n[3] = {sd.n0, sd.n1, sd.n2},
-                 m[3] = {sd.m0, sd.m1, sd.m2};
+                 m[3] = {sd.m0, sd.m1, sd.m2}, k2[3] = {sd.k0, sd.k1, sd.k2};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         if constexpr (P::kMixed) {
             a[k] = n[k] + z[k];
             num[k] = sp.b0 * z[k];
             if (bdf2) num[k] = fma(sp.b2, m[k] - n[k], num[k]);
+            if (bdf3) num[k] = fma(sp.b3, k2[k] - n[k], num[k]);
         } else {
             a[k] = z[k];
             num[k] = fma(sp.b0, z[k], sp.b1 * n[k]);
             if (bdf2) num[k] = fma(sp.b2, m[k], num[k]);
+            if (bdf3) num[k] = fma(sp.b3, k2[k], num[k]);
         }
     }
 }
@@ -191,12 +207,11 @@ __host__ __device__ constexpr bool fin_in_block()
            TX * TY + 2 * (TX + TY) <= NT - 64;
 }
 
-// Launch bounds: NT threads, and for the 16 x 8 tile a register budget that fits four workgroups
-// (five waves per SIMD).
-template <class P, int TX, int TY, int NT, bool NORM_MAX>
-__global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankDev t, Scheme sc, int stage,
-                                                                          int tiles_x, int n_tiles,
-                                                                          IterArgs ia)
+// Launch bounds: NT threads, and for the 16 x 8 tile of the default scheme a register budget that
+// fits four workgroups (five waves per SIMD).  GEN: the general options (file comment).
+template <class P, int TX, int TY, int NT, bool NORM_MAX, bool GEN>
+__global__ void __launch_bounds__(NT, (TX * TY == 128 && !GEN ? 5 : 1))
+    stage_tile(TankDev t, Scheme sc, int stage, int tiles_x, int n_tiles, IterArgs ia)
 {
     using R = typename P::Real;
     using S = typename P::Store;
@@ -255,20 +270,22 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
     }
     const StepParams sp = *t.step;
     const bool bdf2 = sp.b2 != 0.0;
-    SourceData src0 = {P::kMixed ? 0.0 : 1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+    const bool bdf3 = GEN && sp.b3 != 0.0;
+    SourceData src0 = {P::kMixed ? 0.0 : 1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     size_t own_c = ~(size_t)0;  // this thread's first phase-2 cell, if inside the tank
     if (tid < NPOS) {
         int i, j, gi, gj;
         ring_position<TX, TY>(tid, i, j);
         if (locate(x0 + i, t.nx, t.per_x, gi) && locate(y0 + j, t.ny, t.per_y, gj)) {
             own_c = (size_t)gj * t.nx + gi;
-            load_levels(t, own_c, bdf2, src0);
+            load_levels(t, own_c, bdf2, bdf3, src0);
         }
     }
 
     // the buffers follow from the iteration (IterArgs); the stop flag is tested once the loads
     // below are in flight, so that its latency overlaps theirs
     const int stopped = t.status->done;
+    const double dtau_glob = (GEN && sc.global_dtau) ? t.status->dtau_global : 0.0;
     const int cur = ia.cur_off;
     const StageBuffers bufs = stage_buffers(cur, stage);
     const S *qprev = (const S *)t.state[bufs.in];
@@ -309,7 +326,7 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
     // The tile cell of this thread keeps its stage-0 data for phase 4 (mixed form: also the
     // references sx, sy of its left and lower faces, and its level-n density).
     double own_a[3] = {1.0, 0.0, 0.0}, own_z[3] = {0.0, 0.0, 0.0}, own_d[3] = {0.0, 0.0, 0.0};
-    double own_sx = 0.0, own_sy = 0.0, own_lvl = 0.0;
+    double own_sx = 0.0, own_sy = 0.0, own_lvl = 0.0, own_lvl_m = 0.0, own_lvl_n = 0.0;
 
     for (int pidx = tid; pidx < NPOS; pidx += NT) {
         int i, j;
@@ -319,14 +336,20 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
         const int r = (j + 2) * RX + (i + 2);
         CellRecT<R> rec;
         rec.w = {sW[0][r], sW[1][r], sW[2][r], P::kMixed ? R(0) : (R)sP[r]};
-        // a wall face shows the cell its own mirror image (Sec. 2.5)
-        const Prim<R> xm = (f & FLAG_WALL_XM) ? mirror(rec.w, 0, slip)
+        // zero-gradient sides (general options): the cell's faces on the tank's open sides
+        const bool open_xm = GEN && x0 + i == 0 && (t.open & 1);
+        const bool open_xp = GEN && x0 + i == t.nx - 1 && (t.open & 2);
+        const bool open_ym = GEN && y0 + j == 0 && (t.open & 4);
+        const bool open_yp = GEN && y0 + j == t.ny - 1 && (t.open & 8);
+        // a wall face shows the cell its own mirror image (Sec. 2.5), a zero-gradient face the
+        // cell itself
+        const Prim<R> xm = (f & FLAG_WALL_XM) ? (open_xm ? rec.w : mirror(rec.w, 0, slip))
                                               : Prim<R>{sW[0][r - 1], sW[1][r - 1], sW[2][r - 1], R(0)};
-        const Prim<R> xp = (f & FLAG_WALL_XP) ? mirror(rec.w, 0, slip)
+        const Prim<R> xp = (f & FLAG_WALL_XP) ? (open_xp ? rec.w : mirror(rec.w, 0, slip))
                                               : Prim<R>{sW[0][r + 1], sW[1][r + 1], sW[2][r + 1], R(0)};
-        const Prim<R> ym = (f & FLAG_WALL_YM) ? mirror(rec.w, 1, slip)
+        const Prim<R> ym = (f & FLAG_WALL_YM) ? (open_ym ? rec.w : mirror(rec.w, 1, slip))
                                               : Prim<R>{sW[0][r - RX], sW[1][r - RX], sW[2][r - RX], R(0)};
-        const Prim<R> yp = (f & FLAG_WALL_YP) ? mirror(rec.w, 1, slip)
+        const Prim<R> yp = (f & FLAG_WALL_YP) ? (open_yp ? rec.w : mirror(rec.w, 1, slip))
                                               : Prim<R>{sW[0][r + RX], sW[1][r + RX], sW[2][r + RX], R(0)};
         rec.gx = slopes(xm, rec.w, xp, (R)t.inv_dx, k);
         rec.gy = slopes(ym, rec.w, yp, (R)t.inv_dy, k);
@@ -337,10 +360,10 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
             int gi, gj;
             locate(x0 + i, t.nx, t.per_x, gi);
             locate(y0 + j, t.ny, t.per_y, gj);
-            sd = load_source<P>(t, q0, (size_t)gj * t.nx + gi, bdf2);
+            sd = load_source<P>(t, q0, (size_t)gj * t.nx + gi, bdf2, bdf3);
         }
         double a[3], num[3];
-        stage0_terms<P>(sd, sp, bdf2, a, num);
+        stage0_terms<P>(sd, sp, bdf2, bdf3, a, num);
         const double d_r = num[0] * sp.inv_dt, d_ru = num[1] * sp.inv_dt, d_rv = num[2] * sp.inv_dt;
         rec.d_r = (R)d_r;
         rec.d_ru = (R)d_ru;
@@ -370,9 +393,37 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
             own_sx = sx;
             own_sy = sy;
             own_lvl = sd.n0;
+            own_lvl_m = sd.n1;
+            own_lvl_n = sd.n2;
         }
 
-        const FaceStatesT<R> fs = face_states<R>(t, rec, pb_xl, pb_own, pb_yb, pb_own);
+        // the cell's pressure gradient: the new method, or (general options) the k-limiter or
+        // split limiter on p, whose stencil sees the cell's own p across a wall or open face
+        R px = R(0), py = R(0);
+        FaceStatesT<R> fs;
+        if constexpr (GEN) {
+            if (sc.pgrad != 0) {
+                const double pm = sP[r];
+                const double dpr_x = (f & FLAG_WALL_XP) ? 0.0 : sP[r + 1] - pm;
+                const double dpl_x = (f & FLAG_WALL_XM) ? 0.0 : pm - sP[r - 1];
+                const double dpr_y = (f & FLAG_WALL_YP) ? 0.0 : sP[r + RX] - pm;
+                const double dpl_y = (f & FLAG_WALL_YM) ? 0.0 : pm - sP[r - RX];
+                px = (R)pgrad_limited(sc.pgrad, sc.pk, dpr_x, dpl_x, t.inv_dx, (double)xm.r,
+                                      (double)rec.w.r, (double)xp.r, t.gx);
+                py = (R)pgrad_limited(sc.pgrad, sc.pk, dpr_y, dpl_y, t.inv_dy, (double)ym.r,
+                                      (double)rec.w.r, (double)yp.r, t.gy);
+            } else {
+                px = cell_gradp_x(t, rec);
+                py = cell_gradp_y(t, rec);
+            }
+            const R hx = (R)t.half_dx, hy = (R)t.half_dy;
+            fs.xl = state_at(rec.w, rec.gx, px, -hx, pb_xl);
+            fs.xr = state_at(rec.w, rec.gx, px, hx, pb_own);
+            fs.yb = state_at(rec.w, rec.gy, py, -hy, pb_yb);
+            fs.yt = state_at(rec.w, rec.gy, py, hy, pb_own);
+        } else {
+            fs = face_states<R>(t, rec, pb_xl, pb_own, pb_yb, pb_own);
+        }
         const bool row_in = (j >= 0 && j < TY), col_in = (i >= 0 && i < TX);
         if (row_in) {
             if (i >= 0) {  // left face i of the tile's x-faces
@@ -380,7 +431,8 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
                 const Prim<R> s = fs.xl;
                 sXR[0][fi] = s.r; sXR[1][fi] = s.u; sXR[2][fi] = s.v; sXR[3][fi] = s.p;
                 if (f & FLAG_WALL_XM) {
-                    const Prim<R> gs = ghost_state<R>(t, rec, 0, -1, slip, pb_own);
+                    const Prim<R> gs = GEN ? ghost_state_gen<R>(t, sc, rec, 0, -1, open_xm, px, pb_own)
+                                           : ghost_state<R>(t, rec, 0, -1, slip, pb_own);
                     sXL[0][fi] = gs.r; sXL[1][fi] = gs.u; sXL[2][fi] = gs.v; sXL[3][fi] = gs.p;
                 }
             }
@@ -389,7 +441,8 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
                 const Prim<R> s = fs.xr;
                 sXL[0][fi] = s.r; sXL[1][fi] = s.u; sXL[2][fi] = s.v; sXL[3][fi] = s.p;
                 if (f & FLAG_WALL_XP) {
-                    const Prim<R> gs = ghost_state<R>(t, rec, 0, +1, slip, pb_own);
+                    const Prim<R> gs = GEN ? ghost_state_gen<R>(t, sc, rec, 0, +1, open_xp, px, pb_own)
+                                           : ghost_state<R>(t, rec, 0, +1, slip, pb_own);
                     sXR[0][fi] = gs.r; sXR[1][fi] = gs.u; sXR[2][fi] = gs.v; sXR[3][fi] = gs.p;
                 }
             }
@@ -400,7 +453,8 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
                 const Prim<R> s = fs.yb;
                 sYU[0][fi] = s.r; sYU[1][fi] = s.u; sYU[2][fi] = s.v; sYU[3][fi] = s.p;
                 if (f & FLAG_WALL_YM) {
-                    const Prim<R> gs = ghost_state<R>(t, rec, 1, -1, slip, pb_own);
+                    const Prim<R> gs = GEN ? ghost_state_gen<R>(t, sc, rec, 1, -1, open_ym, py, pb_own)
+                                           : ghost_state<R>(t, rec, 1, -1, slip, pb_own);
                     sYL[0][fi] = gs.r; sYL[1][fi] = gs.u; sYL[2][fi] = gs.v; sYL[3][fi] = gs.p;
                 }
             }
@@ -409,7 +463,8 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
                 const Prim<R> s = fs.yt;
                 sYL[0][fi] = s.r; sYL[1][fi] = s.u; sYL[2][fi] = s.v; sYL[3][fi] = s.p;
                 if (f & FLAG_WALL_YP) {
-                    const Prim<R> gs = ghost_state<R>(t, rec, 1, +1, slip, pb_own);
+                    const Prim<R> gs = GEN ? ghost_state_gen<R>(t, sc, rec, 1, +1, open_yp, py, pb_own)
+                                           : ghost_state<R>(t, rec, 1, +1, slip, pb_own);
                     sYU[0][fi] = gs.r; sYU[1][fi] = gs.u; sYU[2][fi] = gs.v; sYU[3][fi] = gs.p;
                 }
             }
@@ -417,7 +472,7 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
     }
     __syncthreads();
 
-    // ---- phase 3: one Osher flux per face --------------------------------------------------
+    // ---- phase 3: one flux per face (Osher's, or with the general options Roe's or the exact) -
     const R beta = (R)t.beta, inv_beta = (R)t.inv_beta;
     for (int fidx = tid; fidx < NFX + NFY; fidx += NT) {
         if (fidx < NFX) {
@@ -426,7 +481,7 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
             if ((fl_ & FLAG_SOLID) && (fr & FLAG_SOLID)) continue;
             const Prim<R> L = {sXL[0][fidx], sXL[1][fidx], sXL[2][fidx], sXL[3][fidx]};
             const Prim<R> Rt = {sXR[0][fidx], sXR[1][fidx], sXR[2][fidx], sXR[3][fidx]};
-            const Vec4<R> F = osher_x(L, Rt, beta, inv_beta);
+            const Vec4<R> F = GEN ? flux_x(sc.flux, L, Rt, beta, inv_beta) : osher_x(L, Rt, beta, inv_beta);
             sXL[0][fidx] = F.a; sXL[1][fidx] = F.b; sXL[2][fidx] = F.c; sXL[3][fidx] = F.d;
         } else {
             const int q = fidx - NFX;
@@ -435,7 +490,7 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
             if ((fb & FLAG_SOLID) && (fu & FLAG_SOLID)) continue;
             const Prim<R> L = {sYL[0][q], sYL[1][q], sYL[2][q], sYL[3][q]};
             const Prim<R> U = {sYU[0][q], sYU[1][q], sYU[2][q], sYU[3][q]};
-            const Vec4<R> F = osher_y(L, U, beta, inv_beta);
+            const Vec4<R> F = GEN ? flux_y(sc.flux, L, U, beta, inv_beta) : osher_y(L, U, beta, inv_beta);
             sYL[0][q] = F.a; sYL[1][q] = F.b; sYL[2][q] = F.c; sYL[3][q] = F.d;
         }
     }
@@ -470,8 +525,9 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
             R4[0] += -own_d[0];
             R4[1] += -own_d[1] + r0 * t.gx;
             R4[2] += -own_d[2] + r0 * t.gy;
-            const double dtau = P::kMixed ? local_dtau_f32(t, t.cfl, r0, own_a[1], own_a[2])
-                                          : local_dtau(t, t.cfl, r0, own_a[1], own_a[2]);
+            const double dtau = (GEN && sc.global_dtau) ? dtau_glob
+                                : (P::kMixed ? local_dtau_f32(t, t.cfl, r0, own_a[1], own_a[2])
+                                             : local_dtau(t, t.cfl, r0, own_a[1], own_a[2]));
             const double ad = alpha * dtau;
             const double api = 1.0 + sp.b0 * ad * sp.inv_dt;
             const double fac = ad * rcp_pos(api);
@@ -495,6 +551,12 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
                 }
                 const double rho_new = P::kMixed ? own_lvl + out[0] : out[0];
                 part[4] = (rho_new > 0.0 && rho_new < INFINITY) ? 0.0 : 1.0;
+                if (GEN && sc.global_dtau && rho_new > 0.0) {
+                    // pseudo-time step of the updated state: the next iteration's stage 0
+                    const double m_new = out[1] + (P::kMixed ? own_lvl_m : 0.0);
+                    const double n_new = out[2] + (P::kMixed ? own_lvl_n : 0.0);
+                    part[5] = local_dtau(t, t.cfl, rho_new, m_new, n_new);
+                }
             }
         }
     }
@@ -509,31 +571,31 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 ? 5 : 1)) stage_tile(TankD
     }
 }
 
-template <class P, int TX, int TY, int NT>
+template <class P, int TX, int TY, int NT, bool GEN>
 int launch_tile(const TankDev &t, const Scheme &sc, int stage, const IterArgs &ia, void *stream)
 {
     const int tiles_x = (t.nx + TX - 1) / TX, tiles_y = (t.ny + TY - 1) / TY;
     const int n_tiles = tiles_x * tiles_y;
     const int blocks = ((n_tiles + 7) / 8) * 8 + (ia.fin && !fin_in_block<TX, TY, NT>() ? 8 : 0);
     if (sc.norm_max)
-        hipLaunchKernelGGL((stage_tile<P, TX, TY, NT, true>), dim3(blocks), dim3(NT), 0,
+        hipLaunchKernelGGL((stage_tile<P, TX, TY, NT, true, GEN>), dim3(blocks), dim3(NT), 0,
                            (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles, ia);
     else
-        hipLaunchKernelGGL((stage_tile<P, TX, TY, NT, false>), dim3(blocks), dim3(NT), 0,
+        hipLaunchKernelGGL((stage_tile<P, TX, TY, NT, false, GEN>), dim3(blocks), dim3(NT), 0,
                            (hipStream_t)stream, t, sc, stage, tiles_x, n_tiles, ia);
     return (int)hipGetLastError();
 }
 
-template <class P>
+template <class P, bool GEN>
 int launch_tile_p(const TankDev &t, const Scheme &sc, int stage, int tile_x, int tile_y,
                   const IterArgs &ia, void *stream)
 {
-    if (tile_x == 32 && tile_y == 8) return launch_tile<P, 32, 8, 256>(t, sc, stage, ia, stream);
-    if (tile_x == 16 && tile_y == 16) return launch_tile<P, 16, 16, 256>(t, sc, stage, ia, stream);
-    if (tile_x == 64 && tile_y == 4) return launch_tile<P, 64, 4, 256>(t, sc, stage, ia, stream);
-    if (tile_x == 3208 && tile_y == 2) return launch_tile<P, 32, 8, 512>(t, sc, stage, ia, stream);
-    if (tile_x == 1616 && tile_y == 2) return launch_tile<P, 16, 16, 512>(t, sc, stage, ia, stream);
-    if (tile_x == 1608 && tile_y == 2) return launch_tile<P, 16, 8, 320>(t, sc, stage, ia, stream);
+    if (tile_x == 32 && tile_y == 8) return launch_tile<P, 32, 8, 256, GEN>(t, sc, stage, ia, stream);
+    if (tile_x == 16 && tile_y == 16) return launch_tile<P, 16, 16, 256, GEN>(t, sc, stage, ia, stream);
+    if (tile_x == 64 && tile_y == 4) return launch_tile<P, 64, 4, 256, GEN>(t, sc, stage, ia, stream);
+    if (tile_x == 3208 && tile_y == 2) return launch_tile<P, 32, 8, 512, GEN>(t, sc, stage, ia, stream);
+    if (tile_x == 1616 && tile_y == 2) return launch_tile<P, 16, 16, 512, GEN>(t, sc, stage, ia, stream);
+    if (tile_x == 1608 && tile_y == 2) return launch_tile<P, 16, 8, 320, GEN>(t, sc, stage, ia, stream);
     return (int)hipErrorInvalidValue;
 }
 
@@ -563,9 +625,12 @@ int launch_stage_tile(const TankDev &t, const Scheme &sc, int stage, int tile_x,
     // the finalize reads the partials of the previous iteration's last stage, which stage 1 would
     // overwrite in the same launch if it were the last stage
     if (ia.fin && (stage != 1 || stage == sc.smax)) return (int)hipErrorInvalidValue;
-    if (sc.bdf > 2 || sc.general) return (int)hipErrorInvalidValue;
-    return sc.mixed ? launch_tile_p<PrecMixed>(t, sc, stage, tile_x, tile_y, ia, stream)
-                    : launch_tile_p<PrecF64>(t, sc, stage, tile_x, tile_y, ia, stream);
+    // the general options and BDF3 run in the GEN instances
+    if (sc.general || sc.bdf > 2)
+        return sc.mixed ? launch_tile_p<PrecMixed, true>(t, sc, stage, tile_x, tile_y, ia, stream)
+                        : launch_tile_p<PrecF64, true>(t, sc, stage, tile_x, tile_y, ia, stream);
+    return sc.mixed ? launch_tile_p<PrecMixed, false>(t, sc, stage, tile_x, tile_y, ia, stream)
+                    : launch_tile_p<PrecF64, false>(t, sc, stage, tile_x, tile_y, ia, stream);
 }
 
 }  // namespace vdac

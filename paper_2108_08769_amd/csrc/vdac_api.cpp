@@ -159,10 +159,10 @@ int check_options(const vdac_options *o)
         return fail(VDAC_E_INVALID, "the mixed precision form runs the row-marching or the tiled "
                     "kernel (tile 0 x 0, -W x L or a 2D tile), not the one-thread-per-cell kernel");
     const bool general = o->flux != VDAC_FLUX_OSHER || o->pgrad != VDAC_PGRAD_NEW || o->local_dtau == 0;
-    if ((general || o->bdf_order == 3) && !auto_tile && !march)
+    if ((general || o->bdf_order == 3) && direct)
         return fail(VDAC_E_INVALID, "the Roe and exact fluxes, the limited pressure gradients, the "
-                    "global pseudo-time step and BDF3 run on the row-marching kernel only (tile 0 x 0 "
-                    "or -W x L)");
+                    "global pseudo-time step and BDF3 run on the row-marching and tiled kernels, not "
+                    "the one-thread-per-cell kernel");
     return VDAC_OK;
 }
 
@@ -358,15 +358,15 @@ void transpose_state(const double *in, double *out, int nx, int ny, bool forward
     }
 }
 
-// Options a tank's sides restrict: zero-gradient sides run on the row-marching kernel, not with
-// the split limiter (whose zero-gradient ghost is not derived here).
+// Options a tank's sides restrict: zero-gradient sides run on the row-marching and tiled kernels,
+// not on the one-thread-per-cell kernel, and not with the split limiter (whose zero-gradient
+// ghost is not derived here).
 int check_tank_options(const vdac_tank *t, int idx, const vdac_options *o)
 {
     if (!has_open_side(t)) return VDAC_OK;
-    const bool auto_tile = o->tile_x == 0 && o->tile_y == 0;
-    if (!auto_tile && o->tile_x > -1)
-        return fail(VDAC_E_INVALID, "tank %d: zero-gradient sides run on the row-marching kernel "
-                    "only (tile 0 x 0 or -W x L)", idx);
+    if (o->tile_x == 1 && o->tile_y == 1)
+        return fail(VDAC_E_INVALID, "tank %d: zero-gradient sides run on the row-marching and tiled "
+                    "kernels, not the one-thread-per-cell kernel", idx);
     if (o->pgrad == VDAC_PGRAD_SPLIT)
         return fail(VDAC_E_INVALID, "tank %d: the split pressure limiter is not available with "
                     "zero-gradient sides", idx);
@@ -1315,9 +1315,7 @@ int autotune_tile(const vdac_tank *tanks, int32_t n_tanks, vdac_options *o, void
     for (int w : {2, 3})
         for (int c : chunks)
             if (c == 1 || c / 2 < max_ny) cand.push_back({-w, c});
-    const bool march_only = base.flux != VDAC_FLUX_OSHER || base.pgrad != VDAC_PGRAD_NEW ||
-                            base.local_dtau == 0 || base.bdf_order == 3 || has_open_side(&tanks[0]);
-    if (n_tanks == 1 && !march_only)
+    if (n_tanks == 1)
         for (auto tl : {std::pair<int, int>{3208, 2}, {1616, 2}, {1608, 2}, {32, 8}, {16, 16}}) cand.push_back(tl);
 
     double best_ms = 0.0;

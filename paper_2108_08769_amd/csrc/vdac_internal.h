@@ -152,9 +152,9 @@ struct Scheme {
 
 // Launch wrappers.  All return hipError_t cast to int.
 //
-// Per-tank launches: tile (1, 1) runs the plain one-thread-per-cell kernel (FP64 only,
-// kernels_f64.hip), the supported 2D tiles the LDS-tiled kernel (stage_tile.hip, FP64 or mixed,
-// default scheme, BDF order up to 2).  Grid-wide
+// Per-tank launches: tile (1, 1) runs the plain one-thread-per-cell kernel (FP64 and the default
+// scheme only, kernels_f64.hip), the supported 2D tiles the LDS-tiled kernel (stage_tile.hip,
+// FP64 or mixed, every option).  Grid-wide
 // launches: the row-marching kernel (stage_march.hip) runs every work unit of every tank from
 // the device unit table in one launch per stage, with `waves_per_block` table entries per
 // workgroup and a register budget of `waves_simd` (2 or 3) waves per SIMD; begin_step and

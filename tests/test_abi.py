@@ -122,10 +122,12 @@ def _create(tanks, opt):
     (lambda t, o: setattr(o, "flux", 3), "flux"),
     (lambda t, o: setattr(o, "pgrad", 3), "pgrad"),
     (lambda t, o: (setattr(o, "pgrad", 1), setattr(o, "p_limiter_k", 3.0)), "p_limiter_k"),
-    (lambda t, o: (setattr(o, "flux", 1), setattr(o, "tile_x", 32), setattr(o, "tile_y", 8)),
-     "row-marching"),
+    (lambda t, o: (setattr(o, "flux", 1), setattr(o, "tile_x", 1), setattr(o, "tile_y", 1)),
+     "one-thread-per-cell"),
     (lambda t, o: (setattr(o, "bdf_order", 3), setattr(o, "tile_x", 1), setattr(o, "tile_y", 1)),
-     "row-marching"),
+     "one-thread-per-cell"),
+    (lambda t, o: (t.bc.__setitem__(3, 2), setattr(o, "tile_x", 1), setattr(o, "tile_y", 1)),
+     "one-thread-per-cell"),
     (lambda t, o: (t.bc.__setitem__(0, 2), setattr(o, "pgrad", 2)), "split"),
 ])
 def test_create_grid_rejects_bad_arguments(change, needle):

@@ -1,7 +1,8 @@
 """GPU path of the further options against the oracle, through the C ABI: the Roe and exact
 (Bassi) fluxes, the k-limiter and split limiter on p, zero-gradient sides with the
 pseudo-time-only mode and global pseudo-time steps (the Riemann problems of Table 2), BDF3, and
-the global real-time step; the mixed form of each against FP64.
+the global real-time step; the mixed form of each against FP64; each in the row-marching kernel
+and in every LDS tile shape.
 
 Bars as in the other parity files: FP64 per field max |gpu - oracle| / max(max |oracle|,
 physical scale) <= 1e-12 with equal iteration counts; mixed against FP64 normwise <= 1e-6 (rho),
@@ -199,8 +200,12 @@ def test_realtime_dt_matches_oracle():
 
 # ---- the mixed form, graphs and batches of the general kernel ---------------------------------
 
-@pytest.mark.parametrize("case", ["roe", "bassi", "limiter", "split", "open", "global", "bdf3"])
-def test_mixed_general_options(case):
+CASES = ["roe", "bassi", "limiter", "split", "open", "global", "bdf3", "combined"]
+
+
+def case_options(case):
+    """(flux/pgrad keywords, workload keywords, sides) of one general-option case; "combined"
+    puts zero-gradient sides, the Roe flux, the k-limiter on p and the global step together."""
     kw, wkargs, bc = {}, {}, (W, W, W, W)
     if case == "roe":
         kw["flux"] = ROE
@@ -216,13 +221,57 @@ def test_mixed_general_options(case):
         wkargs["local_dtau"] = False
     elif case == "bdf3":
         wkargs["bdf"] = 3
-    check_mixed(dam(96, 48, bc=bc, **wkargs), steps=4, pseudo=20, **kw)
+    elif case == "combined":
+        kw.update(flux=ROE, pgrad=LIMITER, pk=2.0)
+        wkargs["local_dtau"] = False
+        bc = (W, O, W, O)
+    return kw, wkargs, bc
 
 
-def test_general_kernel_graph_replay_matches_eager():
+@pytest.mark.parametrize("case", CASES[:-1])
+def test_mixed_general_options(case):
+    kw, wkargs, bc = case_options(case)
+    check_mixed(dam(96, 48, bc=bc, **wkargs), steps=4, pseudo=20, tile=(-2, 8), **kw)
+
+
+# every LDS tile shape: 256-thread 32 x 8, 16 x 16, 64 x 4; 512-thread 32 x 8, 16 x 16; 320-thread 16 x 8
+TILE_SHAPES = [(32, 8), (16, 16), (64, 4), (3208, 2), (1616, 2), (1608, 2)]
+
+
+@pytest.mark.parametrize("tile", TILE_SHAPES)
+@pytest.mark.parametrize("case", CASES)
+def test_general_options_on_tiles(case, tile):
+    """Each general option in the LDS-tiled kernel, on a tank whose sides are not multiples of
+    any tile, against the oracle (four real steps: BDF3 from the third)."""
+    kw, wkargs, bc = case_options(case)
+    check(dam(37, 23, bc=bc, **wkargs), steps=4, pseudo=12, tile=tile, **kw)
+
+
+@pytest.mark.parametrize("tile", [(64, 4), (3208, 2), (1608, 2)])
+@pytest.mark.parametrize("flux", [OSHER, BASSI])
+def test_riemann_problem_on_tiles(flux, tile):
+    """RP1 of Table 2 (a tank one cell tall: zero-gradient sides, global step, no real-time term)
+    in the tiled kernel against the oracle."""
+    rp = table2()[0]
+    wk = rp_workload(rp, 100)
+    t = wk.tanks[0]
+    scales = np.array([np.abs(t.q[0]).max(), np.abs(t.q[0]).max() * 10.0,
+                       np.abs(t.q[0]).max() * 10.0, np.abs(t.q[3]).max()])
+    check(wk, steps=1, pseudo=25, scales=scales, flux=flux, pgrad=LIMITER, pk=1.0, tile=tile)
+
+
+@pytest.mark.parametrize("tile", [(3208, 2), (1608, 2)])
+@pytest.mark.parametrize("case", CASES)
+def test_mixed_general_options_on_tiles(case, tile):
+    kw, wkargs, bc = case_options(case)
+    check_mixed(dam(96, 48, bc=bc, **wkargs), steps=4, pseudo=20, tile=tile, **kw)
+
+
+@pytest.mark.parametrize("tile", [(-2, 8), (3208, 2)], ids=["march", "tile"])
+def test_general_kernel_graph_replay_matches_eager(tile):
     wk = dam(70, 40, bc=(O, W, W, W), local_dtau=False)
-    a = run_gpu(wk, 3, 12, flux=BASSI, pgrad=LIMITER, graph_iters=0)
-    b = run_gpu(wk, 3, 12, flux=BASSI, pgrad=LIMITER, graph_iters=-1)
+    a = run_gpu(wk, 3, 12, flux=BASSI, pgrad=LIMITER, graph_iters=0, tile=tile)
+    b = run_gpu(wk, 3, 12, flux=BASSI, pgrad=LIMITER, graph_iters=-1, tile=tile)
     for x, y in zip(a[0], b[0]):
         np.testing.assert_array_equal(x, y)
     np.testing.assert_array_equal(a[2], b[2])

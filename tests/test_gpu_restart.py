@@ -59,8 +59,6 @@ def run_steps(grid, wk, steps, pseudo, tol):
 @pytest.mark.parametrize("bdf", [1, 2, 3])
 @pytest.mark.parametrize("shape", ["march", "tile"])
 def test_restart_with_history_is_bitwise(precision, bdf, shape):
-    if shape == "tile" and bdf == 3:
-        pytest.skip("BDF3 runs on the row-marching kernel only")
     wk = moving_tanks(2 if shape == "march" else 1)
     wk.bdf = bdf
     tile = (0, 0) if shape == "march" else (32, 8)
