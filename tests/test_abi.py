@@ -129,6 +129,7 @@ def _create(tanks, opt):
     (lambda t, o: (t.bc.__setitem__(3, 2), setattr(o, "tile_x", 1), setattr(o, "tile_y", 1)),
      "one-thread-per-cell"),
     (lambda t, o: (t.bc.__setitem__(0, 2), setattr(o, "pgrad", 2)), "split"),
+    (lambda t, o: (setattr(t, "nx", 16385), setattr(t, "ny", 32768)), "2^29"),
 ])
 def test_create_grid_rejects_bad_arguments(change, needle):
     t, _ = vdac.make_tank(8, 8, 1.0, 1.0)
@@ -164,3 +165,13 @@ def test_create_grid_checks_a_borrowed_workspace(offset, short, code, needle):
                                 ctypes.byref(h))
     assert rc == code and needle in vdac.lib().last_error().decode()
     assert not h.value
+
+
+def test_workspace_at_the_tank_size_limit():
+    """2^29 cells is the largest tank (the row-marching kernel's 32-bit plane offsets): the
+    workspace of one is sized, one more row is refused."""
+    o = vdac.default_options()
+    t, _ = vdac.make_tank(16384, 32768, 4.0, 8.0)
+    assert vdac.workspace_bytes([t], o) > 4 * 8 * (1 << 29)
+    t, _ = vdac.make_tank(16384, 32769, 4.0, 8.0)
+    assert vdac.workspace_bytes([t], o) == 0

@@ -13,6 +13,7 @@ bench.py times (the autotuned stage-kernel shape), on outputs the oracle can com
   the layer interface, the four walls and corners, and seeded interior cells.
 * 512-tank sloshing ensemble.  The whole batched launch runs; the oracle runs a sample of whole
   tanks (the smallest, the largest and seeded ones).
+* A tank of exactly 2^29 cells, the largest a grid takes, with the same window check.
 
 FP64 bar: |gpu - oracle| <= 1e-12 x the field's physical scale (as in the other parity tests).
 Mixed form: the mixed bar (rho 1e-6, rho u and rho v 1e-5, p 1e-4 of the same scales).
@@ -171,3 +172,53 @@ def test_ensemble_512_sampled_tanks(precision):
         worst = np.maximum(worst, err)
         assert np.all(err <= bar), (k, t.nx, t.ny, err)
     print(f"[fullsize] ensemble {precision}: tanks {picks}, worst field error {worst}", flush=True)
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_largest_tank_2_29_cells(precision):
+    """A tank of exactly 2^29 cells, the limit that the row-marching kernel's 32-bit plane offsets
+    set (8-byte elements: the last cell of a plane starts at byte 2^32 - 8): a dam break of
+    16384 x 32768 square cells with an obstacle next to the far corner, one real step of 2
+    pseudo-iterations in the benchmark's shape (-2 x 32), sampled cells against the oracle's
+    windows, the far corner, the last row and column and the obstacle's sides among them.  The
+    grid takes 61 GiB (mixed: 57 GiB) of device memory and the host 35 GB."""
+    nx, ny, pseudo = 16384, 32768, 2
+    assert nx * ny == 1 << 29
+    h = 1.0 / 4096
+    q = np.zeros((4, ny, nx))
+    q[0] = 1.0
+    q[0, :int(2.0 / h), :int(1.0 / h)] = 1000.0
+    solid = np.zeros((ny, nx), np.uint8)
+    solid[ny - 24:ny - 12, nx - 40:nx - 28] = 1
+    t = wl.Tank(nx, ny, nx * h, ny * h, q, gy=-9.81, beta=1100.0, solid=solid)
+    wk = wl.Workload("dam_break_16384x32768", [t], dt=2e-5, steps=1, max_pseudo=pseudo)
+    print(f"[fullsize] {wk.name} {precision}: {nx * ny} cells, shape (-2, 32)", flush=True)
+    grid = vdac.Grid([tank_dict(t)], gpu_options(wk, precision, tile=(-2, 32)))
+    try:
+        grid.set_state(0, q)
+        rc, done = grid.step(wk.dt, pseudo, 0.0, check=False)
+        assert rc == 0 and int(done[0]) == pseudo
+        got = grid.get_state(0)
+    finally:
+        grid.close()
+    np.testing.assert_array_equal(got[:, solid == 1], q[:, solid == 1])
+    samples = [(nx - 1, ny - 1), (nx - 2, ny - 1), (nx - 1, ny - 2), (0, ny - 1), (nx - 1, 0),
+               (nx // 2, ny - 1), (nx - 1, ny // 2), (nx - 41, ny - 18), (nx - 27, ny - 13),
+               (nx - 34, ny - 25), (nx - 34, ny - 11), (4095, 100), (4096, 100), (100, 8191),
+               (100, 8192), (nx // 2, ny // 2)]
+    rng = np.random.default_rng(29)
+    samples += [(int(rng.integers(0, nx)), int(rng.integers(0, ny))) for _ in range(8)]
+    radius = 2 * wk.stages * pseudo + 1
+    # the tank starts at rest with rho_max 1000: its scales from a one-cell stand-in (field_scales
+    # on the whole state would take 17 GB of temporaries)
+    q1 = np.array([1000.0, 0.0, 0.0, 0.0]).reshape(4, 1, 1)
+    scales = field_scales(wl.Tank(1, 1, t.lx, t.ly, q1, gy=t.gy, beta=t.beta))
+    bar = FP64_BAR if precision == "f64" else MIXED_BAR
+    worst = np.zeros(4)
+    for i, j in samples:
+        ref = window_oracle(wk, t, i, j, radius, pseudo)
+        err = np.abs(got[:, j, i] - ref) / scales
+        worst = np.maximum(worst, err)
+        assert np.all(err <= bar), ((i, j), err, got[:, j, i], ref)
+    print(f"[fullsize] {wk.name} {precision}: {len(samples)} cells, worst scaled error per field "
+          f"{worst}", flush=True)
