@@ -204,13 +204,15 @@ int stage_timing_read(const vdac_grid *g, double *kernel_ms, int64_t *launches,
 
 /* Autotuner of the stage-kernel shape.  For the tanks and options given (o's tile fields are
  * ignored on input), builds a scratch grid per candidate shape -- row marching with chunks of
- * 1..64 rows under a 2- and a 3-waves-per-SIMD register budget, and for a single tank with the
- * default scheme also the 2D LDS tiles -- runs one untimed and one timed real step of `iters`
- * pseudo-iterations
- * (1..1000) from the initial rest state, and writes the shape with the least stage-kernel time
- * into o->tile_x, o->tile_y.  The result is cached for the life of the process, keyed by
- * precision, scheme and tank shapes, so later calls with the same key return at once.  Allocates
- * and frees device memory and runs on hip_stream; the kernel time does not depend on the state. */
+ * 1..64 rows (and longer chunks that fill the chip's wave slots a whole number of times) under a
+ * 2- and a 3-waves-per-SIMD register budget, and for a single tank also the 2D LDS tiles -- runs
+ * one untimed and one timed real step of `iters` pseudo-iterations (1..1000) from the initial
+ * rest state, then times the leaders (up to three, within 5% of the fastest) again in three
+ * interleaved rounds of three steps each and writes the shape with the least of those
+ * stage-kernel times into o->tile_x, o->tile_y.  The result is cached for the life of the
+ * process, keyed by precision, scheme and tank shapes, so later calls with the same key return
+ * at once.  Allocates and frees device memory and runs on hip_stream; the kernel time does not
+ * depend on the state. */
 int autotune_tile(const vdac_tank *tanks, int32_t n_tanks, vdac_options *o, void *hip_stream,
                   int32_t iters);
 
