@@ -207,10 +207,11 @@ __host__ __device__ constexpr bool fin_in_block()
            TX * TY + 2 * (TX + TY) <= NT - 64;
 }
 
-// Launch bounds: NT threads, and for the 16 x 8 tile of the default scheme a register budget that
-// fits four workgroups (five waves per SIMD).  GEN: the general options (file comment).
+// Launch bounds: NT threads, and for the mixed form's 16 x 8 tile of the default scheme a register
+// budget that fits four workgroups (five waves per SIMD; the FP64 form reaches 96 VGPRs, five
+// waves, without the bound, and spills with it).  GEN: the general options (file comment).
 template <class P, int TX, int TY, int NT, bool NORM_MAX, bool GEN>
-__global__ void __launch_bounds__(NT, (TX * TY == 128 && !GEN ? 5 : 1))
+__global__ void __launch_bounds__(NT, (TX * TY == 128 && !GEN && P::kMixed ? 5 : 1))
     stage_tile(TankDev t, Scheme sc, int stage, int tiles_x, int n_tiles, IterArgs ia)
 {
     using R = typename P::Real;
