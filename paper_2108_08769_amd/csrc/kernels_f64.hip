@@ -132,7 +132,8 @@ __global__ void __launch_bounds__(kDirectTX *kDirectTY)
             double R4[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const double div = (Fxp[k] - Fxm[k]) * t.inv_dx + (Fyp[k] - Fym[k]) * t.inv_dy;
+                // 1/(2h): the flux functions return twice the face flux
+                const double div = (Fxp[k] - Fxm[k]) * t.flux_dx + (Fyp[k] - Fym[k]) * t.flux_dy;
                 R4[k] = -div + (k < 3 ? src[k] : 0.0);
             }
             const double fac = ad * rcp_pos(api);

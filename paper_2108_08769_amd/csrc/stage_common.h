@@ -39,6 +39,8 @@ __device__ __forceinline__ TankDev load_tank(const TankDev *__restrict__ p)
     t.inv_dy = uni(p->inv_dy);
     t.half_dx = uni(p->half_dx);
     t.half_dy = uni(p->half_dy);
+    t.flux_dx = uni(p->flux_dx);
+    t.flux_dy = uni(p->flux_dy);
     t.gx = uni(p->gx);
     t.gy = uni(p->gy);
     t.beta = uni(p->beta);

@@ -306,6 +306,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
     const R kl = (R)sc.k;
     const double alpha = sc.alpha[stage - 1];
     const double a_dtau = alpha * (t.cfl * (t.dx * t.dy));  // alpha_s CFL dx dy
+    const double fdx = t.flux_dx, fdy = t.flux_dy;  // 1/(2h): the fluxes come doubled
     const double kappa = sp.b0 * a_dtau * sp.inv_dt;
     const size_t plane = t.plane;
     const R hx = (R)t.half_dx, hy = (R)t.half_dy;
@@ -501,10 +502,10 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
             locate_axis(r - 1, t.ny, t.per_y, gj);
             const uint32_t os = (uint32_t)uni(gj) * (uint32_t)t.nx * (uint32_t)sizeof(S) + lof.s;
             if (LAST) {
-                const double R0 = fma(-gbd.a, t.inv_dy, rpart.a);
-                const double R1 = fma(-gbd.b, t.inv_dy, rpart.b);
-                const double R2 = fma(-gbd.c, t.inv_dy, rpart.c);
-                const double R3 = fma(-gbd.d, t.inv_dy, rpart.d);
+                const double R0 = fma(-gbd.a, fdy, rpart.a);
+                const double R1 = fma(-gbd.b, fdy, rpart.b);
+                const double R2 = fma(-gbd.c, fdy, rpart.c);
+                const double R3 = fma(-gbd.d, fdy, rpart.d);
                 const double rn = fma(fac, R0, pre.a);
                 gst(qout, os, (S)rn);
                 gst(qout + plane, os, (S)fma(fac, R1, pre.b));
@@ -531,7 +532,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
                     if (rho_new > 0.0) part5 = fmin(part5, local_dtau(t, t.cfl, rho_new, m_new, n_new));
                 }
             } else {
-                // fac and adt already carry 1/dy here
+                // fac and adt already carry 1/(2 dy) here
                 gst(qout, os, (S)fma(-fac, gbd.a, pre.a));
                 gst(qout + plane, os, (S)fma(-fac, gbd.b, pre.b));
                 gst(qout + 2 * plane, os, (S)fma(-fac, gbd.c, pre.c));
@@ -559,10 +560,10 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
             const Vec4<double> frd = cast4<double>(fr), fld = cast4<double>(fl);
             // -(x-divergence) + lower flux / dy - real-time term + body force
             Vec4<double> rp4;
-            rp4.a = fma(gbd.a, t.inv_dy, -((frd.a - fld.a) * t.inv_dx)) - d_r;
-            rp4.b = fma(gbd.b, t.inv_dy, -((frd.b - fld.b) * t.inv_dx)) + fma(a0, t.gx, -d_ru);
-            rp4.c = fma(gbd.c, t.inv_dy, -((frd.c - fld.c) * t.inv_dx)) + fma(a0, t.gy, -d_rv);
-            rp4.d = fma(gbd.d, t.inv_dy, -((frd.d - fld.d) * t.inv_dx));
+            rp4.a = fma(gbd.a, fdy, -((frd.a - fld.a) * fdx)) - d_r;
+            rp4.b = fma(gbd.b, fdy, -((frd.b - fld.b) * fdx)) + fma(a0, t.gx, -d_ru);
+            rp4.c = fma(gbd.c, fdy, -((frd.c - fld.c) * fdx)) + fma(a0, t.gy, -d_rv);
+            rp4.d = fma(gbd.d, fdy, -((frd.d - fld.d) * fdx));
             if constexpr (P::kMixed) {
                 rp4.b = fma(-sx, t.inv_dx, rp4.b);
                 rp4.c = fma(-sy, t.inv_dy, rp4.c);
@@ -590,8 +591,8 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
             } else {
                 pre = {fma(fc, rp4.a, z.a), fma(fc, rp4.b, z.b), fma(fc, rp4.c, z.c),
                        fma(t.beta * ad, rp4.d, z.d)};
-                fac = fc * t.inv_dy;
-                adt = t.beta * ad * t.inv_dy;
+                fac = fc * fdy;
+                adt = t.beta * ad * fdy;
             }
         }
         const Prim<R> syt = state_at(mid, rec.gy, py, hy, pb_own);

@@ -512,10 +512,11 @@ __global__ void __launch_bounds__(NT, (TX * TY == 128 && !GEN && P::kMixed ? 5 :
             const size_t c = (size_t)gj * t.nx + gi;
             const int xm = j * (TX + 1) + i, ym = j * TX + i;
             double R4[4];
+            const double fdx = t.flux_dx, fdy = t.flux_dy;  // 1/(2h): the faces hold twice the flux
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const double div = ((double)sXL[m][xm + 1] - (double)sXL[m][xm]) * t.inv_dx
-                                   + ((double)sYL[m][ym + TX] - (double)sYL[m][ym]) * t.inv_dy;
+                const double div = ((double)sXL[m][xm + 1] - (double)sXL[m][xm]) * fdx
+                                   + ((double)sYL[m][ym + TX] - (double)sYL[m][ym]) * fdy;
                 R4[m] = -div;
             }
             if constexpr (P::kMixed) {  // the face pressures' references

@@ -733,6 +733,8 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
         d.inv_dy = 1.0 / d.dy;
         d.half_dx = 0.5 * d.dx;
         d.half_dy = 0.5 * d.dy;
+        d.flux_dx = 0.5 * d.inv_dx;
+        d.flux_dy = 0.5 * d.inv_dy;
         d.gx = st[t].gx;
         d.gy = st[t].gy;
         d.beta = st[t].beta;

@@ -209,7 +209,10 @@ __device__ __forceinline__ void gauss_reciprocals(const float rho[3], float ir[3
     ir[2] = rcp_pos(rho[2]);
 }
 
-// F = (F(Q_L) + F(Q_R) - acc)/2 with acc = sum_j (w_j/2) |A_j| dQ.
+// The face flux functions below return TWICE the face flux, 2F: the factor 1/2 goes into the
+// 1/h of the flux divergence, where a power of two scales every result exactly (the divergence
+// comes out bit for bit as with F).  Here 2F = F(Q_L) + F(Q_R) - acc with
+// acc = sum_j (w_j/2) |A_j| dQ.
 template <typename T>
 __device__ __forceinline__ Vec4<T> upwind_flux(const Prim<T> &L, const Prim<T> &R, T mL, T mR,
                                                T dr, T dm, T dn, T dp, T beta, T inv_beta,
@@ -217,10 +220,10 @@ __device__ __forceinline__ Vec4<T> upwind_flux(const Prim<T> &L, const Prim<T> &
 {
     const T a1 = fma(beta, acc.a1b, acc.a1u);
     Vec4<T> F;
-    F.a = T(0.5) * (mL + mR - fma(acc.sau, dr, acc.a0));
-    F.b = T(0.5) * (fma(mL, L.u, L.p) + fma(mR, R.u, R.p) - fma(acc.sau, dm, a1));
-    F.c = T(0.5) * (mL * L.v + mR * R.v - fma(acc.sau, dn, acc.a2));
-    F.d = T(0.5) * (L.u + R.u - fma(acc.sau, dp * inv_beta, acc.a3));
+    F.a = mL + mR - fma(acc.sau, dr, acc.a0);
+    F.b = fma(mL, L.u, L.p) + fma(mR, R.u, R.p) - fma(acc.sau, dm, a1);
+    F.c = mL * L.v + mR * R.v - fma(acc.sau, dn, acc.a2);
+    F.d = L.u + R.u - fma(acc.sau, dp * inv_beta, acc.a3);
     return F;
 }
 
@@ -299,9 +302,9 @@ __device__ __forceinline__ Vec4<T> bassi_x(const Prim<T> &L, const Prim<T> &R, T
     const bool left = us > T(0);
     const T rs = left ? rl4 / (us - l5l) : rr5 / (us - l4r);
     const T vs = left ? L.v : R.v;
-    const T ms = rs * us;
+    const T ms2 = T(2) * (rs * us);  // twice the flux, as the other solvers return it
     (void)inv_beta;
-    return {ms, fma(ms, us, ps), ms * vs, us};
+    return {ms2, fma(ms2, us, T(2) * ps), ms2 * vs, T(2) * us};
 }
 
 // Face flux with normal +y: Algorithm 2 gives t1 = (1, 0, 0) for n = (0, 1, 0), so the rotated

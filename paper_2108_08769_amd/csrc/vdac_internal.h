@@ -108,6 +108,7 @@ struct TankDev {
     double dx, dy;
     double inv_dx, inv_dy;
     double half_dx, half_dy;  // dx/2, dy/2 (face offsets)
+    double flux_dx, flux_dy;  // 1/(2 dx), 1/(2 dy): the flux functions return twice the face flux
     double gx, gy;
     double beta, inv_beta;
     double cfl;
