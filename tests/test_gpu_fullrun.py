@@ -1,4 +1,5 @@
-"""Whole runs against the oracle, error against step (opt-in: VDAC_FULL_RUNS=1).
+"""Whole runs against the oracle, error against step (opt-in: VDAC_FULL_RUNS=1, or a number of
+steps N > 1 to run only the first N of each, rounded down to a multiple of 50).
 
 The other parity files hold the full-size configurations over their first real steps and
 smaller tanks over 20; these run the 512 x 256 dam break for its 500 real steps (up to 100
@@ -22,10 +23,11 @@ from paper_2108_08769_amd import vdac
 from paper_2108_08769_amd import workloads as wl
 from parity import field_errors, field_scales, oracle_problem, plain_errors
 
+FULL = os.environ.get("VDAC_FULL_RUNS", "")
 pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(os.environ.get("VDAC_FULL_RUNS") != "1",
+              pytest.mark.skipif(not FULL.isdigit() or int(FULL) < 1,
                                  reason="whole runs take about an hour of oracle time each; "
-                                        "set VDAC_FULL_RUNS=1")]
+                                        "set VDAC_FULL_RUNS=1 (or a step count)")]
 
 FP64_BAR = 1e-12
 MIXED_BAR = np.array([1e-6, 1e-5, 1e-5, 1e-4])
@@ -53,6 +55,8 @@ def gpu_run(wk, precision, steps, every):
 @pytest.mark.parametrize("name,steps", [("dam_break", 500), ("rayleigh_taylor", 200)])
 def test_whole_run_against_oracle(name, steps):
     every = 50
+    if int(FULL) > 1:
+        steps = max(every, min(steps, int(FULL)) // every * every)
     wk = getattr(wl, name)(precision="f64")
     t = wk.tanks[0]
     sc = field_scales(t)
