@@ -261,6 +261,41 @@ def test_library_owned_workspace_and_side_stream():
     print(f"[parity] workspace/stream variants: iterations {ref[1]}", flush=True)
 
 
+def test_two_grids_in_two_threads_on_two_streams():
+    """Grids are independent: a dam break and an obstacle tank (each with a tolerance, so that
+    its host polls run) stepped at the same time from two host threads, each grid on a stream of
+    its own, give bit for bit the states, iteration counts and norms each gives alone."""
+    import threading
+    import torch
+    cases = [small_dam(45, 27), wl.obstacle_dam_break(n=80)]
+    for wk in cases:
+        wk.dt = 1e-3
+    refs = [_run_grid(wk, 3, 300, tol=1e-3) for wk in cases]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    got, errors = [None, None], []
+
+    def work(i):
+        try:
+            torch.cuda.set_device(0)
+            got[i] = _run_grid(cases[i], 3, 300, tol=1e-3, stream=streams[i])
+        except Exception as e:  # reported below, in the test's own thread
+            errors.append((i, repr(e)))
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=120)
+    torch.cuda.synchronize()
+    assert not errors, errors
+    assert all(not th.is_alive() for th in threads)
+    for (state, its, norms), (rstate, rits, rnorms) in zip(got, refs):
+        np.testing.assert_array_equal(state, rstate)
+        assert its == rits
+        np.testing.assert_array_equal(norms, rnorms)
+    print(f"[parity] two grids in two threads: iterations {got[0][1]} and {got[1][1]}", flush=True)
+
+
 @pytest.mark.parametrize("case", ["dam_break_128x64", "rayleigh_taylor_64x256"])
 def test_fp64_error_against_step(case):
     """Nonlinear runs long enough for rounding differences to be amplified: 20 real steps of 20
