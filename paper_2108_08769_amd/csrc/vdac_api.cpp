@@ -609,9 +609,11 @@ size_t workspace_bytes(const vdac_tank *tanks, int32_t n_tanks, const vdac_optio
         vdac_default_options(&def);
         o = &def;
     }
+    // the same validation as create_grid: 0 exactly for the arguments it rejects as invalid
     if (!tanks || n_tanks < 1 || check_options(o) != VDAC_OK) return 0;
     for (int t = 0; t < n_tanks; ++t)
-        if (check_tank(&tanks[t], t) != VDAC_OK) return 0;
+        if (check_tank(&tanks[t], t) != VDAC_OK || check_tank_options(&tanks[t], t, o) != VDAC_OK)
+            return 0;
     const StoredTanks S = stored_tanks(tanks, n_tanks, o);
     const Plan p = plan_for(S.t.data(), n_tanks, o);
     size_t total = 0;

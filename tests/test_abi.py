@@ -175,3 +175,90 @@ def test_workspace_at_the_tank_size_limit():
     assert vdac.workspace_bytes([t], o) > 4 * 8 * (1 << 29)
     t, _ = vdac.make_tank(16384, 32769, 4.0, 8.0)
     assert vdac.workspace_bytes([t], o) == 0
+
+
+# ---- argument validation as a property: workspace_bytes and create_grid agree ----------------
+
+from hypothesis import HealthCheck, event, given, settings, strategies as st  # noqa: E402
+
+_TANK_OK = {
+    "nx": st.integers(1, 40), "ny": st.integers(1, 40), "lx": st.floats(0.1, 5.0),
+    "ly": st.floats(0.1, 5.0), "gx": st.floats(-10.0, 10.0), "gy": st.floats(-10.0, 10.0),
+    "beta": st.floats(1.0, 2000.0),
+    "bc": st.sampled_from([(0, 0, 0, 0), (1, 1, 0, 0), (0, 0, 1, 1), (2, 0, 0, 2), (1, 1, 2, 2),
+                           (0, 2, 1, 1)]),
+}
+_TANK_BAD = {
+    "nx": st.sampled_from([-1, 0, 16385]), "ny": st.sampled_from([-1, 0, 32769]),
+    "lx": st.sampled_from([0.0, -1.0, float("nan"), float("inf")]),
+    "ly": st.sampled_from([0.0, -1.0, float("nan"), float("inf")]),
+    "gx": st.sampled_from([float("nan"), float("inf")]),
+    "gy": st.sampled_from([float("nan"), float("-inf")]),
+    "beta": st.sampled_from([0.0, -5.0, float("nan"), float("inf")]),
+    "bc": st.sampled_from([(1, 0, 0, 0), (0, 0, 0, 1), (3, 0, 0, 0), (0, -1, 0, 0)]),
+}
+_OPT_OK = {
+    "precision": st.integers(0, 1), "rk_stages": st.integers(1, 8), "last_alpha": st.just(1.0),
+    "cfl_tau": st.floats(0.1, 1.0), "limiter_k": st.floats(1.0, 2.0), "local_dtau": st.integers(0, 1),
+    "bdf_order": st.integers(1, 3), "norm": st.integers(0, 1), "wall_slip": st.integers(0, 1),
+    "graph_iters": st.integers(-1, 20),
+    "tile": st.sampled_from([(0, 0), (1, 1), (32, 8), (16, 16), (64, 4), (3208, 2), (1616, 2),
+                             (1608, 2), (-2, 16), (-3, 5), (-1, 1)]),
+    "flux": st.integers(0, 2), "pgrad": st.integers(0, 2), "p_limiter_k": st.floats(1.0, 2.0),
+}
+_OPT_BAD = {
+    "precision": st.sampled_from([-1, 2]), "rk_stages": st.sampled_from([0, 9]),
+    "last_alpha": st.just(0.9), "cfl_tau": st.sampled_from([0.0, -1.0, float("nan")]),
+    "limiter_k": st.sampled_from([0.5, 2.5]), "local_dtau": st.just(2),
+    "bdf_order": st.sampled_from([0, 4]), "norm": st.just(2), "wall_slip": st.just(2),
+    "graph_iters": st.sampled_from([-2, 1001]),
+    "tile": st.sampled_from([(-4, 8), (32, 9), (0, 5), (-2, 0)]),
+    "flux": st.sampled_from([-1, 3]), "pgrad": st.sampled_from([-1, 3]),
+    "p_limiter_k": st.sampled_from([0.5, 2.5]),
+}
+
+
+@st.composite
+def _arguments(draw):
+    """A valid set of tanks and options, and in half of the draws one field made invalid."""
+    tanks = [draw(st.fixed_dictionaries(_TANK_OK)) for _ in range(draw(st.integers(1, 3)))]
+    opt = draw(st.fixed_dictionaries(_OPT_OK))
+    if draw(st.booleans()):
+        if draw(st.booleans()):
+            t = draw(st.sampled_from(tanks))
+            key = draw(st.sampled_from(sorted(_TANK_BAD)))
+            t[key] = draw(_TANK_BAD[key])
+        else:
+            key = draw(st.sampled_from(sorted(_OPT_BAD)))
+            opt[key] = draw(_OPT_BAD[key])
+    return tanks, opt
+
+
+@settings(max_examples=400, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(args=_arguments())
+def test_workspace_bytes_and_create_grid_agree(args):
+    """workspace_bytes returns 0 exactly for the arguments create_grid rejects as invalid, and
+    neither crashes on any of them; valid arguments get past validation (on a machine without a
+    GPU create_grid then fails at its first allocation)."""
+    tanks, opt = args
+    structs = [vdac.make_tank(t["nx"], t["ny"], t["lx"], t["ly"], t["gx"], t["gy"], t["beta"],
+                              t["bc"])[0] for t in tanks]
+    o = vdac.default_options()
+    o.precision, o.rk_stages = opt["precision"], opt["rk_stages"]
+    for i in range(8):
+        o.rk_alpha[i] = 0.5 if i < opt["rk_stages"] - 1 else (opt["last_alpha"] if i < opt["rk_stages"] else 0.0)
+    o.cfl_tau, o.limiter_k, o.local_dtau = opt["cfl_tau"], opt["limiter_k"], opt["local_dtau"]
+    o.bdf_order, o.norm, o.wall_slip = opt["bdf_order"], opt["norm"], opt["wall_slip"]
+    o.graph_iters, o.tile_x, o.tile_y = opt["graph_iters"], opt["tile"][0], opt["tile"][1]
+    o.flux, o.pgrad, o.p_limiter_k = opt["flux"], opt["pgrad"], opt["p_limiter_k"]
+    ws = vdac.workspace_bytes(structs, o)
+    arr = (vdac.Tank * len(structs))(*structs)
+    h = ctypes.c_void_p()
+    rc = vdac.lib().create_grid(arr, len(structs), ctypes.byref(o), None, 0, None, ctypes.byref(h))
+    if rc == vdac.VDAC_OK:
+        vdac.lib().destroy_grid(h)
+    event("valid" if ws else "invalid")
+    if ws == 0:
+        assert rc == vdac.VDAC_E_INVALID, (rc, vdac.lib().last_error())
+    else:
+        assert rc in (vdac.VDAC_OK, vdac.VDAC_E_NOMEM, vdac.VDAC_E_DEVICE), (rc, vdac.lib().last_error())
