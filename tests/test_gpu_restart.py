@@ -167,6 +167,79 @@ def test_set_state_keeps_the_other_tanks_history(precision):
     assert field_errors(got[0], q, wk.tanks[0].solid, field_scales(wk.tanks[0])).max() > 1e-9
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_random_history_operations_against_oracle(seed):
+    """Seeded random sequences of step_dual_time, set_state, set_history and get_history on a
+    BDF3 batch of two tanks (the tall one stored transposed), checked against a model: per tank
+    the current state and the earlier real-time levels the next step uses (newest first, at most
+    two).  Each step of each tank is held to the oracle given the model's levels, and get_history
+    returns the model's count and levels."""
+    rng = np.random.default_rng(seed)
+    wk = moving_tanks(2)
+    wk.bdf = 3
+    pbs = [oracle_problem(t, wk) for t in wk.tanks]
+
+    def new_state(t):
+        return wl.random_state(t.nx, t.ny, seed=int(rng.integers(1 << 30)), rho_range=(1.0, 5.0),
+                               vel=0.3, p_scale=10.0)
+
+    def near(qi):
+        """an earlier real-time level near the current state (as a restart would restore)"""
+        lv = qi.copy()
+        lv[0] *= 1.0 + 0.02 * rng.uniform(-1.0, 1.0, lv[0].shape)
+        lv[1:3] += 0.02 * rng.uniform(-1.0, 1.0, lv[1:3].shape)
+        return lv
+
+    g = vdac.Grid(tank_dicts(wk), gpu_options(wk))
+    q = [t.q.copy() for t in wk.tanks]
+    hist = [[], []]  # full 4-field states for the oracle, newest first
+    ops = []
+    try:
+        for i, t in enumerate(wk.tanks):
+            g.set_state(i, t.q)
+        for _ in range(10):
+            op = str(rng.choice(["step", "step", "step", "step", "set_state", "set_history",
+                                 "get_history"]))
+            i = int(rng.integers(2))
+            t = wk.tanks[i]
+            if op == "step":
+                k = int(rng.choice([2, 5]))
+                ops.append(f"step({k})")
+                rc, done = g.step(wk.dt, k, 0.0, check=False)
+                assert rc == 0 and np.all(done == k)
+                for j, tj in enumerate(wk.tanks):
+                    qm1 = hist[j][0] if len(hist[j]) >= 1 else None
+                    qm2 = hist[j][1] if len(hist[j]) >= 2 else None
+                    qn, it, _, orc = oracle.step(pbs[j], q[j], wk.dt, k, 0.0, qnm1=qm1, qnm2=qm2)
+                    assert orc == 0 and it == k
+                    hist[j] = ([q[j]] + hist[j])[:2]
+                    q[j] = qn
+                    err = field_errors(g.get_state(j), q[j], tj.solid, field_scales(tj))
+                    assert np.all(err <= TOL), (ops, j, err)
+            elif op == "set_state":
+                ops.append(f"set_state({i})")
+                q[i] = new_state(t)
+                g.set_state(i, q[i])
+                hist[i] = []
+            elif op == "set_history":
+                n = int(rng.integers(0, 3))
+                ops.append(f"set_history({i}, {n})")
+                levels = [near(q[i]) for _ in range(n)]
+                g.set_history(i, np.array([lv[:3] for lv in levels]) if n else np.zeros((0, 3)))
+                hist[i] = levels
+            else:
+                ops.append(f"get_history({i})")
+                got = g.get_history(i)
+                assert len(got) == len(hist[i]), (ops, len(got), len(hist[i]))
+                for a, b in zip(got, hist[i]):
+                    full = np.concatenate([a, b[3:]])  # p is not part of the levels
+                    err = field_errors(full, b, t.solid, field_scales(t))
+                    assert np.all(err <= TOL), (ops, err)
+        print(f"[history] seed {seed}: {' '.join(ops)}", flush=True)
+    finally:
+        g.close()
+
+
 def perturbed_hydrostatic(nx=16, ny=16, seed=0):
     dy = 1.0 / ny
     yc = (np.arange(ny) + 0.5) * dy
