@@ -276,3 +276,37 @@ def test_stage_counts_with_tolerance(stages, tile):
         assert np.all(err <= TOL), err
     for a, b in zip(g_norms, o_norms):
         np.testing.assert_allclose(a, b, rtol=1e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5, 6, 7, 8, 9])
+def test_random_loop_controls_against_oracle(seed):
+    """Algorithm 1's loop controls in random combinations: iteration cap (0, 1 and more),
+    tolerance (none, or one the tanks reach at different iterations), pseudo-iterations per
+    replayed graph (eager launches, automatic, 1 .. 8) and kernel shape, on three tanks in one
+    batch (seeds 1-6) or one tank in the LDS tiles (7-9), two real steps: every tank's iteration
+    counts, states and norms as the oracle's."""
+    rng = np.random.default_rng(100 + seed)
+    tol = float(rng.choice([0.0, 300.0, 100.0, 30.0, 10.0]))
+    cap = int(rng.choice([0, 1, 7, 25, 60, 200]))
+    graph_iters = int(rng.choice([-1, 0, 1, 2, 3, 5, 8]))
+    if seed <= 6:
+        tanks = [perturbed_hydrostatic(16, 16, seed=1), perturbed_hydrostatic(24, 12, seed=2),
+                 perturbed_hydrostatic(20, 20, seed=3)]
+        tile = [(0, 0), (-2, 4), (-2, 16)][int(rng.integers(3))]
+    else:
+        tanks = [perturbed_hydrostatic(24, 12, seed=2)]
+        tile = [(32, 8), (3208, 2), (1608, 2)][int(rng.integers(3))]
+    wk = wl.Workload("loop", tanks, dt=1e-2, steps=1, max_pseudo=1, cfl=0.3)
+    print(f"[loop] seed {seed}: cap {cap} tol {tol} graph_iters {graph_iters} tile {tile}",
+          flush=True)
+    g_states, g_it, g_norms, g_codes = run_gpu(wk, 2, cap, tol=tol, tile=tile, graph_iters=graph_iters)
+    o_states, o_it, o_norms, o_codes = run_oracle(wk, 2, cap, tol=tol)
+    assert all(c == 0 for c in g_codes) and all(c == 0 for c in o_codes)
+    print(f"[loop]   iterations {g_it.tolist()} (oracle {o_it.tolist()})", flush=True)
+    np.testing.assert_array_equal(g_it, o_it)
+    for t, a, b in zip(wk.tanks, g_states, o_states):
+        err = field_errors(a, b, t.solid, field_scales(t))
+        assert np.all(err <= TOL), err
+    if cap > 0:
+        for a, b in zip(g_norms, o_norms):
+            np.testing.assert_allclose(a, b, rtol=1e-7, atol=1e-12)
