@@ -231,6 +231,29 @@ __global__ void __launch_bounds__(256)
 
 // Mixed form: the caller's FP64 state q [4][plane] (rho, rho u, rho v, p) becomes level n (and
 // n-1, n-2 for the first three fields) and zero deviations in all three state buffers.
+// FP64 form: every state buffer and the real-time levels n, n-1, n-2 (rho, rho u, rho v) of a
+// tank from q [4][plane] in device memory, which may be state buffer 0 itself (each thread reads
+// a cell before it writes it), or, q null, the state at rest (rho = 1, rho u = rho v = p = 0).
+__global__ void __launch_bounds__(256) import_f64_kernel(TankDev t, const double *q)
+{
+    const size_t plane = t.plane;
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < plane;
+         c += (size_t)gridDim.x * 256) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double v = q ? q[k * plane + c] : (k == 0 ? 1.0 : 0.0);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) ((double *)t.state[b])[k * plane + c] = v;
+            if (k < 3) {
+                t.level_n[k * plane + c] = v;
+                if (t.level_nm1) t.level_nm1[k * plane + c] = v;
+                if (t.level_nm2) t.level_nm2[k * plane + c] = v;
+            }
+        }
+    }
+}
+
+// q null: the state at rest (rho = 1, rho u = rho v = p = 0).
 __global__ void __launch_bounds__(256) import_mixed_kernel(TankDev t, const double *__restrict__ q)
 {
     const size_t plane = t.plane;
@@ -238,7 +261,7 @@ __global__ void __launch_bounds__(256) import_mixed_kernel(TankDev t, const doub
          c += (size_t)gridDim.x * 256) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const double v = q[k * plane + c];
+            const double v = q ? q[k * plane + c] : (k == 0 ? 1.0 : 0.0);
             t.level_n[k * plane + c] = v;
             if (k < 3 && t.level_nm1) t.level_nm1[k * plane + c] = v;
             if (k < 3 && t.level_nm2) t.level_nm2[k * plane + c] = v;
@@ -361,6 +384,13 @@ int launch_tanks_min(const TankDev *tanks_dev, int first, int n_tanks, int mixed
     if (e != hipSuccess) return (int)e;
     hipLaunchKernelGGL(min_rows_kernel, dim3((unsigned)n_tanks), dim3(256), 0, (hipStream_t)stream,
                        (const double *)scratch, blocks_per_tank, out, out_stride);
+    return (int)hipGetLastError();
+}
+
+int launch_import_f64(const TankDev &t, const double *q, void *stream)
+{
+    hipLaunchKernelGGL(import_f64_kernel, dim3(cell_blocks(t.plane)), dim3(256), 0,
+                       (hipStream_t)stream, t, q);
     return (int)hipGetLastError();
 }
 

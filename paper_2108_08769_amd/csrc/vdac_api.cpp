@@ -549,23 +549,23 @@ int init_dtau_global(vdac_grid *g, int t)
 
 // Uploads an FP64 state [4][plane] into tank t: plain copies into the three state buffers and
 // level n (FP64 form), or through the staging buffer and the import kernel (mixed form).
+// Sets tank t's state buffers and real-time levels to q (host, [4][plane] in the stored
+// orientation), or to the state at rest when q is null, and resets its status.  The host array
+// crosses PCIe once (into the mixed form's staging block, or state buffer 0 in FP64); the
+// import kernel fans it out on the device.
 int upload_state(vdac_grid *g, int t, const double *q)
 {
     const TankDev &d = g->tanks[t].dev;
     hipError_t e = hipSuccess;
-    if (g->sc.mixed) {
-        e = hipMemcpyAsync(g->staging, q, 4 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
-        if (e == hipSuccess) e = (hipError_t)launch_import_mixed(d, g->staging, g->stream);
-    } else {
-        for (int b = 0; b < 3 && e == hipSuccess; ++b)
-            e = hipMemcpyAsync(d.state[b], q, 4 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d.level_n, q, 3 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
-        if (e == hipSuccess && d.level_nm1)
-            e = hipMemcpyAsync(d.level_nm1, q, 3 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
-        if (e == hipSuccess && d.level_nm2)
-            e = hipMemcpyAsync(d.level_nm2, q, 3 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
+    const double *src = nullptr;
+    if (q) {
+        double *dst = g->sc.mixed ? g->staging : (double *)d.state[0];
+        e = hipMemcpyAsync(dst, q, 4 * d.plane * sizeof(double), hipMemcpyHostToDevice, g->stream);
+        src = dst;
     }
+    if (e == hipSuccess)
+        e = (hipError_t)(g->sc.mixed ? launch_import_mixed(d, src, g->stream)
+                                     : launch_import_f64(d, src, g->stream));
     Status st;
     std::memset(&st, 0, sizeof st);
     st.done = 1;  // cur = 0
@@ -783,9 +783,7 @@ int create_grid(const vdac_tank *tanks, int32_t n_tanks, const vdac_options *o,
             return hip_fail(e, "uploading the cell flags");
         }
         // initial state: rho = 1, at rest, p = 0
-        std::vector<double> q(4 * th.dev.plane, 0.0);
-        std::fill(q.begin(), q.begin() + th.dev.plane, 1.0);
-        if ((rc = upload_state(g, t, q.data())) != VDAC_OK) {
+        if ((rc = upload_state(g, t, nullptr)) != VDAC_OK) {
             destroy_grid(g);
             return rc;
         }

@@ -190,7 +190,9 @@ int launch_tanks_min(const TankDev *tanks_dev, int first, int n_tanks, int mixed
                      double cfl, double *scratch, int blocks_per_tank, double *out, int out_stride,
                      void *stream);
 // Conversions between the caller's FP64 conserved state [4][ny][nx] (rho, rho u, rho v, p) in
-// device memory and the mixed form's storage (cur = 0 after import).
+// device memory and the storage: import sets every state buffer (cur = 0 after it) and the
+// real-time levels; q null imports the state at rest (rho = 1, rho u = rho v = p = 0).
+int launch_import_f64(const TankDev &t, const double *q, void *stream);
 int launch_import_mixed(const TankDev &t, const double *q, void *stream);
 int launch_export_mixed(const TankDev &t, int cur, double *q, void *stream);
 // Plane-stream bandwidth reference (n_in, n_out) in {(1, 0), (1, 1), (11, 4)}; blocks = 0: one

@@ -9,6 +9,8 @@
 - Stage counts other than three: with one stage, stage 1 is also the last, so the residual
   finalize of the previous iteration cannot share its launch; with one, two and four stages and a
   tolerance the pseudo-loop stops at the oracle's iteration, with several launch groups per step.
+- A new grid holds the state at rest in every buffer and level until set_state, and steps from it
+  as the oracle does.
 
 FP64 bars as in the other parity files: per field max |gpu - oracle| / max(max |oracle|,
 physical scale) <= 1e-12, equal iteration counts, norms to rtol 1e-7.
@@ -310,3 +312,33 @@ def test_random_loop_controls_against_oracle(seed):
     if cap > 0:
         for a, b in zip(g_norms, o_norms):
             np.testing.assert_allclose(a, b, rtol=1e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+@pytest.mark.parametrize("tile", [(0, 0), (32, 8)])
+def test_new_grid_holds_the_state_at_rest(precision, tile):
+    """Before any set_state every tank holds the state at rest (rho = 1, rho u = rho v = p = 0) in
+    all its buffers and real-time levels: get_state returns it exactly, and three BDF3 steps from
+    it (gravity along both axes, an obstacle, a tank stored reflected in the batch on the
+    row-marching kernel) follow the oracle started from that state."""
+    wk = moving_tanks()
+    wk.bdf = 3
+    for t in wk.tanks:
+        t.q = np.zeros_like(t.q)
+        t.q[0] = 1.0
+    grid = vdac.Grid(tank_dicts(wk), gpu_options(wk, precision=precision, tile=tile))
+    try:
+        for i, t in enumerate(wk.tanks):
+            np.testing.assert_array_equal(grid.get_state(i), t.q)
+        its = run_steps(grid, wk, 3, 8, 0.0)
+        states = [grid.get_state(i) for i in range(len(wk.tanks))]
+    finally:
+        grid.close()
+    o_states, o_its, _, codes = run_oracle(wk, 3, 8)
+    assert all(c == 0 for c in codes)
+    np.testing.assert_array_equal(its, o_its)
+    bar = TOL if precision == "f64" else np.array([1e-6, 1e-5, 1e-5, 1e-4])
+    for t, a, b in zip(wk.tanks, states, o_states):
+        err = field_errors(a, b, t.solid, field_scales(t))
+        print(f"[restart] new grid at rest, {precision} {tile}: {t.nx}x{t.ny} errors {err}", flush=True)
+        assert np.all(err <= bar), err
