@@ -74,6 +74,35 @@ def test_tiny_and_ragged_tanks(nx, ny):
     check(wk, steps=2, pseudo=4)
 
 
+W, P, O = 0, 1, 2
+TINY_SIDES = {"walls": (W, W, W, W), "periodic": (P, P, P, P), "periodic_x": (P, P, W, W),
+              "open": (O, O, O, O), "open_periodic": (O, W, P, P)}
+
+
+TINY_KERNELS = {"march": (0, 0), "march_rows1": (-1, 1), "tile32x8": (32, 8),
+                "tile1608x2": (1608, 2), "plain": (1, 1)}
+TINY_CASES = [pytest.param(nx, ny, sides, kern, id=f"{nx}x{ny}-{sides}-{kern}")
+              for nx, ny in [(1, 1), (1, 4), (4, 1), (2, 2), (2, 5), (3, 2)]
+              for sides in TINY_SIDES for kern in TINY_KERNELS
+              if not (kern == "plain" and O in TINY_SIDES[sides])]
+
+
+@pytest.mark.parametrize("nx,ny,sides,kernel", TINY_CASES)
+def test_tiny_tanks_every_side_and_kernel(nx, ny, sides, kernel):
+    """Tanks of one to five cells a side with every kind of side: a periodic axis of one or two
+    cells is its own neighbour (and its own neighbour's neighbour) through the wrap, an open side
+    copies the only cell; in every kernel family (the one-thread-per-cell kernel takes no open
+    side; the Roe flux with the k-limiter on p stands in for the general options on the tank
+    with open and periodic sides)."""
+    bc = TINY_SIDES[sides]
+    kw = dict(flux=1, pgrad=1, pk=2.0) if sides == "open_periodic" else {}
+    q = wl.random_state(nx, ny, seed=7 * nx + ny, rho_range=(1.0, 3.0), vel=0.2, p_scale=5.0)
+    wk = wl.Workload(f"tiny_{sides}", [wl.Tank(nx, ny, 0.1 * nx, 0.13 * ny, q, gx=0.3, gy=-9.81,
+                                                beta=300.0, bc=bc)],
+                     dt=1e-3, steps=1, max_pseudo=1)
+    check(wk, steps=2, pseudo=4, tile=TINY_KERNELS[kernel], **kw)
+
+
 def test_rayleigh_taylor_periodic():
     wk = wl.rayleigh_taylor(nx=32, ny=96, precision="f64")
     check(wk, steps=3, pseudo=15)
