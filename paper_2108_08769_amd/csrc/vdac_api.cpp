@@ -547,8 +547,6 @@ int init_dtau_global(vdac_grid *g, int t)
                             n_blocks, out, 1, g->stream);
 }
 
-// Uploads an FP64 state [4][plane] into tank t: plain copies into the three state buffers and
-// level n (FP64 form), or through the staging buffer and the import kernel (mixed form).
 // Sets tank t's state buffers and real-time levels to q (host, [4][plane] in the stored
 // orientation), or to the state at rest when q is null, and resets its status.  The host array
 // crosses PCIe once (into the mixed form's staging block, or state buffer 0 in FP64); the
