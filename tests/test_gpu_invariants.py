@@ -1,0 +1,104 @@
+"""Properties of the scheme that hold at any size, checked on every cell of the full 4096 x 4096
+tank in the stage-kernel shapes bench.py times (the row-marching kernel, 2 waves per SIMD, chunks
+of 32 rows in FP64 and 16 in the mixed form) and in the LDS-tiled kernel.  The sampled windows of
+the full-size parity file hold a few dozen cells to the oracle; these hold all of them to what the
+paper's scheme fixes.
+
+* Mass conservation (Sec. 2.1: the continuity equation in conservation form; the fluxes of a
+  face leave one cell and enter its neighbour, and the wall faces of Sec. 2.5 carry no mass).  In
+  a closed tank under one global pseudo-time step the flux divergence sums to zero, and the
+  real-time term sums to zero as long as the total mass equals that of level n, so every stage
+  keeps the total mass to rounding.  A face whose flux the two units beside it (a strip's halo
+  lanes, a chunk's halo rows, a tile's ring) evaluated differently would show here.
+* Mirror symmetry.  A double dam break symmetric about x = L/2 stays symmetric: rho, rho v and p
+  even, rho u odd.  The 60-column strips and the tiles are not laid out symmetrically (4096 =
+  68 x 60 + 16), so mirror cells sit at different places in their strips and tiles.
+
+FP64 bars: total mass to 1e-13 relative; mirror differences to 1e-12 of each field's physical
+scale.  The mixed form stores the state as FP32 deviations from level n, rounded on every stage,
+and takes its fluxes in FP32, whose Gauss-point sums run in opposite orders on mirror faces:
+mass to 1e-12, mirror differences to 1e-9 of the scales.  Measured (2 real steps of 10
+pseudo-iterations): mass 1.1e-16 (FP64) and 9.0e-16 (mixed); mirror differences about 1e-19
+(FP64) and at most 1.1e-11 (mixed) of the scales, both kernel families.
+"""
+import numpy as np
+import pytest
+
+from paper_2108_08769_amd import vdac
+from paper_2108_08769_amd import workloads as wl
+from parity import field_scales, gpu_options
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {("f64", "march"): (-2, 32), ("mixed", "march"): (-2, 16),
+          ("f64", "tile"): (3208, 2), ("mixed", "tile"): (1608, 2)}
+
+
+def run(wk, precision, shape, steps, pseudo):
+    t = wk.tanks[0]
+    tank = dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
+                solid=t.solid)
+    grid = vdac.Grid([tank], gpu_options(wk, precision, tile=shape))
+    try:
+        grid.set_state(0, t.q)
+        for _ in range(steps):
+            rc, done = grid.step(wk.dt, pseudo, 0.0, check=False)
+            assert rc == 0 and int(done[0]) == pseudo, (rc, done)
+        return grid.get_state(0)
+    finally:
+        grid.close()
+
+
+@pytest.mark.parametrize("kernel", ["march", "tile"])
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_mass_conserved_on_the_full_tank(precision, kernel):
+    wk = wl.obstacle_dam_break(precision=precision)
+    wk.local_dtau = False
+    t = wk.tanks[0]
+    fluid = t.solid == 0
+    shape = SHAPES[(precision, kernel)]
+    print(f"[invariants] mass: {wk.name} {precision} shape {shape}, global pseudo-time step, "
+          f"2 steps x 10 pseudo-iterations", flush=True)
+    q = run(wk, precision, shape, steps=2, pseudo=10)
+    m0 = float(np.sum(t.q[0][fluid], dtype=np.float64))
+    m1 = float(np.sum(q[0][fluid], dtype=np.float64))
+    moved = float(np.abs(q[0] - t.q[0])[fluid].max())
+    rel = abs(m1 - m0) / m0
+    print(f"[invariants]   total mass {m0:.17e} -> {m1:.17e}: relative change {rel:.2e} "
+          f"(largest density change of a cell {moved:.3e})", flush=True)
+    assert moved > 1e-6          # the state did move
+    assert rel <= (1e-13 if precision == "f64" else 1e-12), rel
+
+
+def double_dam_break(n=4096):
+    """Water (rho = 1000) at x < 1 and x > 3, y < 2 on a 4 x 4 tank, air (rho = 1) elsewhere, at
+    rest with p = 0, walls, gravity -9.81 in y, beta = 1100, dt = 2e-5."""
+    xc = (np.arange(n) + 0.5) * 4.0 / n
+    yc = (np.arange(n) + 0.5) * 4.0 / n
+    # mirror cells get bitwise mirror states: decide the columns on the left half and reflect
+    left = xc[: n // 2] < 1.0
+    water_x = np.concatenate([left, left[::-1]])
+    q = np.zeros((4, n, n))
+    q[0] = np.where(water_x[None, :] & (yc[:, None] < 2.0), 1000.0, 1.0)
+    t = wl.Tank(n, n, 4.0, 4.0, q, gy=-9.81, beta=1100.0)
+    return wl.Workload(f"double_dam_break_{n}x{n}", [t], dt=2e-5, steps=1, max_pseudo=1)
+
+
+@pytest.mark.parametrize("kernel", ["march", "tile"])
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_mirror_symmetry_on_the_full_tank(precision, kernel):
+    wk = double_dam_break()
+    t = wk.tanks[0]
+    shape = SHAPES[(precision, kernel)]
+    print(f"[invariants] mirror: {wk.name} {precision} shape {shape}, 2 steps x 10 "
+          f"pseudo-iterations", flush=True)
+    q = run(wk, precision, shape, steps=2, pseudo=10)
+    m = q[:, :, ::-1].copy()
+    m[1] = -m[1]
+    sc = field_scales(t)
+    err = np.array([np.abs(q[k] - m[k]).max() / sc[k] for k in range(4)])
+    moved = np.abs(q[1]).max() / sc[1]
+    print(f"[invariants]   mirror differences / scale: rho {err[0]:.2e} rho_u {err[1]:.2e} "
+          f"rho_v {err[2]:.2e} p {err[3]:.2e} (max |rho u| / scale {moved:.2e})", flush=True)
+    assert moved > 1e-6
+    assert np.all(err <= (1e-12 if precision == "f64" else 1e-9)), err
