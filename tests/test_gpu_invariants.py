@@ -13,13 +13,17 @@ paper's scheme fixes.
 * Mirror symmetry.  A double dam break symmetric about x = L/2 stays symmetric: rho, rho v and p
   even, rho u odd.  The 60-column strips and the tiles are not laid out symmetrically (4096 =
   68 x 60 + 16), so mirror cells sit at different places in their strips and tiles.
+* Transpose symmetry.  A tank symmetric about its diagonal (state, obstacle and gravity) stays
+  symmetric, although the kernels take the x and y faces by different code.
 
-FP64 bars: total mass to 1e-13 relative; mirror differences to 1e-12 of each field's physical
-scale.  The mixed form stores the state as FP32 deviations from level n, rounded on every stage,
+FP64 bars: total mass to 1e-13 relative; mirror and transpose differences to 1e-12 of each
+field's physical scale.  The mixed form stores the state as FP32 deviations from level n, rounded on every stage,
 and takes its fluxes in FP32, whose Gauss-point sums run in opposite orders on mirror faces:
-mass to 1e-12, mirror differences to 1e-9 of the scales.  Measured (2 real steps of 10
+mass to 1e-12, mirror and transpose differences to 1e-9 of the scales.  Measured (2 real steps of 10
 pseudo-iterations): mass 1.1e-16 (FP64) and 9.0e-16 (mixed); mirror differences about 1e-19
-(FP64) and at most 1.1e-11 (mixed) of the scales, both kernel families.
+(FP64) and at most 1.1e-11 (mixed) of the scales, both kernel families; transpose differences
+1.1e-19 of the scales in the FP64 row-marching kernel (its x and y sums run in different orders)
+and none at all in the other three.
 """
 import numpy as np
 import pytest
@@ -100,5 +104,48 @@ def test_mirror_symmetry_on_the_full_tank(precision, kernel):
     moved = np.abs(q[1]).max() / sc[1]
     print(f"[invariants]   mirror differences / scale: rho {err[0]:.2e} rho_u {err[1]:.2e} "
           f"rho_v {err[2]:.2e} p {err[3]:.2e} (max |rho u| / scale {moved:.2e})", flush=True)
+    assert moved > 1e-6
+    assert np.all(err <= (1e-12 if precision == "f64" else 1e-9)), err
+
+
+def corner_dam_break(n=4096):
+    """A tank symmetric about its diagonal: water (rho = 1000) in the L-shaped region x < 2, y < 1
+    or x < 1, y < 2 of a 4 x 4 tank, a square obstacle on the diagonal (2.5 < x, y < 2.7),
+    gravity of 9.81 along the diagonal towards the corner (0, 0), beta = 1100, dt = 2e-5."""
+    c = (np.arange(n) + 0.5) * 4.0 / n
+    x, y = c[None, :], c[:, None]
+    water = ((x < 2.0) & (y < 1.0)) | ((x < 1.0) & (y < 2.0))
+    q = np.zeros((4, n, n))
+    q[0] = np.where(water, 1000.0, 1.0)
+    solid = ((x > 2.5) & (x < 2.7) & (y > 2.5) & (y < 2.7)).astype(np.uint8)
+    g = -9.81 / np.sqrt(2.0)
+    t = wl.Tank(n, n, 4.0, 4.0, q, gx=g, gy=g, beta=1100.0, solid=solid)
+    return wl.Workload(f"corner_dam_break_{n}x{n}", [t], dt=2e-5, steps=1, max_pseudo=1)
+
+
+@pytest.mark.parametrize("kernel", ["march", "tile"])
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_transpose_symmetry_on_the_full_tank(precision, kernel):
+    """The scheme is the same with x and y exchanged (per-axis slopes and limiters, the flux
+    rotated to each face, the pressure gradient's x and y forms, the symmetric pseudo-time step),
+    so a tank symmetric about its diagonal stays symmetric: rho and p equal their transposes and
+    rho u that of rho v.  The row-marching kernel takes the x faces across the lanes of a wave
+    and the y faces down its march, and the tiles are 32 x 8, so this holds the two code paths
+    of every cell against each other."""
+    wk = corner_dam_break()
+    t = wk.tanks[0]
+    assert np.array_equal(t.q[0], t.q[0].T) and np.array_equal(t.solid, t.solid.T)
+    shape = SHAPES[(precision, kernel)]
+    print(f"[invariants] transpose: {wk.name} {precision} shape {shape}, 2 steps x 10 "
+          f"pseudo-iterations", flush=True)
+    q = run(wk, precision, shape, steps=2, pseudo=10)
+    fluid = t.solid == 0
+    sc = field_scales(t)
+    pairs = [(q[0], q[0].T), (q[1], q[2].T), (q[2], q[1].T), (q[3], q[3].T)]
+    err = np.array([np.abs(a - b)[fluid].max() / sc[k] for k, (a, b) in enumerate(pairs)])
+    moved = max(np.abs(q[1]).max(), np.abs(q[2]).max()) / sc[1]
+    print(f"[invariants]   transpose differences / scale: rho {err[0]:.2e} rho_u {err[1]:.2e} "
+          f"rho_v {err[2]:.2e} p {err[3]:.2e} (max |rho u|, |rho v| / scale {moved:.2e})",
+          flush=True)
     assert moved > 1e-6
     assert np.all(err <= (1e-12 if precision == "f64" else 1e-9)), err
