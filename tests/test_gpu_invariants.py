@@ -17,10 +17,10 @@ paper's scheme fixes.
   symmetric, although the kernels take the x and y faces by different code.
 
 FP64 bars: total mass to 1e-13 relative; mirror and transpose differences to 1e-12 of each
-field's physical scale.  The mixed form stores the state as FP32 deviations from level n, rounded on every stage,
-and takes its fluxes in FP32, whose Gauss-point sums run in opposite orders on mirror faces:
-mass to 1e-12, mirror and transpose differences to 1e-9 of the scales.  Measured (2 real steps of 10
-pseudo-iterations): mass 1.1e-16 (FP64) and 9.0e-16 (mixed); mirror differences about 1e-19
+field's physical scale.  The mixed form stores the state as FP32 deviations from level n,
+rounded on every stage, and takes its fluxes in FP32, whose Gauss-point sums run in opposite
+orders on mirror faces: mass to 1e-12, mirror and transpose differences to 1e-9 of the scales.
+Measured (2 real steps of 10 pseudo-iterations): mass 1.1e-16 (FP64) and 9.0e-16 (mixed); mirror differences about 1e-19
 (FP64) and at most 1.1e-11 (mixed) of the scales, both kernel families; transpose differences
 1.1e-19 of the scales in the FP64 row-marching kernel (its x and y sums run in different orders)
 and none at all in the other three.
