@@ -26,10 +26,14 @@ FP64 bars: total mass to 1e-13 relative; mirror and transpose differences to 1e-
 field's physical scale.  The mixed form stores the state as FP32 deviations from level n,
 rounded on every stage, and takes its fluxes in FP32, whose Gauss-point sums run in opposite
 orders on mirror faces: mass to 1e-12, mirror and transpose differences to 1e-9 of the scales.
-Measured (2 real steps of 10 pseudo-iterations): mass 1.1e-16 (FP64) and 9.0e-16 (mixed); mirror differences about 1e-19
-(FP64) and at most 1.1e-11 (mixed) of the scales, both kernel families; transpose differences
-1.1e-19 of the scales in the FP64 row-marching kernel (its x and y sums run in different orders)
-and none at all in the other three.
+Measured (3 real steps of 10 pseudo-iterations, each option set): mass within 2.3e-15 in
+every form; mirror differences about 1e-19 of the scales (FP64) and at most 2.2e-11 (mixed);
+transpose differences at most 2.3e-16 (FP64 row marching, whose x and y sums run in different
+orders) and 1.6e-11 (mixed row marching), none at all in the tiles.
+
+The mass, mirror and transpose checks each run with the Osher flux and the new pressure gradient
+(BDF1), the Roe flux with BDF2, the exact flux with the k-limiter on p (k = 2), and the split
+limiter (k = 1.5) with BDF3, so the general kernels meet the full size too.
 """
 import numpy as np
 import pytest
@@ -44,11 +48,21 @@ SHAPES = {("f64", "march"): (-2, 32), ("mixed", "march"): (-2, 16),
           ("f64", "tile"): (3208, 2), ("mixed", "tile"): (1608, 2)}
 
 
-def run(wk, precision, shape, steps, pseudo, with_norms=False):
+# option sets of the general kernels (flux 0 Osher, 1 Roe, 2 exact; pgrad 0 new, 1 k-limiter
+# on p, 2 split limiter), with the BDF order of the run
+OPTIONS = {
+    "osher": (dict(), 1),
+    "roe_bdf2": (dict(flux=1), 2),
+    "exact_plimiter": (dict(flux=2, pgrad=1, pk=2.0), 1),
+    "split_bdf3": (dict(pgrad=2, pk=1.5), 3),
+}
+
+
+def run(wk, precision, shape, steps, pseudo, with_norms=False, **kw):
     t = wk.tanks[0]
     tank = dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
                 solid=t.solid)
-    grid = vdac.Grid([tank], gpu_options(wk, precision, tile=shape))
+    grid = vdac.Grid([tank], gpu_options(wk, precision, tile=shape, **kw))
     try:
         grid.set_state(0, t.q)
         for _ in range(steps):
@@ -61,17 +75,22 @@ def run(wk, precision, shape, steps, pseudo, with_norms=False):
         grid.close()
 
 
+@pytest.mark.parametrize("options", list(OPTIONS))
 @pytest.mark.parametrize("kernel", ["march", "tile"])
 @pytest.mark.parametrize("precision", ["f64", "mixed"])
-def test_mass_conserved_on_the_full_tank(precision, kernel):
+def test_mass_conserved_on_the_full_tank(precision, kernel, options):
+    """Also with the Roe and exact fluxes, the limiters on p and BDF2 and BDF3 (Table 1: the
+    real-time coefficients sum to zero, and every level holds the same total mass)."""
+    kw, bdf = OPTIONS[options]
     wk = wl.obstacle_dam_break(precision=precision)
     wk.local_dtau = False
+    wk.bdf = bdf
     t = wk.tanks[0]
     fluid = t.solid == 0
     shape = SHAPES[(precision, kernel)]
-    print(f"[invariants] mass: {wk.name} {precision} shape {shape}, global pseudo-time step, "
-          f"2 steps x 10 pseudo-iterations", flush=True)
-    q = run(wk, precision, shape, steps=2, pseudo=10)
+    print(f"[invariants] mass: {wk.name} {precision} shape {shape} {options}, global pseudo-time "
+          f"step, 3 steps x 10 pseudo-iterations", flush=True)
+    q = run(wk, precision, shape, steps=3, pseudo=10, **kw)
     m0 = float(np.sum(t.q[0][fluid], dtype=np.float64))
     m1 = float(np.sum(q[0][fluid], dtype=np.float64))
     moved = float(np.abs(q[0] - t.q[0])[fluid].max())
@@ -96,15 +115,18 @@ def double_dam_break(n=4096):
     return wl.Workload(f"double_dam_break_{n}x{n}", [t], dt=2e-5, steps=1, max_pseudo=1)
 
 
+@pytest.mark.parametrize("options", list(OPTIONS))
 @pytest.mark.parametrize("kernel", ["march", "tile"])
 @pytest.mark.parametrize("precision", ["f64", "mixed"])
-def test_mirror_symmetry_on_the_full_tank(precision, kernel):
+def test_mirror_symmetry_on_the_full_tank(precision, kernel, options):
+    kw, bdf = OPTIONS[options]
     wk = double_dam_break()
+    wk.bdf = bdf
     t = wk.tanks[0]
     shape = SHAPES[(precision, kernel)]
-    print(f"[invariants] mirror: {wk.name} {precision} shape {shape}, 2 steps x 10 "
+    print(f"[invariants] mirror: {wk.name} {precision} shape {shape} {options}, 3 steps x 10 "
           f"pseudo-iterations", flush=True)
-    q = run(wk, precision, shape, steps=2, pseudo=10)
+    q = run(wk, precision, shape, steps=3, pseudo=10, **kw)
     m = q[:, :, ::-1].copy()
     m[1] = -m[1]
     sc = field_scales(t)
@@ -131,22 +153,25 @@ def corner_dam_break(n=4096):
     return wl.Workload(f"corner_dam_break_{n}x{n}", [t], dt=2e-5, steps=1, max_pseudo=1)
 
 
+@pytest.mark.parametrize("options", list(OPTIONS))
 @pytest.mark.parametrize("kernel", ["march", "tile"])
 @pytest.mark.parametrize("precision", ["f64", "mixed"])
-def test_transpose_symmetry_on_the_full_tank(precision, kernel):
+def test_transpose_symmetry_on_the_full_tank(precision, kernel, options):
     """The scheme is the same with x and y exchanged (per-axis slopes and limiters, the flux
     rotated to each face, the pressure gradient's x and y forms, the symmetric pseudo-time step),
     so a tank symmetric about its diagonal stays symmetric: rho and p equal their transposes and
     rho u that of rho v.  The row-marching kernel takes the x faces across the lanes of a wave
     and the y faces down its march, and the tiles are 32 x 8, so this holds the two code paths
     of every cell against each other."""
+    kw, bdf = OPTIONS[options]
     wk = corner_dam_break()
+    wk.bdf = bdf
     t = wk.tanks[0]
     assert np.array_equal(t.q[0], t.q[0].T) and np.array_equal(t.solid, t.solid.T)
     shape = SHAPES[(precision, kernel)]
-    print(f"[invariants] transpose: {wk.name} {precision} shape {shape}, 2 steps x 10 "
+    print(f"[invariants] transpose: {wk.name} {precision} shape {shape} {options}, 3 steps x 10 "
           f"pseudo-iterations", flush=True)
-    q = run(wk, precision, shape, steps=2, pseudo=10)
+    q = run(wk, precision, shape, steps=3, pseudo=10, **kw)
     fluid = t.solid == 0
     sc = field_scales(t)
     pairs = [(q[0], q[0].T), (q[1], q[2].T), (q[2], q[1].T), (q[3], q[3].T)]
