@@ -266,8 +266,10 @@ def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
             roofline = {"bound": "hbm" if resident else "llc",
                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": None if traffic is None else round(traffic / 1e9, 6),
-                        "traffic_unit": "GB per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)",
+                        "traffic": None if traffic is None else int(round(traffic)),
+                        "traffic_unit": "bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)",
+                        "traffic_vs_algorithmic": (None if traffic is None
+                                                   else round(traffic / bytes_per_launch, 4)),
                         "kernel": "stage", "avg_launch_us": round(avg_s * 1e6, 3),
                         "launches": launches, "bytes_per_launch": bytes_per_launch,
                         "timed_ms_in_brackets": round(kms, 3),
