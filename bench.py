@@ -196,7 +196,8 @@ def measure(vdac, np, torch, wk, args, tune, tile, flux, pgrad, timing=True):
                   solid=t.solid) for t in wk.tanks]
     opts = vdac.make_options(precision=wk.precision, stages=wk.stages, alpha=wk.alpha, cfl=wk.cfl,
                              k=wk.k, bdf=wk.bdf, tile=tile, graph_iters=args.graph_iters,
-                             flux=flux, pgrad=pgrad, pk=args.pk, local_dtau=wk.local_dtau)
+                             flux=flux, pgrad=pgrad, pk=args.pk, local_dtau=wk.local_dtau,
+                             persistent=args.persistent)
     if tune and not args.unbatched:
         # untimed: the tuner times each candidate shape on scratch grids of the same tanks
         opts = vdac.autotune(tanks, opts, iters=5)
@@ -365,6 +366,8 @@ def main():
     ap.add_argument("--pk", type=float, default=1.0, help="k of the limiter on p")
     ap.add_argument("--global-dtau", action="store_true", help="one pseudo-time step per tank")
     ap.add_argument("--bdf", type=int, default=0, help="BDF order (0: the workload's)")
+    ap.add_argument("--persistent", action="store_true",
+                    help="one persistent launch per stage (row-marching kernel)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run that an FP64 line reports beside it")
     ap.add_argument("--no-extra", action="store_true",
@@ -436,7 +439,8 @@ def main():
                    "graph_iters": args.graph_iters,
                    "dt": wk.dt, "max_pseudo": wk.max_pseudo, "tol": wk.tol,
                    "rk_stages": wk.stages, "pseudo_iterations": iters, "flux": args.flux,
-                   "pgrad": args.pgrad, "local_dtau": bool(wk.local_dtau), "bdf": wk.bdf},
+                   "pgrad": args.pgrad, "local_dtau": bool(wk.local_dtau), "bdf": wk.bdf,
+                   "persistent": bool(args.persistent)},
         "roofline": roofline,
     }
     if args.workload == "sloshing_ensemble":

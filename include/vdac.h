@@ -101,6 +101,10 @@ typedef struct {
     int32_t flux;        /* VDAC_FLUX_* */
     int32_t pgrad;       /* VDAC_PGRAD_* */
     double p_limiter_k;  /* k of the limiter on p for VDAC_PGRAD_LIMITER / _SPLIT, in [1, 2] */
+    int32_t persistent;  /* row-marching kernel: 0 one wave per work unit of the stage launch;
+                            1 one persistent launch per stage, only as many workgroups as the
+                            chip holds at once, each wave looping over its share of the units
+                            (same results bit for bit); ignored by the other kernels */
 } vdac_options;
 /* Options other than the defaults of flux, pgrad and local_dtau, BDF3 and zero-gradient sides
  * run on the row-marching and tiled stage kernels, not on the one-thread-per-cell kernel (tile
@@ -108,7 +112,7 @@ typedef struct {
 
 /* Fills o with the defaults: FP64, 3 stages alpha = (1/3, 1/2, 1), CFL_tau 0.48, minmod,
  * local dtau, backward Euler, RMS norm, no-slip walls, automatic tiles, automatic graphs, Osher
- * flux, new pressure gradient. */
+ * flux, new pressure gradient, one wave per work unit (not persistent). */
 void vdac_default_options(vdac_options *o);
 
 /* Device bytes create_grid needs for these tanks and options (0 on invalid arguments). */

@@ -146,6 +146,8 @@ int check_options(const vdac_options *o)
         return fail(VDAC_E_INVALID, "norm must be VDAC_NORM_RMS or VDAC_NORM_MAX");
     if (o->wall_slip != 0 && o->wall_slip != 1)
         return fail(VDAC_E_INVALID, "wall_slip must be 0 or 1");
+    if (o->persistent != 0 && o->persistent != 1)
+        return fail(VDAC_E_INVALID, "persistent must be 0 or 1");
     if (o->graph_iters < -1 || o->graph_iters > 1000)
         return fail(VDAC_E_INVALID, "graph_iters must lie in [-1, 1000]");
     const bool auto_tile = o->tile_x == 0 && o->tile_y == 0;
@@ -864,6 +866,9 @@ int launch_iterations(vdac_grid *g, hipStream_t stream, int n_iter, int first_it
         ia.cur_off = cur_of_iter(first_iter + it, g->sc.smax);
         ia.n_fin = 0;
         ia.n_tanks = nt;
+        ia.persist = g->opt.persistent;
+        ia.stride = 0;
+        ia.n_entries = 0;
         for (int s = 1; s <= g->sc.smax; ++s) {
             ia.fin = (defer && s == 1 && it > 0) ? 1 : 0;
             if (pl.kind == KIND_MARCH) {
@@ -1254,7 +1259,8 @@ std::string tune_key(const vdac_tank *tanks, int n_tanks, const vdac_options *o)
     std::string k = std::to_string(o->precision) + "/" + std::to_string(o->rk_stages) + "/" +
                     std::to_string(o->bdf_order) + "/" + std::to_string(o->norm) + "/" +
                     std::to_string((int)o->limiter_k) + "/" + std::to_string(o->flux) + "/" +
-                    std::to_string(o->pgrad) + "/" + std::to_string(o->local_dtau);
+                    std::to_string(o->pgrad) + "/" + std::to_string(o->local_dtau) + "/" +
+                    std::to_string(o->persistent);
     for (int t = 0; t < n_tanks; ++t)
         k += ":" + std::to_string(tanks[t].nx) + "x" + std::to_string(tanks[t].ny) + "/" +
              std::to_string(tanks[t].bc[0]) + std::to_string(tanks[t].bc[1]) +

@@ -57,6 +57,10 @@ struct IterArgs {
     int32_t fin;
     int32_t n_fin;
     int32_t n_tanks;
+    int32_t persist;    // host side: launch the row-marching kernel persistently
+    int32_t stride;     // row-marching kernel: 0 one unit per wave; > 0 a persistent launch, whose
+                        // waves take every stride-th entry of the unit table
+    int32_t n_entries;  // row-marching kernel: entries in the unit table
 };
 
 

@@ -61,6 +61,7 @@ class Options(ctypes.Structure):
         ("flux", ctypes.c_int32),
         ("pgrad", ctypes.c_int32),
         ("p_limiter_k", ctypes.c_double),
+        ("persistent", ctypes.c_int32),
     ]
 
 
@@ -152,7 +153,7 @@ def default_options() -> Options:
 
 def make_options(precision="f64", stages=3, alpha=(1.0 / 3.0, 0.5, 1.0), cfl=0.48, k=1.0,
                  bdf=1, norm=NORM_RMS, wall_slip=False, tile=(0, 0), graph_iters=0, flux=0,
-                 pgrad=0, pk=1.0, local_dtau=True) -> Options:
+                 pgrad=0, pk=1.0, local_dtau=True, persistent=False) -> Options:
     o = default_options()
     o.precision = {"f64": FP64, "mixed": FP32_MIXED}[precision] if isinstance(precision, str) \
         else int(precision)
@@ -168,6 +169,7 @@ def make_options(precision="f64", stages=3, alpha=(1.0 / 3.0, 0.5, 1.0), cfl=0.4
     o.graph_iters = int(graph_iters)
     o.flux, o.pgrad, o.p_limiter_k = int(flux), int(pgrad), float(pk)
     o.local_dtau = int(bool(local_dtau))
+    o.persistent = int(bool(persistent))
     return o
 
 

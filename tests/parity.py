@@ -10,11 +10,11 @@ from paper_2108_08769_amd import workloads as wl
 
 
 def gpu_options(wk: wl.Workload, precision=None, norm=0, wall_slip=False, tile=(0, 0),
-                graph_iters=0, flux=0, pgrad=0, pk=1.0):
+                graph_iters=0, flux=0, pgrad=0, pk=1.0, persistent=False):
     return vdac.make_options(precision=precision or wk.precision, stages=wk.stages,
                              alpha=wk.alpha, cfl=wk.cfl, k=wk.k, bdf=wk.bdf, norm=norm,
                              wall_slip=wall_slip, tile=tile, graph_iters=graph_iters, flux=flux,
-                             pgrad=pgrad, pk=pk, local_dtau=wk.local_dtau)
+                             pgrad=pgrad, pk=pk, local_dtau=wk.local_dtau, persistent=persistent)
 
 
 def oracle_problem(t: wl.Tank, wk: wl.Workload, wall_slip=False, flux=0, pgrad=0, pk=1.0):

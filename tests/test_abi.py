@@ -121,6 +121,7 @@ def _create(tanks, opt):
     (lambda t, o: setattr(o, "local_dtau", 2), "local"),
     (lambda t, o: setattr(o, "flux", 3), "flux"),
     (lambda t, o: setattr(o, "pgrad", 3), "pgrad"),
+    (lambda t, o: setattr(o, "persistent", 2), "persistent"),
     (lambda t, o: (setattr(o, "pgrad", 1), setattr(o, "p_limiter_k", 3.0)), "p_limiter_k"),
     (lambda t, o: (setattr(o, "flux", 1), setattr(o, "tile_x", 1), setattr(o, "tile_y", 1)),
      "one-thread-per-cell"),
@@ -205,6 +206,7 @@ _OPT_OK = {
     "tile": st.sampled_from([(0, 0), (1, 1), (32, 8), (16, 16), (64, 4), (3208, 2), (1616, 2),
                              (1608, 2), (-2, 16), (-3, 5), (-1, 1)]),
     "flux": st.integers(0, 2), "pgrad": st.integers(0, 2), "p_limiter_k": st.floats(1.0, 2.0),
+    "persistent": st.integers(0, 1),
 }
 _OPT_BAD = {
     "precision": st.sampled_from([-1, 2]), "rk_stages": st.sampled_from([0, 9]),
@@ -214,7 +216,7 @@ _OPT_BAD = {
     "graph_iters": st.sampled_from([-2, 1001]),
     "tile": st.sampled_from([(-4, 8), (32, 9), (0, 5), (-2, 0)]),
     "flux": st.sampled_from([-1, 3]), "pgrad": st.sampled_from([-1, 3]),
-    "p_limiter_k": st.sampled_from([0.5, 2.5]),
+    "p_limiter_k": st.sampled_from([0.5, 2.5]), "persistent": st.sampled_from([-1, 2]),
 }
 
 
@@ -251,6 +253,7 @@ def test_workspace_bytes_and_create_grid_agree(args):
     o.bdf_order, o.norm, o.wall_slip = opt["bdf_order"], opt["norm"], opt["wall_slip"]
     o.graph_iters, o.tile_x, o.tile_y = opt["graph_iters"], opt["tile"][0], opt["tile"][1]
     o.flux, o.pgrad, o.p_limiter_k = opt["flux"], opt["pgrad"], opt["p_limiter_k"]
+    o.persistent = opt["persistent"]
     ws = vdac.workspace_bytes(structs, o)
     arr = (vdac.Tank * len(structs))(*structs)
     h = ctypes.c_void_p()

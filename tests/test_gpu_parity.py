@@ -577,3 +577,77 @@ def test_set_state_rejects_bad_density():
         assert e.value.code == vdac.VDAC_E_INVALID
     finally:
         grid.close()
+
+
+# ---- one persistent launch per stage -------------------------------------------------------
+
+def _run_both(wk, shape, steps, pseudo, tol, precision, **kw):
+    """The same run with one wave per unit and with persistent launches: states, iteration
+    counts and norms of each."""
+    tanks = [dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc,
+                  solid=t.solid) for t in wk.tanks]
+    out = []
+    for persistent in (False, True):
+        grid = vdac.Grid(tanks, gpu_options(wk, precision, tile=shape, persistent=persistent, **kw))
+        try:
+            for i, t in enumerate(wk.tanks):
+                grid.set_state(i, t.q)
+            its = []
+            for _ in range(steps):
+                rc, done = grid.step(wk.dt, pseudo, tol, check=False)
+                assert rc == 0, rc
+                its.append(np.asarray(done).copy())
+            out.append(([grid.get_state(i) for i in range(len(wk.tanks))], np.array(its),
+                        np.array([grid.residual_norm(i) for i in range(len(wk.tanks))])))
+        finally:
+            grid.close()
+    return out
+
+
+def _assert_same(a, b):
+    for x, y in zip(a[0], b[0]):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_persistent_launch_on_the_full_ensemble(precision):
+    """The 512-tank ensemble in the bench's shape (row marching, chunks of 16 rows, 4 waves per
+    workgroup): 13k units; the persistent launch holds 512 workgroups, so every wave takes about
+    26 units in turn.  Bit for bit the one-wave-per-unit launch."""
+    wk = wl.sloshing_ensemble(precision=precision)
+    print(f"[persistent] ensemble {precision}", flush=True)
+    a, b = _run_both(wk, (-2, 16), steps=2, pseudo=5, tol=0.0, precision=precision)
+    _assert_same(a, b)
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_persistent_launch_with_tanks_stopping_apart(precision):
+    """64 tanks of the ensemble with a tolerance (50, on the residual norms of rho, rho u,
+    rho v and p, the last of them about 40 to 100 in these tanks), so that tanks stop at different
+    pseudo-iterations while their units still come up in the persistent waves' loops (a stopped
+    tank's unit is skipped and the wave goes on to its next one); chunks of one row (27k units)."""
+    full = wl.sloshing_ensemble(precision=precision)
+    wk = wl.Workload("ensemble_64", full.tanks[:64], dt=full.dt, steps=1, max_pseudo=1,
+                     precision=precision)
+    print(f"[persistent] 64 tanks with a tolerance, {precision}", flush=True)
+    a, b = _run_both(wk, (-2, 1), steps=2, pseudo=60, tol=50.0, precision=precision)
+    assert len(np.unique(a[1][-1])) > 1, a[1]        # the tanks did stop apart
+    _assert_same(a, b)
+
+
+@pytest.mark.parametrize("local_dtau", [True, False], ids=["local", "global"])
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_persistent_launch_general_kernel(precision, local_dtau):
+    """The general kernel (Roe flux, k-limiter on p; local pseudo-time steps, whose finalize of
+    the previous iteration runs in workgroups in front of stage 1, or one global step) with BDF3
+    on the 512 x 256 dam break in chunks of one row (2304 units, one wave per workgroup, 2048 of
+    them in the persistent launch)."""
+    wk = wl.dam_break(precision=precision)
+    wk.local_dtau = local_dtau
+    wk.bdf = 3
+    print(f"[persistent] general kernel, {precision}, local dtau {local_dtau}", flush=True)
+    a, b = _run_both(wk, (-2, 1), steps=4, pseudo=6, tol=0.0, precision=precision,
+                     flux=1, pgrad=1, pk=1.5)
+    _assert_same(a, b)
