@@ -663,7 +663,7 @@ __global__ void __launch_bounds__(kLanes *kMaxWavesPerBlock, WAVES)
             auto sum = [](double a, double b) { return a + b; };
             auto mx = [](double a, double b) { return combine<true>(a, b); };
             auto mn = [](double a, double b) { return fmin(a, b); };
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < kPartialWidth; ++k) {
                 const double x = (k == 5) ? wave_reduce_to_lane63(part[k], INFINITY, mn)
                                           : ((NORM_MAX && k < 4) ? wave_reduce_to_lane63(part[k], 0.0, mx)
