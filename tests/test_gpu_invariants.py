@@ -25,6 +25,9 @@ paper's scheme fixes.
 * Hydrostatic balance (Sec. 2.3.2): the exact discrete two-layer hydrostatic state stays at rest
   around the benchmark's obstacle; measured momenta 1.2e-13 (FP64) and 7.5e-12 (mixed), pressure
   changes 3.7e-16 and 1.0e-14 of its largest value.
+* The steady state does not depend on the pseudo-time CFL number: the 64 x 64 two-layer tank run
+  to residuals below 1e-9 with CFL_tau 0.48 and 0.3 (69k and 111k pseudo-iterations) ends in the
+  same pressure to 2.5e-15 with momenta of 4.7e-10.
 
 FP64 bars: total mass to 1e-13 relative; mirror and transpose differences to 1e-12 of each
 field's physical scale.  The mixed form stores the state as FP32 deviations from level n,
@@ -345,3 +348,36 @@ def test_mass_conserved_in_every_tank_of_the_ensemble(precision):
           f"{bar[worst]:.2e})", flush=True)
     assert change.max() > 1e-6
     assert np.all(rel <= bar), (worst, rel[worst], bar[worst])
+
+
+@pytest.mark.parametrize("kernel", ["march", "tile"])
+def test_steady_state_independent_of_the_pseudo_time_cfl(kernel):
+    """At the incompressible limit the pseudo-time path does not matter (Algorithm 1 iterates
+    to the state whose pseudo-time derivative vanishes): the 64 x 64 two-layer tank of the first
+    benchmark configuration, from p = 0, run to residual norms below 1e-9 with CFL_tau 0.48 and
+    0.3 (local steps, one real step of 1e-2), reaches the same state: p minus its mean (local
+    steps do not keep the total p) to 1e-8 of its size, momenta below 1e-8."""
+    from paper_2108_08769_amd import workloads as wl2
+    shape = (-2, 1) if kernel == "march" else (32, 8)
+    outs, its = [], []
+    for cfl in (0.48, 0.3):
+        wk = wl2.hydrostatic()
+        wk.cfl = cfl
+        t = wk.tanks[0]
+        tank = dict(nx=t.nx, ny=t.ny, lx=t.lx, ly=t.ly, gx=t.gx, gy=t.gy, beta=t.beta, bc=t.bc)
+        grid = vdac.Grid([tank], gpu_options(wk, "f64", tile=shape))
+        try:
+            grid.set_state(0, t.q)
+            rc, done = grid.step(1e-2, 200000, 1e-9, check=False)
+            assert rc == 0 and int(done[0]) < 200000, (rc, done)
+            outs.append(grid.get_state(0))
+            its.append(int(done[0]))
+        finally:
+            grid.close()
+    p0 = outs[0][3] - outs[0][3].mean()
+    p1 = outs[1][3] - outs[1][3].mean()
+    dp = np.abs(p0 - p1).max() / np.abs(p0).max()
+    mom = max(np.abs(o[1:3]).max() for o in outs)
+    print(f"[invariants] steady state, {kernel}: {its} iterations (CFL 0.48, 0.3), p difference "
+          f"{dp:.2e} of max |p - mean|, momenta {mom:.2e}", flush=True)
+    assert dp <= 1e-8 and mom <= 1e-8, (dp, mom)
