@@ -292,3 +292,26 @@ def test_general_kernel_batch_equals_single_tanks():
         got = unreflect_state(single[0][0]) if tr else single[0][0]
         np.testing.assert_array_equal(batch[0][i], got, err_msg=f"tank {i} (transposed {tr})")
     assert [stored_transposed_in_batch(t) for t in tanks] == [False, False, True]
+
+
+def test_pressure_gradient_comparison_of_sec_3_3_1():
+    """The first real step of the 20 x 20 dam break of Sec. 3.3.1 (Osher, minmod on rho, u, v,
+    three stages, CFL 0.48, local steps, dt = 0.01, beta = 1100; water at x < 0.4, y < 0.8 of the
+    unit square; 3000 pseudo-iterations) with the new pressure gradient and the split limiter
+    with superbee and with minmod: each against the oracle at the FP64 bar, and the paper's
+    ordering of how much the water beside the free surface is compressed (the new method least,
+    the split minmod limiter most) on the GPU."""
+    n = 20
+    xc = (np.arange(n) + 0.5) / n
+    q = np.zeros((4, n, n))
+    q[0] = np.where((xc[None, :] < 0.4) & (xc[:, None] < 0.8), 1000.0, 1.0)
+    comp = {}
+    for name, pgrad, pk in [("new", NEW, 1.0), ("split-superbee", SPLIT, 2.0),
+                            ("split-minmod", SPLIT, 1.0)]:
+        wk = wl.Workload(f"sec331_{name}", [wl.Tank(n, n, 1.0, 1.0, q, gy=-9.81, beta=1100.0)],
+                         dt=0.01, steps=1, max_pseudo=1)
+        check(wk, steps=1, pseudo=3000, pgrad=pgrad, pk=pk)
+        states = run_gpu(wk, 1, 3000, pgrad=pgrad, pk=pk)[0]
+        comp[name] = states[0][0, 0, 7] - 1000.0     # lowest row, the cell left of x = 0.4
+    print(f"[next] Sec. 3.3.1 compression of the water beside the surface: {comp}", flush=True)
+    assert 0.0 < comp["new"] < comp["split-superbee"] < comp["split-minmod"], comp
