@@ -315,3 +315,35 @@ def test_pressure_gradient_comparison_of_sec_3_3_1():
         comp[name] = states[0][0, 0, 7] - 1000.0     # lowest row, the cell left of x = 0.4
     print(f"[next] Sec. 3.3.1 compression of the water beside the surface: {comp}", flush=True)
     assert 0.0 < comp["new"] < comp["split-superbee"] < comp["split-minmod"], comp
+
+
+@pytest.mark.parametrize("method", ["new", "split-minmod", "split-superbee", "minmod", "superbee"])
+def test_hydrostatic_comparison_of_sec_3_2(method):
+    """Sec. 3.2: a 20-cell column (gravity 9.81 along x, water on the +x half, beta = 2000, local
+    pseudo-time steps at CFL 0.98, one real step of dt = 0.05 from rest with p = 0,
+    pseudo-iterations until every residual norm is below 1e-5).  The GPU stops at the oracle's iteration with the
+    oracle's state; the new gradient and the split limiters end at rest (|u| < 1e-8), the
+    k-limiter applied to p (minmod, superbee) leaves spurious speeds (|u| > 1e-6)."""
+    pgrad, pk = {"new": (NEW, 1.0), "split-minmod": (SPLIT, 1.0), "split-superbee": (SPLIT, 2.0),
+                 "minmod": (LIMITER, 1.0), "superbee": (LIMITER, 2.0)}[method]
+    nx = 20
+    xc = (np.arange(nx) + 0.5) / nx
+    q = np.zeros((4, 1, nx))
+    q[0] = np.where(xc > 0.5, 1000.0, 1.0)
+    wk = wl.Workload(f"sec32_{method}", [wl.Tank(nx, 1, 1.0, 1.0 / nx, q, gx=9.81, gy=0.0,
+                                                  beta=2000.0)],
+                     dt=0.05, steps=1, max_pseudo=1, cfl=0.98)
+    g = run_gpu(wk, 1, 20000, tol=1e-5, pgrad=pgrad, pk=pk)
+    o = run_oracle(wk, 1, 20000, tol=1e-5, pgrad=pgrad, pk=pk)
+    assert g[3] == [0] and o[3] == [0], (g[3], o[3])
+    np.testing.assert_array_equal(g[1], o[1])
+    t = wk.tanks[0]
+    err = field_errors(g[0][0], o[0][0], None, field_scales(t))
+    umax = np.abs(g[0][0][1] / g[0][0][0]).max()
+    print(f"[next] Sec. 3.2 {method}: {int(g[1][0, 0])} pseudo-iterations, max |u| {umax:.3e}, "
+          f"field errors {err}", flush=True)
+    assert np.all(err <= TOL), err
+    if method in ("new", "split-minmod", "split-superbee"):
+        assert umax < 1e-8
+    else:
+        assert umax > 1e-6
