@@ -140,7 +140,7 @@ def rp_workload(rp, nx):
 
 
 @pytest.mark.parametrize("flux", [OSHER, ROE, BASSI])
-@pytest.mark.parametrize("rp_index", [0, 1, 4])
+@pytest.mark.parametrize("rp_index", [0, 1, 2, 3, 4])
 def test_riemann_problems_of_table2(rp_index, flux):
     rp = table2()[rp_index]
     wk = rp_workload(rp, 100)
