@@ -249,10 +249,11 @@ def test_general_options_on_tiles(case, tile):
 
 @pytest.mark.parametrize("tile", [(64, 4), (3208, 2), (1608, 2)])
 @pytest.mark.parametrize("flux", [OSHER, BASSI])
-def test_riemann_problem_on_tiles(flux, tile):
-    """RP1 of Table 2 (a tank one cell tall: zero-gradient sides, global step, no real-time term)
-    in the tiled kernel against the oracle."""
-    rp = table2()[0]
+@pytest.mark.parametrize("rp_index", [0, 1, 2, 3, 4])
+def test_riemann_problem_on_tiles(rp_index, flux, tile):
+    """The Riemann problems of Table 2 (a tank one cell tall: zero-gradient sides, global step,
+    no real-time term) in the tiled kernel against the oracle."""
+    rp = table2()[rp_index]
     wk = rp_workload(rp, 100)
     t = wk.tanks[0]
     scales = np.array([np.abs(t.q[0]).max(), np.abs(t.q[0]).max() * 10.0,
